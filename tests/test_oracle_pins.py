@@ -1,0 +1,406 @@
+"""Pins of the FP64 oracle against what the paper and the mathematics fix.
+
+None of these compares the oracle with itself: every expected value is a
+closed form, a textbook property, a number printed in the paper, or an
+invariant, chosen so that a dropped term, a wrong sign, a wrong index or a
+transposed table fails at least one of them.
+"""
+import math
+import os
+
+import numpy as np
+import pytest
+
+from oracle import fc_table
+from oracle.fcgram import FCGram, fc_derivative_lines, fc_extend_lines
+from oracle.ns import Oracle, Problem
+import workloads as W
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _read_kv(name):
+    out = {}
+    for line in open(os.path.join(GOLDEN, name)):
+        if line.startswith("#") or not line.strip():
+            continue
+        k, v = line.split()
+        out[k] = float(v)
+    return out
+
+
+# ---------------------------------------------------------------- FC tables
+@pytest.mark.parametrize("d,C", [(5, 25), (5, 31)])
+def test_gram_basis_orthonormal(d, C):
+    Q, A, M, K = fc_table.fc_tables(d, C)
+    assert np.abs(Q.T @ Q - np.eye(d)).max() < 1e-15
+    # Q spans the polynomials of degree < d on the matching points: the
+    # projector Q Q^T reproduces every monomial t^k, k < d
+    t = np.arange(d, dtype=float)
+    for k in range(d):
+        assert np.abs(Q @ (Q.T @ t ** k) - t ** k).max() < 1e-11 * max(1, (d - 1) ** k)
+
+
+@pytest.mark.parametrize("d,C", [(5, 25), (5, 31)])
+def test_blend_fit_residuals(d, C):
+    assert max(fc_table.fit_residuals(d, C)) <= 1e-16
+
+
+def test_table_size_matches_paper():
+    # App. B: "231 numbers" for the C = 33, d = 7 tables used in the paper
+    _, A, _, _ = fc_table.fc_tables(7, 33)
+    assert A.size == 231
+
+
+def test_continuation_composition():
+    # M_r = A_r Q_r^T (App. B, block form A f = A_l Q_l^T f_l + A_r Q_r^T f_r)
+    Q, A, M, _ = fc_table.fc_tables(5, 25)
+    assert np.abs(M - A @ Q.T).max() < 1e-12 * np.abs(M).max()
+
+
+# ------------------------------------------------------------ fc_extend
+def _demo():
+    g = _read_kv("fc_demo_function.txt")
+    a, b, e = g["a"], g["b"], g["g"]
+    f = lambda z: np.sin(a * z) * np.sin(b * z) * np.exp(e * z)  # noqa: E731
+    df = lambda z: (a * np.cos(a * z) * np.sin(b * z) + b * np.sin(a * z) * np.cos(b * z)  # noqa: E731
+                    + e * np.sin(a * z) * np.sin(b * z)) * np.exp(e * z)
+    return g, f, df
+
+
+def test_extend_identity_and_linearity():
+    r = W.rng(11)
+    f = r.standard_normal((7, 41))
+    g = r.standard_normal((7, 41))
+    ef = fc_extend_lines(f, 5, 25)
+    assert ef.shape == (7, 66)
+    assert np.array_equal(ef[:, :41], f)
+    eg = fc_extend_lines(g, 5, 25)
+    efg = fc_extend_lines(2.0 * f - 3.0 * g, 5, 25)
+    assert np.abs(efg - (2 * ef - 3 * eg)).max() < 1e-10
+
+
+def test_extension_is_smooth_periodic_on_paper_example():
+    # Sec. 3 worked example: the continued data is periodic without Gibbs
+    # ringing, i.e. its Fourier coefficients decay, unlike the plain data's
+    g, f, _ = _demo()
+    n, C, d = int(g["n"]), int(g["C"]), int(g["d"])
+    z = np.linspace(0.0, 1.0, n)
+    fc = fc_extend_lines(f(z)[None], d, C)[0]
+    spec_c = np.abs(np.fft.rfft(fc)) / (n + C)
+    spec_p = np.abs(np.fft.rfft(f(z))) / n
+    assert spec_c[-5:].max() < 1e-3 * spec_c.max()
+    assert spec_p[-5:].max() > 1e-3 * spec_p.max()     # Gibbs without FC
+
+
+# ------------------------------------------------------------ fc_derivative
+def test_fc_derivative_high_order_convergence():
+    _, f, df = _demo()
+    errs = []
+    ns = (65, 129, 257, 513)
+    for n in ns:
+        z = np.linspace(0.0, 1.0, n)
+        d1 = fc_derivative_lines(f(z)[None], 5, 25, 1.0, 1)[0]
+        errs.append(np.abs(d1 - df(z)).max())
+    rates = [math.log2(errs[i] / errs[i + 1]) for i in range(len(errs) - 1)]
+    assert min(rates) > 3.5, (errs, rates)
+    assert errs[-1] < 1e-5
+
+
+def test_fc_derivative_interior_better_than_boundary():
+    _, f, df = _demo()
+    n = 257
+    z = np.linspace(0.0, 1.0, n)
+    e = np.abs(fc_derivative_lines(f(z)[None], 5, 25, 1.0, 1)[0] - df(z))
+    assert e[n // 4: 3 * n // 4].max() < 0.05 * e.max()
+
+
+def test_fc_second_derivative_convergence():
+    gk, f, _ = _demo()
+    a, b, g = gk["a"], gk["b"], gk["g"]
+
+    def d2(z):
+        # second derivative of sin(az) sin(bz) e^{gz}, by the product rule
+        s1, c1, s2, c2, e = np.sin(a * z), np.cos(a * z), np.sin(b * z), np.cos(b * z), np.exp(g * z)
+        u = s1 * s2
+        du = a * c1 * s2 + b * s1 * c2
+        ddu = -(a * a + b * b) * s1 * s2 + 2 * a * b * c1 * c2
+        return (ddu + 2 * g * du + g * g * u) * e
+    errs = []
+    for n in (129, 257, 513):
+        z = np.linspace(0.0, 1.0, n)
+        errs.append(np.abs(fc_derivative_lines(f(z)[None], 5, 25, 1.0, 2)[0] - d2(z)).max())
+    assert math.log2(errs[0] / errs[1]) > 2.5 and math.log2(errs[1] / errs[2]) > 2.5, errs
+
+
+def test_fc_derivative_mirror():
+    # z -> Lz - z maps the derivative of a line to minus the reversed
+    # derivative; this pins the left table M_l = J M_r J
+    r = W.rng(12)
+    z = np.linspace(0, 1, 97)
+    f = np.cos(3 * z + 0.4) * np.exp(z) + 0.1 * r.standard_normal() * z ** 3
+    d1 = fc_derivative_lines(f[None], 5, 25, 1.0, 1)[0]
+    d1m = fc_derivative_lines(f[::-1][None], 5, 25, 1.0, 1)[0]
+    assert np.abs(d1m + d1[::-1]).max() < 1e-10 * np.abs(d1).max()
+
+
+def test_fc_derivative_of_polynomial_low_degree():
+    # Gram projection is exact on degree < d: derivatives of low-degree
+    # polynomials are accurate to the blend fit residual level
+    z = np.linspace(0, 2.0, 65)
+    f = 1.0 + 0.5 * z - 0.25 * z ** 2
+    d1 = fc_derivative_lines(f[None], 5, 25, 2.0, 1)[0]
+    assert np.abs(d1 - (0.5 - 0.5 * z)).max() < 1e-9
+
+
+# ------------------------------------------------------------ periodic derivatives
+def _oracle(nx=16, ny=12, nz=33, lx=2 * np.pi, ly=3.0, lz=1.0, **kw):
+    return Oracle(Problem(nx=nx, ny=ny, nz=nz, lx=lx, ly=ly, lz=lz, nu=kw.pop("nu", 0.0),
+                          C=kw.pop("C", 25), **kw))
+
+
+def test_periodic_derivatives_exact_on_trig_polynomials():
+    o = _oracle()
+    x, y, z = W.grid(16, 12, 33, 2 * np.pi, 3.0, 1.0)
+    X, Y = np.meshgrid(x, y, indexing="xy")
+    ky = 2 * np.pi * 2 / 3.0
+    f2 = np.cos(3 * X) * np.sin(ky * Y)
+    f = (1 + z)[:, None, None] * f2[None]
+    q, dx, dy, dz = o._phys_with_grad(o.to_spec(f))
+    assert np.abs(q - f).max() < 1e-13
+    assert np.abs(dx - (1 + z)[:, None, None] * (-3 * np.sin(3 * X) * np.sin(ky * Y))[None]).max() < 1e-12
+    assert np.abs(dy - (1 + z)[:, None, None] * (ky * np.cos(3 * X) * np.cos(ky * Y))[None]).max() < 1e-12
+    assert np.abs(dz - f2[None]).max() < 1e-9
+
+
+# ------------------------------------------------------------ rhs_nonlinear
+def _analytic_v(x, y, z, lx, ly):
+    X, Y = np.meshgrid(x, y, indexing="xy")
+    k1, k2 = 2 * np.pi / lx, 2 * np.pi / ly
+    Z = z[:, None, None]
+    u = np.sin(k1 * X)[None] * (Z * (1 - Z) + 0.3)
+    v = np.cos(k2 * Y)[None] * np.exp(-Z)
+    w = (np.sin(k1 * X) * np.cos(k2 * Y))[None] * Z ** 2
+    ux = k1 * np.cos(k1 * X)[None] * (Z * (1 - Z) + 0.3)
+    uz = np.sin(k1 * X)[None] * (1 - 2 * Z)
+    vy = -k2 * np.sin(k2 * Y)[None] * np.exp(-Z)
+    vz = -v
+    wx = (k1 * np.cos(k1 * X) * np.cos(k2 * Y))[None] * Z ** 2
+    wy = (-k2 * np.sin(k1 * X) * np.sin(k2 * Y))[None] * Z ** 2
+    wz = (np.sin(k1 * X) * np.cos(k2 * Y))[None] * 2 * Z
+    nl_u = -(u * ux + w * uz)
+    nl_v = -(v * vy + w * vz)
+    nl_w = -(u * wx + v * wy + w * wz)
+    th = np.cos(k1 * X)[None] * np.sin(np.pi * Z)
+    thx = -k1 * np.sin(k1 * X)[None] * np.sin(np.pi * Z)
+    thz = np.pi * np.cos(k1 * X)[None] * np.cos(np.pi * Z)
+    nl_t = -(u * thx + w * thz)
+    return np.stack([u, v, w]), np.stack([nl_u, nl_v, nl_w]), th, nl_t
+
+
+def test_rhs_nonlinear_closed_form():
+    errs = []
+    for nz in (33, 65, 129):
+        o = _oracle(nx=16, ny=16, nz=nz, lx=2.0, ly=2.0, lz=1.0, boussinesq=True)
+        x, y, z = W.grid(16, 16, nz, 2.0, 2.0, 1.0)
+        v, nl, th, nlt = _analytic_v(x, y, z, 2.0, 2.0)
+        got, gott = o.rhs_nonlinear(v, th)
+        errs.append(max(np.abs(got - nl).max(), np.abs(gott - nlt).max()))
+    assert errs[-1] < 1e-6 and errs[0] / errs[-1] > 50, errs
+
+
+# ------------------------------------------------------------ pressure projection
+def _manufactured(nz, seed=3):
+    nx, ny, lx, ly, lz = 16, 16, 2 * np.pi, 2 * np.pi, 1.0
+    x, y, z = W.grid(nx, ny, nz, lx, ly, lz)
+    vs = W.solenoidal_noise(nx, ny, nz, lx, ly, lz, 2, 2, 1.0, seed)
+    X, Y = np.meshgrid(x, y, indexing="xy")
+    Z = z[:, None, None]
+    # phi: periodic in x, y, not periodic in z (non-zero normal derivative)
+    P = np.exp(0.7 * Z) + Z ** 3
+    dP = 0.7 * np.exp(0.7 * Z) + 3 * Z ** 2
+    T = (np.cos(X + 2 * Y) + 0.5)[None]
+    gphi = np.stack([(-np.sin(X + 2 * Y))[None] * P, (-2 * np.sin(X + 2 * Y))[None] * P,
+                     T * dP])
+    return vs, gphi, (nx, ny, lx, ly, lz)
+
+
+def test_projection_manufactured_solution():
+    c = 0.5
+    errs, gerrs = [], []
+    for nz in (33, 65, 129):
+        vs, gphi, (nx, ny, lx, ly, lz) = _manufactured(nz)
+        o = _oracle(nx=nx, ny=ny, nz=nz, lx=lx, ly=ly, lz=lz)
+        v, gp = o.pressure_project(vs + gphi, c)
+        errs.append(np.abs(v - vs).max())
+        # wall tangential gradient in p units: grad_par(phi)/c at both walls
+        gerrs.append(max(np.abs(gp[0, i] - gphi[i][0] / c).max() +
+                         np.abs(gp[1, i] - gphi[i][-1] / c).max() for i in (0, 1)))
+    assert errs[-1] < 1e-6 and errs[0] / errs[-1] > 30, errs
+    assert gerrs[-1] < 1e-5, gerrs
+
+
+def test_projection_harmonic_pressure_removed():
+    # v* = grad phi with phi harmonic, phi = cos(x) cos(y) (a e^{g(z-Lz)} + b e^{-gz}),
+    # g = sqrt(2): the closed-form homogeneous solution of Sec. 4.2 removes it
+    nz = 65
+    o = _oracle(nx=8, ny=8, nz=nz, lx=2 * np.pi, ly=2 * np.pi, lz=1.0)
+    x, y, z = W.grid(8, 8, nz, 2 * np.pi, 2 * np.pi, 1.0)
+    X, Y = np.meshgrid(x, y, indexing="xy")
+    g = math.sqrt(2.0)
+    a, b = 0.7, -0.4
+    Z = z[:, None, None]
+    prof = a * np.exp(g * (Z - 1)) + b * np.exp(-g * Z)
+    dprof = g * (a * np.exp(g * (Z - 1)) - b * np.exp(-g * Z))
+    cc = (np.cos(X) * np.cos(Y))[None]
+    gphi = np.stack([(-np.sin(X) * np.cos(Y))[None] * prof,
+                     (-np.cos(X) * np.sin(Y))[None] * prof, cc * dprof])
+    v, _ = o.pressure_project(gphi, 1.0)
+    assert np.abs(v).max() < 1e-6
+
+
+def test_projection_mean_mode_D_term():
+    # a uniform normal velocity is removed entirely (the (0,0) mode, D term)
+    o = _oracle(nx=8, ny=8, nz=33)
+    vs = np.zeros((3, 33, 8, 8))
+    vs[2] = 0.37
+    v, _ = o.pressure_project(vs, 1.0)
+    assert np.abs(v[2]).max() < 1e-12
+
+
+def test_projection_wall_normal_velocity_and_divergence():
+    # Sec. 6: <w^2_wall> = O(1e-35) (zero to rounding) after the projection;
+    # FC divergence is small and decreases with resolution
+    divs = []
+    for nz in (33, 65):
+        o = _oracle(nx=16, ny=16, nz=nz, lx=2 * np.pi, ly=2 * np.pi)
+        vs = W.smooth_field(16, 16, nz, 2 * np.pi, 2 * np.pi, 1.0, 5)
+        vstar = np.stack([vs, np.roll(vs, 3, axis=2), np.roll(vs, 5, axis=1)])
+        Vs = [o.to_spec(a) for a in vstar]
+        Vn, _, _ = o.project(Vs, 1.0)
+        v = np.stack([o.to_phys(V) for V in Vn])
+        scale = np.sqrt(np.mean(vstar ** 2))
+        assert np.mean(v[2][0] ** 2) < 1e-28 * scale ** 2
+        assert np.mean(v[2][-1] ** 2) < 1e-28 * scale ** 2
+        divs.append(np.sqrt(np.mean(o.divergence(Vn) ** 2)) / scale)
+    assert divs[1] < divs[0] and divs[1] < 1e-3, divs
+
+
+# ------------------------------------------------------------ time stepping
+def _rk2_amp(z):
+    return 1.0 + z + 0.5 * z * z
+
+
+def test_scalar_diffusion_eigenmode_rk2_amplification():
+    # v = 0, gamma = 0: theta = cos(kx x) sin(pi z/Lz) decays per step by
+    # R(-lambda dt) = 1 - lambda dt + (lambda dt)^2/2 for o = 2 (up to FC error),
+    # visibly different from the exact exp(-lambda dt)
+    nz, kx, kappa, dt, n = 17, 12, 0.02, 0.02, 10
+    o = _oracle(nx=32, ny=8, nz=nz, lx=2 * np.pi, ly=2 * np.pi, lz=1.0,
+                boussinesq=True, kappa=kappa, gamma=0.0)
+    x, y, z = W.grid(32, 8, nz, 2 * np.pi, 2 * np.pi, 1.0)
+    X, _ = np.meshgrid(x, y, indexing="xy")
+    th0 = np.cos(kx * X)[None] * np.sin(np.pi * z)[:, None, None]
+    o.set_state(np.zeros((3, nz, 8, 32)), th0)
+    o.rk_step(dt, n)
+    v, th, _ = o.get_state()
+    lam = kappa * (kx ** 2 + np.pi ** 2)
+    assert np.abs(th - _rk2_amp(-lam * dt) ** n * th0).max() < 2e-5
+    assert np.abs(th - math.exp(-lam * dt * n) * th0).max() > 1e-4
+    assert np.abs(v).max() == 0.0
+
+
+def test_stokes_shear_mode_decay():
+    # u = cos(ky y) sin(pi z), v = w = 0 is solenoidal, has no advection and
+    # no pressure: it decays by R(-nu (ky^2 + pi^2) dt) per step
+    nz, ky, nu, dt, n = 17, 12, 0.02, 0.02, 10
+    o = _oracle(nx=8, ny=32, nz=nz, lx=2 * np.pi, ly=2 * np.pi, lz=1.0, nu=nu)
+    x, y, z = W.grid(8, 32, nz, 2 * np.pi, 2 * np.pi, 1.0)
+    _, Y = np.meshgrid(x, y, indexing="xy")
+    u0 = np.cos(ky * Y)[None] * np.sin(np.pi * z)[:, None, None]
+    o.set_state(np.stack([u0, 0 * u0, 0 * u0]))
+    o.rk_step(dt, n)
+    v, _, _ = o.get_state()
+    lam = nu * (ky ** 2 + np.pi ** 2)
+    assert np.abs(v[0] - _rk2_amp(-lam * dt) ** n * u0).max() < 2e-5
+    assert np.abs(v[0] - math.exp(-lam * dt * n) * u0).max() > 1e-4
+    assert np.abs(v[1:]).max() < 1e-12
+
+
+def test_poiseuille_held_steady():
+    # Sec. 6 laminar solution: a steady state of the step (drift at rounding)
+    w = W.get("channel_32x32x33")
+    o = Oracle(Problem(**w.problem_kwargs()))
+    x, y, z = W.grid(w.nx, w.ny, w.nz, w.lx, w.ly, w.lz)
+    U = W.laminar_profile(z, w.forcing_x, w.nu, w.lz)
+    v0 = np.zeros((3, w.nz, w.ny, w.nx))
+    v0[0] = U[:, None, None]
+    o.set_state(v0)
+    o.rk_step(w.dt, 100)
+    v, _, _ = o.get_state()
+    assert np.abs(v - v0).max() < 1e-10 * np.abs(U).max()
+
+
+def test_laminar_runs_reynolds_match_table1():
+    # Table 1, run L1: Re = Lz <v_x>/nu and Re_c = delta v_x(delta)/nu of the
+    # laminar profile with the printed mean gradient and viscosity (333 vs the
+    # printed 330, 250 vs 260); L1 is also held steady by the step at its
+    # printed grid.  (The printed Re of L2 and L3 exceed what their laminar
+    # profile gives by 5-11%, so those rows are kept for reference only.)
+    rows = [l.split() for l in open(os.path.join(GOLDEN, "table1_laminar.txt"))
+            if l.strip() and not l.startswith("#")]
+    for row in rows[:1]:
+        nx, ny, nz, C, d = map(int, row[1:6])
+        dp, nu, re, rec = map(float, row[6:10])
+        z = np.linspace(0, 1.0, 20001)
+        U = W.laminar_profile(z, dp, nu, 1.0)
+        re_got = np.trapezoid(U, z) / nu
+        rec_got = 0.5 * U[10000] / nu
+        assert abs(re_got / re - 1) < 0.015, (row[0], re_got)
+        assert abs(rec_got / rec - 1) < 0.05, (row[0], rec_got)
+    nx, ny, nz, C, d = map(int, rows[0][1:6])
+    dp, nu = float(rows[0][6]), float(rows[0][7])
+    o = Oracle(Problem(nx=nx, ny=ny, nz=nz, lx=4 * np.pi, ly=2 * np.pi, lz=1.0, nu=nu,
+                       d=d, C=C, forcing_x=dp))
+    z = np.arange(nz) / (nz - 1)
+    U = W.laminar_profile(z, dp, nu, 1.0)
+    v0 = np.zeros((3, nz, ny, nx))
+    v0[0] = U[:, None, None]
+    o.set_state(v0)
+    o.rk_step(1e-3, 50)
+    v, _, _ = o.get_state()
+    assert np.abs(v - v0).max() < 1e-10
+
+
+def test_channel_step_wall_and_divergence_invariants():
+    # Sec. 6: the normal wall velocity stays at rounding level and the mean
+    # squared divergence stays small and dt-independent
+    w = W.get("channel_32x32x33")
+    o = Oracle(Problem(**w.problem_kwargs()))
+    v0, _ = w.initial_state()
+    o.set_state(v0)
+    o.rk_step(w.dt, 10)
+    v, _, p = o.get_state()
+    assert np.isfinite(v).all() and np.isfinite(p).all()
+    assert np.mean(v[2][0] ** 2) < 1e-30 and np.mean(v[2][-1] ** 2) < 1e-30
+    assert np.mean(o.divergence(o.Vt) ** 2) < 1e-10
+
+
+def test_wall_slip_second_order_in_dt():
+    # Sec. 4.1/4.4 and Sec. 6 (wall slip figure): the tangential wall velocity
+    # left by the splitting is O(dt^o), here o = 2, so halving dt divides the
+    # rms slip by ~4 (an O(dt) scheme would give ~2).  At coarse resolution
+    # a dt-independent floor set by the FC divergence error appears below
+    # ~1e-6, so the pin uses dt large enough for the splitting term to lead.
+    slips = []
+    for dt in (1.6e-2, 8e-3):
+        w = W.channel(16, 16, 65, 1000.0, dt=dt, steps=int(round(0.064 / dt)),
+                      noise_rms=0.5, kmax=2, mmax=2)
+        o = Oracle(Problem(**w.problem_kwargs()))
+        v0, _ = w.initial_state()
+        o.set_state(v0)
+        o.rk_step(dt, w.steps)
+        v, _, _ = o.get_state()
+        slips.append(math.sqrt(np.mean(v[0][0] ** 2) + np.mean(v[1][0] ** 2)))
+    ratio = slips[0] / slips[1]
+    assert 3.5 < ratio < 4.5, (slips, ratio)
