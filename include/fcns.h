@@ -1,0 +1,147 @@
+/*
+ * fcns.h -- C ABI of the MI355X FC-Gram pseudospectral solver for
+ * incompressible flow in a cuboid with two periodic directions (x, y) and one
+ * walled direction (z), after Fontana, Bruno, Mininni & Dmitruk, "Fourier
+ * Continuation method for incompressible fluids with boundaries" (2020).
+ *
+ * Problem (Sec. 2): dv/dt + (v.grad)v = -grad p + nu lap v + G x
+ *                   [+ gamma theta z, Sec. 7],  div v = 0,
+ *                   v = 0 (and theta = 0) at z = 0 and z = Lz,
+ * periodic in x and y.  Grid: x_q = q Lx/nx, y_r = r Ly/ny,
+ * z_s = s Lz/(nz-1) (nz counts both walls).
+ *
+ * Conventions shared by all calls
+ *  - Pointers named in the signatures are DEVICE pointers unless a comment
+ *    says HOST.  The caller owns every pointer it passes; the context copies
+ *    what it keeps (the FC table) and owns all device state and scratch, which
+ *    is allocated once by fcns_create.  No call below fcns_create allocates.
+ *  - Physical fields are float64 arrays [nz][ny][nx] (x fastest); a vector
+ *    field is 3 such arrays back to back (x, y, z components).
+ *  - All work is enqueued on the HIP stream given to fcns_create and is
+ *    asynchronous with respect to the host; results are complete once that
+ *    stream is synchronized.  One context per stream; calls on one context
+ *    must not overlap.
+ *  - Errors are returned as status codes; fcns_last_error() gives a message.
+ *    The library never aborts the process.
+ */
+#ifndef FCNS_H
+#define FCNS_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct fcns_ctx fcns_ctx;
+
+typedef enum {
+  FCNS_OK = 0,
+  FCNS_EINVAL = -1,     /* bad argument, shape or unsupported size */
+  FCNS_ENOMEM = -2,     /* device allocation failed in fcns_create */
+  FCNS_EDEVICE = -3,    /* a HIP call or kernel launch failed */
+  FCNS_ENONFINITE = -4, /* a non-finite value was found in the state */
+  FCNS_ESTATE = -5      /* call out of order (e.g. rk_step before set_state) */
+} fcns_status;
+
+enum { FCNS_FP64 = 0, FCNS_MIXED = 1 };
+
+typedef struct {
+  int32_t nx, ny, nz;   /* nx, ny even; nz includes both walls; nz + C even
+                           (the continued length N' = nz + C, eq. k) */
+  double lx, ly, lz;    /* box lengths */
+  int32_t fc_d, fc_C;   /* matching points d and continuation points C (Sec. 3) */
+  const double* fc_table; /* HOST: Q_r (d x d, column j = Gram polynomial j at
+                             the d right matching points) followed by A_r (C x d,
+                             column j = blend-to-zero extension of Gram
+                             polynomial j at the C continuation points), both
+                             row-major float64 (App. B).  Copied at create. */
+  double nu;            /* kinematic viscosity */
+  double forcing_x;     /* body force G along +x (channel mean pressure
+                           gradient, Sec. 6); 0 for none */
+  int32_t boussinesq;   /* 1: also carry theta (Sec. 7) */
+  double kappa, gamma;  /* thermal diffusivity and buoyancy rate (Boussinesq) */
+  int32_t rk_order;     /* o of the time-splitting RK (Sec. 4.4); only 2 */
+  double filter_beta;   /* exponential filter (Sec. 4.3); 0 -> 16 ln 10 */
+  double filter_2p;     /* filter order 2p; 0 -> 100 */
+  int32_t precision;    /* FCNS_FP64 (only mode implemented) */
+  int32_t keep_pressure;/* 1: rk_step also keeps the pressure of its last stage
+                           (one extra mixed-space field write per step) */
+} fcns_problem;
+
+/* Create a context: validates the problem, builds the FFT plans, copies the
+ * FC table (forming M_r = A_r Q_r^T in extended precision on the host) and
+ * allocates all device buffers.  hip_stream: a hipStream_t (NULL = default
+ * stream).  On failure *out is NULL.  Limits: nx <= 512, ny <= 1024,
+ * N' = nz + C <= 512, at most 12 radix stages per transform length. */
+fcns_status fcns_create(const fcns_problem* prob, void* hip_stream, fcns_ctx** out);
+
+/* Release all device memory of the context (synchronizes its stream). */
+fcns_status fcns_destroy(fcns_ctx* ctx);
+
+/* FC-Gram continuation of real lines (Sec. 3, eq. fc:continuation; App. B):
+ * out[l*out_ls + s*out_ps] = in[l*in_ls + s*in_ps] for s < nz, and for
+ * s = nz + i (i < C): sum_j M_r[i][j] f[nz-d+j] + sum_j M_l[i][j] f[j] with
+ * M_l = J M_r J.  nlines >= 0 lines of the context's nz points.  in/out must
+ * not overlap.  Strides are in elements. */
+fcns_status fcns_fc_extend(fcns_ctx* ctx, const double* in, int64_t nlines, int64_t in_ps,
+                           int64_t in_ls, double* out, int64_t out_ps, int64_t out_ls);
+
+/* FC spectral derivative along z of real lines of nz points (Sec. 3 and the
+ * derivative rule of Sec. 4.2): out = R IFFT[(i k~z)^order FFT(E f)] for
+ * order 1 (Nyquist mode zeroed) and R IFFT[-kz^2 FFT(E f)] for order 2.
+ * Line l point s at in[l*ls + s*ps]; out uses the same strides. */
+fcns_status fcns_fc_derivative(fcns_ctx* ctx, int32_t order, const double* in, int64_t nlines,
+                               int64_t ps, int64_t ls, double* out);
+
+/* Advective term -(v.grad)v (and -(v.grad)theta when theta != NULL; needs a
+ * Boussinesq context) from the FC-continued transform of v (Sec. 4.2:
+ * derivatives in Fourier space, products in physical space, no padding).
+ * filtered = 1 also applies the exponential filter of Sec. 4.3 to the result.
+ * Outputs are physical fields like the inputs. */
+fcns_status fcns_rhs_nonlinear(fcns_ctx* ctx, const double* v, const double* theta,
+                               int32_t filtered, double* nl_v, double* nl_theta);
+
+/* Pressure projection of a physical field v* with stage coefficient c > 0
+ * (Sec. 4.2 and Sec. 4.4 steps 3-5): v_out = v* - grad phi, phi = c p, with the
+ * inhomogeneous part solved in continued Fourier space and the homogeneous
+ * part in closed form so that v_out.z = 0 at the walls.  gradp_wall
+ * (nullable): tangential pressure gradient at the walls, float64
+ * [2 walls (z=0, z=Lz)][2 comps (x, y)][ny][nx], in p units. */
+fcns_status fcns_pressure_project(fcns_ctx* ctx, const double* v_star, double c, double* v_out,
+                                  double* gradp_wall);
+
+/* Set the state from physical fields (theta required iff Boussinesq); the
+ * wall pressure gradient used by the first stage is reset to 0. */
+fcns_status fcns_set_state(fcns_ctx* ctx, const double* v, const double* theta);
+
+/* Advance nsteps steps of the o-stage time-splitting Runge-Kutta scheme of
+ * Sec. 4.4 with time step dt (stage coefficients c_j = dt/(o-j+1)).
+ * Asynchronous on the context stream. */
+fcns_status fcns_rk_step(fcns_ctx* ctx, double dt, int32_t nsteps);
+
+/* Physical state.  theta (nullable) for Boussinesq contexts; p (nullable)
+ * needs keep_pressure and at least one step, and is returned with zero mean. */
+fcns_status fcns_get_state(fcns_ctx* ctx, double* v, double* theta, double* p);
+
+/* Continued spectral state for checkpoint / restart: field f (0..2 velocity,
+ * 3 theta) as complex128 [N'][ny][nx/2+1] (interleaved re, im), continued
+ * (kx, ky, kz) coefficients with unnormalized forward FFTs.  get copies the
+ * state out; set replaces it (and resets the stored wall gradient to the one
+ * passed in wall_grad, complex128 [2][2][ny][nx/2+1], or to 0 if NULL). */
+fcns_status fcns_get_spectral(fcns_ctx* ctx, int32_t field, double* out);
+fcns_status fcns_set_spectral(fcns_ctx* ctx, const double* const* fields, const double* wall_grad);
+fcns_status fcns_get_wall_grad(fcns_ctx* ctx, double* out);
+
+/* Sizes of the context: N' and the number of transported fields. */
+int32_t fcns_npr(const fcns_ctx* ctx);
+
+/* Message for the last error on this context (or on creation when ctx is
+ * NULL). */
+const char* fcns_last_error(const fcns_ctx* ctx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FCNS_H */

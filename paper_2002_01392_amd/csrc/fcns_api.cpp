@@ -1,0 +1,546 @@
+// Host side of the C ABI: problem validation, FFT plans, tables, buffers and
+// the sequence of kernel launches for each entry point.
+#include <math.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/fcns.h"
+#include "kernels.hpp"
+
+using namespace fcns;
+
+struct fcns_ctx {
+  fcns_problem prob;
+  hipStream_t stream = nullptr;
+  Geom g{};
+  int nf = 3;          // transported fields
+  bool big_z = false, big_x = false, big_y = false;
+  FFTPlan plz{}, plx{}, ply{};
+  // device tables
+  cpx<double>* twz = nullptr;
+  cpx<double>* twx = nullptr;
+  cpx<double>* twy = nullptr;
+  double* fcM = nullptr;
+  double* sigx = nullptr;
+  double* sigy = nullptr;
+  double* sigz = nullptr;
+  std::vector<double> hostM;
+  // device buffers (complex, counts in elements)
+  long long S = 0, M = 0;  // one continued spectral / one mixed field
+  cpx<double>* P = nullptr;    // V^t (nf fields)
+  cpx<double>* Q = nullptr;    // V^(j) (nf fields)
+  cpx<double>* VS = nullptr;   // V* / scratch (nf fields)
+  cpx<double>* MV = nullptr;   // mixed v_f, dv_f/dz at slots 2f, 2f+1
+  cpx<double>* MVT = nullptr;  // scratch copy of MV for the standalone calls
+  cpx<double>* XYB = nullptr;  // (kx, y, z): q_f, dq_f/dy, dq_f/dz at 3f..3f+2
+  cpx<double>* NLB = nullptr;  // nonlinear term (nf fields)
+  cpx<double>* PM = nullptr;   // mixed pressure
+  cpx<double>* GW = nullptr;   // wall tangential gradient [2][2][npen]
+  cpx<double>* GWT = nullptr;  // scratch wall gradient
+  bool has_state = false;
+  bool has_pressure = false;
+  std::string err;
+};
+
+static std::string g_create_err;
+
+static fcns_status fail(fcns_ctx* c, fcns_status st, const std::string& msg) {
+  if (c)
+    c->err = msg;
+  else
+    g_create_err = msg;
+  return st;
+}
+
+static fcns_status check_hip(fcns_ctx* c, hipError_t e, const char* what) {
+  if (e == hipSuccess) return FCNS_OK;
+  return fail(c, FCNS_EDEVICE, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+static fcns_status check_launch(fcns_ctx* c, const char* what) {
+  return check_hip(c, hipGetLastError(), what);
+}
+
+// ---------------------------------------------------------------- plans
+// Radices 8 first, then 4, 2 and odd primes ascending (at most 12 stages).
+static bool make_plan(int n, FFTPlan& pl, bool& big) {
+  memset(&pl, 0, sizeof(pl));
+  pl.n = n;
+  big = false;
+  int m = n;
+  std::vector<int> rs;
+  while (m % 8 == 0) { rs.push_back(8); m /= 8; }
+  while (m % 4 == 0) { rs.push_back(4); m /= 4; }
+  while (m % 2 == 0) { rs.push_back(2); m /= 2; }
+  for (int p = 3; m > 1 && p <= m; p += 2)
+    while (m % p == 0) {
+      rs.push_back(p);
+      m /= p;
+    }
+  if (m != 1 || (int)rs.size() > FFT_MAX_STAGES) return false;
+  pl.nst = (int)rs.size();
+  for (int s = 0; s < pl.nst; ++s) {
+    pl.r[s] = rs[s];
+    if (rs[s] > 8) big = true;  // 29, 47 and other primes
+  }
+  return true;
+}
+
+static std::vector<cpx<double>> twiddles(int n) {
+  std::vector<cpx<double>> t(n);
+  const long double pi = 3.141592653589793238462643383279502884L;
+  for (int q = 0; q < n; ++q) {
+    const long double a = -2.0L * pi * (long double)q / (long double)n;
+    t[q] = mk((double)cosl(a), (double)sinl(a));
+  }
+  return t;
+}
+
+static std::vector<double> filter_table(int n, int nstore, bool half, double beta, double two_p) {
+  std::vector<double> s(nstore);
+  for (int i = 0; i < nstore; ++i) {
+    const int m = half ? i : ((2 * i < n) ? i : i - n);
+    const double eta = 2.0 * fabs((double)m) / (double)n;
+    s[i] = exp(-beta * pow(eta, two_p));
+  }
+  return s;
+}
+
+template <typename T>
+static fcns_status upload(fcns_ctx* c, T** dst, const T* src, size_t n) {
+  if (hipMalloc((void**)dst, n * sizeof(T)) != hipSuccess)
+    return fail(c, FCNS_ENOMEM, "device allocation of a table failed");
+  return check_hip(c, hipMemcpy(*dst, src, n * sizeof(T), hipMemcpyHostToDevice), "table upload");
+}
+
+static fcns_status alloc(fcns_ctx* c, cpx<double>** p, long long n) {
+  if (hipMalloc((void**)p, (size_t)n * sizeof(cpx<double>)) != hipSuccess)
+    return fail(c, FCNS_ENOMEM, "device allocation failed");
+  return FCNS_OK;
+}
+
+static void free_all(fcns_ctx* c) {
+  void* ps[] = {c->twz, c->twx, c->twy, c->fcM, c->sigx, c->sigy, c->sigz, c->P, c->Q,
+                c->VS, c->MV, c->MVT, c->XYB, c->NLB, c->PM, c->GW, c->GWT};
+  for (void* p : ps)
+    if (p) (void)hipFree(p);
+}
+
+static ZArgs zargs(const fcns_ctx* c) {
+  ZArgs a;
+  a.g = c->g;
+  a.pl = c->plz;
+  a.tw = c->twz;
+  a.tw64 = c->twz;
+  a.fc = c->fcM;
+  a.sigx = c->sigx;
+  a.sigy = c->sigy;
+  a.sigz = c->sigz;
+  return a;
+}
+static YArgs yargs(const fcns_ctx* c) {
+  YArgs a;
+  a.ny = c->g.ny;
+  a.nkx = c->g.nkx;
+  a.kys = c->g.kys;
+  a.pl = c->ply;
+  a.tw = c->twy;
+  return a;
+}
+static XArgs xargs(const fcns_ctx* c) {
+  XArgs a;
+  a.nx = c->g.nx;
+  a.nkx = c->g.nkx;
+  a.ny = c->g.ny;
+  a.kxs = c->g.kxs;
+  a.pl = c->plx;
+  a.tw = c->twx;
+  return a;
+}
+
+// ---------------------------------------------------------------- create
+extern "C" fcns_status fcns_create(const fcns_problem* prob, void* hip_stream, fcns_ctx** out) {
+  if (!out) return fail(nullptr, FCNS_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (!prob) return fail(nullptr, FCNS_EINVAL, "problem is NULL");
+  const fcns_problem& p = *prob;
+  if (p.nx < 4 || p.ny < 4 || p.nx % 2 || p.ny % 2)
+    return fail(nullptr, FCNS_EINVAL, "nx and ny must be even and >= 4");
+  if (p.fc_d < 2 || p.fc_C < 1 || p.nz < 2 * p.fc_d)
+    return fail(nullptr, FCNS_EINVAL, "need d >= 2, C >= 1 and nz >= 2d");
+  if ((p.nz + p.fc_C) % 2) return fail(nullptr, FCNS_EINVAL, "nz + C must be even");
+  if (!(p.lx > 0 && p.ly > 0 && p.lz > 0)) return fail(nullptr, FCNS_EINVAL, "box lengths must be > 0");
+  if (p.rk_order != 2) return fail(nullptr, FCNS_EINVAL, "only rk_order = 2 is implemented");
+  if (p.precision != FCNS_FP64) return fail(nullptr, FCNS_EINVAL, "only FCNS_FP64 is implemented");
+  if (!p.fc_table) return fail(nullptr, FCNS_EINVAL, "fc_table is NULL");
+  if (p.nx > 512 || p.ny > 1024) return fail(nullptr, FCNS_EINVAL, "need nx <= 512 and ny <= 1024");
+  const int npr = p.nz + p.fc_C;
+  if (npr > z_max_npr()) return fail(nullptr, FCNS_EINVAL, "N' = nz + C must be <= 512");
+
+  fcns_ctx* c = new fcns_ctx();
+  c->prob = p;
+  c->prob.fc_table = nullptr;
+  c->stream = (hipStream_t)hip_stream;
+  c->nf = p.boussinesq ? 4 : 3;
+  Geom& g = c->g;
+  g.nx = p.nx;
+  g.ny = p.ny;
+  g.nz = p.nz;
+  g.nkx = p.nx / 2 + 1;
+  g.npr = npr;
+  g.C = p.fc_C;
+  g.d = p.fc_d;
+  g.npen = (long long)g.nkx * g.ny;
+  g.lx = p.lx;
+  g.ly = p.ly;
+  g.lz = p.lz;
+  g.dz = p.lz / (p.nz - 1);
+  g.lzp = npr * g.dz;
+  g.kxs = 2.0 * M_PI / p.lx;
+  g.kys = 2.0 * M_PI / p.ly;
+  g.kzs = 2.0 * M_PI / g.lzp;
+
+  if (!make_plan(npr, c->plz, c->big_z) || !make_plan(p.nx, c->plx, c->big_x) ||
+      !make_plan(p.ny, c->ply, c->big_y)) {
+    delete c;
+    return fail(nullptr, FCNS_EINVAL, "unsupported transform length (more than 12 radix stages)");
+  }
+
+  // M_r = A_r Q_r^T in extended precision (App. B)
+  const int d = p.fc_d, C = p.fc_C;
+  const double* Qr = p.fc_table;
+  const double* Ar = p.fc_table + d * d;
+  c->hostM.resize((size_t)C * d);
+  for (int i = 0; i < C; ++i)
+    for (int j = 0; j < d; ++j) {
+      long double acc = 0.0L;
+      for (int k = 0; k < d; ++k) acc += (long double)Ar[i * d + k] * (long double)Qr[j * d + k];
+      c->hostM[(size_t)i * d + j] = (double)acc;
+    }
+
+  const double beta = p.filter_beta > 0 ? p.filter_beta : 16.0 * log(10.0);
+  const double two_p = p.filter_2p > 0 ? p.filter_2p : 100.0;
+  c->prob.filter_beta = beta;
+  c->prob.filter_2p = two_p;
+  auto twz = twiddles(npr), twx = twiddles(p.nx), twy = twiddles(p.ny);
+  auto sx = filter_table(p.nx, g.nkx, true, beta, two_p);
+  auto sy = filter_table(p.ny, p.ny, false, beta, two_p);
+  auto sz = filter_table(npr, npr, false, beta, two_p);
+  fcns_status st = FCNS_OK;
+  if ((st = upload(c, &c->twz, twz.data(), twz.size())) ||
+      (st = upload(c, &c->twx, twx.data(), twx.size())) ||
+      (st = upload(c, &c->twy, twy.data(), twy.size())) ||
+      (st = upload(c, &c->fcM, c->hostM.data(), c->hostM.size())) ||
+      (st = upload(c, &c->sigx, sx.data(), sx.size())) ||
+      (st = upload(c, &c->sigy, sy.data(), sy.size())) ||
+      (st = upload(c, &c->sigz, sz.data(), sz.size()))) {
+    g_create_err = c->err;
+    free_all(c);
+    delete c;
+    return st;
+  }
+  c->S = (long long)npr * g.npen;
+  c->M = (long long)p.nz * g.npen;
+  const int nf = c->nf;
+  if ((st = alloc(c, &c->P, nf * c->S)) || (st = alloc(c, &c->Q, nf * c->S)) ||
+      (st = alloc(c, &c->VS, nf * c->S)) || (st = alloc(c, &c->MV, 2 * nf * c->M)) ||
+      (st = alloc(c, &c->MVT, 2 * nf * c->M)) || (st = alloc(c, &c->XYB, 3 * nf * c->M)) ||
+      (st = alloc(c, &c->NLB, nf * c->M)) || (st = alloc(c, &c->PM, c->M)) ||
+      (st = alloc(c, &c->GW, 4 * g.npen)) || (st = alloc(c, &c->GWT, 4 * g.npen))) {
+    g_create_err = c->err;
+    free_all(c);
+    delete c;
+    return st;
+  }
+  launch_fill(c->GW, 4 * g.npen, c->stream);
+  if ((st = check_launch(c, "fill")) != FCNS_OK) {
+    g_create_err = c->err;
+    free_all(c);
+    delete c;
+    return st;
+  }
+  *out = c;
+  return FCNS_OK;
+}
+
+extern "C" fcns_status fcns_destroy(fcns_ctx* c) {
+  if (!c) return FCNS_OK;
+  (void)hipStreamSynchronize(c->stream);
+  free_all(c);
+  delete c;
+  return FCNS_OK;
+}
+
+extern "C" const char* fcns_last_error(const fcns_ctx* c) {
+  return c ? c->err.c_str() : g_create_err.c_str();
+}
+
+extern "C" int32_t fcns_npr(const fcns_ctx* c) { return c ? c->g.npr : 0; }
+
+// ---------------------------------------------------------------- pieces
+// physical fields (nfields consecutive [nz][ny][nx] arrays) -> mixed (kx, ky, z)
+static void phys_to_mixed(fcns_ctx* c, const double* phys, int nfields, cpx<double>* mixed) {
+  const Geom& g = c->g;
+  const long long pfs = (long long)g.nz * g.ny * g.nx;
+  launch_x_r2c(xargs(c), c->big_x, phys, mixed, pfs, c->M, (long long)g.nz * g.ny, nfields,
+               c->stream);
+  launch_y(yargs(c), c->big_y, false, 0, mixed, mixed, nullptr, c->M, c->M, g.nz, nfields,
+           c->stream);
+}
+
+// mixed (kx, ky, z) fields at stride mstride -> physical; scratch: XYB
+static void mixed_to_phys(fcns_ctx* c, const cpx<double>* mixed, long long mstride, int nfields,
+                          double* phys, int nplanes) {
+  const Geom& g = c->g;
+  const long long plane = (long long)g.ny * g.nkx;
+  const long long xfs = (long long)nplanes * plane;
+  launch_y(yargs(c), c->big_y, true, 0, mixed, c->XYB, nullptr, mstride, xfs, nplanes, nfields,
+           c->stream);
+  launch_x_c2r(xargs(c), c->big_x, c->XYB, phys, xfs, (long long)nplanes * g.ny * g.nx,
+               (long long)nplanes * g.ny, nfields, c->stream);
+}
+
+// nonlinear term of the fields whose mixed v_f, dv_f/dz are in mv (slots 2f,
+// 2f+1) into NLB (mixed if fwd_y, else (kx, y, z))
+static void nonlinear_from_mixed(fcns_ctx* c, const cpx<double>* mv, int nfields, bool fwd_y) {
+  const Geom& g = c->g;
+  const long long M = c->M;
+  launch_y(yargs(c), c->big_y, true, 1, mv, c->XYB, c->XYB + M, 2 * M, 3 * M, g.nz, nfields,
+           c->stream);
+  launch_y(yargs(c), c->big_y, true, 0, mv + M, c->XYB + 2 * M, nullptr, 2 * M, 3 * M, g.nz,
+           nfields, c->stream);
+  launch_x_nl(xargs(c), c->big_x, c->XYB, c->NLB, M, (long long)g.nz * g.ny, nfields, c->stream);
+  if (fwd_y)
+    launch_y(yargs(c), c->big_y, false, 0, c->NLB, c->NLB, nullptr, M, M, g.nz, nfields,
+             c->stream);
+}
+
+// ---------------------------------------------------------------- entry points
+extern "C" fcns_status fcns_fc_extend(fcns_ctx* c, const double* in, int64_t nlines, int64_t in_ps,
+                                      int64_t in_ls, double* out, int64_t out_ps, int64_t out_ls) {
+  if (!c) return FCNS_EINVAL;
+  if (nlines < 0) return fail(c, FCNS_EINVAL, "nlines < 0");
+  if (nlines == 0) return FCNS_OK;
+  if (!in || !out) return fail(c, FCNS_EINVAL, "NULL pointer");
+  launch_fc_extend(in, nlines, in_ps, in_ls, out, out_ps, out_ls, c->g.nz, c->g.C, c->g.d, c->fcM,
+                   c->stream);
+  return check_launch(c, "fc_extend");
+}
+
+extern "C" fcns_status fcns_fc_derivative(fcns_ctx* c, int32_t order, const double* in,
+                                          int64_t nlines, int64_t ps, int64_t ls, double* out) {
+  if (!c) return FCNS_EINVAL;
+  if (order != 1 && order != 2) return fail(c, FCNS_EINVAL, "order must be 1 or 2");
+  if (nlines < 0) return fail(c, FCNS_EINVAL, "nlines < 0");
+  if (nlines == 0) return FCNS_OK;
+  if (!in || !out) return fail(c, FCNS_EINVAL, "NULL pointer");
+  launch_fc_derivative(zargs(c), c->big_z, in, out, nlines, ps, ls, order, c->stream);
+  return check_launch(c, "fc_derivative");
+}
+
+
+// continued spectral state of `nfields` mixed fields (stride M) into dst
+// (stride S), then the mixed v, dv/dz of the state into mv (slots 2f, 2f+1)
+static void mixed_to_state(fcns_ctx* c, const cpx<double>* mixed, int nfields, cpx<double>* dst,
+                           cpx<double>* mv) {
+  launch_z_fwd(zargs(c), c->big_z, mixed, dst, c->M, c->S, nfields, 0, c->stream);
+  if (mv)
+    launch_z_back(zargs(c), c->big_z, dst, mv, mv + c->M, c->S, 2 * c->M, nfields, c->stream);
+}
+
+extern "C" fcns_status fcns_set_state(fcns_ctx* c, const double* v, const double* theta) {
+  if (!c) return FCNS_EINVAL;
+  if (!v) return fail(c, FCNS_EINVAL, "v is NULL");
+  if (c->prob.boussinesq && !theta) return fail(c, FCNS_EINVAL, "theta required (Boussinesq)");
+  phys_to_mixed(c, v, 3, c->XYB);
+  if (c->nf == 4) phys_to_mixed(c, theta, 1, c->XYB + 3 * c->M);
+  mixed_to_state(c, c->XYB, c->nf, c->P, c->MV);
+  launch_fill(c->GW, 4 * c->g.npen, c->stream);
+  fcns_status st = check_launch(c, "set_state");
+  if (st == FCNS_OK) {
+    c->has_state = true;
+    c->has_pressure = false;
+  }
+  return st;
+}
+
+// One RK stage j of o (Sec. 4.4), c = dt/(o-j+1).
+static void rk_stage(fcns_ctx* c, int j, int o, double dt) {
+  const Geom& g = c->g;
+  const long long S = c->S, M = c->M;
+  const int nf = c->nf;
+  const double cj = dt / (double)(o - j + 1);
+  cpx<double>* W = (j == 1) ? c->P : c->Q;
+  cpx<double>* OUT = (j == o) ? c->P : c->Q;
+  // y-back, x-pass with products, y-fwd: nonlinear term in mixed space
+  nonlinear_from_mixed(c, c->MV, nf, true);
+  // stage A: pressureless update, wall injection, FC re-extension
+  StageAArgs A{};
+  for (int f = 0; f < nf; ++f) {
+    A.nl[f] = c->NLB + f * M;
+    A.vt[f] = c->P + f * S;
+    A.w[f] = W + f * S;
+    A.out[f] = (f < 3) ? c->VS + f * S : OUT + f * S;
+    A.buoy[f] = nullptr;
+  }
+  if (nf == 4) {
+    A.buoy[2] = c->MV + (2 * 3) * M;  // mixed theta of the previous stage
+    A.buoy[3] = c->MV + (2 * 2) * M;  // mixed w of the previous stage
+  }
+  A.gwall = c->GW;
+  A.c = cj;
+  A.nu = c->prob.nu;
+  A.kappa = c->prob.kappa;
+  A.gamma = c->prob.gamma;
+  A.forcing_sum = c->prob.forcing_x * (double)g.nx * (double)g.ny;
+  launch_z_stageA(zargs(c), c->big_z, A, nf, c->stream);
+  // stage B: projection, next-stage wall gradient, mixed v and dv/dz
+  StageBArgs B{};
+  for (int i = 0; i < 3; ++i) {
+    B.vs[i] = c->VS + i * S;
+    B.vout[i] = OUT + i * S;
+    B.mv[i] = c->MV + (2 * i) * M;
+    B.mdz[i] = c->MV + (2 * i + 1) * M;
+  }
+  B.gwall = c->GW;
+  B.pmix = (c->prob.keep_pressure && j == o) ? c->PM : nullptr;
+  B.c = cj;
+  launch_z_stageB(zargs(c), c->big_z, B, c->stream);
+  if (nf == 4)
+    launch_z_back(zargs(c), c->big_z, OUT + 3 * S, c->MV + 6 * M, c->MV + 7 * M, S, 2 * M, 1,
+                  c->stream);
+}
+
+extern "C" fcns_status fcns_rk_step(fcns_ctx* c, double dt, int32_t nsteps) {
+  if (!c) return FCNS_EINVAL;
+  if (!c->has_state) return fail(c, FCNS_ESTATE, "rk_step before set_state");
+  if (!(dt > 0.0) || nsteps < 0) return fail(c, FCNS_EINVAL, "need dt > 0 and nsteps >= 0");
+  const int o = c->prob.rk_order;
+  for (int n = 0; n < nsteps; ++n)
+    for (int j = 1; j <= o; ++j) rk_stage(c, j, o, dt);
+  fcns_status st = check_launch(c, "rk_step");
+  if (st == FCNS_OK && nsteps > 0 && c->prob.keep_pressure) c->has_pressure = true;
+  return st;
+}
+
+extern "C" fcns_status fcns_get_state(fcns_ctx* c, double* v, double* theta, double* p) {
+  if (!c) return FCNS_EINVAL;
+  if (!c->has_state) return fail(c, FCNS_ESTATE, "get_state before set_state");
+  if (p && !c->has_pressure)
+    return fail(c, FCNS_ESTATE, "pressure needs keep_pressure and at least one step");
+  const long long M = c->M;
+  if (v || theta) {
+    // R IFFT of the continued state, then the inverse xy transforms
+    launch_z_back(zargs(c), c->big_z, c->P, c->MVT, nullptr, c->S, M, c->nf, c->stream);
+    if (v) mixed_to_phys(c, c->MVT, M, 3, v, c->g.nz);
+    if (theta && c->nf == 4) mixed_to_phys(c, c->MVT + 3 * M, M, 1, theta, c->g.nz);
+  }
+  if (p) {
+    launch_sub_mean00(c->PM, c->g.npen, c->g.nz, 1.0, c->stream);
+    mixed_to_phys(c, c->PM, M, 1, p, c->g.nz);
+  }
+  return check_launch(c, "get_state");
+}
+
+extern "C" fcns_status fcns_rhs_nonlinear(fcns_ctx* c, const double* v, const double* theta,
+                                          int32_t filtered, double* nl_v, double* nl_theta) {
+  if (!c) return FCNS_EINVAL;
+  if (!v || !nl_v) return fail(c, FCNS_EINVAL, "NULL pointer");
+  if (theta && c->nf != 4) return fail(c, FCNS_EINVAL, "theta needs a Boussinesq context");
+  if (theta && !nl_theta) return fail(c, FCNS_EINVAL, "nl_theta is NULL");
+  const int nf = theta ? 4 : 3;
+  const long long M = c->M;
+  phys_to_mixed(c, v, 3, c->XYB);
+  if (theta) phys_to_mixed(c, theta, 1, c->XYB + 3 * M);
+  mixed_to_state(c, c->XYB, nf, c->VS, c->MVT);
+  nonlinear_from_mixed(c, c->MVT, nf, filtered != 0);
+  if (filtered) {
+    launch_z_fwd(zargs(c), c->big_z, c->NLB, c->VS, M, c->S, nf, 1, c->stream);
+    launch_z_back(zargs(c), c->big_z, c->VS, c->NLB, nullptr, c->S, M, nf, c->stream);
+    mixed_to_phys(c, c->NLB, M, 3, nl_v, c->g.nz);
+    if (theta) mixed_to_phys(c, c->NLB + 3 * M, M, 1, nl_theta, c->g.nz);
+  } else {
+    const Geom& g = c->g;
+    const long long pfs = (long long)g.nz * g.ny * g.nx;
+    launch_x_c2r(xargs(c), c->big_x, c->NLB, nl_v, M, pfs, (long long)g.nz * g.ny, 3, c->stream);
+    if (theta)
+      launch_x_c2r(xargs(c), c->big_x, c->NLB + 3 * M, nl_theta, M, pfs, (long long)g.nz * g.ny,
+                   1, c->stream);
+  }
+  return check_launch(c, "rhs_nonlinear");
+}
+
+extern "C" fcns_status fcns_pressure_project(fcns_ctx* c, const double* v_star, double cj,
+                                             double* v_out, double* gradp_wall) {
+  if (!c) return FCNS_EINVAL;
+  if (!v_star || !v_out) return fail(c, FCNS_EINVAL, "NULL pointer");
+  if (!(cj > 0.0)) return fail(c, FCNS_EINVAL, "c must be > 0");
+  const long long M = c->M, S = c->S;
+  phys_to_mixed(c, v_star, 3, c->XYB);
+  launch_z_fwd(zargs(c), c->big_z, c->XYB, c->VS, M, S, 3, 0, c->stream);
+  StageBArgs B{};
+  for (int i = 0; i < 3; ++i) {
+    B.vs[i] = c->VS + i * S;
+    B.vout[i] = c->VS + i * S;
+    B.mv[i] = c->MVT + (2 * i) * M;
+    B.mdz[i] = c->MVT + (2 * i + 1) * M;
+  }
+  B.gwall = c->GWT;
+  B.pmix = nullptr;
+  B.c = cj;
+  launch_z_stageB(zargs(c), c->big_z, B, c->stream);
+  mixed_to_phys(c, c->MVT, 2 * M, 3, v_out, c->g.nz);
+  if (gradp_wall) mixed_to_phys(c, c->GWT, 0, 1, gradp_wall, 4);
+  return check_launch(c, "pressure_project");
+}
+
+extern "C" fcns_status fcns_get_spectral(fcns_ctx* c, int32_t field, double* out) {
+  if (!c) return FCNS_EINVAL;
+  if (!c->has_state) return fail(c, FCNS_ESTATE, "no state");
+  if (field < 0 || field >= c->nf || !out) return fail(c, FCNS_EINVAL, "bad field or NULL");
+  return check_hip(c,
+                   hipMemcpyAsync(out, c->P + field * c->S, c->S * sizeof(cpx<double>),
+                                  hipMemcpyDeviceToDevice, c->stream),
+                   "get_spectral");
+}
+
+extern "C" fcns_status fcns_set_spectral(fcns_ctx* c, const double* const* fields,
+                                         const double* wall_grad) {
+  if (!c) return FCNS_EINVAL;
+  if (!fields) return fail(c, FCNS_EINVAL, "NULL fields");
+  for (int f = 0; f < c->nf; ++f) {
+    if (!fields[f]) return fail(c, FCNS_EINVAL, "NULL field");
+    fcns_status st = check_hip(c,
+                               hipMemcpyAsync(c->P + f * c->S, fields[f], c->S * sizeof(cpx<double>),
+                                              hipMemcpyDeviceToDevice, c->stream),
+                               "set_spectral");
+    if (st != FCNS_OK) return st;
+  }
+  if (wall_grad) {
+    fcns_status st = check_hip(c,
+                               hipMemcpyAsync(c->GW, wall_grad, 4 * c->g.npen * sizeof(cpx<double>),
+                                              hipMemcpyDeviceToDevice, c->stream),
+                               "set_spectral");
+    if (st != FCNS_OK) return st;
+  } else {
+    launch_fill(c->GW, 4 * c->g.npen, c->stream);
+  }
+  launch_z_back(zargs(c), c->big_z, c->P, c->MV, c->MV + c->M, c->S, 2 * c->M, c->nf, c->stream);
+  fcns_status st = check_launch(c, "set_spectral");
+  if (st == FCNS_OK) {
+    c->has_state = true;
+    c->has_pressure = false;
+  }
+  return st;
+}
+
+extern "C" fcns_status fcns_get_wall_grad(fcns_ctx* c, double* out) {
+  if (!c || !out) return FCNS_EINVAL;
+  return check_hip(c,
+                   hipMemcpyAsync(out, c->GW, 4 * c->g.npen * sizeof(cpx<double>),
+                                  hipMemcpyDeviceToDevice, c->stream),
+                   "get_wall_grad");
+}

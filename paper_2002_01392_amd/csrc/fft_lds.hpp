@@ -1,0 +1,236 @@
+// Batched 1D FFTs of lines held in LDS, for one workgroup.
+//
+// Layout: element i of line l sits at buf[l * ls + i * es].  The thread
+// mapping puts the line index fastest, so with interleaved lines (es = number
+// of lines, ls = 1) every wave touches consecutive LDS addresses.
+//
+// Algorithm: mixed-radix Stockham autosort, decimation in time, ping-pong
+// between two LDS buffers.  For a stage with radix R and ns = product of the
+// earlier radices, butterfly j reads x[j + m n/R] (m < R), multiplies by
+// w^{m k} with k = j mod ns and w = exp(-2 pi i / (ns R)), and writes X_m to
+// ((j - k) R + k) + m ns; the output is in natural order.  Only the forward
+// transform (exp(-2 pi i jk/n), unnormalized) is provided: callers obtain the
+// inverse as conj(FFT(conj(x))) by conjugating in their own loads and stores.
+//
+// Codelets: radix 2, 4, 8 in closed form; odd primes use the symmetric form
+// of a prime-length DFT (a_q = x_q + x_{R-q}, b_q = x_q - x_{R-q}), which takes
+// (R-1)^2 real multiply-adds per pair of outputs instead of R^2 complex ones,
+// with cos and sin read from the length-n twiddle table at a wave-uniform
+// index (LDS broadcast).  3, 5, 7, 29 and 47 are unrolled in registers; any
+// other odd prime runs a compact loop that reads its inputs from LDS.
+#pragma once
+#include "fcns_common.hpp"
+
+namespace fcns {
+
+constexpr int FFT_MAX_STAGES = 12;
+
+struct FFTPlan {
+  int n;
+  int nst;
+  int r[FFT_MAX_STAGES];
+};
+
+// ---------------------------------------------------------------- codelets
+template <typename T>
+__device__ __forceinline__ void dft4_reg(cpx<T>& a0, cpx<T>& a1, cpx<T>& a2, cpx<T>& a3) {
+  const cpx<T> s02 = a0 + a2, d02 = a0 - a2, s13 = a1 + a3;
+  const cpx<T> d13 = mul_mi(a1 - a3);
+  a0 = s02 + s13;
+  a2 = s02 - s13;
+  a1 = d02 + d13;
+  a3 = d02 - d13;
+}
+
+template <typename T, int R>
+struct Codelet;
+
+template <typename T>
+struct Codelet<T, 2> {
+  __device__ __forceinline__ static void run(cpx<T>* v, cpx<T>* dst, int os, const cpx<T>*, int) {
+    dst[0] = v[0] + v[1];
+    dst[os] = v[0] - v[1];
+  }
+};
+
+template <typename T>
+struct Codelet<T, 4> {
+  __device__ __forceinline__ static void run(cpx<T>* v, cpx<T>* dst, int os, const cpx<T>*, int) {
+    cpx<T> a0 = v[0], a1 = v[1], a2 = v[2], a3 = v[3];
+    dft4_reg<T>(a0, a1, a2, a3);
+    dst[0] = a0;
+    dst[os] = a1;
+    dst[2 * os] = a2;
+    dst[3 * os] = a3;
+  }
+};
+
+template <typename T>
+struct Codelet<T, 8> {
+  __device__ __forceinline__ static void run(cpx<T>* v, cpx<T>* dst, int os, const cpx<T>*, int) {
+    // n = n1 + 4 n2: even outputs from a = x_n1 + x_n1+4, odd outputs from
+    // b = (x_n1 - x_n1+4) w8^n1, w8 = exp(-i pi/4)
+    const T h = T(0.70710678118654752440084436210484903928483593768847);
+    cpx<T> a0 = v[0] + v[4], a1 = v[1] + v[5], a2 = v[2] + v[6], a3 = v[3] + v[7];
+    cpx<T> b0 = v[0] - v[4], b1 = v[1] - v[5], b2 = v[2] - v[6], b3 = v[3] - v[7];
+    b1 = mk((b1.x + b1.y) * h, (b1.y - b1.x) * h);
+    b2 = mul_mi(b2);
+    b3 = mk((b3.y - b3.x) * h, -(b3.x + b3.y) * h);
+    dft4_reg<T>(a0, a1, a2, a3);
+    dft4_reg<T>(b0, b1, b2, b3);
+    dst[0] = a0;
+    dst[2 * os] = a1;
+    dst[4 * os] = a2;
+    dst[6 * os] = a3;
+    dst[os] = b0;
+    dst[3 * os] = b1;
+    dst[5 * os] = b2;
+    dst[7 * os] = b3;
+  }
+};
+
+// Odd prime P in registers.  tw: n-point table exp(-2 pi i q / n); st = n/P.
+template <typename T, int P>
+struct CodeletOdd {
+  __device__ __forceinline__ static void run(cpx<T>* v, cpx<T>* dst, int os, const cpx<T>* tw,
+                                             int st) {
+    constexpr int H = (P - 1) / 2;
+    cpx<T> a[H], b[H];
+    const cpx<T> x0 = v[0];
+    cpx<T> s = x0;
+#pragma unroll
+    for (int q = 1; q <= H; ++q) {
+      a[q - 1] = v[q] + v[P - q];
+      b[q - 1] = v[q] - v[P - q];
+      s = s + a[q - 1];
+    }
+    dst[0] = s;
+#pragma unroll
+    for (int k = 1; k <= H; ++k) {
+      cpx<T> re = x0, im = zero<T>();
+#pragma unroll
+      for (int q = 1; q <= H; ++q) {
+        const cpx<T> w = tw[((q * k) % P) * st];  // cos - i sin
+        re = re + a[q - 1] * w.x;
+        im = im + b[q - 1] * (-w.y);
+      }
+      // X_k = re - i im, X_{P-k} = re + i im
+      dst[k * os] = re + mul_mi(im);
+      dst[(P - k) * os] = re + mul_i(im);
+    }
+  }
+};
+template <typename T> struct Codelet<T, 3> : CodeletOdd<T, 3> {};
+template <typename T> struct Codelet<T, 5> : CodeletOdd<T, 5> {};
+template <typename T> struct Codelet<T, 7> : CodeletOdd<T, 7> {};
+template <typename T> struct Codelet<T, 29> : CodeletOdd<T, 29> {};
+template <typename T> struct Codelet<T, 47> : CodeletOdd<T, 47> {};
+
+// ---------------------------------------------------------------- one stage
+template <typename T, int R>
+__device__ __forceinline__ void fft_stage(const cpx<T>* __restrict__ src, cpx<T>* __restrict__ dst,
+                                          int L, int es, int ls, int n, int ns,
+                                          const cpx<T>* __restrict__ tw, int tid, int nt) {
+  const int nr = n / R;
+  const int nb = L * nr;
+  const int tws = n / (ns * R);
+  for (int g = tid; g < nb; g += nt) {
+    const int l = g % L, j = g / L;
+    const int k = j % ns;
+    const cpx<T>* s = src + l * ls + j * es;
+    cpx<T> v[R];
+#pragma unroll
+    for (int m = 0; m < R; ++m) v[m] = s[m * nr * es];
+    if (ns > 1) {
+#pragma unroll
+      for (int m = 1; m < R; ++m) v[m] = v[m] * tw[m * k * tws];
+    }
+    Codelet<T, R>::run(v, dst + l * ls + ((j - k) * R + k) * es, ns * es, tw, n / R);
+  }
+}
+
+// Any odd prime R at run time: twiddle the butterfly's own inputs in place in
+// src (no other thread reads them), then form each output pair from LDS.
+template <typename T>
+__device__ __forceinline__ void fft_stage_prime(cpx<T>* __restrict__ src, cpx<T>* __restrict__ dst,
+                                                int R, int L, int es, int ls, int n, int ns,
+                                                const cpx<T>* __restrict__ tw, int tid, int nt) {
+  const int nr = n / R;
+  const int nb = L * nr;
+  const int tws = n / (ns * R);
+  const int st = n / R;
+  const int H = (R - 1) / 2;
+  for (int g = tid; g < nb; g += nt) {
+    const int l = g % L, j = g / L;
+    const int k = j % ns;
+    cpx<T>* s = src + l * ls + j * es;
+    const int is = nr * es;
+    if (ns > 1)
+      for (int m = 1; m < R; ++m) s[m * is] = s[m * is] * tw[m * k * tws];
+    cpx<T>* d = dst + l * ls + ((j - k) * R + k) * es;
+    const int os = ns * es;
+    const cpx<T> x0 = s[0];
+    cpx<T> sum = x0;
+    for (int q = 1; q <= H; ++q) sum = sum + s[q * is] + s[(R - q) * is];
+    d[0] = sum;
+    for (int kk = 1; kk <= H; ++kk) {
+      cpx<T> re = x0, im = zero<T>();
+      int qk = 0;
+      for (int q = 1; q <= H; ++q) {
+        qk += kk;
+        if (qk >= R) qk -= R;
+        const cpx<T> w = tw[qk * st];
+        const cpx<T> xa = s[q * is], xb = s[(R - q) * is];
+        re = re + (xa + xb) * w.x;
+        im = im + (xa - xb) * (-w.y);
+      }
+      d[kk * os] = re + mul_mi(im);
+      d[(R - kk) * os] = re + mul_i(im);
+    }
+  }
+}
+
+// ---------------------------------------------------------------- driver
+// Forward FFT of L lines of pl.n points.  The input is in buf0; buf1 is
+// scratch of the same size.  Returns the buffer holding the result.  All
+// threads of the workgroup must call it, after a barrier that makes the
+// input visible; it synchronises before returning.
+// BIG: also dispatch radix 29, 47 and the run-time odd-prime stage.
+template <typename T, int L, bool BIG>
+__device__ __forceinline__ cpx<T>* fft_fwd(cpx<T>* buf0, cpx<T>* buf1, int es, int ls,
+                                           const FFTPlan& pl, const cpx<T>* __restrict__ tw,
+                                           int tid, int nt) {
+  int ns = 1;
+  const int n = pl.n;
+  cpx<T>* src = buf0;
+  cpx<T>* dst = buf1;
+  for (int s = 0; s < pl.nst; ++s) {
+    const int r = pl.r[s];
+    switch (r) {
+      case 2: fft_stage<T, 2>(src, dst, L, es, ls, n, ns, tw, tid, nt); break;
+      case 3: fft_stage<T, 3>(src, dst, L, es, ls, n, ns, tw, tid, nt); break;
+      case 4: fft_stage<T, 4>(src, dst, L, es, ls, n, ns, tw, tid, nt); break;
+      case 5: fft_stage<T, 5>(src, dst, L, es, ls, n, ns, tw, tid, nt); break;
+      case 7: fft_stage<T, 7>(src, dst, L, es, ls, n, ns, tw, tid, nt); break;
+      case 8: fft_stage<T, 8>(src, dst, L, es, ls, n, ns, tw, tid, nt); break;
+      default:
+        if constexpr (BIG) {
+          if (r == 29)
+            fft_stage<T, 29>(src, dst, L, es, ls, n, ns, tw, tid, nt);
+          else if (r == 47)
+            fft_stage<T, 47>(src, dst, L, es, ls, n, ns, tw, tid, nt);
+          else
+            fft_stage_prime<T>(src, dst, r, L, es, ls, n, ns, tw, tid, nt);
+        }
+        break;
+    }
+    __syncthreads();
+    cpx<T>* t = src;
+    src = dst;
+    dst = t;
+    ns *= r;
+  }
+  return src;
+}
+
+}  // namespace fcns

@@ -1,0 +1,117 @@
+// Internal launch interface between the C-ABI host code and the HIP kernels.
+#pragma once
+#include "fcns_common.hpp"
+#include "fft_lds.hpp"
+
+namespace fcns {
+
+// z kernels: ZPB pencils per workgroup of ZNT threads
+constexpr int ZPB = 8;
+constexpr int ZNT = 256;
+// y kernels: YL lines (consecutive kx) per workgroup
+constexpr int YL = 4;
+constexpr int YNT = 256;
+// x kernels: XR rows per workgroup (XR/2 complex lines)
+constexpr int XR = 8;
+constexpr int XNT = 256;
+
+struct ZArgs {
+  Geom g;
+  FFTPlan pl;             // N'-point plan (lines = ZPB, threads = ZNT)
+  const void* tw;         // N' twiddles in the transform precision
+  const cpx<double>* tw64;  // N' twiddles in FP64 (wall sums)
+  const double* fc;       // M_r, C x d row-major
+  const double* sigx;     // filter factors per direction (nkx, ny, N')
+  const double* sigy;
+  const double* sigz;
+};
+
+struct StageAArgs {
+  const cpx<double>* nl[4];   // mixed nonlinear term per field
+  const cpx<double>* vt[4];   // continued state at t
+  const cpx<double>* w[4];    // continued state of the previous stage
+  cpx<double>* out[4];        // V* (velocity) or Theta^(j) (temperature)
+  const cpx<double>* buoy[4]; // mixed theta (for w) / w (for theta), or null
+  const cpx<double>* gwall;   // [2 walls][2 comps][npen], p units
+  double c;                   // stage coefficient c_j
+  double nu, kappa, gamma;
+  double forcing_sum;         // body force times nx*ny (mixed (0,0) mode)
+};
+
+struct StageBArgs {
+  const cpx<double>* vs[3];   // V*
+  cpx<double>* vout[3];       // projected continued velocity
+  cpx<double>* mv[3];         // mixed v
+  cpx<double>* mdz[3];        // mixed dv/dz
+  cpx<double>* gwall;         // out: next-stage wall tangential gradient (or null)
+  cpx<double>* pmix;          // out: mixed pressure (or null)
+  double c;
+};
+
+struct YArgs {
+  int ny, nkx;
+  double kys;
+  FFTPlan pl;        // ny-point plan (lines = YL, threads = YNT)
+  const void* tw;    // ny twiddles
+};
+
+struct XArgs {
+  int nx, nkx, ny;
+  double kxs;
+  FFTPlan pl;        // nx-point plan (lines = XR/2, threads = XNT)
+  const void* tw;    // nx twiddles
+};
+
+int z_max_npr();
+size_t z_lds_bytes(const Geom& g);
+
+// Dynamic LDS above 64 KiB needs an explicit per-kernel opt-in.
+#define FCNS_LAUNCH(K, GRID, BLOCK, SH, ST, ...)        \
+  do {                                                  \
+    allow_lds(K, SH);                                   \
+    hipLaunchKernelGGL(K, GRID, BLOCK, SH, ST, __VA_ARGS__); \
+  } while (0)
+template <typename K>
+inline void allow_lds(K kernel, size_t bytes) {
+  if (bytes > 65536)
+    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(kernel),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+}
+
+void launch_z_fwd(const ZArgs& a, bool big, const cpx<double>* src, cpx<double>* dst,
+                  long long sfs, long long dfs, int nfields, int filter, hipStream_t st);
+void launch_z_back(const ZArgs& a, bool big, const cpx<double>* src, cpx<double>* dst,
+                   cpx<double>* dzdst, long long sfstride, long long mfstride, int nfields,
+                   hipStream_t st);
+void launch_z_stageA(const ZArgs& a, bool big, const StageAArgs& s, int nfields, hipStream_t st);
+void launch_z_stageB(const ZArgs& a, bool big, const StageBArgs& s, hipStream_t st);
+void launch_fc_extend(const double* in, long long nlines, long long ips, long long ils, double* out,
+                      long long ops, long long ols, int nz, int C, int d, const double* M,
+                      hipStream_t st);
+void launch_fc_derivative(const ZArgs& a, bool big, const double* in, double* out,
+                          long long nlines, long long ps, long long ls, int order,
+                          hipStream_t st);
+
+// y: lines are (plane, kx) pairs, element ky; arrays [nplanes][ny][nkx].
+// mode 0: dst = FFT (inverse scaled by 1/ny); mode 1 (inverse only): also
+// dst2 = inverse FFT of i k~y times the input.
+void launch_y(const YArgs& a, bool big, bool inv, int mode, const cpx<double>* src,
+              cpx<double>* dst, cpx<double>* dst2, long long sfstride, long long dfstride,
+              int nplanes, int nfields, hipStream_t st);
+// x: rows are (plane, y) pairs; physical rows of nx reals <-> nkx complex.
+void launch_x_r2c(const XArgs& a, bool big, const double* phys, cpx<double>* xy,
+                  long long pfstride, long long xfstride, long long nrows, int nfields,
+                  hipStream_t st);
+void launch_x_c2r(const XArgs& a, bool big, const cpx<double>* xy, double* phys,
+                  long long xfstride, long long pfstride, long long nrows, int nfields,
+                  hipStream_t st);
+// fused c2r + products + r2c: xyb holds, per field f, q_f, dq_f/dy, dq_f/dz at
+// field slots 3f, 3f+1, 3f+2; nl gets -(v.grad) q_f at slot f.
+void launch_x_nl(const XArgs& a, bool big, const cpx<double>* xyb, cpx<double>* nl,
+                 long long fstride, long long nrows, int nfields, hipStream_t st);
+
+// small helpers
+void launch_fill(cpx<double>* p, long long n, hipStream_t st);
+void launch_sub_mean00(cpx<double>* pmix, long long npen, int nz, double scale, hipStream_t st);
+
+}  // namespace fcns

@@ -1,0 +1,620 @@
+// Wall-normal (z) kernels: FC-Gram continuation, FFTs of the continued
+// lines, the RK stage combine with the splitting boundary conditions, and the
+// pressure projection with its closed-form homogeneous part.
+//
+// Data layout (complex, x fastest): mixed (kx, ky, z) fields are [nz][ny][nkx],
+// continued spectral (kx, ky, kz) fields are [N'][ny][nkx].  A pencil is one
+// (kx, ky) pair, p = ky * nkx + kx.  A workgroup owns ZPB consecutive pencils
+// and stages their lines in LDS as X[l * ZPB + pb] (pencil index fastest), so
+// every global row access is ZPB consecutive complex values.
+//
+// Inverse transforms use IFFT(y) = conj(FFT(conj(y))) / N' with the
+// conjugations folded into the surrounding loads and stores.
+#include "kernels.hpp"
+
+namespace fcns {
+
+// ---------------------------------------------------------------- LDS layout
+// [tw: N' cpx<T>][M: C*d double, padded to 16 B][X0: NX cpx<T>][X1: NX cpx<T>]
+// with NX = max(N' * ZPB, 4 * ZNT) (X1 also serves the reduction scratch).
+template <typename T>
+struct ZLds {
+  cpx<T>* tw;
+  double* M;
+  cpx<T>* X0;
+  cpx<T>* X1;
+  __device__ ZLds(char* base, const Geom& g) {
+    tw = reinterpret_cast<cpx<T>*>(base);
+    size_t off = g.npr * sizeof(cpx<T>);
+    M = reinterpret_cast<double*>(base + off);
+    off += ((g.C * g.d * sizeof(double) + 15) / 16) * 16;
+    X0 = reinterpret_cast<cpx<T>*>(base + off);
+    const int nx = max(g.npr * ZPB, 4 * ZNT * (int)(sizeof(cpx<double>) / sizeof(cpx<T>)));
+    X1 = X0 + nx;
+  }
+};
+
+template <typename T>
+size_t zshared_bytes(const Geom& g) {
+  const size_t a = (size_t)g.npr * ZPB, b = 4 * ZNT * (sizeof(cpx<double>) / sizeof(cpx<T>));
+  const size_t nx = a > b ? a : b;
+  return g.npr * sizeof(cpx<T>) + ((g.C * g.d * sizeof(double) + 15) / 16) * 16 +
+         2 * nx * sizeof(cpx<T>);
+}
+
+template <typename T>
+__device__ __forceinline__ void z_setup(const ZLds<T>& s, const ZArgs& a, int tid) {
+  const cpx<T>* gtw = reinterpret_cast<const cpx<T>*>(a.tw);
+  for (int i = tid; i < a.g.npr; i += ZNT) s.tw[i] = gtw[i];
+  for (int i = tid; i < a.g.C * a.g.d; i += ZNT) s.M[i] = a.fc[i];
+}
+
+// Rows nz..nz+C-1 of every line: f^c = M_r f_r + M_l f_l with M_l = J M_r J
+// (Sec. 3 continuation formula; App. B block form A f = A_l Q_l^T f_l +
+// A_r Q_r^T f_r with M = A Q^T).
+template <typename T>
+__device__ __forceinline__ void z_extend(cpx<T>* X, const double* __restrict__ M, int nz, int C,
+                                         int d, int tid) {
+  for (int e = tid; e < C * ZPB; e += ZNT) {
+    const int i = e / ZPB, pb = e % ZPB;
+    double ar = 0.0, ai = 0.0;
+    for (int j = 0; j < d; ++j) {
+      const double mr = M[i * d + j];
+      const cpx<T> fr = X[(nz - d + j) * ZPB + pb];
+      ar += mr * (double)fr.x;
+      ai += mr * (double)fr.y;
+    }
+    for (int j = 0; j < d; ++j) {
+      const double ml = M[(C - 1 - i) * d + (d - 1 - j)];
+      const cpx<T> fl = X[j * ZPB + pb];
+      ar += ml * (double)fl.x;
+      ai += ml * (double)fl.y;
+    }
+    X[(nz + i) * ZPB + pb] = mk((T)ar, (T)ai);
+  }
+}
+
+__device__ __forceinline__ void pencil_k(const Geom& g, long long p, double& kx_o, double& ky_o,
+                                         double& kx_t, double& ky_t, int& ix, int& iy) {
+  iy = (int)(p / g.nkx);
+  ix = (int)(p - (long long)iy * g.nkx);
+  kx_t = g.kxs * ix;
+  kx_o = (2 * ix == g.nx) ? 0.0 : kx_t;
+  ky_t = k_true(iy, g.ny, g.kys);
+  ky_o = k_odd(iy, g.ny, g.kys);
+}
+
+// ---------------------------------------------------------------- z forward
+// mixed -> continued spectral: F_z = FFT_N' o E (times the filter if asked).
+template <typename T, bool BIG>
+__global__ __launch_bounds__(ZNT) void k_z_fwd(ZArgs a, const cpx<double>* __restrict__ src,
+                                               cpx<double>* __restrict__ dst, long long sfs,
+                                               long long dfs, int filter) {
+  extern __shared__ __align__(16) char smem[];
+  const int tid = threadIdx.x;
+  const Geom& g = a.g;
+  const ZLds<T> L(smem, g);
+  src += blockIdx.y * sfs;
+  dst += blockIdx.y * dfs;
+  const long long p0 = (long long)blockIdx.x * ZPB;
+  z_setup<T>(L, a, tid);
+  for (int e = tid; e < g.nz * ZPB; e += ZNT) {
+    const long long p = p0 + e % ZPB;
+    L.X0[e] = (p < g.npen) ? cvt<T>(src[(long long)(e / ZPB) * g.npen + p]) : zero<T>();
+  }
+  __syncthreads();
+  z_extend<T>(L.X0, L.M, g.nz, g.C, g.d, tid);
+  __syncthreads();
+  const cpx<T>* R = fft_fwd<T, ZPB, BIG>(L.X0, L.X1, ZPB, 1, a.pl, L.tw, tid, ZNT);
+  for (int e = tid; e < g.npr * ZPB; e += ZNT) {
+    const int l = e / ZPB;
+    const long long p = p0 + e % ZPB;
+    if (p >= g.npen) continue;
+    cpx<double> v = cvt<double>(R[e]);
+    if (filter) {
+      const int iy = (int)(p / g.nkx), ix = (int)(p - (long long)iy * g.nkx);
+      v = v * (a.sigz[l] * a.sigy[iy] * a.sigx[ix]);
+    }
+    dst[(long long)l * g.npen + p] = v;
+  }
+}
+
+// ---------------------------------------------------------------- z back
+// continued spectral -> mixed: B_z = R o IFFT (and B_z(i k~z .) into dzdst).
+template <typename T, bool BIG, int OWN>
+__global__ __launch_bounds__(ZNT) void k_z_back(ZArgs a, const cpx<double>* __restrict__ src,
+                                                cpx<double>* __restrict__ dst,
+                                                cpx<double>* __restrict__ dzdst,
+                                                long long sfs, long long mfs) {
+  extern __shared__ __align__(16) char smem[];
+  const int tid = threadIdx.x;
+  const Geom& g = a.g;
+  const ZLds<T> L(smem, g);
+  src += blockIdx.y * sfs;
+  dst += blockIdx.y * mfs;
+  if (dzdst) dzdst += blockIdx.y * mfs;
+  const long long p0 = (long long)blockIdx.x * ZPB;
+  z_setup<T>(L, a, tid);
+  const int tot = g.npr * ZPB;
+  cpx<double> keep[OWN];
+#pragma unroll
+  for (int r = 0; r < OWN; ++r) {
+    const int e = tid + r * ZNT;
+    keep[r] = zero<double>();
+    if (e < tot) {
+      const long long p = p0 + e % ZPB;
+      if (p < g.npen) keep[r] = src[(long long)(e / ZPB) * g.npen + p];
+    }
+  }
+  const double inv = 1.0 / g.npr;
+  const int npass = dzdst ? 2 : 1;
+  for (int pass = 0; pass < npass; ++pass) {
+#pragma unroll
+    for (int r = 0; r < OWN; ++r) {
+      const int e = tid + r * ZNT;
+      if (e < tot) {
+        cpx<double> v = keep[r];
+        if (pass == 1) v = mul_i(v) * k_odd(e / ZPB, g.npr, g.kzs);
+        L.X0[e] = cvt<T>(conj(v));
+      }
+    }
+    __syncthreads();
+    const cpx<T>* R = fft_fwd<T, ZPB, BIG>(L.X0, L.X1, ZPB, 1, a.pl, L.tw, tid, ZNT);
+    cpx<double>* __restrict__ out = pass ? dzdst : dst;
+    for (int e = tid; e < g.nz * ZPB; e += ZNT) {
+      const long long p = p0 + e % ZPB;
+      if (p < g.npen) out[(long long)(e / ZPB) * g.npen + p] = conj(cvt<double>(R[e])) * inv;
+    }
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------- stage A
+// One field per blockIdx.y (0..2 velocity, 3 temperature).  Sec. 4.4 steps
+// 1-3 up to the FC-Gram transform of v*:
+//   N = sigma F_z(NL);  S = V^t + c (N - diff |k|^2 W);  v* = B_z S, plus the
+//   body force / buoyancy at the physical points, then the wall injection
+//   v*_par = c grad_par p_prev (theta = 0) and V* = F_z v*.
+template <typename T, bool BIG>
+__global__ __launch_bounds__(ZNT) void k_z_stageA(ZArgs a, StageAArgs s) {
+  extern __shared__ __align__(16) char smem[];
+  const int tid = threadIdx.x;
+  const Geom& g = a.g;
+  const ZLds<T> L(smem, g);
+  const int f = blockIdx.y;
+  const long long p0 = (long long)blockIdx.x * ZPB;
+  z_setup<T>(L, a, tid);
+  const cpx<double>* __restrict__ nl = s.nl[f];
+  const cpx<double>* __restrict__ vt = s.vt[f];
+  const cpx<double>* __restrict__ w = s.w[f];
+  const cpx<double>* __restrict__ buoy = s.buoy[f];
+  const double c = s.c;
+  const double diff = (f == 3) ? s.kappa : s.nu;
+  const double inv = 1.0 / g.npr;
+  cpx<T>* R = L.X0;
+  for (int pass = 0; pass < 3; ++pass) {
+    if (pass == 0) {
+      // nonlinear term at the physical points, continued
+      for (int e = tid; e < g.nz * ZPB; e += ZNT) {
+        const long long p = p0 + e % ZPB;
+        L.X0[e] = (p < g.npen) ? cvt<T>(nl[(long long)(e / ZPB) * g.npen + p]) : zero<T>();
+      }
+      __syncthreads();
+      z_extend<T>(L.X0, L.M, g.nz, g.C, g.d, tid);
+      __syncthreads();
+    } else if (pass == 1) {
+      // S = V^t + c (sigma N - diff |k|^2 W), conjugated for the inverse
+      for (int e = tid; e < g.npr * ZPB; e += ZNT) {
+        const int l = e / ZPB;
+        const long long p = p0 + e % ZPB;
+        cpx<double> S = zero<double>();
+        if (p < g.npen) {
+          double kxo, kyo, kxt, kyt;
+          int ix, iy;
+          pencil_k(g, p, kxo, kyo, kxt, kyt, ix, iy);
+          const double kzt = k_true(l, g.npr, g.kzs);
+          const double k2 = kxt * kxt + kyt * kyt + kzt * kzt;
+          const double sig = a.sigz[l] * a.sigy[iy] * a.sigx[ix];
+          const long long gi = (long long)l * g.npen + p;
+          S = vt[gi] + (cvt<double>(R[e]) * sig - w[gi] * (diff * k2)) * c;
+        }
+        L.X0[e] = cvt<T>(conj(S));
+      }
+      __syncthreads();
+    } else {
+      // v* at the physical points: forcing, buoyancy, wall injection
+      for (int e = tid; e < g.nz * ZPB; e += ZNT) {
+        const int z = e / ZPB;
+        const long long p = p0 + e % ZPB;
+        cpx<double> v = zero<double>();
+        if (p < g.npen) {
+          v = conj(cvt<double>(R[e])) * inv;
+          if (f == 0 && p == 0) v.x += c * s.forcing_sum;
+          if (buoy) v = v + buoy[(long long)z * g.npen + p] * (c * s.gamma);
+          if (z == 0 || z == g.nz - 1) {
+            const int wall = (z == 0) ? 0 : 1;
+            if (f < 2) v = s.gwall[(wall * 2 + f) * g.npen + p] * c;
+            if (f == 3) v = zero<double>();
+          }
+        }
+        L.X0[e] = cvt<T>(v);
+      }
+      __syncthreads();
+      z_extend<T>(L.X0, L.M, g.nz, g.C, g.d, tid);
+      __syncthreads();
+    }
+    R = fft_fwd<T, ZPB, BIG>(L.X0, L.X1, ZPB, 1, a.pl, L.tw, tid, ZNT);
+  }
+  cpx<double>* __restrict__ out = s.out[f];
+  for (int e = tid; e < g.npr * ZPB; e += ZNT) {
+    const long long p = p0 + e % ZPB;
+    if (p < g.npen) out[(long long)(e / ZPB) * g.npen + p] = cvt<double>(R[e]);
+  }
+}
+
+// ---------------------------------------------------------------- stage B
+// Pressure projection of V* (Sec. 4.2; Sec. 4.4 steps 3-5) in increment units
+// phi = c p:
+//   s = (k~ . V*) / |k~|^2, grad phi^I = k~ s (phi^I = -i s);
+//   b, t = wall values of B_z(V*_z - k~z s);
+//   gamma = |k~_h|, A = (t - b E)/(gamma (1 - E^2)), B = -(b - t E)/(...),
+//   E = exp(-gamma Lz); H = grad(A e^{gamma (z - Lz)} + B e^{-gamma z})
+//   (gamma = 0: H = (0, 0, D), D = (b + t)/2);
+//   V = V* - k~ s - F_z H; next-stage wall gradient (k~ B_z s + H)_par / c.
+// The two exponentials are continued as the real and imaginary parts of one
+// line; F_z(e+ + i e-) splits into F_z e+ and F_z e- by conjugate symmetry.
+template <typename T, bool BIG, int OWN>
+__global__ __launch_bounds__(ZNT) void k_z_stageB(ZArgs a, StageBArgs s) {
+  extern __shared__ __align__(16) char smem[];
+  __shared__ cpx<double> coef[ZPB * 5];  // b, t, s0, s1 then A, B, D
+  __shared__ double gam_s[ZPB];
+  const int tid = threadIdx.x;
+  const Geom& g = a.g;
+  const ZLds<T> L(smem, g);
+  const long long p0 = (long long)blockIdx.x * ZPB;
+  const int pb_me = tid % ZPB;
+  const long long p_me = p0 + pb_me;
+  const bool valid_me = p_me < g.npen;
+  z_setup<T>(L, a, tid);
+  const cpx<double>* __restrict__ gtw = a.tw64;
+  const int tot = g.npr * ZPB;
+  const double inv = 1.0 / g.npr;
+  const bool pm = s.pmix != nullptr;
+
+  double kxo, kyo, kxt, kyt;
+  int ix, iy;
+  pencil_k(g, valid_me ? p_me : 0, kxo, kyo, kxt, kyt, ix, iy);
+  const double kh2 = kxo * kxo + kyo * kyo;
+
+  // 1. V* (owned elements) and the wall sums of B_z(V*_z - k~z s) and B_z(s)
+  cpx<double> V[3][OWN];
+  cpx<double> sb = zero<double>(), st = zero<double>(), s0 = zero<double>(),
+              s1 = zero<double>();
+#pragma unroll
+  for (int r = 0; r < OWN; ++r) {
+    const int e = tid + r * ZNT;
+#pragma unroll
+    for (int i = 0; i < 3; ++i) V[i][r] = zero<double>();
+    if (e < tot && valid_me) {
+      const int l = e / ZPB;
+      const long long gi = (long long)l * g.npen + p_me;
+#pragma unroll
+      for (int i = 0; i < 3; ++i) V[i][r] = s.vs[i][gi];
+      const double kz = k_odd(l, g.npr, g.kzs);
+      const double k2 = kh2 + kz * kz;
+      cpx<double> sv = zero<double>();
+      if (k2 > 0.0) sv = (V[0][r] * kxo + V[1][r] * kyo + V[2][r] * kz) * (1.0 / k2);
+      const cpx<double> rz = V[2][r] - sv * kz;
+      // e^{+2 pi i l (nz-1)/N'} = conj(tw[l (nz-1) mod N'])
+      const cpx<double> et = conj(gtw[(int)(((long long)l * (g.nz - 1)) % g.npr)]);
+      sb = sb + rz;
+      st = st + rz * et;
+      s0 = s0 + sv;
+      s1 = s1 + sv * et;
+    }
+  }
+  cpx<double>* red = reinterpret_cast<cpx<double>*>(L.X1);
+  red[tid * 4 + 0] = sb;
+  red[tid * 4 + 1] = st;
+  red[tid * 4 + 2] = s0;
+  red[tid * 4 + 3] = s1;
+  __syncthreads();
+  if (tid < ZPB * 4) {
+    const int pb = tid % ZPB, q = tid / ZPB;
+    cpx<double> acc = zero<double>();
+    for (int m = 0; m < ZNT / ZPB; ++m) acc = acc + red[(pb + m * ZPB) * 4 + q];
+    coef[pb * 5 + q] = acc * inv;  // b, t, s0, s1
+  }
+  __syncthreads();
+  // 2. homogeneous coefficients and the wall gradient for the next stage
+  if (tid < ZPB) {
+    const int pb = tid;
+    const long long p = p0 + pb;
+    double qkxo, qkyo, qkxt, qkyt;
+    int qix, qiy;
+    pencil_k(g, p < g.npen ? p : 0, qkxo, qkyo, qkxt, qkyt, qix, qiy);
+    const cpx<double> b = coef[pb * 5 + 0], t = coef[pb * 5 + 1];
+    const cpx<double> sw0 = coef[pb * 5 + 2], sw1 = coef[pb * 5 + 3];
+    const double gam = sqrt(qkxo * qkxo + qkyo * qkyo);
+    cpx<double> A = zero<double>(), B = zero<double>(), D = zero<double>();
+    double E = 0.0;
+    if (gam > 0.0) {
+      E = exp(-gam * g.lz);
+      const double den = 1.0 / (gam * (1.0 - E * E));
+      A = (t - b * E) * den;
+      B = (b - t * E) * (-den);
+    } else {
+      D = (b + t) * 0.5;
+    }
+    gam_s[pb] = gam;
+    if (p < g.npen && s.gwall) {
+      // H_par at the walls: i k~ (A e+ + B e-) with e+(0) = E, e-(0) = 1,
+      // e+(Lz) = 1, e-(Lz) = E
+      const cpx<double> h0 = mul_i(A * E + B), h1 = mul_i(A + B * E);
+      const double ic = 1.0 / s.c;
+      s.gwall[(0 * 2 + 0) * g.npen + p] = (sw0 + h0) * (qkxo * ic);
+      s.gwall[(0 * 2 + 1) * g.npen + p] = (sw0 + h0) * (qkyo * ic);
+      s.gwall[(1 * 2 + 0) * g.npen + p] = (sw1 + h1) * (qkxo * ic);
+      s.gwall[(1 * 2 + 1) * g.npen + p] = (sw1 + h1) * (qkyo * ic);
+    }
+    coef[pb * 5 + 0] = A;
+    coef[pb * 5 + 1] = B;
+    coef[pb * 5 + 2] = D;
+  }
+  __syncthreads();
+  const cpx<double> A = coef[pb_me * 5 + 0], B = coef[pb_me * 5 + 1], D = coef[pb_me * 5 + 2];
+  const double gam = gam_s[pb_me];
+
+  // passes: 0 = F_z(e+ + i e-); 1 = pressure (optional); 2..7 = v_i, dv_i/dz
+  cpx<T>* Xo = L.X1;
+  for (int pass = 0; pass < 8; ++pass) {
+    if (pass == 1 && !pm) continue;
+    cpx<T>* in = L.X0;
+    if (pass == 0) {
+      for (int e = tid; e < g.nz * ZPB; e += ZNT) {
+        const int z = e / ZPB;
+        const double gm = gam_s[e % ZPB];
+        const double zz = z * g.dz;
+        L.X0[e] = (gm > 0.0) ? mk((T)exp(gm * (zz - g.lz)), (T)exp(-gm * zz)) : mk((T)1, (T)0);
+      }
+      __syncthreads();
+      z_extend<T>(L.X0, L.M, g.nz, g.C, g.d, tid);
+      __syncthreads();
+    } else if (pass == 1) {
+      in = Xo;
+    } else {
+      const int i = (pass - 2) >> 1, dz = (pass - 2) & 1;
+#pragma unroll
+      for (int r = 0; r < OWN; ++r) {
+        const int e = tid + r * ZNT;
+        if (e < tot) {
+          cpx<double> v = (i == 0) ? V[0][r] : ((i == 1) ? V[1][r] : V[2][r]);
+          if (dz) v = mul_i(v) * k_odd(e / ZPB, g.npr, g.kzs);
+          L.X0[e] = cvt<T>(conj(v));
+        }
+      }
+      __syncthreads();
+    }
+    cpx<T>* other = (in == L.X0) ? L.X1 : L.X0;
+    const cpx<T>* R = fft_fwd<T, ZPB, BIG>(in, other, ZPB, 1, a.pl, L.tw, tid, ZNT);
+    if (pass == 0) {
+      // V = V* - k~ s - H^ in registers; store the continued state
+      Xo = (R == L.X0) ? L.X1 : L.X0;
+#pragma unroll
+      for (int r = 0; r < OWN; ++r) {
+        const int e = tid + r * ZNT;
+        if (e < tot && valid_me) {
+          const int l = e / ZPB;
+          const int lm = (l == 0) ? 0 : g.npr - l;
+          const cpx<double> xl = cvt<double>(R[e]), xm = conj(cvt<double>(R[lm * ZPB + pb_me]));
+          const cpx<double> ep = (xl + xm) * 0.5;
+          const cpx<double> em = mul_mi(xl - xm) * 0.5;
+          const double kz = k_odd(l, g.npr, g.kzs);
+          const double k2 = kh2 + kz * kz;
+          cpx<double> sv = zero<double>();
+          if (k2 > 0.0) sv = (V[0][r] * kxo + V[1][r] * kyo + V[2][r] * kz) * (1.0 / k2);
+          cpx<double> hx = zero<double>(), hy = zero<double>(), hz;
+          if (gam > 0.0) {
+            const cpx<double> sym = A * ep + B * em;
+            hx = mul_i(sym) * kxo;
+            hy = mul_i(sym) * kyo;
+            hz = (A * ep - B * em) * gam;
+          } else {
+            hz = D * ep;
+          }
+          V[0][r] = V[0][r] - sv * kxo - hx;
+          V[1][r] = V[1][r] - sv * kyo - hy;
+          V[2][r] = V[2][r] - sv * kz - hz;
+          const long long gi = (long long)l * g.npen + p_me;
+#pragma unroll
+          for (int i = 0; i < 3; ++i) s.vout[i][gi] = V[i][r];
+          if (pm) Xo[e] = cvt<T>(conj(mul_mi(sv)));  // phi^I = -i s
+        } else if (e < tot && pm) {
+          Xo[e] = zero<T>();
+        }
+      }
+    } else if (pass == 1) {
+      // pressure in mixed space: (B_z(-i s) + phi^H) / c
+      for (int e = tid; e < g.nz * ZPB; e += ZNT) {
+        const int z = e / ZPB, pb = e % ZPB;
+        const long long p = p0 + pb;
+        if (p >= g.npen) continue;
+        const double zz = z * g.dz;
+        const double gm = gam_s[pb];
+        cpx<double> ph;
+        if (gm > 0.0)
+          ph = coef[pb * 5 + 0] * exp(gm * (zz - g.lz)) + coef[pb * 5 + 1] * exp(-gm * zz);
+        else
+          ph = coef[pb * 5 + 2] * zz;
+        s.pmix[(long long)z * g.npen + p] = (conj(cvt<double>(R[e])) * inv + ph) * (1.0 / s.c);
+      }
+    } else {
+      const int i = (pass - 2) >> 1, dz = (pass - 2) & 1;
+      cpx<double>* __restrict__ dst = dz ? s.mdz[i] : s.mv[i];
+      for (int e = tid; e < g.nz * ZPB; e += ZNT) {
+        const long long p = p0 + e % ZPB;
+        if (p < g.npen) dst[(long long)(e / ZPB) * g.npen + p] = conj(cvt<double>(R[e])) * inv;
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------- fc_extend
+// Strided real lines, one thread per line.
+__global__ __launch_bounds__(256) void k_fc_extend(const double* __restrict__ in, long long nlines,
+                                                   long long ips, long long ils,
+                                                   double* __restrict__ out, long long ops,
+                                                   long long ols, int nz, int C, int d,
+                                                   const double* __restrict__ M) {
+  const long long line = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (line >= nlines) return;
+  const double* f = in + line * ils;
+  double* o = out + line * ols;
+  for (int s = 0; s < nz; ++s) o[s * ops] = f[s * ips];
+  for (int i = 0; i < C; ++i) {
+    double acc = 0.0;
+    for (int j = 0; j < d; ++j) acc += M[i * d + j] * f[(nz - d + j) * ips];
+    for (int j = 0; j < d; ++j) acc += M[(C - 1 - i) * d + (d - 1 - j)] * f[j * ips];
+    o[(nz + i) * ops] = acc;
+  }
+}
+
+// ---------------------------------------------------------------- fc_derivative
+// Two real lines per complex line (line 2q real part, 2q+1 imaginary part):
+// the multipliers i k~z (Nyquist zeroed) and -kz^2 map real lines to real
+// lines, so the packed transform differentiates both at once.
+template <bool BIG>
+__global__ __launch_bounds__(ZNT) void k_fc_derivative(ZArgs a, const double* __restrict__ in,
+                                                       double* __restrict__ out, long long nlines,
+                                                       long long ps, long long ls, int order) {
+  extern __shared__ __align__(16) char smem[];
+  const int tid = threadIdx.x;
+  const Geom& g = a.g;
+  const ZLds<double> L(smem, g);
+  z_setup<double>(L, a, tid);
+  const long long q0 = (long long)blockIdx.x * ZPB;
+  for (int e = tid; e < g.nz * ZPB; e += ZNT) {
+    const int z = e / ZPB, pb = e % ZPB;
+    const long long l0 = 2 * (q0 + pb), l1 = l0 + 1;
+    const double re = (l0 < nlines) ? in[l0 * ls + z * ps] : 0.0;
+    const double im = (l1 < nlines) ? in[l1 * ls + z * ps] : 0.0;
+    L.X0[e] = mk(re, im);
+  }
+  __syncthreads();
+  z_extend<double>(L.X0, L.M, g.nz, g.C, g.d, tid);
+  __syncthreads();
+  const cpx<double>* R = L.X0;
+  for (int pass = 0; pass < 2; ++pass) {
+    if (pass == 1) {
+      for (int e = tid; e < g.npr * ZPB; e += ZNT) {
+        const int l = e / ZPB;
+        cpx<double> v = R[e];
+        if (order == 1) {
+          v = mul_i(v) * k_odd(l, g.npr, g.kzs);
+        } else {
+          const double k = k_true(l, g.npr, g.kzs);
+          v = v * (-k * k);
+        }
+        L.X0[e] = conj(v);
+      }
+      __syncthreads();
+    }
+    R = fft_fwd<double, ZPB, BIG>(L.X0, L.X1, ZPB, 1, a.pl, L.tw, tid, ZNT);
+  }
+  const double inv = 1.0 / g.npr;
+  for (int e = tid; e < g.nz * ZPB; e += ZNT) {
+    const int z = e / ZPB, pb = e % ZPB;
+    const long long l0 = 2 * (q0 + pb), l1 = l0 + 1;
+    const cpx<double> v = conj(R[e]) * inv;
+    if (l0 < nlines) out[l0 * ls + z * ps] = v.x;
+    if (l1 < nlines) out[l1 * ls + z * ps] = v.y;
+  }
+}
+
+// ---------------------------------------------------------------- launchers
+static int pick_own(int npr) {
+  const int need = (npr * ZPB + ZNT - 1) / ZNT;
+  if (need <= 4) return 4;
+  if (need <= 9) return 9;
+  return 16;
+}
+
+int z_max_npr() { return 16 * ZNT / ZPB; }
+
+#define FCNS_OWN_SWITCH(OWNV, CALL)                 \
+  switch (OWNV) {                                   \
+    case 4: { constexpr int OWN = 4; CALL; } break; \
+    case 9: { constexpr int OWN = 9; CALL; } break; \
+    default: { constexpr int OWN = 16; CALL; } break; \
+  }
+
+void launch_z_fwd(const ZArgs& a, bool big, const cpx<double>* src, cpx<double>* dst,
+                  long long sfs, long long dfs, int nfields, int filter, hipStream_t st) {
+  dim3 grid((unsigned)((a.g.npen + ZPB - 1) / ZPB), nfields);
+  const size_t sh = zshared_bytes<double>(a.g);
+  if (big)
+    FCNS_LAUNCH((k_z_fwd<double, true>), grid, dim3(ZNT), sh, st, a, src, dst, sfs, dfs, filter);
+  else
+    FCNS_LAUNCH((k_z_fwd<double, false>), grid, dim3(ZNT), sh, st, a, src, dst, sfs, dfs, filter);
+}
+
+void launch_z_back(const ZArgs& a, bool big, const cpx<double>* src, cpx<double>* dst,
+                   cpx<double>* dzdst, long long sfs, long long mfs, int nfields,
+                   hipStream_t st) {
+  dim3 grid((unsigned)((a.g.npen + ZPB - 1) / ZPB), nfields);
+  const size_t sh = zshared_bytes<double>(a.g);
+  const int own = pick_own(a.g.npr);
+  if (big) {
+    FCNS_OWN_SWITCH(own, FCNS_LAUNCH((k_z_back<double, true, OWN>), grid, dim3(ZNT), sh, st,
+                                            a, src, dst, dzdst, sfs, mfs))
+  } else {
+    FCNS_OWN_SWITCH(own, FCNS_LAUNCH((k_z_back<double, false, OWN>), grid, dim3(ZNT), sh, st,
+                                            a, src, dst, dzdst, sfs, mfs))
+  }
+}
+
+void launch_z_stageA(const ZArgs& a, bool big, const StageAArgs& s, int nfields, hipStream_t st) {
+  dim3 grid((unsigned)((a.g.npen + ZPB - 1) / ZPB), nfields);
+  const size_t sh = zshared_bytes<double>(a.g);
+  if (big)
+    FCNS_LAUNCH((k_z_stageA<double, true>), grid, dim3(ZNT), sh, st, a, s);
+  else
+    FCNS_LAUNCH((k_z_stageA<double, false>), grid, dim3(ZNT), sh, st, a, s);
+}
+
+void launch_z_stageB(const ZArgs& a, bool big, const StageBArgs& s, hipStream_t st) {
+  dim3 grid((unsigned)((a.g.npen + ZPB - 1) / ZPB), 1);
+  const size_t sh = zshared_bytes<double>(a.g);
+  const int own = pick_own(a.g.npr);
+  if (big) {
+    FCNS_OWN_SWITCH(own, FCNS_LAUNCH((k_z_stageB<double, true, OWN>), grid, dim3(ZNT), sh, st, a, s))
+  } else {
+    FCNS_OWN_SWITCH(own, FCNS_LAUNCH((k_z_stageB<double, false, OWN>), grid, dim3(ZNT), sh, st, a, s))
+  }
+}
+
+void launch_fc_extend(const double* in, long long nlines, long long ips, long long ils, double* out,
+                      long long ops, long long ols, int nz, int C, int d, const double* M,
+                      hipStream_t st) {
+  const int nt = 256;
+  dim3 grid((unsigned)((nlines + nt - 1) / nt));
+  FCNS_LAUNCH(k_fc_extend, grid, dim3(nt), 0, st, in, nlines, ips, ils, out, ops, ols, nz,
+                     C, d, M);
+}
+
+void launch_fc_derivative(const ZArgs& a, bool big, const double* in, double* out,
+                          long long nlines, long long ps, long long ls, int order,
+                          hipStream_t st) {
+  const long long nq = (nlines + 1) / 2;
+  dim3 grid((unsigned)((nq + ZPB - 1) / ZPB));
+  const size_t sh = zshared_bytes<double>(a.g);
+  if (big)
+    FCNS_LAUNCH(k_fc_derivative<true>, grid, dim3(ZNT), sh, st, a, in, out, nlines, ps, ls, order);
+  else
+    FCNS_LAUNCH(k_fc_derivative<false>, grid, dim3(ZNT), sh, st, a, in, out, nlines, ps, ls, order);
+}
+
+size_t z_lds_bytes(const Geom& g) { return zshared_bytes<double>(g); }
+
+}  // namespace fcns

@@ -1,0 +1,198 @@
+"""GPU (HIP, through the C ABI) versus the FP64 oracle, element by element.
+
+Tolerance: 1e-11 relative L2 for FP64 results (the bar the solver is built
+to), tighter where the operation is a single short chain of roundings.
+Sizes span several workgroup tiles with ragged tails, both FFT code paths
+(N' with only small radices, and N' = 58 = 2 * 29 and 282 = 2 * 3 * 47), and
+the edge cases of the interface.
+"""
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle.fcgram import fc_derivative_lines, fc_extend_lines
+from oracle.ns import Oracle, Problem
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def fcns():
+    if not torch.cuda.is_available():
+        pytest.skip("no HIP device")
+    import paper_2002_01392_amd as P
+    P.load_library()
+    return P
+
+
+def rel_l2(a, b):
+    a = a.detach().cpu().numpy() if hasattr(a, "detach") else np.asarray(a)
+    b = np.asarray(b)
+    nb = np.linalg.norm(b)
+    return float(np.linalg.norm(a - b) / (nb if nb > 0 else 1.0))
+
+
+def solver(P, nx, ny, nz, C=25, lx=2 * np.pi, ly=2 * np.pi, lz=1.0, nu=0.0, **kw):
+    return P.Solver(nx, ny, nz, lx, ly, lz, nu, d=5, C=C, **kw)
+
+
+# ------------------------------------------------------------------ fc_extend / fc_derivative
+@pytest.mark.parametrize("nz,C,nlines", [(33, 25, 7), (65, 31, 300), (257, 31, 1031),
+                                         (257, 25, 129)])
+def test_fc_extend_parity(fcns, nz, C, nlines):
+    s = solver(fcns, 8, 8, nz, C=C)
+    f = W.rng(100 + nz).standard_normal((nlines, nz))
+    got = s.fc_extend(torch.from_numpy(f))
+    torch.cuda.synchronize()
+    ref = fc_extend_lines(f, 5, C)
+    assert np.array_equal(got[:, :nz].cpu().numpy(), f)
+    assert rel_l2(got, ref) < 1e-14
+
+
+@pytest.mark.parametrize("nz,C,nlines", [(33, 25, 5), (65, 31, 77), (257, 31, 513),
+                                         (257, 25, 40), (129, 31, 16)])
+@pytest.mark.parametrize("order", [1, 2])
+def test_fc_derivative_parity(fcns, nz, C, nlines, order):
+    s = solver(fcns, 8, 8, nz, C=C, lz=1.7)
+    z = np.linspace(0, 1.7, nz)
+    r = W.rng(7 * nz + order)
+    f = np.stack([np.sin(r.uniform(1, 9) * z + r.uniform()) * np.exp(r.uniform(-1, 1) * z)
+                  for _ in range(nlines)])
+    got = s.fc_derivative(torch.from_numpy(f), order)
+    torch.cuda.synchronize()
+    ref = fc_derivative_lines(f, 5, C, 1.7, order)
+    assert rel_l2(got, ref) < 1e-12
+
+
+def test_empty_and_invalid_inputs(fcns):
+    s = solver(fcns, 8, 8, 33)
+    out = s.fc_extend(torch.zeros((0, 33), dtype=torch.float64))
+    assert out.shape == (0, 58)
+    with pytest.raises(fcns.FcnsError) as e:
+        s.rk_step(1e-3, 1)
+    assert e.value.code == -5
+    with pytest.raises(fcns.FcnsError):
+        solver(fcns, 9, 8, 33)            # odd nx
+    with pytest.raises(fcns.FcnsError):
+        solver(fcns, 8, 8, 34)            # odd N' = 59
+    with pytest.raises(fcns.FcnsError):
+        s.fc_derivative(torch.zeros((2, 33), dtype=torch.float64), order=3)
+
+
+# ------------------------------------------------------------------ transforms and state
+@pytest.mark.parametrize("nx,ny,nz,C", [(16, 12, 33, 25), (24, 20, 65, 31), (64, 40, 97, 31)])
+def test_state_round_trip_and_spectrum(fcns, nx, ny, nz, C):
+    lx, ly, lz = 2.0, 3.0, 1.3
+    s = fcns.Solver(nx, ny, nz, lx, ly, lz, 0.01, d=5, C=C)
+    v = np.stack([W.smooth_field(nx, ny, nz, lx, ly, lz, 10 + i) for i in range(3)])
+    s.set_state(torch.from_numpy(v))
+    got, _, _ = s.get_state()
+    spec = s.get_spectral(0)
+    torch.cuda.synchronize()
+    assert rel_l2(got, v) < 1e-13
+    o = Oracle(Problem(nx=nx, ny=ny, nz=nz, lx=lx, ly=ly, lz=lz, nu=0.01, C=C))
+    o.set_state(v)
+    assert rel_l2(spec, o.Vt[0]) < 1e-13
+
+
+# ------------------------------------------------------------------ nonlinear term
+@pytest.mark.parametrize("filtered", [False, True])
+@pytest.mark.parametrize("nx,ny,nz,C", [(16, 16, 33, 25), (32, 24, 65, 31)])
+def test_rhs_nonlinear_parity(fcns, filtered, nx, ny, nz, C):
+    lx, ly, lz = 2.0, 2.0, 1.0
+    s = fcns.Solver(nx, ny, nz, lx, ly, lz, 0.01, d=5, C=C, boussinesq=True, kappa=0.01,
+                    gamma=1.0)
+    v = np.stack([W.smooth_field(nx, ny, nz, lx, ly, lz, 20 + i) for i in range(3)])
+    th = W.smooth_field(nx, ny, nz, lx, ly, lz, 30)
+    nlv, nlt = s.rhs_nonlinear(torch.from_numpy(v), torch.from_numpy(th), filtered)
+    torch.cuda.synchronize()
+    o = Oracle(Problem(nx=nx, ny=ny, nz=nz, lx=lx, ly=ly, lz=lz, nu=0.01, C=C,
+                       boussinesq=True, kappa=0.01, gamma=1.0))
+    rv, rt = o.rhs_nonlinear(v, th, filtered)
+    assert rel_l2(nlv, rv) < 1e-12
+    assert rel_l2(nlt, rt) < 1e-12
+
+
+# ------------------------------------------------------------------ projection
+@pytest.mark.parametrize("nx,ny,nz,C,c", [(16, 16, 33, 25, 0.5), (32, 24, 65, 31, 1e-3),
+                                          (20, 36, 129, 31, 2.0)])
+def test_pressure_project_parity(fcns, nx, ny, nz, C, c):
+    lx, ly, lz = 2 * np.pi, 3.0, 1.0
+    s = fcns.Solver(nx, ny, nz, lx, ly, lz, 0.0, d=5, C=C)
+    vs = np.stack([W.smooth_field(nx, ny, nz, lx, ly, lz, 40 + i) for i in range(3)])
+    v, gp = s.pressure_project(torch.from_numpy(vs), c)
+    torch.cuda.synchronize()
+    o = Oracle(Problem(nx=nx, ny=ny, nz=nz, lx=lx, ly=ly, lz=lz, nu=0.0, C=C))
+    rv, rg = o.pressure_project(vs, c)
+    assert rel_l2(v, rv) < 1e-11
+    assert rel_l2(gp, rg) < 1e-11
+    # v_z vanishes at the walls to rounding (Sec. 6: <w^2_wall> ~ 1e-35)
+    vz = v[2].cpu().numpy()
+    assert np.abs(vz[0]).max() < 1e-12 * np.abs(vs).max()
+    assert np.abs(vz[-1]).max() < 1e-12 * np.abs(vs).max()
+
+
+# ------------------------------------------------------------------ time stepping
+def _run_pair(fcns, w, steps, keep_pressure=True):
+    v0, th0 = w.initial_state()
+    s = fcns.Solver.from_workload(w, keep_pressure=keep_pressure)
+    s.set_state(torch.from_numpy(v0), torch.from_numpy(th0) if th0 is not None else None)
+    s.rk_step(w.dt, steps)
+    v, th, p = s.get_state(pressure=keep_pressure)
+    gw = s.get_wall_grad()
+    torch.cuda.synchronize()
+    o = Oracle(Problem(**w.problem_kwargs()))
+    o.set_state(v0, th0)
+    o.rk_step(w.dt, steps)
+    rv, rth, rp = o.get_state()
+    return (v, th, p, gw), (rv, rth, rp, o.G)
+
+
+def test_rk_channel_small_workload(fcns):
+    # the 32x32x33 channel workload (d = 5, C = 25, N' = 58), its 10 steps
+    w = W.get("channel_32x32x33")
+    (v, _, p, gw), (rv, _, rp, rg) = _run_pair(fcns, w, w.steps)
+    assert rel_l2(v, rv) < 1e-11
+    assert rel_l2(p, rp) < 1e-10
+    assert rel_l2(gw, rg) < 1e-10
+
+
+def test_rk_rayleigh_benard_small(fcns):
+    w = W.rayleigh_benard(32, 24, 33, 1e5, C=31, dt=2e-3, steps=8, kmax=3, mmax=3,
+                          noise_rms=1e-2)
+    (v, th, p, _), (rv, rth, rp, _) = _run_pair(fcns, w, w.steps)
+    assert rel_l2(th, rth) < 1e-11
+    assert rel_l2(v, rv) < 1e-10
+    assert rel_l2(p, rp) < 1e-9
+
+
+def test_rk_channel_big_prime_length(fcns):
+    # N' = 282 = 2 * 3 * 47 (the C = 25 table on nz = 257) on a narrow grid
+    w = W.channel(16, 8, 257, 2000.0, d=5, C=25, dt=5e-4, steps=3, seed=9, noise_rms=0.05)
+    (v, _, _, _), (rv, _, _, _) = _run_pair(fcns, w, w.steps, keep_pressure=False)
+    assert rel_l2(v, rv) < 1e-11
+
+
+def test_rk_is_deterministic_and_restartable(fcns):
+    w = W.get("channel_32x32x33")
+    v0, _ = w.initial_state()
+    a = fcns.Solver.from_workload(w)
+    a.set_state(torch.from_numpy(v0))
+    a.rk_step(w.dt, 4)
+    snap = [a.get_spectral(f).clone() for f in range(3)]
+    gw = a.get_wall_grad().clone()
+    a.rk_step(w.dt, 3)
+    va, _, _ = a.get_state()
+    b = fcns.Solver.from_workload(w)
+    b.set_spectral(snap, gw)
+    b.rk_step(w.dt, 3)
+    vb, _, _ = b.get_state()
+    c = fcns.Solver.from_workload(w)
+    c.set_state(torch.from_numpy(v0))
+    c.rk_step(w.dt, 7)
+    vc, _, _ = c.get_state()
+    torch.cuda.synchronize()
+    assert torch.equal(va, vb)     # resume is bitwise identical
+    assert torch.equal(va, vc)     # and so is a repeated run
