@@ -1,7 +1,9 @@
 """GPU (HIP, through the C ABI) versus the FP64 oracle, element by element.
 
 Tolerance: 1e-11 relative L2 for FP64 results (the bar the solver is built
-to), tighter where the operation is a single short chain of roundings.
+to), tighter where no FC continuation is involved.  The continuation tables
+have entries up to ~1e4 (App. B: the ill-conditioning sits in the tables),
+so one continuation already carries ~1e-12 relative rounding noise.
 Sizes span several workgroup tiles with ragged tails, both FFT code paths
 (N' with only small radices, and N' = 58 = 2 * 29 and 282 = 2 * 3 * 47), and
 the edge cases of the interface.
@@ -63,7 +65,7 @@ def test_fc_derivative_parity(fcns, nz, C, nlines, order):
     got = s.fc_derivative(torch.from_numpy(f), order)
     torch.cuda.synchronize()
     ref = fc_derivative_lines(f, 5, C, 1.7, order)
-    assert rel_l2(got, ref) < 1e-12
+    assert rel_l2(got, ref) < 1e-11
 
 
 def test_empty_and_invalid_inputs(fcns):
@@ -91,10 +93,10 @@ def test_state_round_trip_and_spectrum(fcns, nx, ny, nz, C):
     got, _, _ = s.get_state()
     spec = s.get_spectral(0)
     torch.cuda.synchronize()
-    assert rel_l2(got, v) < 1e-13
+    assert rel_l2(got, v) < 1e-12
     o = Oracle(Problem(nx=nx, ny=ny, nz=nz, lx=lx, ly=ly, lz=lz, nu=0.01, C=C))
     o.set_state(v)
-    assert rel_l2(spec, o.Vt[0]) < 1e-13
+    assert rel_l2(spec, o.Vt[0]) < 1e-11
 
 
 # ------------------------------------------------------------------ nonlinear term
@@ -111,8 +113,8 @@ def test_rhs_nonlinear_parity(fcns, filtered, nx, ny, nz, C):
     o = Oracle(Problem(nx=nx, ny=ny, nz=nz, lx=lx, ly=ly, lz=lz, nu=0.01, C=C,
                        boussinesq=True, kappa=0.01, gamma=1.0))
     rv, rt = o.rhs_nonlinear(v, th, filtered)
-    assert rel_l2(nlv, rv) < 1e-12
-    assert rel_l2(nlt, rt) < 1e-12
+    assert rel_l2(nlv, rv) < 1e-11
+    assert rel_l2(nlt, rt) < 1e-11
 
 
 # ------------------------------------------------------------------ projection
