@@ -1,0 +1,226 @@
+"""Benchmark of the FC-Gram RK step on one MI355X.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME]
+
+Prints one JSON line: grid-point RK-substeps per second (physical points
+nx*ny*nz times RK stages, o = 2 per step) over K timed steps after W warmup
+steps, with inputs resident in HBM; the roofline of the dominant kernel
+(algorithmic bytes per launch over its mean event-timed duration on the
+solver stream); and the FP64 oracle timed on a bounded sample of the same
+workload on the host cores.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = ("grid-point RK-substeps/sec (FP64 & mixed) + p50/p99 step latency in batched "
+          "serving")
+UNIT = "grid-point RK-substeps/s"
+HBM_PEAK_GBPS = 8000.0
+CSRC = os.path.join(ROOT, "paper_2002_01392_amd", "csrc")
+PROFILES = os.path.join(ROOT, "profiles")
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for fn in sorted(os.listdir(CSRC)):
+        with open(os.path.join(CSRC, fn), "rb") as fh:
+            h.update(fn.encode())
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def field_bytes(w):
+    """(M, S): bytes of one complex128 mixed field and one continued field."""
+    nkx = w.nx // 2 + 1
+    M = w.nz * w.ny * nkx * 16
+    S = (w.nz + w.C) * w.ny * nkx * 16
+    return M, S
+
+
+def algorithmic_bytes(w, cls, stage, keep_pressure=False):
+    """Bytes one launch of a kernel class must move (each array read or written
+    once).  F = transported fields, M / S = one mixed / continued field."""
+    F = w.nfields
+    M, S = field_bytes(w)
+    rb = w.boussinesq
+    if cls == "y_back_dy":
+        return 3 * F * M            # read q^, write q and dq/dy
+    if cls == "y_back_dz":
+        return 2 * F * M
+    if cls == "x_nl":
+        return 4 * F * M            # read q, dq/dy, dq/dz; write NL
+    if cls == "y_fwd":
+        return 2 * F * M
+    if cls == "z_stageA":
+        reads_state = F * S if stage == 1 else 2 * F * S   # V^t (= W at stage 1), W
+        return F * M + reads_state + F * S + (2 * M if rb else 0)
+    if cls == "z_stageB":
+        return 6 * S + 6 * M + (M if keep_pressure else 0)
+    if cls == "z_back_theta":
+        return S + 2 * M
+    raise KeyError(cls)
+
+
+def pass_model_bytes(w):
+    """The four-pass model per substep: 14 F M + 3 F S."""
+    M, S = field_bytes(w)
+    return 14 * w.nfields * M + 3 * w.nfields * S
+
+
+def cpu_baseline(w, seconds_hint=20.0):
+    """The FP64 oracle (as it stands) on a bounded sample: one RK step of the
+    same workload parameters and wall-normal grid on a reduced horizontal
+    grid, BLAS limited to one thread (numpy's FFT is single-threaded)."""
+    import numpy as np
+    from dataclasses import replace
+    from threadpoolctl import threadpool_limits
+
+    from oracle.ns import Oracle, Problem
+    nxs = max(16, min(w.nx, 128))
+    nys = max(16, min(w.ny, 128))
+    ws = replace(w, nx=nxs, ny=nys, lx=w.lx * nxs / w.nx, ly=w.ly * nys / w.ny)
+    v0, th0 = ws.initial_state()
+    with threadpool_limits(limits=1):
+        o = Oracle(Problem(**ws.problem_kwargs()))
+        o.set_state(v0, th0)
+        t0 = time.perf_counter()
+        o.rk_step(ws.dt, 1)
+        el = time.perf_counter() - t0
+    pts = ws.nx * ws.ny * ws.nz
+    return {"value": pts * 2 / el, "unit": UNIT, "cores": 1, "kind": "oracle",
+            "sample": (f"1 RK2 step (2 substeps) of {w.name}'s parameters, nz={w.nz}, C={w.C}, "
+                       f"on a {nxs}x{nys} horizontal grid (box scaled to keep dx, dy), "
+                       f"{el:.1f} s, numpy FFT, BLAS 1 thread")}
+
+
+def load_traffic(w, kernel, src_hash):
+    """HBM bytes per launch from the committed rocprofv3 PMC summary, if it was
+    taken on the current kernel sources and workload."""
+    p = os.path.join(PROFILES, f"pmc_{kernel}_{w.name}.json")
+    if not os.path.exists(p):
+        return None
+    try:
+        d = json.load(open(p))
+    except Exception:
+        return None
+    if d.get("source_hash") != src_hash or d.get("workload") != w.name:
+        return None
+    return d.get("hbm_bytes_per_launch")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="rb_512x512x257")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--timing", type=int, default=1, help="event-time kernels in the timed region")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import workloads as W
+    from paper_2002_01392_amd import Solver
+
+    w = W.get(args.workload)
+    print(f"[bench] workload {w.name}: building initial state", file=sys.stderr, flush=True)
+    v0, th0 = w.initial_state()
+    s = Solver.from_workload(w)
+    s.set_state(torch.from_numpy(v0), torch.from_numpy(th0) if th0 is not None else None)
+    del v0, th0
+    torch.cuda.synchronize()
+    print(f"[bench] warmup {args.warmup} steps", file=sys.stderr, flush=True)
+    s.rk_step(w.dt, args.warmup)
+    torch.cuda.synchronize()
+
+    if args.timing:
+        s.set_timing(True)
+        s.timing_reset()
+    stream = s.stream
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]
+    print(f"[bench] timing {args.steps} steps", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ev[0].record(stream)
+    for k in range(args.steps):
+        s.rk_step(w.dt, 1)
+        ev[k + 1].record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    step_ms = np.array([ev[k].elapsed_time(ev[k + 1]) for k in range(args.steps)])
+    total_ms = float(ev[0].elapsed_time(ev[-1]))
+    rep = s.timing_report() if args.timing else {}
+    v, th, _ = s.get_state()
+    finite = bool(torch.isfinite(v).all().item()) and (th is None or bool(torch.isfinite(th).all().item()))
+    torch.cuda.synchronize()
+
+    pts = w.nx * w.ny * w.nz
+    substeps = 2 * args.steps
+    ms_per_step = total_ms / args.steps
+    value = pts * substeps / (total_ms / 1e3)
+
+    roof = None
+    kernels = {}
+    src_hash = kernel_source_hash()
+    if rep:
+        tot = {k: ms for k, (n, ms) in rep.items() if n > 0}
+        dom = max(tot, key=tot.get)
+        n_dom, ms_dom = rep[dom]
+        per_launch_s = ms_dom / n_dom / 1e3
+        b = 0.5 * (algorithmic_bytes(w, dom, 1) + algorithmic_bytes(w, dom, 2))
+        ach = b / per_launch_s / 1e9
+        traffic = load_traffic(w, dom, src_hash)
+        roof = {"bound": "hbm", "kernel": dom, "achieved": round(ach, 1), "peak": HBM_PEAK_GBPS,
+                "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBPS, 4), "traffic": traffic,
+                "bytes_per_launch": int(b), "mean_launch_ms": round(ms_dom / n_dom, 4)}
+        for k, (n, ms) in rep.items():
+            if n == 0:
+                continue
+            bk = 0.5 * (algorithmic_bytes(w, k, 1) + algorithmic_bytes(w, k, 2))
+            kernels[k] = {"launches": n, "mean_ms": round(ms / n, 4),
+                          "GBps": round(bk / (ms / n / 1e3) / 1e9, 1),
+                          "share": round(ms / sum(tot.values()), 4)}
+    pm = pass_model_bytes(w)
+    pass_model = {"bytes_per_substep": pm,
+                  "GBps": round(pm / (total_ms / 1e3 / substeps) / 1e9, 1),
+                  "frac": round(pm / (total_ms / 1e3 / substeps) / 1e9 / HBM_PEAK_GBPS, 4)}
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        print("[bench] cpu baseline (oracle)", file=sys.stderr, flush=True)
+        cpu = cpu_baseline(w)
+
+    out = {
+        "metric": METRIC, "value": value, "unit": UNIT, "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms_per_step, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": w.name, "grid": [w.nx, w.ny, w.nz], "box": [w.lx, w.ly, w.lz],
+                   "fc_d": w.d, "fc_C": w.C, "N_prime": w.nz + w.C, "fields": w.nfields,
+                   "dt": w.dt, "rk_order": 2, "nu": w.nu, "kappa": w.kappa, "gamma": w.gamma,
+                   "forcing_x": w.forcing_x},
+        "step_ms_p50": float(np.percentile(step_ms, 50)),
+        "step_ms_p99": float(np.percentile(step_ms, 99)),
+        "wall_s": wall, "state_finite": finite,
+        "roofline": roof, "pass_model": pass_model, "kernels": kernels,
+        "cpu_baseline": cpu, "kernel_source_hash": src_hash,
+    }
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

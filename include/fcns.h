@@ -133,6 +133,18 @@ fcns_status fcns_get_spectral(fcns_ctx* ctx, int32_t field, double* out);
 fcns_status fcns_set_spectral(fcns_ctx* ctx, const double* const* fields, const double* wall_grad);
 fcns_status fcns_get_wall_grad(fcns_ctx* ctx, double* out);
 
+/* Kernel timing for tracing and roofline reports.  While enabled, every
+ * kernel that rk_step launches is bracketed by HIP events recorded on the
+ * context stream (small extra launch latency).  Classes: y_back_dy,
+ * y_back_dz, x_nl, y_fwd, z_stageA, z_stageB, z_back_theta. */
+fcns_status fcns_set_timing(fcns_ctx* ctx, int32_t enable);
+fcns_status fcns_timing_reset(fcns_ctx* ctx);
+/* Synchronizes the stream, then fills up to max classes: names (HOST,
+ * 32 chars each, NUL-terminated), counts (HOST, launches) and ms (HOST,
+ * summed event durations since the last reset); *n = classes written. */
+fcns_status fcns_timing_report(fcns_ctx* ctx, int32_t max, int32_t* n, char* names,
+                               int64_t* counts, double* ms);
+
 /* Sizes of the context: N' and the number of transported fields. */
 int32_t fcns_npr(const fcns_ctx* ctx);
 

@@ -50,6 +50,9 @@ SIGNATURES = {
     "fcns_set_spectral": (ctypes.c_int, [_P, ctypes.POINTER(_P), _P]),
     "fcns_get_wall_grad": (ctypes.c_int, [_P, _P]),
     "fcns_npr": (ctypes.c_int32, [_P]),
+    "fcns_set_timing": (ctypes.c_int, [_P, _I32]),
+    "fcns_timing_reset": (ctypes.c_int, [_P]),
+    "fcns_timing_report": (ctypes.c_int, [_P, _I32, ctypes.POINTER(_I32), _P, _P, _P]),
     "fcns_last_error": (ctypes.c_char_p, [_P]),
 }
 
@@ -229,6 +232,25 @@ class Solver:
         wg = wall_grad.to(self.device).contiguous() if wall_grad is not None else None
         self._check(self.lib.fcns_set_spectral(self.ctx, arr, _ptr(wg)))
         self._keep = (fs, wg)
+
+    def set_timing(self, enable=True):
+        self._check(self.lib.fcns_set_timing(self.ctx, int(bool(enable))))
+
+    def timing_reset(self):
+        self._check(self.lib.fcns_timing_reset(self.ctx))
+
+    def timing_report(self):
+        """{kernel class: (launches, total ms)} since the last reset."""
+        n = ctypes.c_int32()
+        names = ctypes.create_string_buffer(32 * 16)
+        counts = (ctypes.c_int64 * 16)()
+        ms = (ctypes.c_double * 16)()
+        self._check(self.lib.fcns_timing_report(self.ctx, 16, ctypes.byref(n), names, counts, ms))
+        out = {}
+        for i in range(n.value):
+            nm = names.raw[32 * i:32 * (i + 1)].split(b"\0")[0].decode()
+            out[nm] = (int(counts[i]), float(ms[i]))
+        return out
 
     def synchronize(self):
         self.stream.synchronize()

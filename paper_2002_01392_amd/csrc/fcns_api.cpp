@@ -43,7 +43,53 @@ struct fcns_ctx {
   bool has_state = false;
   bool has_pressure = false;
   std::string err;
+  // kernel timing (HIP events around every rk_step launch)
+  bool timing = false;
+  std::vector<hipEvent_t> evpool;
+  size_t evnext = 0;
+  struct Rec {
+    int cls;
+    hipEvent_t a, b;
+  };
+  std::vector<Rec> recs;
+  Rec cur{};
+  double tms[16] = {};
+  long long tcnt[16] = {};
 };
+
+// Kernel classes timed by fcns_set_timing.
+enum { T_YBACK_DY = 0, T_YBACK_DZ, T_XNL, T_YFWD, T_ZSTAGEA, T_ZSTAGEB, T_ZBACK_TH, T_NCLS };
+static const char* kTimingNames[T_NCLS] = {"y_back_dy", "y_back_dz", "x_nl", "y_fwd",
+                                           "z_stageA", "z_stageB", "z_back_theta"};
+
+static void timing_flush(fcns_ctx* c) {
+  if (c->recs.empty()) return;
+  (void)hipStreamSynchronize(c->stream);
+  for (const auto& r : c->recs) {
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, r.a, r.b) == hipSuccess) {
+      c->tms[r.cls] += ms;
+      c->tcnt[r.cls] += 1;
+    }
+  }
+  c->recs.clear();
+  c->evnext = 0;
+}
+
+static void tbeg(fcns_ctx* c, int cls) {
+  if (!c->timing) return;
+  if (c->evnext + 2 > c->evpool.size()) timing_flush(c);
+  c->cur.cls = cls;
+  c->cur.a = c->evpool[c->evnext++];
+  (void)hipEventRecord(c->cur.a, c->stream);
+}
+
+static void tend(fcns_ctx* c) {
+  if (!c->timing) return;
+  c->cur.b = c->evpool[c->evnext++];
+  (void)hipEventRecord(c->cur.b, c->stream);
+  c->recs.push_back(c->cur);
+}
 
 static std::string g_create_err;
 
@@ -123,6 +169,8 @@ static fcns_status alloc(fcns_ctx* c, cpx<double>** p, long long n) {
 }
 
 static void free_all(fcns_ctx* c) {
+  for (hipEvent_t e : c->evpool) (void)hipEventDestroy(e);
+  c->evpool.clear();
   void* ps[] = {c->twz, c->twx, c->twy, c->fcM, c->sigx, c->sigy, c->sigz, c->P, c->Q,
                 c->VS, c->MV, c->MVT, c->XYB, c->NLB, c->PM, c->GW, c->GWT};
   for (void* p : ps)
@@ -145,6 +193,7 @@ static YArgs yargs(const fcns_ctx* c) {
   YArgs a;
   a.ny = c->g.ny;
   a.nkx = c->g.nkx;
+  a.nkxp = c->g.nkxp;
   a.kys = c->g.kys;
   a.pl = c->ply;
   a.tw = c->twy;
@@ -154,6 +203,7 @@ static XArgs xargs(const fcns_ctx* c) {
   XArgs a;
   a.nx = c->g.nx;
   a.nkx = c->g.nkx;
+  a.nkxp = c->g.nkxp;
   a.ny = c->g.ny;
   a.kxs = c->g.kxs;
   a.pl = c->plx;
@@ -190,10 +240,11 @@ extern "C" fcns_status fcns_create(const fcns_problem* prob, void* hip_stream, f
   g.ny = p.ny;
   g.nz = p.nz;
   g.nkx = p.nx / 2 + 1;
+  g.nkxp = (g.nkx + 3) / 4 * 4;
   g.npr = npr;
   g.C = p.fc_C;
   g.d = p.fc_d;
-  g.npen = (long long)g.nkx * g.ny;
+  g.npen = (long long)g.nkxp * g.ny;
   g.lx = p.lx;
   g.ly = p.ly;
   g.lz = p.lz;
@@ -295,7 +346,7 @@ static void phys_to_mixed(fcns_ctx* c, const double* phys, int nfields, cpx<doub
 static void mixed_to_phys(fcns_ctx* c, const cpx<double>* mixed, long long mstride, int nfields,
                           double* phys, int nplanes) {
   const Geom& g = c->g;
-  const long long plane = (long long)g.ny * g.nkx;
+  const long long plane = (long long)g.ny * g.nkxp;
   const long long xfs = (long long)nplanes * plane;
   launch_y(yargs(c), c->big_y, true, 0, mixed, c->XYB, nullptr, mstride, xfs, nplanes, nfields,
            c->stream);
@@ -308,14 +359,23 @@ static void mixed_to_phys(fcns_ctx* c, const cpx<double>* mixed, long long mstri
 static void nonlinear_from_mixed(fcns_ctx* c, const cpx<double>* mv, int nfields, bool fwd_y) {
   const Geom& g = c->g;
   const long long M = c->M;
+  tbeg(c, T_YBACK_DY);
   launch_y(yargs(c), c->big_y, true, 1, mv, c->XYB, c->XYB + M, 2 * M, 3 * M, g.nz, nfields,
            c->stream);
+  tend(c);
+  tbeg(c, T_YBACK_DZ);
   launch_y(yargs(c), c->big_y, true, 0, mv + M, c->XYB + 2 * M, nullptr, 2 * M, 3 * M, g.nz,
            nfields, c->stream);
+  tend(c);
+  tbeg(c, T_XNL);
   launch_x_nl(xargs(c), c->big_x, c->XYB, c->NLB, M, (long long)g.nz * g.ny, nfields, c->stream);
-  if (fwd_y)
+  tend(c);
+  if (fwd_y) {
+    tbeg(c, T_YFWD);
     launch_y(yargs(c), c->big_y, false, 0, c->NLB, c->NLB, nullptr, M, M, g.nz, nfields,
              c->stream);
+    tend(c);
+  }
 }
 
 // ---------------------------------------------------------------- entry points
@@ -396,7 +456,9 @@ static void rk_stage(fcns_ctx* c, int j, int o, double dt) {
   A.kappa = c->prob.kappa;
   A.gamma = c->prob.gamma;
   A.forcing_sum = c->prob.forcing_x * (double)g.nx * (double)g.ny;
+  tbeg(c, T_ZSTAGEA);
   launch_z_stageA(zargs(c), c->big_z, A, nf, c->stream);
+  tend(c);
   // stage B: projection, next-stage wall gradient, mixed v and dv/dz
   StageBArgs B{};
   for (int i = 0; i < 3; ++i) {
@@ -408,10 +470,15 @@ static void rk_stage(fcns_ctx* c, int j, int o, double dt) {
   B.gwall = c->GW;
   B.pmix = (c->prob.keep_pressure && j == o) ? c->PM : nullptr;
   B.c = cj;
+  tbeg(c, T_ZSTAGEB);
   launch_z_stageB(zargs(c), c->big_z, B, c->stream);
-  if (nf == 4)
+  tend(c);
+  if (nf == 4) {
+    tbeg(c, T_ZBACK_TH);
     launch_z_back(zargs(c), c->big_z, OUT + 3 * S, c->MV + 6 * M, c->MV + 7 * M, S, 2 * M, 1,
                   c->stream);
+    tend(c);
+  }
 }
 
 extern "C" fcns_status fcns_rk_step(fcns_ctx* c, double dt, int32_t nsteps) {
@@ -501,9 +568,11 @@ extern "C" fcns_status fcns_get_spectral(fcns_ctx* c, int32_t field, double* out
   if (!c) return FCNS_EINVAL;
   if (!c->has_state) return fail(c, FCNS_ESTATE, "no state");
   if (field < 0 || field >= c->nf || !out) return fail(c, FCNS_EINVAL, "bad field or NULL");
+  const size_t w = c->g.nkx * sizeof(cpx<double>), ld = c->g.nkxp * sizeof(cpx<double>);
   return check_hip(c,
-                   hipMemcpyAsync(out, c->P + field * c->S, c->S * sizeof(cpx<double>),
-                                  hipMemcpyDeviceToDevice, c->stream),
+                   hipMemcpy2DAsync(out, w, c->P + field * c->S, ld, w,
+                                    (size_t)c->g.npr * c->g.ny, hipMemcpyDeviceToDevice,
+                                    c->stream),
                    "get_spectral");
 }
 
@@ -513,16 +582,19 @@ extern "C" fcns_status fcns_set_spectral(fcns_ctx* c, const double* const* field
   if (!fields) return fail(c, FCNS_EINVAL, "NULL fields");
   for (int f = 0; f < c->nf; ++f) {
     if (!fields[f]) return fail(c, FCNS_EINVAL, "NULL field");
+    const size_t w = c->g.nkx * sizeof(cpx<double>), ld = c->g.nkxp * sizeof(cpx<double>);
     fcns_status st = check_hip(c,
-                               hipMemcpyAsync(c->P + f * c->S, fields[f], c->S * sizeof(cpx<double>),
-                                              hipMemcpyDeviceToDevice, c->stream),
+                               hipMemcpy2DAsync(c->P + f * c->S, ld, fields[f], w, w,
+                                                (size_t)c->g.npr * c->g.ny,
+                                                hipMemcpyDeviceToDevice, c->stream),
                                "set_spectral");
     if (st != FCNS_OK) return st;
   }
   if (wall_grad) {
+    const size_t w = c->g.nkx * sizeof(cpx<double>), ld = c->g.nkxp * sizeof(cpx<double>);
     fcns_status st = check_hip(c,
-                               hipMemcpyAsync(c->GW, wall_grad, 4 * c->g.npen * sizeof(cpx<double>),
-                                              hipMemcpyDeviceToDevice, c->stream),
+                               hipMemcpy2DAsync(c->GW, ld, wall_grad, w, w, (size_t)4 * c->g.ny,
+                                                hipMemcpyDeviceToDevice, c->stream),
                                "set_spectral");
     if (st != FCNS_OK) return st;
   } else {
@@ -539,8 +611,49 @@ extern "C" fcns_status fcns_set_spectral(fcns_ctx* c, const double* const* field
 
 extern "C" fcns_status fcns_get_wall_grad(fcns_ctx* c, double* out) {
   if (!c || !out) return FCNS_EINVAL;
+  const size_t w = c->g.nkx * sizeof(cpx<double>), ld = c->g.nkxp * sizeof(cpx<double>);
   return check_hip(c,
-                   hipMemcpyAsync(out, c->GW, 4 * c->g.npen * sizeof(cpx<double>),
-                                  hipMemcpyDeviceToDevice, c->stream),
+                   hipMemcpy2DAsync(out, w, c->GW, ld, w, (size_t)4 * c->g.ny,
+                                    hipMemcpyDeviceToDevice, c->stream),
                    "get_wall_grad");
+}
+
+// ---------------------------------------------------------------- timing
+extern "C" fcns_status fcns_set_timing(fcns_ctx* c, int32_t enable) {
+  if (!c) return FCNS_EINVAL;
+  if (enable && c->evpool.empty()) {
+    c->evpool.resize(4096);
+    for (auto& e : c->evpool)
+      if (hipEventCreate(&e) != hipSuccess) return fail(c, FCNS_EDEVICE, "hipEventCreate failed");
+  }
+  if (!enable) timing_flush(c);
+  c->timing = enable != 0;
+  return FCNS_OK;
+}
+
+extern "C" fcns_status fcns_timing_reset(fcns_ctx* c) {
+  if (!c) return FCNS_EINVAL;
+  timing_flush(c);
+  for (int i = 0; i < T_NCLS; ++i) {
+    c->tms[i] = 0.0;
+    c->tcnt[i] = 0;
+  }
+  return FCNS_OK;
+}
+
+extern "C" fcns_status fcns_timing_report(fcns_ctx* c, int32_t max, int32_t* n, char* names,
+                                          int64_t* counts, double* ms) {
+  if (!c || !n) return FCNS_EINVAL;
+  timing_flush(c);
+  const int k = max < T_NCLS ? max : T_NCLS;
+  for (int i = 0; i < k; ++i) {
+    if (names) {
+      strncpy(names + 32 * i, kTimingNames[i], 31);
+      names[32 * i + 31] = 0;
+    }
+    if (counts) counts[i] = c->tcnt[i];
+    if (ms) ms[i] = c->tms[i];
+  }
+  *n = k;
+  return FCNS_OK;
 }

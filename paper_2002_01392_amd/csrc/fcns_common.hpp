@@ -62,9 +62,10 @@ __host__ __device__ __forceinline__ cpx<D> cvt(cpx<S> a) {
 struct Geom {
   int nx, ny, nz;       // physical grid; nz includes both walls
   int nkx;              // nx/2 + 1 stored kx modes
+  int nkxp;             // row stride in kx: nkx rounded up to a multiple of 4 (64 B)
   int npr;              // N' = nz + C, continued points in z
   int C, d;             // FC continuation / matching points
-  long long npen;       // pencils = nkx * ny
+  long long npen;       // pencil slots = nkxp * ny (kx >= nkx are padding)
   double lx, ly, lz;    // box
   double dz, lzp;       // dz = lz/(nz-1), Lz' = N' dz
   double kxs, kys, kzs; // 2 pi / lx, 2 pi / ly, 2 pi / Lz'

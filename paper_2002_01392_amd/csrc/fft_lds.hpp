@@ -126,6 +126,16 @@ template <typename T> struct Codelet<T, 7> : CodeletOdd<T, 7> {};
 template <typename T> struct Codelet<T, 29> : CodeletOdd<T, 29> {};
 template <typename T> struct Codelet<T, 47> : CodeletOdd<T, 47> {};
 
+// j mod ns for 0 <= j < 2^24 without an integer division: the float quotient
+// is off by at most one, which the two corrections absorb.
+__device__ __forceinline__ int fast_mod(int j, int ns, float rcp) {
+  const int q = (int)((float)j * rcp);
+  int r = j - q * ns;
+  r += (r < 0) ? ns : 0;
+  r -= (r >= ns) ? ns : 0;
+  return r;
+}
+
 // ---------------------------------------------------------------- one stage
 template <typename T, int R>
 __device__ __forceinline__ void fft_stage(const cpx<T>* __restrict__ src, cpx<T>* __restrict__ dst,
@@ -134,9 +144,10 @@ __device__ __forceinline__ void fft_stage(const cpx<T>* __restrict__ src, cpx<T>
   const int nr = n / R;
   const int nb = L * nr;
   const int tws = n / (ns * R);
+  const float rcp = 1.0f / (float)ns;
   for (int g = tid; g < nb; g += nt) {
     const int l = g % L, j = g / L;
-    const int k = j % ns;
+    const int k = fast_mod(j, ns, rcp);
     const cpx<T>* s = src + l * ls + j * es;
     cpx<T> v[R];
 #pragma unroll
@@ -160,9 +171,10 @@ __device__ __forceinline__ void fft_stage_prime(cpx<T>* __restrict__ src, cpx<T>
   const int tws = n / (ns * R);
   const int st = n / R;
   const int H = (R - 1) / 2;
+  const float rcp = 1.0f / (float)ns;
   for (int g = tid; g < nb; g += nt) {
     const int l = g % L, j = g / L;
-    const int k = j % ns;
+    const int k = fast_mod(j, ns, rcp);
     cpx<T>* s = src + l * ls + j * es;
     const int is = nr * es;
     if (ns > 1)

@@ -8,12 +8,14 @@ namespace fcns {
 // z kernels: ZPB pencils per workgroup of ZNT threads
 constexpr int ZPB = 8;
 constexpr int ZNT = 256;
+constexpr int ZLS = ZNT / ZPB;  // rows a thread steps over (its pencil is tid % ZPB)
 // y kernels: YL lines (consecutive kx) per workgroup
 constexpr int YL = 4;
 constexpr int YNT = 256;
-// x kernels: XR rows per workgroup (XR/2 complex lines)
+constexpr long long Y_GRID = 1024;  // persistent y workgroups per field
+// x kernels: XR rows per workgroup (XR/2 complex lines); nx <= XNT
 constexpr int XR = 8;
-constexpr int XNT = 256;
+constexpr int XNT = 512;
 
 struct ZArgs {
   Geom g;
@@ -49,14 +51,14 @@ struct StageBArgs {
 };
 
 struct YArgs {
-  int ny, nkx;
+  int ny, nkx, nkxp;
   double kys;
   FFTPlan pl;        // ny-point plan (lines = YL, threads = YNT)
   const void* tw;    // ny twiddles
 };
 
 struct XArgs {
-  int nx, nkx, ny;
+  int nx, nkx, nkxp, ny;
   double kxs;
   FFTPlan pl;        // nx-point plan (lines = XR/2, threads = XNT)
   const void* tw;    // nx twiddles
@@ -92,13 +94,14 @@ void launch_fc_derivative(const ZArgs& a, bool big, const double* in, double* ou
                           long long nlines, long long ps, long long ls, int order,
                           hipStream_t st);
 
-// y: lines are (plane, kx) pairs, element ky; arrays [nplanes][ny][nkx].
+// y: lines are (plane, kx) pairs, element ky; arrays [nplanes][ny][nkxp].
 // mode 0: dst = FFT (inverse scaled by 1/ny); mode 1 (inverse only): also
 // dst2 = inverse FFT of i k~y times the input.
 void launch_y(const YArgs& a, bool big, bool inv, int mode, const cpx<double>* src,
               cpx<double>* dst, cpx<double>* dst2, long long sfstride, long long dfstride,
               int nplanes, int nfields, hipStream_t st);
-// x: rows are (plane, y) pairs; physical rows of nx reals <-> nkx complex.
+// x: rows are (plane, y) pairs; physical rows of nx reals <-> nkx complex
+// (row stride nkxp).
 void launch_x_r2c(const XArgs& a, bool big, const double* phys, cpx<double>* xy,
                   long long pfstride, long long xfstride, long long nrows, int nfields,
                   hipStream_t st);

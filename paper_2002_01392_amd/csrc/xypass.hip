@@ -2,7 +2,8 @@
 // fused x-pass that evaluates the advective products in physical space.
 //
 // Layouts (x fastest): physical real fields [planes][ny][nx]; (kx, y) and
-// (kx, ky) complex fields [planes][ny][nkx], nkx = nx/2 + 1.  Inverse
+// (kx, ky) complex fields [planes][ny][nkxp] holding nkx = nx/2 + 1 modes per
+// row, the row stride nkxp padded to a multiple of 4 (64 B).  Inverse
 // transforms use IFFT(y) = conj(FFT(conj(y))) / n with the conjugations folded
 // into loads and stores.
 #include "kernels.hpp"
@@ -10,16 +11,19 @@
 namespace fcns {
 
 // ---------------------------------------------------------------- y pass
-// Lines q = plane * nkx + kx; a workgroup takes YL consecutive lines, staged
-// in LDS as X[ky * YL + l].  mode 1 (inverse only): a second pass transforms
-// i k~y times the input into dst2.
+// Lines q = plane * nkxp + kx; a tile is YL consecutive lines, staged in LDS
+// as X[ky * YL + l].  Each thread keeps one line of the tile (l = tid % YL,
+// YNT being a multiple of YL) and the rows ky = tid / YL + r * YNT / YL.
+// Workgroups loop over tiles and load the next tile into registers before
+// transforming the current one, so the loads overlap the FFT.  mode 1
+// (inverse only): a second pass transforms i k~y times the input into dst2.
 template <typename T, bool BIG, int OWN>
 __global__ __launch_bounds__(YNT) void k_y(YArgs a, const cpx<double>* src, cpx<double>* dst,
                                            cpx<double>* dst2, long long sfs, long long dfs,
                                            long long nlines, int inv, int mode) {
   extern __shared__ __align__(16) char smem[];
   const int tid = threadIdx.x;
-  const int ny = a.ny, nkx = a.nkx;
+  const int ny = a.ny, nkx = a.nkx, nkxp = a.nkxp;
   cpx<T>* tw = reinterpret_cast<cpx<T>*>(smem);
   cpx<T>* X0 = tw + ny;
   cpx<T>* X1 = X0 + ny * YL;
@@ -28,53 +32,73 @@ __global__ __launch_bounds__(YNT) void k_y(YArgs a, const cpx<double>* src, cpx<
   if (mode == 1) dst2 += blockIdx.y * dfs;
   const cpx<T>* gtw = reinterpret_cast<const cpx<T>*>(a.tw);
   for (int i = tid; i < ny; i += YNT) tw[i] = gtw[i];
-  const long long q0 = (long long)blockIdx.x * YL;
-  const int tot = ny * YL;
-  cpx<double> keep[OWN];
-#pragma unroll
-  for (int r = 0; r < OWN; ++r) {
-    const int e = tid + r * YNT;
-    keep[r] = zero<double>();
-    if (e < tot) {
-      const int ky = e / YL;
-      const long long q = q0 + e % YL;
-      if (q < nlines) {
-        const long long pl = q / nkx, kx = q - pl * nkx;
-        keep[r] = src[(pl * ny + ky) * nkx + kx];
-      }
-    }
-  }
+  const int l = tid % YL, ky0 = tid / YL;
+  constexpr int KYS = YNT / YL;
+  const long long ntiles = (nlines + YL - 1) / YL;
   const double sc = inv ? 1.0 / ny : 1.0;
   const int npass = (mode == 1) ? 2 : 1;
-  for (int pass = 0; pass < npass; ++pass) {
+  cpx<double> cur[OWN], nxt[OWN];
+  long long t = blockIdx.x;
+  auto line_base = [&](long long tt, bool& ok) {
+    const long long q = tt * YL + l;
+    const long long pl = q / nkxp, kx = q - pl * nkxp;
+    ok = q < nlines && kx < nkx;
+    return ok ? pl * ny * nkxp + kx : 0;  // element ky at base + ky * nkxp
+  };
+  {
+    bool ok;
+    const long long base = line_base(t, ok);
 #pragma unroll
     for (int r = 0; r < OWN; ++r) {
-      const int e = tid + r * YNT;
-      if (e < tot) {
-        cpx<double> v = keep[r];
-        if (pass == 1) v = mul_i(v) * k_odd(e / YL, ny, a.kys);
-        X0[e] = cvt<T>(inv ? conj(v) : v);
-      }
+      const int ky = ky0 + r * KYS;
+      cur[r] = (ok && ky < ny) ? src[base + (long long)ky * nkxp] : zero<double>();
     }
-    __syncthreads();
-    const cpx<T>* R = fft_fwd<T, YL, BIG>(X0, X1, YL, 1, a.pl, tw, tid, YNT);
-    cpx<double>* out = pass ? dst2 : dst;
-    for (int e = tid; e < tot; e += YNT) {
-      const int ky = e / YL;
-      const long long q = q0 + e % YL;
-      if (q < nlines) {
-        const long long pl = q / nkx, kx = q - pl * nkx;
-        const cpx<double> v = cvt<double>(R[e]);
-        out[(pl * ny + ky) * nkx + kx] = (inv ? conj(v) : v) * sc;
-      }
+  }
+  for (; t < ntiles; t += gridDim.x) {
+    bool ok, okn;
+    const long long base = line_base(t, ok);
+    const long long tn = t + gridDim.x;
+    const long long basen = line_base(tn, okn);
+#pragma unroll
+    for (int r = 0; r < OWN; ++r) {
+      const int ky = ky0 + r * KYS;
+      nxt[r] = (okn && ky < ny) ? src[basen + (long long)ky * nkxp] : zero<double>();
     }
-    __syncthreads();
+    for (int pass = 0; pass < npass; ++pass) {
+#pragma unroll
+      for (int r = 0; r < OWN; ++r) {
+        const int ky = ky0 + r * KYS;
+        if (ky < ny) {
+          cpx<double> v = cur[r];
+          if (pass == 1) v = mul_i(v) * k_odd(ky, ny, a.kys);
+          X0[ky * YL + l] = cvt<T>(inv ? conj(v) : v);
+        }
+      }
+      __syncthreads();
+      const cpx<T>* R = fft_fwd<T, YL, BIG>(X0, X1, YL, 1, a.pl, tw, tid, YNT);
+      cpx<double>* out = pass ? dst2 : dst;
+      if (ok) {
+#pragma unroll
+        for (int r = 0; r < OWN; ++r) {
+          const int ky = ky0 + r * KYS;
+          if (ky < ny) {
+            const cpx<double> v = cvt<double>(R[ky * YL + l]);
+            out[base + (long long)ky * nkxp] = (inv ? conj(v) : v) * sc;
+          }
+        }
+      }
+      __syncthreads();
+    }
+#pragma unroll
+    for (int r = 0; r < OWN; ++r) cur[r] = nxt[r];
   }
 }
 
 // ---------------------------------------------------------------- x helpers
 // Rows r0..r0+XR-1; two real rows (2a, 2a+1) share complex line a:
-// z[n] = x_2a[n] + i x_2a+1[n], staged in LDS as X[n * XL + a].
+// z[n] = x_2a[n] + i x_2a+1[n], staged in LDS line-contiguous as
+// X[a * ls + n] with the odd stride ls = nx + 1 (conflict-free banks for the
+// line-fastest thread mapping of the FFT).
 constexpr int XL = XR / 2;
 
 // Pack the spectra A (row 2a), B (row 2a+1) of two real rows into the
@@ -83,52 +107,48 @@ constexpr int XL = XR / 2;
 // and kx = nx/2 bins are dropped, as a c2r transform does.  dx: multiply by
 // i k~x first.
 template <typename T>
-__device__ __forceinline__ void x_pack_c2r(cpx<T>* X, const cpx<double>* __restrict__ xy,
+__device__ __forceinline__ void x_pack_c2r(cpx<T>* X, int ls, const cpx<double>* __restrict__ xy,
                                            long long r0, long long nrows, const XArgs& a,
                                            bool dx, int tid) {
-  const int nx = a.nx, nkx = a.nkx;
-  for (int e = tid; e < XL * nkx; e += XNT) {
-    const int al = e / nkx, k = e - al * nkx;
+  const int nx = a.nx, nkx = a.nkx, nkxp = a.nkxp;
+#pragma unroll
+  for (int al = 0; al < XL; ++al) {
     const long long ra = r0 + 2 * al, rb = ra + 1;
-    cpx<double> A = (ra < nrows) ? xy[ra * nkx + k] : zero<double>();
-    cpx<double> B = (rb < nrows) ? xy[rb * nkx + k] : zero<double>();
-    if (dx) {
-      const double kx = (2 * k == nx) ? 0.0 : a.kxs * k;
-      A = mul_i(A) * kx;
-      B = mul_i(B) * kx;
+    for (int k = tid; k < nkx; k += XNT) {
+      cpx<double> A = (ra < nrows) ? xy[ra * nkxp + k] : zero<double>();
+      cpx<double> B = (rb < nrows) ? xy[rb * nkxp + k] : zero<double>();
+      if (dx) {
+        const double kx = (2 * k == nx) ? 0.0 : a.kxs * k;
+        A = mul_i(A) * kx;
+        B = mul_i(B) * kx;
+      }
+      if (k == 0 || 2 * k == nx) {
+        A.y = 0.0;
+        B.y = 0.0;
+      }
+      // Z[k] = A + i B, Z[nx - k] = conj(A) + i conj(B); store conjugates
+      X[al * ls + k] = cvt<T>(conj(mk(A.x - B.y, A.y + B.x)));
+      if (k > 0 && 2 * k < nx) X[al * ls + nx - k] = cvt<T>(conj(mk(A.x + B.y, B.x - A.y)));
     }
-    if (k == 0 || 2 * k == nx) {
-      A.y = 0.0;
-      B.y = 0.0;
-    }
-    // Z[k] = A + i B, Z[nx - k] = conj(A) + i conj(B); store conjugates
-    X[k * XL + al] = cvt<T>(conj(mk(A.x - B.y, A.y + B.x)));
-    if (k > 0 && 2 * k < nx) X[(nx - k) * XL + al] = cvt<T>(conj(mk(A.x + B.y, B.x - A.y)));
   }
 }
 
 // Unpack the forward transform of two packed real rows into their r2c spectra.
 template <typename T>
-__device__ __forceinline__ void x_unpack_r2c(const cpx<T>* X, cpx<double>* __restrict__ xy,
+__device__ __forceinline__ void x_unpack_r2c(const cpx<T>* X, int ls, cpx<double>* __restrict__ xy,
                                              long long r0, long long nrows, const XArgs& a,
                                              int tid) {
-  const int nx = a.nx, nkx = a.nkx;
-  for (int e = tid; e < XL * nkx; e += XNT) {
-    const int al = e / nkx, k = e - al * nkx;
-    const cpx<double> Z = cvt<double>(X[k * XL + al]);
-    const cpx<double> Zm = conj(cvt<double>(X[((nx - k) % nx) * XL + al]));
+  const int nx = a.nx, nkx = a.nkx, nkxp = a.nkxp;
+#pragma unroll
+  for (int al = 0; al < XL; ++al) {
     const long long ra = r0 + 2 * al, rb = ra + 1;
-    if (ra < nrows) xy[ra * nkx + k] = (Z + Zm) * 0.5;
-    if (rb < nrows) xy[rb * nkx + k] = mul_mi(Z - Zm) * 0.5;
+    for (int k = tid; k < nkx; k += XNT) {
+      const cpx<double> Z = cvt<double>(X[al * ls + k]);
+      const cpx<double> Zm = conj(cvt<double>(X[al * ls + ((k == 0) ? 0 : nx - k)]));
+      if (ra < nrows) xy[ra * nkxp + k] = (Z + Zm) * 0.5;
+      if (rb < nrows) xy[rb * nkxp + k] = mul_mi(Z - Zm) * 0.5;
+    }
   }
-}
-
-// physical value of row rl, column n in an inverse-transformed packed buffer
-// (conjugated forward output): real part for even rows, imaginary for odd
-template <typename T>
-__device__ __forceinline__ double x_phys(const cpx<T>* R, int rl, int n) {
-  const cpx<T> z = R[n * XL + (rl >> 1)];
-  return (rl & 1) ? -(double)z.y : (double)z.x;
 }
 
 // ---------------------------------------------------------------- x r2c / c2r
@@ -138,24 +158,25 @@ __global__ __launch_bounds__(XNT) void k_x_r2c(XArgs a, const double* __restrict
                                                long long xfs, long long nrows) {
   extern __shared__ __align__(16) char smem[];
   const int tid = threadIdx.x;
-  const int nx = a.nx;
+  const int nx = a.nx, ls = nx + 1;
   cpx<T>* tw = reinterpret_cast<cpx<T>*>(smem);
   cpx<T>* X0 = tw + nx;
-  cpx<T>* X1 = X0 + nx * XL;
+  cpx<T>* X1 = X0 + XL * ls;
   phys += blockIdx.y * pfs;
   xy += blockIdx.y * xfs;
   const cpx<T>* gtw = reinterpret_cast<const cpx<T>*>(a.tw);
   for (int i = tid; i < nx; i += XNT) tw[i] = gtw[i];
   const long long r0 = (long long)blockIdx.x * XR;
   T* Xs = reinterpret_cast<T*>(X0);
-  for (int e = tid; e < XR * nx; e += XNT) {
-    const int rl = e / nx, n = e - rl * nx;
+#pragma unroll
+  for (int rl = 0; rl < XR; ++rl) {
     const long long r = r0 + rl;
-    Xs[2 * (n * XL + (rl >> 1)) + (rl & 1)] = (r < nrows) ? (T)phys[r * nx + n] : T(0);
+    for (int n = tid; n < nx; n += XNT)
+      Xs[2 * ((rl >> 1) * ls + n) + (rl & 1)] = (r < nrows) ? (T)phys[r * nx + n] : T(0);
   }
   __syncthreads();
-  const cpx<T>* R = fft_fwd<T, XL, BIG>(X0, X1, XL, 1, a.pl, tw, tid, XNT);
-  x_unpack_r2c<T>(R, xy, r0, nrows, a, tid);
+  const cpx<T>* R = fft_fwd<T, XL, BIG>(X0, X1, 1, ls, a.pl, tw, tid, XNT);
+  x_unpack_r2c<T>(R, ls, xy, r0, nrows, a, tid);
 }
 
 template <typename T, bool BIG>
@@ -164,23 +185,28 @@ __global__ __launch_bounds__(XNT) void k_x_c2r(XArgs a, const cpx<double>* __res
                                                long long pfs, long long nrows) {
   extern __shared__ __align__(16) char smem[];
   const int tid = threadIdx.x;
-  const int nx = a.nx;
+  const int nx = a.nx, ls = nx + 1;
   cpx<T>* tw = reinterpret_cast<cpx<T>*>(smem);
   cpx<T>* X0 = tw + nx;
-  cpx<T>* X1 = X0 + nx * XL;
+  cpx<T>* X1 = X0 + XL * ls;
   phys += blockIdx.y * pfs;
   xy += blockIdx.y * xfs;
   const cpx<T>* gtw = reinterpret_cast<const cpx<T>*>(a.tw);
   for (int i = tid; i < nx; i += XNT) tw[i] = gtw[i];
   const long long r0 = (long long)blockIdx.x * XR;
-  x_pack_c2r<T>(X0, xy, r0, nrows, a, false, tid);
+  x_pack_c2r<T>(X0, ls, xy, r0, nrows, a, false, tid);
   __syncthreads();
-  const cpx<T>* R = fft_fwd<T, XL, BIG>(X0, X1, XL, 1, a.pl, tw, tid, XNT);
+  const cpx<T>* R = fft_fwd<T, XL, BIG>(X0, X1, 1, ls, a.pl, tw, tid, XNT);
   const double sc = 1.0 / nx;
-  for (int e = tid; e < XR * nx; e += XNT) {
-    const int rl = e / nx, n = e - rl * nx;
-    const long long r = r0 + rl;
-    if (r < nrows) phys[r * nx + n] = x_phys<T>(R, rl, n) * sc;
+#pragma unroll
+  for (int al = 0; al < XL; ++al) {
+    const long long ra = r0 + 2 * al, rb = ra + 1;
+    for (int n = tid; n < nx; n += XNT) {
+      // z = conj(R) / nx: row 2a = Re z, row 2a+1 = Im z
+      const cpx<T> z = R[al * ls + n];
+      if (ra < nrows) phys[ra * nx + n] = (double)z.x * sc;
+      if (rb < nrows) phys[rb * nx + n] = -(double)z.y * sc;
+    }
   }
 }
 
@@ -189,75 +215,105 @@ __global__ __launch_bounds__(XNT) void k_x_c2r(XArgs a, const cpx<double>* __res
 // rows (Sec. 4.2: derivatives in Fourier space, products in real space, no
 // padding), then its r2c transform.  Passes: 0-2 physical u, v, w; then per
 // field f: dq/dx, dq/dy, dq/dz (inverse), and the forward transform of NL_f.
-template <typename T, bool BIG, int OWN>
+// Thread tid < nkx owns spectral column k = tid of the XR rows (nkx <= XNT)
+// and loads the next pass's inputs while the current pass is transformed;
+// thread tid < nx owns physical column n = tid.
+template <typename T, bool BIG>
 __global__ __launch_bounds__(XNT) void k_x_nl(XArgs a, const cpx<double>* __restrict__ xyb,
                                               cpx<double>* __restrict__ nl, long long fs,
                                               long long nrows, int nfields) {
   extern __shared__ __align__(16) char smem[];
   const int tid = threadIdx.x;
-  const int nx = a.nx;
+  const int nx = a.nx, nkx = a.nkx, nkxp = a.nkxp, ls = nx + 1;
   cpx<T>* tw = reinterpret_cast<cpx<T>*>(smem);
   cpx<T>* X0 = tw + nx;
-  cpx<T>* X1 = X0 + nx * XL;
+  cpx<T>* X1 = X0 + XL * ls;
   const cpx<T>* gtw = reinterpret_cast<const cpx<T>*>(a.tw);
   for (int i = tid; i < nx; i += XNT) tw[i] = gtw[i];
   const long long r0 = (long long)blockIdx.x * XR;
-  const int tot = XR * nx;
+  const bool own = tid < nx, ownk = tid < nkx;
+  const int n = tid, k = tid;
   const double sc = 1.0 / nx;
-  double U[3][OWN];
-  double acc[OWN];
-  const int npass = 3 + 4 * nfields;
-  for (int pass = 0; pass < npass; ++pass) {
-    // which transform: comp c (pass < 3), else field f and sub-pass k
-    const int f = (pass - 3) >> 2, k = (pass - 3) & 3;
-    const bool fwd = pass >= 3 && k == 3;
-    if (!fwd) {
-      const cpx<double>* src;
-      bool dx = false;
-      if (pass < 3) {
-        src = xyb + (3 * pass) * fs;
-      } else if (k == 0) {
-        src = xyb + (3 * f) * fs;
-        dx = true;
-      } else {
-        src = xyb + (3 * f + k) * fs;
-      }
-      x_pack_c2r<T>(X0, src, r0, nrows, a, dx, tid);
-    } else {
-      T* Xw = reinterpret_cast<T*>(X0);
+  const double kx = (2 * k == nx) ? 0.0 : a.kxs * k;
+  double U[3][XR];
+  double acc[XR];
+  cpx<double> in[XR];
+  // source slot of c2r pass p (-1: forward pass)
+  auto slot = [&](int p) {
+    if (p < 3) return 3 * p;
+    const int f = (p - 3) >> 2, kk = (p - 3) & 3;
+    return kk == 3 ? -1 : 3 * f + (kk == 0 ? 0 : kk);
+  };
+  auto load = [&](int p) {
+    const int sl = slot(p);
+    if (sl < 0 || !ownk) return;
+    const cpx<double>* src = xyb + sl * fs;
 #pragma unroll
-      for (int r = 0; r < OWN; ++r) {
-        const int e = tid + r * XNT;
-        if (e < tot) {
-          const int rl = e / nx, n = e - rl * nx;
-          Xw[2 * (n * XL + (rl >> 1)) + (rl & 1)] = (T)acc[r];
+    for (int r = 0; r < XR; ++r)
+      in[r] = (r0 + r < nrows) ? src[(r0 + r) * nkxp + k] : zero<double>();
+  };
+  const int npass = 3 + 4 * nfields;
+  load(0);
+  for (int pass = 0; pass < npass; ++pass) {
+    const int f = (pass - 3) >> 2, kk = (pass - 3) & 3;
+    const bool fwd = pass >= 3 && kk == 3;
+    if (!fwd) {
+      if (ownk) {
+        const bool dx = pass >= 3 && kk == 0;
+#pragma unroll
+        for (int al = 0; al < XL; ++al) {
+          cpx<double> A = in[2 * al], B = in[2 * al + 1];
+          if (dx) {
+            A = mul_i(A) * kx;
+            B = mul_i(B) * kx;
+          }
+          if (k == 0 || 2 * k == nx) {
+            A.y = 0.0;
+            B.y = 0.0;
+          }
+          // Z[k] = A + i B, Z[nx - k] = conj(A) + i conj(B); stored conjugated
+          X0[al * ls + k] = cvt<T>(conj(mk(A.x - B.y, A.y + B.x)));
+          if (k > 0 && 2 * k < nx) X0[al * ls + nx - k] = cvt<T>(conj(mk(A.x + B.y, B.x - A.y)));
         }
       }
+    } else if (own) {
+#pragma unroll
+      for (int al = 0; al < XL; ++al)
+        X0[al * ls + n] = mk((T)acc[2 * al], (T)acc[2 * al + 1]);
     }
+    // next pass's spectral inputs, in flight during this pass's transform
+    int pn = pass + 1;
+    if (pn < npass && slot(pn) < 0) ++pn;
+    if (pn < npass) load(pn);
     __syncthreads();
-    const cpx<T>* R = fft_fwd<T, XL, BIG>(X0, X1, XL, 1, a.pl, tw, tid, XNT);
-    if (pass < 3) {
+    const cpx<T>* R = fft_fwd<T, XL, BIG>(X0, X1, 1, ls, a.pl, tw, tid, XNT);
+    if (!fwd) {
+      if (own) {
+        double v[XR];
 #pragma unroll
-      for (int r = 0; r < OWN; ++r) {
-        const int e = tid + r * XNT;
-        const int rl = e / nx, n = e - rl * nx;
-        const double v = (e < tot) ? x_phys<T>(R, rl, n) * sc : 0.0;
-        if (pass == 0) U[0][r] = v;
-        else if (pass == 1) U[1][r] = v;
-        else U[2][r] = v;
-      }
-    } else if (!fwd) {
+        for (int al = 0; al < XL; ++al) {
+          const cpx<T> z = R[al * ls + n];
+          v[2 * al] = (double)z.x * sc;
+          v[2 * al + 1] = -(double)z.y * sc;
+        }
+        if (pass < 3) {
 #pragma unroll
-      for (int r = 0; r < OWN; ++r) {
-        const int e = tid + r * XNT;
-        const int rl = e / nx, n = e - rl * nx;
-        const double d = (e < tot) ? x_phys<T>(R, rl, n) * sc : 0.0;
-        const double u = (k == 0) ? U[0][r] : ((k == 1) ? U[1][r] : U[2][r]);
-        if (k == 0) acc[r] = -u * d;
-        else acc[r] -= u * d;
+          for (int r = 0; r < XR; ++r) {
+            if (pass == 0) U[0][r] = v[r];
+            else if (pass == 1) U[1][r] = v[r];
+            else U[2][r] = v[r];
+          }
+        } else {
+#pragma unroll
+          for (int r = 0; r < XR; ++r) {
+            const double u = (kk == 0) ? U[0][r] : ((kk == 1) ? U[1][r] : U[2][r]);
+            if (kk == 0) acc[r] = -u * v[r];
+            else acc[r] -= u * v[r];
+          }
+        }
       }
     } else {
-      x_unpack_r2c<T>(R, nl + f * fs, r0, nrows, a, tid);
+      x_unpack_r2c<T>(R, ls, nl + f * fs, r0, nrows, a, tid);
     }
     __syncthreads();
   }
@@ -291,10 +347,11 @@ __global__ void k_sub_mean00(cpx<double>* pmix, long long npen, int nz) {
 void launch_y(const YArgs& a, bool big, bool inv, int mode, const cpx<double>* src,
               cpx<double>* dst, cpx<double>* dst2, long long sfs, long long dfs, int nplanes,
               int nfields, hipStream_t st) {
-  const long long nlines = (long long)nplanes * a.nkx;
-  dim3 grid((unsigned)((nlines + YL - 1) / YL), nfields);
+  const long long nlines = (long long)nplanes * a.nkxp;
+  const long long ntiles = (nlines + YL - 1) / YL;
+  dim3 grid((unsigned)(ntiles < Y_GRID ? ntiles : Y_GRID), nfields);
   const size_t sh = (size_t)a.ny * (2 * YL + 1) * sizeof(cpx<double>);
-  const int need = (a.ny * YL + YNT - 1) / YNT;
+  const int need = (a.ny + YNT / YL - 1) / (YNT / YL);
   const int iv = inv ? 1 : 0;
 #define FCNS_Y(BIGV, OWNV)                                                                    \
   FCNS_LAUNCH((k_y<double, BIGV, OWNV>), grid, dim3(YNT), sh, st, a, src, dst, dst2, sfs, \
@@ -310,7 +367,7 @@ void launch_y(const YArgs& a, bool big, bool inv, int mode, const cpx<double>* s
 void launch_x_r2c(const XArgs& a, bool big, const double* phys, cpx<double>* xy, long long pfs,
                   long long xfs, long long nrows, int nfields, hipStream_t st) {
   dim3 grid((unsigned)((nrows + XR - 1) / XR), nfields);
-  const size_t sh = (size_t)a.nx * (2 * XL + 1) * sizeof(cpx<double>);
+  const size_t sh = ((size_t)a.nx + 2 * XL * (a.nx + 1)) * sizeof(cpx<double>);
   if (big)
     FCNS_LAUNCH((k_x_r2c<double, true>), grid, dim3(XNT), sh, st, a, phys, xy, pfs, xfs, nrows);
   else
@@ -320,7 +377,7 @@ void launch_x_r2c(const XArgs& a, bool big, const double* phys, cpx<double>* xy,
 void launch_x_c2r(const XArgs& a, bool big, const cpx<double>* xy, double* phys, long long xfs,
                   long long pfs, long long nrows, int nfields, hipStream_t st) {
   dim3 grid((unsigned)((nrows + XR - 1) / XR), nfields);
-  const size_t sh = (size_t)a.nx * (2 * XL + 1) * sizeof(cpx<double>);
+  const size_t sh = ((size_t)a.nx + 2 * XL * (a.nx + 1)) * sizeof(cpx<double>);
   if (big)
     FCNS_LAUNCH((k_x_c2r<double, true>), grid, dim3(XNT), sh, st, a, xy, phys, xfs, pfs, nrows);
   else
@@ -330,17 +387,11 @@ void launch_x_c2r(const XArgs& a, bool big, const cpx<double>* xy, double* phys,
 void launch_x_nl(const XArgs& a, bool big, const cpx<double>* xyb, cpx<double>* nl,
                  long long fs, long long nrows, int nfields, hipStream_t st) {
   dim3 grid((unsigned)((nrows + XR - 1) / XR));
-  const size_t sh = (size_t)a.nx * (2 * XL + 1) * sizeof(cpx<double>);
-  const int need = (XR * a.nx + XNT - 1) / XNT;
-#define FCNS_X(BIGV, OWNV)                                                                    \
-  FCNS_LAUNCH((k_x_nl<double, BIGV, OWNV>), grid, dim3(XNT), sh, st, a, xyb, nl, fs, nrows, \
-                     nfields)
-  if (big) {
-    if (need <= 4) FCNS_X(true, 4); else if (need <= 8) FCNS_X(true, 8); else FCNS_X(true, 16);
-  } else {
-    if (need <= 4) FCNS_X(false, 4); else if (need <= 8) FCNS_X(false, 8); else FCNS_X(false, 16);
-  }
-#undef FCNS_X
+  const size_t sh = ((size_t)a.nx + 2 * XL * (a.nx + 1)) * sizeof(cpx<double>);
+  if (big)
+    FCNS_LAUNCH((k_x_nl<double, true>), grid, dim3(XNT), sh, st, a, xyb, nl, fs, nrows, nfields);
+  else
+    FCNS_LAUNCH((k_x_nl<double, false>), grid, dim3(XNT), sh, st, a, xyb, nl, fs, nrows, nfields);
 }
 
 void launch_fill(cpx<double>* p, long long n, hipStream_t st) {

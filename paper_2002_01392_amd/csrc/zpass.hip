@@ -2,9 +2,11 @@
 // lines, the RK stage combine with the splitting boundary conditions, and the
 // pressure projection with its closed-form homogeneous part.
 //
-// Data layout (complex, x fastest): mixed (kx, ky, z) fields are [nz][ny][nkx],
-// continued spectral (kx, ky, kz) fields are [N'][ny][nkx].  A pencil is one
-// (kx, ky) pair, p = ky * nkx + kx.  A workgroup owns ZPB consecutive pencils
+// Data layout (complex, x fastest): mixed (kx, ky, z) fields are
+// [nz][ny][nkxp], continued spectral (kx, ky, kz) fields are [N'][ny][nkxp],
+// with the kx row padded to nkxp (a multiple of 4, so that 4-line tiles of
+// the y pass are 64-byte aligned).  A pencil is one (kx, ky) pair,
+// p = ky * nkxp + kx; slots with kx >= nkx are padding and never touched.  A workgroup owns ZPB consecutive pencils
 // and stages their lines in LDS as X[l * ZPB + pb] (pencil index fastest), so
 // every global row access is ZPB consecutive complex values.
 //
@@ -76,12 +78,17 @@ __device__ __forceinline__ void z_extend(cpx<T>* X, const double* __restrict__ M
 
 __device__ __forceinline__ void pencil_k(const Geom& g, long long p, double& kx_o, double& ky_o,
                                          double& kx_t, double& ky_t, int& ix, int& iy) {
-  iy = (int)(p / g.nkx);
-  ix = (int)(p - (long long)iy * g.nkx);
+  iy = (int)(p / g.nkxp);
+  ix = (int)(p - (long long)iy * g.nkxp);
   kx_t = g.kxs * ix;
   kx_o = (2 * ix == g.nx) ? 0.0 : kx_t;
   ky_t = k_true(iy, g.ny, g.kys);
   ky_o = k_odd(iy, g.ny, g.kys);
+}
+
+// A pencil slot holds data when it is inside the array and not kx padding.
+__device__ __forceinline__ bool pencil_valid(const Geom& g, long long p) {
+  return p < g.npen && (int)(p % g.nkxp) < g.nkx;
 }
 
 // ---------------------------------------------------------------- z forward
@@ -98,23 +105,24 @@ __global__ __launch_bounds__(ZNT) void k_z_fwd(ZArgs a, const cpx<double>* __res
   dst += blockIdx.y * dfs;
   const long long p0 = (long long)blockIdx.x * ZPB;
   z_setup<T>(L, a, tid);
-  for (int e = tid; e < g.nz * ZPB; e += ZNT) {
-    const long long p = p0 + e % ZPB;
-    L.X0[e] = (p < g.npen) ? cvt<T>(src[(long long)(e / ZPB) * g.npen + p]) : zero<T>();
-  }
+  const int pb = tid % ZPB, lt = tid / ZPB;
+  const long long p = p0 + pb;
+  const bool pv = pencil_valid(g, p);
+  for (int z = lt; z < g.nz; z += ZLS)
+    L.X0[z * ZPB + pb] = pv ? cvt<T>(src[(long long)z * g.npen + p]) : zero<T>();
   __syncthreads();
   z_extend<T>(L.X0, L.M, g.nz, g.C, g.d, tid);
   __syncthreads();
   const cpx<T>* R = fft_fwd<T, ZPB, BIG>(L.X0, L.X1, ZPB, 1, a.pl, L.tw, tid, ZNT);
-  for (int e = tid; e < g.npr * ZPB; e += ZNT) {
-    const int l = e / ZPB;
-    const long long p = p0 + e % ZPB;
-    if (p >= g.npen) continue;
-    cpx<double> v = cvt<double>(R[e]);
-    if (filter) {
-      const int iy = (int)(p / g.nkx), ix = (int)(p - (long long)iy * g.nkx);
-      v = v * (a.sigz[l] * a.sigy[iy] * a.sigx[ix]);
-    }
+  if (!pv) return;
+  double sxy = 1.0;
+  if (filter) {
+    const int iy = (int)(p / g.nkxp), ix = (int)(p - (long long)iy * g.nkxp);
+    sxy = a.sigy[iy] * a.sigx[ix];
+  }
+  for (int l = lt; l < g.npr; l += ZLS) {
+    cpx<double> v = cvt<double>(R[l * ZPB + pb]);
+    if (filter) v = v * (a.sigz[l] * sxy);
     dst[(long long)l * g.npen + p] = v;
   }
 }
@@ -136,15 +144,14 @@ __global__ __launch_bounds__(ZNT) void k_z_back(ZArgs a, const cpx<double>* __re
   const long long p0 = (long long)blockIdx.x * ZPB;
   z_setup<T>(L, a, tid);
   const int tot = g.npr * ZPB;
+  const int pb = tid % ZPB, lt = tid / ZPB;
+  const long long p = p0 + pb;
+  const bool pv = pencil_valid(g, p);
   cpx<double> keep[OWN];
 #pragma unroll
   for (int r = 0; r < OWN; ++r) {
-    const int e = tid + r * ZNT;
-    keep[r] = zero<double>();
-    if (e < tot) {
-      const long long p = p0 + e % ZPB;
-      if (p < g.npen) keep[r] = src[(long long)(e / ZPB) * g.npen + p];
-    }
+    const int l = lt + r * ZLS;
+    keep[r] = (pv && l < g.npr) ? src[(long long)l * g.npen + p] : zero<double>();
   }
   const double inv = 1.0 / g.npr;
   const int npass = dzdst ? 2 : 1;
@@ -154,17 +161,16 @@ __global__ __launch_bounds__(ZNT) void k_z_back(ZArgs a, const cpx<double>* __re
       const int e = tid + r * ZNT;
       if (e < tot) {
         cpx<double> v = keep[r];
-        if (pass == 1) v = mul_i(v) * k_odd(e / ZPB, g.npr, g.kzs);
+        if (pass == 1) v = mul_i(v) * k_odd(lt + r * ZLS, g.npr, g.kzs);
         L.X0[e] = cvt<T>(conj(v));
       }
     }
     __syncthreads();
     const cpx<T>* R = fft_fwd<T, ZPB, BIG>(L.X0, L.X1, ZPB, 1, a.pl, L.tw, tid, ZNT);
     cpx<double>* __restrict__ out = pass ? dzdst : dst;
-    for (int e = tid; e < g.nz * ZPB; e += ZNT) {
-      const long long p = p0 + e % ZPB;
-      if (p < g.npen) out[(long long)(e / ZPB) * g.npen + p] = conj(cvt<double>(R[e])) * inv;
-    }
+    if (pv)
+      for (int z = lt; z < g.nz; z += ZLS)
+        out[(long long)z * g.npen + p] = conj(cvt<double>(R[z * ZPB + pb])) * inv;
     __syncthreads();
   }
 }
@@ -175,7 +181,7 @@ __global__ __launch_bounds__(ZNT) void k_z_back(ZArgs a, const cpx<double>* __re
 //   N = sigma F_z(NL);  S = V^t + c (N - diff |k|^2 W);  v* = B_z S, plus the
 //   body force / buoyancy at the physical points, then the wall injection
 //   v*_par = c grad_par p_prev (theta = 0) and V* = F_z v*.
-template <typename T, bool BIG>
+template <typename T, bool BIG, int OWN>
 __global__ __launch_bounds__(ZNT) void k_z_stageA(ZArgs a, StageAArgs s) {
   extern __shared__ __align__(16) char smem[];
   const int tid = threadIdx.x;
@@ -191,43 +197,57 @@ __global__ __launch_bounds__(ZNT) void k_z_stageA(ZArgs a, StageAArgs s) {
   const double c = s.c;
   const double diff = (f == 3) ? s.kappa : s.nu;
   const double inv = 1.0 / g.npr;
+  const int pb = tid % ZPB, lt = tid / ZPB;
+  const long long p = p0 + pb;
+  const bool pv = pencil_valid(g, p);
+  double kxo, kyo, kxt, kyt;
+  int ix, iy;
+  pencil_k(g, pv ? p : 0, kxo, kyo, kxt, kyt, ix, iy);
+  const double kh2 = kxt * kxt + kyt * kyt;
+  const double sxy = a.sigy[iy] * a.sigx[ix];
   cpx<T>* R = L.X0;
+  for (int z = lt; z < g.nz; z += ZLS)
+    L.X0[z * ZPB + pb] = pv ? cvt<T>(nl[(long long)z * g.npen + p]) : zero<T>();
+  // the continued state of this pencil, in flight during the first transform
+  cpx<double> vtr[OWN], wr[OWN];
+#pragma unroll
+  for (int r = 0; r < OWN; ++r) {
+    const int l = lt + r * ZLS;
+    const long long gi = (long long)l * g.npen + p;
+    const bool ok = pv && l < g.npr;
+    vtr[r] = ok ? vt[gi] : zero<double>();
+    wr[r] = ok ? w[gi] : zero<double>();
+  }
   for (int pass = 0; pass < 3; ++pass) {
     if (pass == 0) {
-      // nonlinear term at the physical points, continued
-      for (int e = tid; e < g.nz * ZPB; e += ZNT) {
-        const long long p = p0 + e % ZPB;
-        L.X0[e] = (p < g.npen) ? cvt<T>(nl[(long long)(e / ZPB) * g.npen + p]) : zero<T>();
-      }
+      // nonlinear term at the physical points (loaded above), continued
       __syncthreads();
       z_extend<T>(L.X0, L.M, g.nz, g.C, g.d, tid);
       __syncthreads();
     } else if (pass == 1) {
       // S = V^t + c (sigma N - diff |k|^2 W), conjugated for the inverse
-      for (int e = tid; e < g.npr * ZPB; e += ZNT) {
-        const int l = e / ZPB;
-        const long long p = p0 + e % ZPB;
-        cpx<double> S = zero<double>();
-        if (p < g.npen) {
-          double kxo, kyo, kxt, kyt;
-          int ix, iy;
-          pencil_k(g, p, kxo, kyo, kxt, kyt, ix, iy);
-          const double kzt = k_true(l, g.npr, g.kzs);
-          const double k2 = kxt * kxt + kyt * kyt + kzt * kzt;
-          const double sig = a.sigz[l] * a.sigy[iy] * a.sigx[ix];
-          const long long gi = (long long)l * g.npen + p;
-          S = vt[gi] + (cvt<double>(R[e]) * sig - w[gi] * (diff * k2)) * c;
+#pragma unroll
+      for (int r = 0; r < OWN; ++r) {
+        const int l = lt + r * ZLS;
+        if (l < g.npr) {
+          const int e = l * ZPB + pb;
+          cpx<double> S = zero<double>();
+          if (pv) {
+            const double kzt = k_true(l, g.npr, g.kzs);
+            const double k2 = kh2 + kzt * kzt;
+            const double sig = a.sigz[l] * sxy;
+            S = vtr[r] + (cvt<double>(R[e]) * sig - wr[r] * (diff * k2)) * c;
+          }
+          L.X0[e] = cvt<T>(conj(S));
         }
-        L.X0[e] = cvt<T>(conj(S));
       }
       __syncthreads();
     } else {
       // v* at the physical points: forcing, buoyancy, wall injection
-      for (int e = tid; e < g.nz * ZPB; e += ZNT) {
-        const int z = e / ZPB;
-        const long long p = p0 + e % ZPB;
+      for (int z = lt; z < g.nz; z += ZLS) {
+        const int e = z * ZPB + pb;
         cpx<double> v = zero<double>();
-        if (p < g.npen) {
+        if (pv) {
           v = conj(cvt<double>(R[e])) * inv;
           if (f == 0 && p == 0) v.x += c * s.forcing_sum;
           if (buoy) v = v + buoy[(long long)z * g.npen + p] * (c * s.gamma);
@@ -246,10 +266,8 @@ __global__ __launch_bounds__(ZNT) void k_z_stageA(ZArgs a, StageAArgs s) {
     R = fft_fwd<T, ZPB, BIG>(L.X0, L.X1, ZPB, 1, a.pl, L.tw, tid, ZNT);
   }
   cpx<double>* __restrict__ out = s.out[f];
-  for (int e = tid; e < g.npr * ZPB; e += ZNT) {
-    const long long p = p0 + e % ZPB;
-    if (p < g.npen) out[(long long)(e / ZPB) * g.npen + p] = cvt<double>(R[e]);
-  }
+  if (pv)
+    for (int l = lt; l < g.npr; l += ZLS) out[(long long)l * g.npen + p] = cvt<double>(R[l * ZPB + pb]);
 }
 
 // ---------------------------------------------------------------- stage B
@@ -274,7 +292,7 @@ __global__ __launch_bounds__(ZNT) void k_z_stageB(ZArgs a, StageBArgs s) {
   const long long p0 = (long long)blockIdx.x * ZPB;
   const int pb_me = tid % ZPB;
   const long long p_me = p0 + pb_me;
-  const bool valid_me = p_me < g.npen;
+  const bool valid_me = pencil_valid(g, p_me);
   z_setup<T>(L, a, tid);
   const cpx<double>* __restrict__ gtw = a.tw64;
   const int tot = g.npr * ZPB;
@@ -290,13 +308,14 @@ __global__ __launch_bounds__(ZNT) void k_z_stageB(ZArgs a, StageBArgs s) {
   cpx<double> V[3][OWN];
   cpx<double> sb = zero<double>(), st = zero<double>(), s0 = zero<double>(),
               s1 = zero<double>();
+  const int lt = tid / ZPB;
 #pragma unroll
   for (int r = 0; r < OWN; ++r) {
     const int e = tid + r * ZNT;
 #pragma unroll
     for (int i = 0; i < 3; ++i) V[i][r] = zero<double>();
     if (e < tot && valid_me) {
-      const int l = e / ZPB;
+      const int l = lt + r * ZLS;
       const long long gi = (long long)l * g.npen + p_me;
 #pragma unroll
       for (int i = 0; i < 3; ++i) V[i][r] = s.vs[i][gi];
@@ -332,7 +351,8 @@ __global__ __launch_bounds__(ZNT) void k_z_stageB(ZArgs a, StageBArgs s) {
     const long long p = p0 + pb;
     double qkxo, qkyo, qkxt, qkyt;
     int qix, qiy;
-    pencil_k(g, p < g.npen ? p : 0, qkxo, qkyo, qkxt, qkyt, qix, qiy);
+    const bool qv = pencil_valid(g, p);
+    pencil_k(g, qv ? p : 0, qkxo, qkyo, qkxt, qkyt, qix, qiy);
     const cpx<double> b = coef[pb * 5 + 0], t = coef[pb * 5 + 1];
     const cpx<double> sw0 = coef[pb * 5 + 2], sw1 = coef[pb * 5 + 3];
     const double gam = sqrt(qkxo * qkxo + qkyo * qkyo);
@@ -347,7 +367,7 @@ __global__ __launch_bounds__(ZNT) void k_z_stageB(ZArgs a, StageBArgs s) {
       D = (b + t) * 0.5;
     }
     gam_s[pb] = gam;
-    if (p < g.npen && s.gwall) {
+    if (qv && s.gwall) {
       // H_par at the walls: i k~ (A e+ + B e-) with e+(0) = E, e-(0) = 1,
       // e+(Lz) = 1, e-(Lz) = E
       const cpx<double> h0 = mul_i(A * E + B), h1 = mul_i(A + B * E);
@@ -371,11 +391,10 @@ __global__ __launch_bounds__(ZNT) void k_z_stageB(ZArgs a, StageBArgs s) {
     if (pass == 1 && !pm) continue;
     cpx<T>* in = L.X0;
     if (pass == 0) {
-      for (int e = tid; e < g.nz * ZPB; e += ZNT) {
-        const int z = e / ZPB;
-        const double gm = gam_s[e % ZPB];
+      for (int z = lt; z < g.nz; z += ZLS) {
         const double zz = z * g.dz;
-        L.X0[e] = (gm > 0.0) ? mk((T)exp(gm * (zz - g.lz)), (T)exp(-gm * zz)) : mk((T)1, (T)0);
+        L.X0[z * ZPB + pb_me] =
+            (gam > 0.0) ? mk((T)exp(gam * (zz - g.lz)), (T)exp(-gam * zz)) : mk((T)1, (T)0);
       }
       __syncthreads();
       z_extend<T>(L.X0, L.M, g.nz, g.C, g.d, tid);
@@ -389,7 +408,7 @@ __global__ __launch_bounds__(ZNT) void k_z_stageB(ZArgs a, StageBArgs s) {
         const int e = tid + r * ZNT;
         if (e < tot) {
           cpx<double> v = (i == 0) ? V[0][r] : ((i == 1) ? V[1][r] : V[2][r]);
-          if (dz) v = mul_i(v) * k_odd(e / ZPB, g.npr, g.kzs);
+          if (dz) v = mul_i(v) * k_odd(lt + r * ZLS, g.npr, g.kzs);
           L.X0[e] = cvt<T>(conj(v));
         }
       }
@@ -404,7 +423,7 @@ __global__ __launch_bounds__(ZNT) void k_z_stageB(ZArgs a, StageBArgs s) {
       for (int r = 0; r < OWN; ++r) {
         const int e = tid + r * ZNT;
         if (e < tot && valid_me) {
-          const int l = e / ZPB;
+          const int l = lt + r * ZLS;
           const int lm = (l == 0) ? 0 : g.npr - l;
           const cpx<double> xl = cvt<double>(R[e]), xm = conj(cvt<double>(R[lm * ZPB + pb_me]));
           const cpx<double> ep = (xl + xm) * 0.5;
@@ -435,26 +454,23 @@ __global__ __launch_bounds__(ZNT) void k_z_stageB(ZArgs a, StageBArgs s) {
       }
     } else if (pass == 1) {
       // pressure in mixed space: (B_z(-i s) + phi^H) / c
-      for (int e = tid; e < g.nz * ZPB; e += ZNT) {
-        const int z = e / ZPB, pb = e % ZPB;
-        const long long p = p0 + pb;
-        if (p >= g.npen) continue;
-        const double zz = z * g.dz;
-        const double gm = gam_s[pb];
-        cpx<double> ph;
-        if (gm > 0.0)
-          ph = coef[pb * 5 + 0] * exp(gm * (zz - g.lz)) + coef[pb * 5 + 1] * exp(-gm * zz);
-        else
-          ph = coef[pb * 5 + 2] * zz;
-        s.pmix[(long long)z * g.npen + p] = (conj(cvt<double>(R[e])) * inv + ph) * (1.0 / s.c);
-      }
+      if (valid_me)
+        for (int z = lt; z < g.nz; z += ZLS) {
+          const double zz = z * g.dz;
+          cpx<double> ph;
+          if (gam > 0.0)
+            ph = A * exp(gam * (zz - g.lz)) + B * exp(-gam * zz);
+          else
+            ph = D * zz;
+          s.pmix[(long long)z * g.npen + p_me] =
+              (conj(cvt<double>(R[z * ZPB + pb_me])) * inv + ph) * (1.0 / s.c);
+        }
     } else {
       const int i = (pass - 2) >> 1, dz = (pass - 2) & 1;
       cpx<double>* __restrict__ dst = dz ? s.mdz[i] : s.mv[i];
-      for (int e = tid; e < g.nz * ZPB; e += ZNT) {
-        const long long p = p0 + e % ZPB;
-        if (p < g.npen) dst[(long long)(e / ZPB) * g.npen + p] = conj(cvt<double>(R[e])) * inv;
-      }
+      if (valid_me)
+        for (int z = lt; z < g.nz; z += ZLS)
+          dst[(long long)z * g.npen + p_me] = conj(cvt<double>(R[z * ZPB + pb_me])) * inv;
     }
     __syncthreads();
   }
@@ -577,10 +593,12 @@ void launch_z_back(const ZArgs& a, bool big, const cpx<double>* src, cpx<double>
 void launch_z_stageA(const ZArgs& a, bool big, const StageAArgs& s, int nfields, hipStream_t st) {
   dim3 grid((unsigned)((a.g.npen + ZPB - 1) / ZPB), nfields);
   const size_t sh = zshared_bytes<double>(a.g);
-  if (big)
-    FCNS_LAUNCH((k_z_stageA<double, true>), grid, dim3(ZNT), sh, st, a, s);
-  else
-    FCNS_LAUNCH((k_z_stageA<double, false>), grid, dim3(ZNT), sh, st, a, s);
+  const int own = pick_own(a.g.npr);
+  if (big) {
+    FCNS_OWN_SWITCH(own, FCNS_LAUNCH((k_z_stageA<double, true, OWN>), grid, dim3(ZNT), sh, st, a, s))
+  } else {
+    FCNS_OWN_SWITCH(own, FCNS_LAUNCH((k_z_stageA<double, false, OWN>), grid, dim3(ZNT), sh, st, a, s))
+  }
 }
 
 void launch_z_stageB(const ZArgs& a, bool big, const StageBArgs& s, hipStream_t st) {
