@@ -64,9 +64,9 @@ def algorithmic_bytes(w, cls, stage, keep_pressure=False):
         reads_state = F * S if stage == 1 else 2 * F * S   # V^t (= W at stage 1), W
         return F * M + reads_state + F * S + (2 * M if rb else 0)
     if cls == "z_stageB":
-        return 6 * S + 6 * M + (M if keep_pressure else 0)
-    if cls == "z_back_theta":
-        return S + 2 * M
+        return 6 * S + (M if keep_pressure else 0)   # read V*, write V
+    if cls == "z_back":
+        return F * S + 2 * F * M                     # read V, write v and dv/dz
     raise KeyError(cls)
 
 
@@ -125,6 +125,8 @@ def main():
     ap.add_argument("--workload", default="rb_512x512x257")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--timing", type=int, default=1, help="event-time kernels in the timed region")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run one plain device copy of 1 GiB (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported",
@@ -168,6 +170,13 @@ def main():
     v, th, _ = s.get_state()
     finite = bool(torch.isfinite(v).all().item()) and (th is None or bool(torch.isfinite(th).all().item()))
     torch.cuda.synchronize()
+
+    if args.copy_calibration:
+        a = torch.ones(1 << 27, dtype=torch.float64, device="cuda")
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
 
     pts = w.nx * w.ny * w.nz
     substeps = 2 * args.steps

@@ -136,7 +136,7 @@ fcns_status fcns_get_wall_grad(fcns_ctx* ctx, double* out);
 /* Kernel timing for tracing and roofline reports.  While enabled, every
  * kernel that rk_step launches is bracketed by HIP events recorded on the
  * context stream (small extra launch latency).  Classes: y_back_dy,
- * y_back_dz, x_nl, y_fwd, z_stageA, z_stageB, z_back_theta. */
+ * y_back_dz, x_nl, y_fwd, z_stageA, z_stageB, z_back. */
 fcns_status fcns_set_timing(fcns_ctx* ctx, int32_t enable);
 fcns_status fcns_timing_reset(fcns_ctx* ctx);
 /* Synchronizes the stream, then fills up to max classes: names (HOST,

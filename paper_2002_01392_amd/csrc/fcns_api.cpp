@@ -2,6 +2,7 @@
 // the sequence of kernel launches for each entry point.
 #include <math.h>
 #include <stdio.h>
+#include <stdlib.h>
 #include <string.h>
 
 #include <string>
@@ -20,9 +21,10 @@ struct fcns_ctx {
   bool big_z = false, big_x = false, big_y = false;
   FFTPlan plz{}, plx{}, ply{};
   // device tables
-  cpx<double>* twz = nullptr;
+  cpx<double>* twz = nullptr;   // plan twiddle tables
   cpx<double>* twx = nullptr;
   cpx<double>* twy = nullptr;
+  cpx<double>* rootz = nullptr; // N' roots of unity (wall sums)
   double* fcM = nullptr;
   double* sigx = nullptr;
   double* sigy = nullptr;
@@ -58,9 +60,9 @@ struct fcns_ctx {
 };
 
 // Kernel classes timed by fcns_set_timing.
-enum { T_YBACK_DY = 0, T_YBACK_DZ, T_XNL, T_YFWD, T_ZSTAGEA, T_ZSTAGEB, T_ZBACK_TH, T_NCLS };
+enum { T_YBACK_DY = 0, T_YBACK_DZ, T_XNL, T_YFWD, T_ZSTAGEA, T_ZSTAGEB, T_ZBACK, T_NCLS };
 static const char* kTimingNames[T_NCLS] = {"y_back_dy", "y_back_dz", "x_nl", "y_fwd",
-                                           "z_stageA", "z_stageB", "z_back_theta"};
+                                           "z_stageA", "z_stageB", "z_back"};
 
 static void timing_flush(fcns_ctx* c) {
   if (c->recs.empty()) return;
@@ -112,7 +114,10 @@ static fcns_status check_launch(fcns_ctx* c, const char* what) {
 
 // ---------------------------------------------------------------- plans
 // Radices 8 first, then 4, 2 and odd primes ascending (at most 12 stages).
-static bool make_plan(int n, FFTPlan& pl, bool& big) {
+// Also lays out the twiddle table: per stage with ns > 1 the factors
+// w^{m k} = exp(-2 pi i m k / (ns R)) as [m-1][k], and per odd-radix stage its
+// R roots exp(-2 pi i q / R).
+static bool make_plan(int n, FFTPlan& pl, bool& big, std::vector<cpx<double>>& table) {
   memset(&pl, 0, sizeof(pl));
   pl.n = n;
   big = false;
@@ -128,14 +133,36 @@ static bool make_plan(int n, FFTPlan& pl, bool& big) {
     }
   if (m != 1 || (int)rs.size() > FFT_MAX_STAGES) return false;
   pl.nst = (int)rs.size();
+  const long double pi = 3.141592653589793238462643383279502884L;
+  auto root = [&](long long num, long long den) {
+    const long double a = -2.0L * pi * (long double)num / (long double)den;
+    return mk((double)cosl(a), (double)sinl(a));
+  };
+  table.clear();
+  long long ns = 1;
   for (int s = 0; s < pl.nst; ++s) {
-    pl.r[s] = rs[s];
-    if (rs[s] > 8) big = true;  // 29, 47 and other primes
+    const int R = rs[s];
+    pl.r[s] = R;
+    if (R > 8) big = true;  // 29, 47 and other primes
+    pl.toff[s] = -1;
+    pl.coff[s] = -1;
+    if (ns > 1) {
+      pl.toff[s] = (int)table.size();
+      for (int mm = 1; mm < R; ++mm)
+        for (long long k = 0; k < ns; ++k) table.push_back(root((long long)mm * k, ns * R));
+    }
+    if (R % 2 == 1) {
+      pl.coff[s] = (int)table.size();
+      for (int q = 0; q < R; ++q) table.push_back(root(q, R));
+    }
+    ns *= R;
   }
+  if (table.empty()) table.push_back(mk(1.0, 0.0));
+  pl.tsize = (int)table.size();
   return true;
 }
 
-static std::vector<cpx<double>> twiddles(int n) {
+static std::vector<cpx<double>> roots(int n) {
   std::vector<cpx<double>> t(n);
   const long double pi = 3.141592653589793238462643383279502884L;
   for (int q = 0; q < n; ++q) {
@@ -171,7 +198,7 @@ static fcns_status alloc(fcns_ctx* c, cpx<double>** p, long long n) {
 static void free_all(fcns_ctx* c) {
   for (hipEvent_t e : c->evpool) (void)hipEventDestroy(e);
   c->evpool.clear();
-  void* ps[] = {c->twz, c->twx, c->twy, c->fcM, c->sigx, c->sigy, c->sigz, c->P, c->Q,
+  void* ps[] = {c->twz, c->twx, c->twy, c->rootz, c->fcM, c->sigx, c->sigy, c->sigz, c->P, c->Q,
                 c->VS, c->MV, c->MVT, c->XYB, c->NLB, c->PM, c->GW, c->GWT};
   for (void* p : ps)
     if (p) (void)hipFree(p);
@@ -182,7 +209,7 @@ static ZArgs zargs(const fcns_ctx* c) {
   a.g = c->g;
   a.pl = c->plz;
   a.tw = c->twz;
-  a.tw64 = c->twz;
+  a.tw64 = c->rootz;
   a.fc = c->fcM;
   a.sigx = c->sigx;
   a.sigy = c->sigy;
@@ -230,6 +257,7 @@ extern "C" fcns_status fcns_create(const fcns_problem* prob, void* hip_stream, f
   const int npr = p.nz + p.fc_C;
   if (npr > z_max_npr()) return fail(nullptr, FCNS_EINVAL, "N' = nz + C must be <= 512");
 
+  if (const char* v = getenv("FCNS_XNL_VARIANT")) x_nl_variant = atoi(v);
   fcns_ctx* c = new fcns_ctx();
   c->prob = p;
   c->prob.fc_table = nullptr;
@@ -254,8 +282,9 @@ extern "C" fcns_status fcns_create(const fcns_problem* prob, void* hip_stream, f
   g.kys = 2.0 * M_PI / p.ly;
   g.kzs = 2.0 * M_PI / g.lzp;
 
-  if (!make_plan(npr, c->plz, c->big_z) || !make_plan(p.nx, c->plx, c->big_x) ||
-      !make_plan(p.ny, c->ply, c->big_y)) {
+  std::vector<cpx<double>> twz, twx, twy;
+  if (!make_plan(npr, c->plz, c->big_z, twz) || !make_plan(p.nx, c->plx, c->big_x, twx) ||
+      !make_plan(p.ny, c->ply, c->big_y, twy)) {
     delete c;
     return fail(nullptr, FCNS_EINVAL, "unsupported transform length (more than 12 radix stages)");
   }
@@ -276,7 +305,7 @@ extern "C" fcns_status fcns_create(const fcns_problem* prob, void* hip_stream, f
   const double two_p = p.filter_2p > 0 ? p.filter_2p : 100.0;
   c->prob.filter_beta = beta;
   c->prob.filter_2p = two_p;
-  auto twz = twiddles(npr), twx = twiddles(p.nx), twy = twiddles(p.ny);
+  auto rz = roots(npr);
   auto sx = filter_table(p.nx, g.nkx, true, beta, two_p);
   auto sy = filter_table(p.ny, p.ny, false, beta, two_p);
   auto sz = filter_table(npr, npr, false, beta, two_p);
@@ -284,6 +313,7 @@ extern "C" fcns_status fcns_create(const fcns_problem* prob, void* hip_stream, f
   if ((st = upload(c, &c->twz, twz.data(), twz.size())) ||
       (st = upload(c, &c->twx, twx.data(), twx.size())) ||
       (st = upload(c, &c->twy, twy.data(), twy.size())) ||
+      (st = upload(c, &c->rootz, rz.data(), rz.size())) ||
       (st = upload(c, &c->fcM, c->hostM.data(), c->hostM.size())) ||
       (st = upload(c, &c->sigx, sx.data(), sx.size())) ||
       (st = upload(c, &c->sigy, sy.data(), sy.size())) ||
@@ -464,8 +494,6 @@ static void rk_stage(fcns_ctx* c, int j, int o, double dt) {
   for (int i = 0; i < 3; ++i) {
     B.vs[i] = c->VS + i * S;
     B.vout[i] = OUT + i * S;
-    B.mv[i] = c->MV + (2 * i) * M;
-    B.mdz[i] = c->MV + (2 * i + 1) * M;
   }
   B.gwall = c->GW;
   B.pmix = (c->prob.keep_pressure && j == o) ? c->PM : nullptr;
@@ -473,12 +501,10 @@ static void rk_stage(fcns_ctx* c, int j, int o, double dt) {
   tbeg(c, T_ZSTAGEB);
   launch_z_stageB(zargs(c), c->big_z, B, c->stream);
   tend(c);
-  if (nf == 4) {
-    tbeg(c, T_ZBACK_TH);
-    launch_z_back(zargs(c), c->big_z, OUT + 3 * S, c->MV + 6 * M, c->MV + 7 * M, S, 2 * M, 1,
-                  c->stream);
-    tend(c);
-  }
+  // mixed v_f, dv_f/dz of the new state for the next stage's x/y passes
+  tbeg(c, T_ZBACK);
+  launch_z_back(zargs(c), c->big_z, OUT, c->MV, c->MV + M, S, 2 * M, nf, c->stream);
+  tend(c);
 }
 
 extern "C" fcns_status fcns_rk_step(fcns_ctx* c, double dt, int32_t nsteps) {
@@ -552,14 +578,13 @@ extern "C" fcns_status fcns_pressure_project(fcns_ctx* c, const double* v_star, 
   for (int i = 0; i < 3; ++i) {
     B.vs[i] = c->VS + i * S;
     B.vout[i] = c->VS + i * S;
-    B.mv[i] = c->MVT + (2 * i) * M;
-    B.mdz[i] = c->MVT + (2 * i + 1) * M;
   }
   B.gwall = c->GWT;
   B.pmix = nullptr;
   B.c = cj;
   launch_z_stageB(zargs(c), c->big_z, B, c->stream);
-  mixed_to_phys(c, c->MVT, 2 * M, 3, v_out, c->g.nz);
+  launch_z_back(zargs(c), c->big_z, c->VS, c->MVT, nullptr, S, M, 3, c->stream);
+  mixed_to_phys(c, c->MVT, M, 3, v_out, c->g.nz);
   if (gradp_wall) mixed_to_phys(c, c->GWT, 0, 1, gradp_wall, 4);
   return check_launch(c, "pressure_project");
 }

@@ -15,9 +15,14 @@
 // Codelets: radix 2, 4, 8 in closed form; odd primes use the symmetric form
 // of a prime-length DFT (a_q = x_q + x_{R-q}, b_q = x_q - x_{R-q}), which takes
 // (R-1)^2 real multiply-adds per pair of outputs instead of R^2 complex ones,
-// with cos and sin read from the length-n twiddle table at a wave-uniform
-// index (LDS broadcast).  3, 5, 7, 29 and 47 are unrolled in registers; any
-// other odd prime runs a compact loop that reads its inputs from LDS.
+// with cos and sin read at a wave-uniform index (LDS broadcast).  3, 5, 7, 29
+// and 47 are unrolled in registers; any other odd prime runs a compact loop
+// that reads its inputs from LDS.
+//
+// Twiddle table (built on the host, copied to LDS): for every stage with
+// ns > 1 the factors w^{m k}, stored [m-1][k] so that the lanes of a wave,
+// which hold consecutive k, read consecutive addresses; for every odd-radix
+// stage the R roots exp(-2 pi i q / R).
 #pragma once
 #include "fcns_common.hpp"
 
@@ -29,6 +34,9 @@ struct FFTPlan {
   int n;
   int nst;
   int r[FFT_MAX_STAGES];
+  int toff[FFT_MAX_STAGES];  // stage twiddles [m-1][k] (ns > 1), else -1
+  int coff[FFT_MAX_STAGES];  // roots of unity of odd radices, else -1
+  int tsize;                 // complex entries of the whole table
 };
 
 // ---------------------------------------------------------------- codelets
@@ -47,7 +55,7 @@ struct Codelet;
 
 template <typename T>
 struct Codelet<T, 2> {
-  __device__ __forceinline__ static void run(cpx<T>* v, cpx<T>* dst, int os, const cpx<T>*, int) {
+  __device__ __forceinline__ static void run(cpx<T>* v, cpx<T>* dst, int os, const cpx<T>*) {
     dst[0] = v[0] + v[1];
     dst[os] = v[0] - v[1];
   }
@@ -55,7 +63,7 @@ struct Codelet<T, 2> {
 
 template <typename T>
 struct Codelet<T, 4> {
-  __device__ __forceinline__ static void run(cpx<T>* v, cpx<T>* dst, int os, const cpx<T>*, int) {
+  __device__ __forceinline__ static void run(cpx<T>* v, cpx<T>* dst, int os, const cpx<T>*) {
     cpx<T> a0 = v[0], a1 = v[1], a2 = v[2], a3 = v[3];
     dft4_reg<T>(a0, a1, a2, a3);
     dst[0] = a0;
@@ -67,7 +75,7 @@ struct Codelet<T, 4> {
 
 template <typename T>
 struct Codelet<T, 8> {
-  __device__ __forceinline__ static void run(cpx<T>* v, cpx<T>* dst, int os, const cpx<T>*, int) {
+  __device__ __forceinline__ static void run(cpx<T>* v, cpx<T>* dst, int os, const cpx<T>*) {
     // n = n1 + 4 n2: even outputs from a = x_n1 + x_n1+4, odd outputs from
     // b = (x_n1 - x_n1+4) w8^n1, w8 = exp(-i pi/4)
     const T h = T(0.70710678118654752440084436210484903928483593768847);
@@ -89,11 +97,10 @@ struct Codelet<T, 8> {
   }
 };
 
-// Odd prime P in registers.  tw: n-point table exp(-2 pi i q / n); st = n/P.
+// Odd prime P in registers.  cw: the P roots exp(-2 pi i q / P).
 template <typename T, int P>
 struct CodeletOdd {
-  __device__ __forceinline__ static void run(cpx<T>* v, cpx<T>* dst, int os, const cpx<T>* tw,
-                                             int st) {
+  __device__ __forceinline__ static void run(cpx<T>* v, cpx<T>* dst, int os, const cpx<T>* cw) {
     constexpr int H = (P - 1) / 2;
     cpx<T> a[H], b[H];
     const cpx<T> x0 = v[0];
@@ -110,7 +117,7 @@ struct CodeletOdd {
       cpx<T> re = x0, im = zero<T>();
 #pragma unroll
       for (int q = 1; q <= H; ++q) {
-        const cpx<T> w = tw[((q * k) % P) * st];  // cos - i sin
+        const cpx<T> w = cw[(q * k) % P];  // cos - i sin
         re = re + a[q - 1] * w.x;
         im = im + b[q - 1] * (-w.y);
       }
@@ -140,10 +147,10 @@ __device__ __forceinline__ int fast_mod(int j, int ns, float rcp) {
 template <typename T, int R>
 __device__ __forceinline__ void fft_stage(const cpx<T>* __restrict__ src, cpx<T>* __restrict__ dst,
                                           int L, int es, int ls, int n, int ns,
-                                          const cpx<T>* __restrict__ tw, int tid, int nt) {
+                                          const cpx<T>* __restrict__ tws,
+                                          const cpx<T>* __restrict__ cw, int tid, int nt) {
   const int nr = n / R;
   const int nb = L * nr;
-  const int tws = n / (ns * R);
   const float rcp = 1.0f / (float)ns;
   for (int g = tid; g < nb; g += nt) {
     const int l = g % L, j = g / L;
@@ -154,9 +161,9 @@ __device__ __forceinline__ void fft_stage(const cpx<T>* __restrict__ src, cpx<T>
     for (int m = 0; m < R; ++m) v[m] = s[m * nr * es];
     if (ns > 1) {
 #pragma unroll
-      for (int m = 1; m < R; ++m) v[m] = v[m] * tw[m * k * tws];
+      for (int m = 1; m < R; ++m) v[m] = v[m] * tws[(m - 1) * ns + k];
     }
-    Codelet<T, R>::run(v, dst + l * ls + ((j - k) * R + k) * es, ns * es, tw, n / R);
+    Codelet<T, R>::run(v, dst + l * ls + ((j - k) * R + k) * es, ns * es, cw);
   }
 }
 
@@ -165,11 +172,10 @@ __device__ __forceinline__ void fft_stage(const cpx<T>* __restrict__ src, cpx<T>
 template <typename T>
 __device__ __forceinline__ void fft_stage_prime(cpx<T>* __restrict__ src, cpx<T>* __restrict__ dst,
                                                 int R, int L, int es, int ls, int n, int ns,
-                                                const cpx<T>* __restrict__ tw, int tid, int nt) {
+                                                const cpx<T>* __restrict__ tws,
+                                                const cpx<T>* __restrict__ cw, int tid, int nt) {
   const int nr = n / R;
   const int nb = L * nr;
-  const int tws = n / (ns * R);
-  const int st = n / R;
   const int H = (R - 1) / 2;
   const float rcp = 1.0f / (float)ns;
   for (int g = tid; g < nb; g += nt) {
@@ -178,7 +184,7 @@ __device__ __forceinline__ void fft_stage_prime(cpx<T>* __restrict__ src, cpx<T>
     cpx<T>* s = src + l * ls + j * es;
     const int is = nr * es;
     if (ns > 1)
-      for (int m = 1; m < R; ++m) s[m * is] = s[m * is] * tw[m * k * tws];
+      for (int m = 1; m < R; ++m) s[m * is] = s[m * is] * tws[(m - 1) * ns + k];
     cpx<T>* d = dst + l * ls + ((j - k) * R + k) * es;
     const int os = ns * es;
     const cpx<T> x0 = s[0];
@@ -191,7 +197,7 @@ __device__ __forceinline__ void fft_stage_prime(cpx<T>* __restrict__ src, cpx<T>
       for (int q = 1; q <= H; ++q) {
         qk += kk;
         if (qk >= R) qk -= R;
-        const cpx<T> w = tw[qk * st];
+        const cpx<T> w = cw[qk];
         const cpx<T> xa = s[q * is], xb = s[(R - q) * is];
         re = re + (xa + xb) * w.x;
         im = im + (xa - xb) * (-w.y);
@@ -204,10 +210,11 @@ __device__ __forceinline__ void fft_stage_prime(cpx<T>* __restrict__ src, cpx<T>
 
 // ---------------------------------------------------------------- driver
 // Forward FFT of L lines of pl.n points.  The input is in buf0; buf1 is
-// scratch of the same size.  Returns the buffer holding the result.  All
-// threads of the workgroup must call it, after a barrier that makes the
-// input visible; it synchronises before returning.
-// BIG: also dispatch radix 29, 47 and the run-time odd-prime stage.
+// scratch of the same size; tw is the plan's twiddle table (in LDS).
+// Returns the buffer holding the result.  All threads of the workgroup must
+// call it, after a barrier that makes the input visible; it synchronises
+// before returning.  BIG: also dispatch radix 29, 47 and the run-time
+// odd-prime stage.
 template <typename T, int L, bool BIG>
 __device__ __forceinline__ cpx<T>* fft_fwd(cpx<T>* buf0, cpx<T>* buf1, int es, int ls,
                                            const FFTPlan& pl, const cpx<T>* __restrict__ tw,
@@ -218,21 +225,23 @@ __device__ __forceinline__ cpx<T>* fft_fwd(cpx<T>* buf0, cpx<T>* buf1, int es, i
   cpx<T>* dst = buf1;
   for (int s = 0; s < pl.nst; ++s) {
     const int r = pl.r[s];
+    const cpx<T>* tws = tw + (pl.toff[s] < 0 ? 0 : pl.toff[s]);
+    const cpx<T>* cw = tw + (pl.coff[s] < 0 ? 0 : pl.coff[s]);
     switch (r) {
-      case 2: fft_stage<T, 2>(src, dst, L, es, ls, n, ns, tw, tid, nt); break;
-      case 3: fft_stage<T, 3>(src, dst, L, es, ls, n, ns, tw, tid, nt); break;
-      case 4: fft_stage<T, 4>(src, dst, L, es, ls, n, ns, tw, tid, nt); break;
-      case 5: fft_stage<T, 5>(src, dst, L, es, ls, n, ns, tw, tid, nt); break;
-      case 7: fft_stage<T, 7>(src, dst, L, es, ls, n, ns, tw, tid, nt); break;
-      case 8: fft_stage<T, 8>(src, dst, L, es, ls, n, ns, tw, tid, nt); break;
+      case 2: fft_stage<T, 2>(src, dst, L, es, ls, n, ns, tws, cw, tid, nt); break;
+      case 3: fft_stage<T, 3>(src, dst, L, es, ls, n, ns, tws, cw, tid, nt); break;
+      case 4: fft_stage<T, 4>(src, dst, L, es, ls, n, ns, tws, cw, tid, nt); break;
+      case 5: fft_stage<T, 5>(src, dst, L, es, ls, n, ns, tws, cw, tid, nt); break;
+      case 7: fft_stage<T, 7>(src, dst, L, es, ls, n, ns, tws, cw, tid, nt); break;
+      case 8: fft_stage<T, 8>(src, dst, L, es, ls, n, ns, tws, cw, tid, nt); break;
       default:
         if constexpr (BIG) {
           if (r == 29)
-            fft_stage<T, 29>(src, dst, L, es, ls, n, ns, tw, tid, nt);
+            fft_stage<T, 29>(src, dst, L, es, ls, n, ns, tws, cw, tid, nt);
           else if (r == 47)
-            fft_stage<T, 47>(src, dst, L, es, ls, n, ns, tw, tid, nt);
+            fft_stage<T, 47>(src, dst, L, es, ls, n, ns, tws, cw, tid, nt);
           else
-            fft_stage_prime<T>(src, dst, r, L, es, ls, n, ns, tw, tid, nt);
+            fft_stage_prime<T>(src, dst, r, L, es, ls, n, ns, tws, cw, tid, nt);
         }
         break;
     }

@@ -43,8 +43,6 @@ struct StageAArgs {
 struct StageBArgs {
   const cpx<double>* vs[3];   // V*
   cpx<double>* vout[3];       // projected continued velocity
-  cpx<double>* mv[3];         // mixed v
-  cpx<double>* mdz[3];        // mixed dv/dz
   cpx<double>* gwall;         // out: next-stage wall tangential gradient (or null)
   cpx<double>* pmix;          // out: mixed pressure (or null)
   double c;
@@ -112,6 +110,7 @@ void launch_x_c2r(const XArgs& a, bool big, const cpx<double>* xy, double* phys,
 // field slots 3f, 3f+1, 3f+2; nl gets -(v.grad) q_f at slot f.
 void launch_x_nl(const XArgs& a, bool big, const cpx<double>* xyb, cpx<double>* nl,
                  long long fstride, long long nrows, int nfields, hipStream_t st);
+extern int x_nl_variant;  // tile shape of the x pass (tuning)
 
 // small helpers
 void launch_fill(cpx<double>* p, long long n, hipStream_t st);

@@ -25,13 +25,13 @@ __global__ __launch_bounds__(YNT) void k_y(YArgs a, const cpx<double>* src, cpx<
   const int tid = threadIdx.x;
   const int ny = a.ny, nkx = a.nkx, nkxp = a.nkxp;
   cpx<T>* tw = reinterpret_cast<cpx<T>*>(smem);
-  cpx<T>* X0 = tw + ny;
+  cpx<T>* X0 = tw + a.pl.tsize;
   cpx<T>* X1 = X0 + ny * YL;
   src += blockIdx.y * sfs;
   dst += blockIdx.y * dfs;
   if (mode == 1) dst2 += blockIdx.y * dfs;
   const cpx<T>* gtw = reinterpret_cast<const cpx<T>*>(a.tw);
-  for (int i = tid; i < ny; i += YNT) tw[i] = gtw[i];
+  for (int i = tid; i < a.pl.tsize; i += YNT) tw[i] = gtw[i];
   const int l = tid % YL, ky0 = tid / YL;
   constexpr int KYS = YNT / YL;
   const long long ntiles = (nlines + YL - 1) / YL;
@@ -160,12 +160,12 @@ __global__ __launch_bounds__(XNT) void k_x_r2c(XArgs a, const double* __restrict
   const int tid = threadIdx.x;
   const int nx = a.nx, ls = nx + 1;
   cpx<T>* tw = reinterpret_cast<cpx<T>*>(smem);
-  cpx<T>* X0 = tw + nx;
+  cpx<T>* X0 = tw + a.pl.tsize;
   cpx<T>* X1 = X0 + XL * ls;
   phys += blockIdx.y * pfs;
   xy += blockIdx.y * xfs;
   const cpx<T>* gtw = reinterpret_cast<const cpx<T>*>(a.tw);
-  for (int i = tid; i < nx; i += XNT) tw[i] = gtw[i];
+  for (int i = tid; i < a.pl.tsize; i += XNT) tw[i] = gtw[i];
   const long long r0 = (long long)blockIdx.x * XR;
   T* Xs = reinterpret_cast<T*>(X0);
 #pragma unroll
@@ -187,12 +187,12 @@ __global__ __launch_bounds__(XNT) void k_x_c2r(XArgs a, const cpx<double>* __res
   const int tid = threadIdx.x;
   const int nx = a.nx, ls = nx + 1;
   cpx<T>* tw = reinterpret_cast<cpx<T>*>(smem);
-  cpx<T>* X0 = tw + nx;
+  cpx<T>* X0 = tw + a.pl.tsize;
   cpx<T>* X1 = X0 + XL * ls;
   phys += blockIdx.y * pfs;
   xy += blockIdx.y * xfs;
   const cpx<T>* gtw = reinterpret_cast<const cpx<T>*>(a.tw);
-  for (int i = tid; i < nx; i += XNT) tw[i] = gtw[i];
+  for (int i = tid; i < a.pl.tsize; i += XNT) tw[i] = gtw[i];
   const long long r0 = (long long)blockIdx.x * XR;
   x_pack_c2r<T>(X0, ls, xy, r0, nrows, a, false, tid);
   __syncthreads();
@@ -211,33 +211,31 @@ __global__ __launch_bounds__(XNT) void k_x_c2r(XArgs a, const cpx<double>* __res
 }
 
 // ---------------------------------------------------------------- x pass with products
-// NL_f = -(u dq_f/dx + v dq_f/dy + w dq_f/dz) at the physical points of XR
+// NL_f = -(u dq_f/dx + v dq_f/dy + w dq_f/dz) at the physical points of RR
 // rows (Sec. 4.2: derivatives in Fourier space, products in real space, no
 // padding), then its r2c transform.  Passes: 0-2 physical u, v, w; then per
 // field f: dq/dx, dq/dy, dq/dz (inverse), and the forward transform of NL_f.
-// Thread tid < nkx owns spectral column k = tid of the XR rows (nkx <= XNT)
-// and loads the next pass's inputs while the current pass is transformed;
-// thread tid < nx owns physical column n = tid.
-template <typename T, bool BIG>
-__global__ __launch_bounds__(XNT) void k_x_nl(XArgs a, const cpx<double>* __restrict__ xyb,
-                                              cpx<double>* __restrict__ nl, long long fs,
-                                              long long nrows, int nfields) {
+// A workgroup of NT threads owns spectral columns k = tid + c NT and physical
+// columns n = tid + c NT (c < CC, CC NT >= nx) of its RR rows; each thread
+// loads the next pass's spectral inputs while the current pass is transformed.
+template <typename T, bool BIG, int RR, int NT, int CC>
+__global__ __launch_bounds__(NT) void k_x_nl(XArgs a, const cpx<double>* __restrict__ xyb,
+                                             cpx<double>* __restrict__ nl, long long fs,
+                                             long long nrows, int nfields) {
+  constexpr int LL = RR / 2;
   extern __shared__ __align__(16) char smem[];
   const int tid = threadIdx.x;
   const int nx = a.nx, nkx = a.nkx, nkxp = a.nkxp, ls = nx + 1;
   cpx<T>* tw = reinterpret_cast<cpx<T>*>(smem);
-  cpx<T>* X0 = tw + nx;
-  cpx<T>* X1 = X0 + XL * ls;
+  cpx<T>* X0 = tw + a.pl.tsize;
+  cpx<T>* X1 = X0 + LL * ls;
   const cpx<T>* gtw = reinterpret_cast<const cpx<T>*>(a.tw);
-  for (int i = tid; i < nx; i += XNT) tw[i] = gtw[i];
-  const long long r0 = (long long)blockIdx.x * XR;
-  const bool own = tid < nx, ownk = tid < nkx;
-  const int n = tid, k = tid;
+  for (int i = tid; i < a.pl.tsize; i += NT) tw[i] = gtw[i];
+  const long long r0 = (long long)blockIdx.x * RR;
   const double sc = 1.0 / nx;
-  const double kx = (2 * k == nx) ? 0.0 : a.kxs * k;
-  double U[3][XR];
-  double acc[XR];
-  cpx<double> in[XR];
+  double U[3][CC][RR];
+  double acc[CC][RR];
+  cpx<double> in[CC][RR];
   // source slot of c2r pass p (-1: forward pass)
   auto slot = [&](int p) {
     if (p < 3) return 3 * p;
@@ -246,11 +244,15 @@ __global__ __launch_bounds__(XNT) void k_x_nl(XArgs a, const cpx<double>* __rest
   };
   auto load = [&](int p) {
     const int sl = slot(p);
-    if (sl < 0 || !ownk) return;
+    if (sl < 0) return;
     const cpx<double>* src = xyb + sl * fs;
 #pragma unroll
-    for (int r = 0; r < XR; ++r)
-      in[r] = (r0 + r < nrows) ? src[(r0 + r) * nkxp + k] : zero<double>();
+    for (int c = 0; c < CC; ++c) {
+      const int k = tid + c * NT;
+#pragma unroll
+      for (int r = 0; r < RR; ++r)
+        in[c][r] = (k < nkx && r0 + r < nrows) ? src[(r0 + r) * nkxp + k] : zero<double>();
+    }
   };
   const int npass = 3 + 4 * nfields;
   load(0);
@@ -258,62 +260,87 @@ __global__ __launch_bounds__(XNT) void k_x_nl(XArgs a, const cpx<double>* __rest
     const int f = (pass - 3) >> 2, kk = (pass - 3) & 3;
     const bool fwd = pass >= 3 && kk == 3;
     if (!fwd) {
-      if (ownk) {
-        const bool dx = pass >= 3 && kk == 0;
+      const bool dx = pass >= 3 && kk == 0;
 #pragma unroll
-        for (int al = 0; al < XL; ++al) {
-          cpx<double> A = in[2 * al], B = in[2 * al + 1];
-          if (dx) {
-            A = mul_i(A) * kx;
-            B = mul_i(B) * kx;
+      for (int c = 0; c < CC; ++c) {
+        const int k = tid + c * NT;
+        if (k < nkx) {
+          const double kx = (2 * k == nx) ? 0.0 : a.kxs * k;
+#pragma unroll
+          for (int al = 0; al < LL; ++al) {
+            cpx<double> A = in[c][2 * al], B = in[c][2 * al + 1];
+            if (dx) {
+              A = mul_i(A) * kx;
+              B = mul_i(B) * kx;
+            }
+            if (k == 0 || 2 * k == nx) {
+              A.y = 0.0;
+              B.y = 0.0;
+            }
+            // Z[k] = A + i B, Z[nx - k] = conj(A) + i conj(B); stored conjugated
+            X0[al * ls + k] = cvt<T>(conj(mk(A.x - B.y, A.y + B.x)));
+            if (k > 0 && 2 * k < nx) X0[al * ls + nx - k] = cvt<T>(conj(mk(A.x + B.y, B.x - A.y)));
           }
-          if (k == 0 || 2 * k == nx) {
-            A.y = 0.0;
-            B.y = 0.0;
-          }
-          // Z[k] = A + i B, Z[nx - k] = conj(A) + i conj(B); stored conjugated
-          X0[al * ls + k] = cvt<T>(conj(mk(A.x - B.y, A.y + B.x)));
-          if (k > 0 && 2 * k < nx) X0[al * ls + nx - k] = cvt<T>(conj(mk(A.x + B.y, B.x - A.y)));
         }
       }
-    } else if (own) {
+    } else {
 #pragma unroll
-      for (int al = 0; al < XL; ++al)
-        X0[al * ls + n] = mk((T)acc[2 * al], (T)acc[2 * al + 1]);
+      for (int c = 0; c < CC; ++c) {
+        const int n = tid + c * NT;
+        if (n < nx) {
+#pragma unroll
+          for (int al = 0; al < LL; ++al)
+            X0[al * ls + n] = mk((T)acc[c][2 * al], (T)acc[c][2 * al + 1]);
+        }
+      }
     }
     // next pass's spectral inputs, in flight during this pass's transform
     int pn = pass + 1;
     if (pn < npass && slot(pn) < 0) ++pn;
     if (pn < npass) load(pn);
     __syncthreads();
-    const cpx<T>* R = fft_fwd<T, XL, BIG>(X0, X1, 1, ls, a.pl, tw, tid, XNT);
+    const cpx<T>* R = fft_fwd<T, LL, BIG>(X0, X1, 1, ls, a.pl, tw, tid, NT);
     if (!fwd) {
-      if (own) {
-        double v[XR];
 #pragma unroll
-        for (int al = 0; al < XL; ++al) {
+      for (int c = 0; c < CC; ++c) {
+        const int n = tid + c * NT;
+        if (n >= nx) continue;
+        double v[RR];
+#pragma unroll
+        for (int al = 0; al < LL; ++al) {
           const cpx<T> z = R[al * ls + n];
           v[2 * al] = (double)z.x * sc;
           v[2 * al + 1] = -(double)z.y * sc;
         }
         if (pass < 3) {
 #pragma unroll
-          for (int r = 0; r < XR; ++r) {
-            if (pass == 0) U[0][r] = v[r];
-            else if (pass == 1) U[1][r] = v[r];
-            else U[2][r] = v[r];
+          for (int r = 0; r < RR; ++r) {
+            if (pass == 0) U[0][c][r] = v[r];
+            else if (pass == 1) U[1][c][r] = v[r];
+            else U[2][c][r] = v[r];
           }
         } else {
 #pragma unroll
-          for (int r = 0; r < XR; ++r) {
-            const double u = (kk == 0) ? U[0][r] : ((kk == 1) ? U[1][r] : U[2][r]);
-            if (kk == 0) acc[r] = -u * v[r];
-            else acc[r] -= u * v[r];
+          for (int r = 0; r < RR; ++r) {
+            const double u = (kk == 0) ? U[0][c][r] : ((kk == 1) ? U[1][c][r] : U[2][c][r]);
+            if (kk == 0) acc[c][r] = -u * v[r];
+            else acc[c][r] -= u * v[r];
           }
         }
       }
     } else {
-      x_unpack_r2c<T>(R, ls, nl + f * fs, r0, nrows, a, tid);
+      // unpack the r2c spectra of the RR rows
+#pragma unroll
+      for (int al = 0; al < LL; ++al) {
+        const long long ra = r0 + 2 * al, rb = ra + 1;
+        cpx<double>* dst = nl + f * fs;
+        for (int k = tid; k < nkx; k += NT) {
+          const cpx<double> Z = cvt<double>(R[al * ls + k]);
+          const cpx<double> Zm = conj(cvt<double>(R[al * ls + ((k == 0) ? 0 : nx - k)]));
+          if (ra < nrows) dst[ra * nkxp + k] = (Z + Zm) * 0.5;
+          if (rb < nrows) dst[rb * nkxp + k] = mul_mi(Z - Zm) * 0.5;
+        }
+      }
     }
     __syncthreads();
   }
@@ -350,7 +377,7 @@ void launch_y(const YArgs& a, bool big, bool inv, int mode, const cpx<double>* s
   const long long nlines = (long long)nplanes * a.nkxp;
   const long long ntiles = (nlines + YL - 1) / YL;
   dim3 grid((unsigned)(ntiles < Y_GRID ? ntiles : Y_GRID), nfields);
-  const size_t sh = (size_t)a.ny * (2 * YL + 1) * sizeof(cpx<double>);
+  const size_t sh = ((size_t)a.pl.tsize + (size_t)a.ny * 2 * YL) * sizeof(cpx<double>);
   const int need = (a.ny + YNT / YL - 1) / (YNT / YL);
   const int iv = inv ? 1 : 0;
 #define FCNS_Y(BIGV, OWNV)                                                                    \
@@ -367,7 +394,7 @@ void launch_y(const YArgs& a, bool big, bool inv, int mode, const cpx<double>* s
 void launch_x_r2c(const XArgs& a, bool big, const double* phys, cpx<double>* xy, long long pfs,
                   long long xfs, long long nrows, int nfields, hipStream_t st) {
   dim3 grid((unsigned)((nrows + XR - 1) / XR), nfields);
-  const size_t sh = ((size_t)a.nx + 2 * XL * (a.nx + 1)) * sizeof(cpx<double>);
+  const size_t sh = ((size_t)a.pl.tsize + 2 * XL * (a.nx + 1)) * sizeof(cpx<double>);
   if (big)
     FCNS_LAUNCH((k_x_r2c<double, true>), grid, dim3(XNT), sh, st, a, phys, xy, pfs, xfs, nrows);
   else
@@ -377,21 +404,33 @@ void launch_x_r2c(const XArgs& a, bool big, const double* phys, cpx<double>* xy,
 void launch_x_c2r(const XArgs& a, bool big, const cpx<double>* xy, double* phys, long long xfs,
                   long long pfs, long long nrows, int nfields, hipStream_t st) {
   dim3 grid((unsigned)((nrows + XR - 1) / XR), nfields);
-  const size_t sh = ((size_t)a.nx + 2 * XL * (a.nx + 1)) * sizeof(cpx<double>);
+  const size_t sh = ((size_t)a.pl.tsize + 2 * XL * (a.nx + 1)) * sizeof(cpx<double>);
   if (big)
     FCNS_LAUNCH((k_x_c2r<double, true>), grid, dim3(XNT), sh, st, a, xy, phys, xfs, pfs, nrows);
   else
     FCNS_LAUNCH((k_x_c2r<double, false>), grid, dim3(XNT), sh, st, a, xy, phys, xfs, pfs, nrows);
 }
 
+int x_nl_variant = 1;  // 0: 8 rows x 512 threads, 1: 4 rows x 256 threads (faster on gfx950)
+
+template <bool BIG, int RR, int NT, int CC>
+static void launch_x_nl_v(const XArgs& a, const cpx<double>* xyb, cpx<double>* nl, long long fs,
+                          long long nrows, int nfields, hipStream_t st) {
+  dim3 grid((unsigned)((nrows + RR - 1) / RR));
+  const size_t sh = ((size_t)a.pl.tsize + 2 * (RR / 2) * (a.nx + 1)) * sizeof(cpx<double>);
+  FCNS_LAUNCH((k_x_nl<double, BIG, RR, NT, CC>), grid, dim3(NT), sh, st, a, xyb, nl, fs, nrows,
+              nfields);
+}
+
 void launch_x_nl(const XArgs& a, bool big, const cpx<double>* xyb, cpx<double>* nl,
                  long long fs, long long nrows, int nfields, hipStream_t st) {
-  dim3 grid((unsigned)((nrows + XR - 1) / XR));
-  const size_t sh = ((size_t)a.nx + 2 * XL * (a.nx + 1)) * sizeof(cpx<double>);
-  if (big)
-    FCNS_LAUNCH((k_x_nl<double, true>), grid, dim3(XNT), sh, st, a, xyb, nl, fs, nrows, nfields);
-  else
-    FCNS_LAUNCH((k_x_nl<double, false>), grid, dim3(XNT), sh, st, a, xyb, nl, fs, nrows, nfields);
+  if (x_nl_variant == 1) {
+    if (big) launch_x_nl_v<true, 4, 256, 2>(a, xyb, nl, fs, nrows, nfields, st);
+    else launch_x_nl_v<false, 4, 256, 2>(a, xyb, nl, fs, nrows, nfields, st);
+  } else {
+    if (big) launch_x_nl_v<true, 8, 512, 1>(a, xyb, nl, fs, nrows, nfields, st);
+    else launch_x_nl_v<false, 8, 512, 1>(a, xyb, nl, fs, nrows, nfields, st);
+  }
 }
 
 void launch_fill(cpx<double>* p, long long n, hipStream_t st) {

@@ -17,7 +17,7 @@
 namespace fcns {
 
 // ---------------------------------------------------------------- LDS layout
-// [tw: N' cpx<T>][M: C*d double, padded to 16 B][X0: NX cpx<T>][X1: NX cpx<T>]
+// [tw: plan table cpx<T>][M: C*d double, padded to 16 B][X0: NX cpx<T>][X1: NX cpx<T>]
 // with NX = max(N' * ZPB, 4 * ZNT) (X1 also serves the reduction scratch).
 template <typename T>
 struct ZLds {
@@ -25,9 +25,9 @@ struct ZLds {
   double* M;
   cpx<T>* X0;
   cpx<T>* X1;
-  __device__ ZLds(char* base, const Geom& g) {
+  __device__ ZLds(char* base, const Geom& g, int tsize) {
     tw = reinterpret_cast<cpx<T>*>(base);
-    size_t off = g.npr * sizeof(cpx<T>);
+    size_t off = ((tsize * sizeof(cpx<T>) + 15) / 16) * 16;
     M = reinterpret_cast<double*>(base + off);
     off += ((g.C * g.d * sizeof(double) + 15) / 16) * 16;
     X0 = reinterpret_cast<cpx<T>*>(base + off);
@@ -37,17 +37,17 @@ struct ZLds {
 };
 
 template <typename T>
-size_t zshared_bytes(const Geom& g) {
+size_t zshared_bytes(const Geom& g, int tsize) {
   const size_t a = (size_t)g.npr * ZPB, b = 4 * ZNT * (sizeof(cpx<double>) / sizeof(cpx<T>));
   const size_t nx = a > b ? a : b;
-  return g.npr * sizeof(cpx<T>) + ((g.C * g.d * sizeof(double) + 15) / 16) * 16 +
+  return ((tsize * sizeof(cpx<T>) + 15) / 16) * 16 + ((g.C * g.d * sizeof(double) + 15) / 16) * 16 +
          2 * nx * sizeof(cpx<T>);
 }
 
 template <typename T>
 __device__ __forceinline__ void z_setup(const ZLds<T>& s, const ZArgs& a, int tid) {
   const cpx<T>* gtw = reinterpret_cast<const cpx<T>*>(a.tw);
-  for (int i = tid; i < a.g.npr; i += ZNT) s.tw[i] = gtw[i];
+  for (int i = tid; i < a.pl.tsize; i += ZNT) s.tw[i] = gtw[i];
   for (int i = tid; i < a.g.C * a.g.d; i += ZNT) s.M[i] = a.fc[i];
 }
 
@@ -100,7 +100,7 @@ __global__ __launch_bounds__(ZNT) void k_z_fwd(ZArgs a, const cpx<double>* __res
   extern __shared__ __align__(16) char smem[];
   const int tid = threadIdx.x;
   const Geom& g = a.g;
-  const ZLds<T> L(smem, g);
+  const ZLds<T> L(smem, g, a.pl.tsize);
   src += blockIdx.y * sfs;
   dst += blockIdx.y * dfs;
   const long long p0 = (long long)blockIdx.x * ZPB;
@@ -137,7 +137,7 @@ __global__ __launch_bounds__(ZNT) void k_z_back(ZArgs a, const cpx<double>* __re
   extern __shared__ __align__(16) char smem[];
   const int tid = threadIdx.x;
   const Geom& g = a.g;
-  const ZLds<T> L(smem, g);
+  const ZLds<T> L(smem, g, a.pl.tsize);
   src += blockIdx.y * sfs;
   dst += blockIdx.y * mfs;
   if (dzdst) dzdst += blockIdx.y * mfs;
@@ -186,7 +186,7 @@ __global__ __launch_bounds__(ZNT) void k_z_stageA(ZArgs a, StageAArgs s) {
   extern __shared__ __align__(16) char smem[];
   const int tid = threadIdx.x;
   const Geom& g = a.g;
-  const ZLds<T> L(smem, g);
+  const ZLds<T> L(smem, g, a.pl.tsize);
   const int f = blockIdx.y;
   const long long p0 = (long long)blockIdx.x * ZPB;
   z_setup<T>(L, a, tid);
@@ -281,21 +281,22 @@ __global__ __launch_bounds__(ZNT) void k_z_stageA(ZArgs a, StageAArgs s) {
 //   V = V* - k~ s - F_z H; next-stage wall gradient (k~ B_z s + H)_par / c.
 // The two exponentials are continued as the real and imaginary parts of one
 // line; F_z(e+ + i e-) splits into F_z e+ and F_z e- by conjugate symmetry.
-template <typename T, bool BIG, int OWN>
+// V* is streamed twice (wall sums, then the update) instead of being held in
+// registers; the mixed v, dv/dz of the result come from k_z_back.
+template <typename T, bool BIG>
 __global__ __launch_bounds__(ZNT) void k_z_stageB(ZArgs a, StageBArgs s) {
   extern __shared__ __align__(16) char smem[];
   __shared__ cpx<double> coef[ZPB * 5];  // b, t, s0, s1 then A, B, D
   __shared__ double gam_s[ZPB];
   const int tid = threadIdx.x;
   const Geom& g = a.g;
-  const ZLds<T> L(smem, g);
+  const ZLds<T> L(smem, g, a.pl.tsize);
   const long long p0 = (long long)blockIdx.x * ZPB;
-  const int pb_me = tid % ZPB;
+  const int pb_me = tid % ZPB, lt = tid / ZPB;
   const long long p_me = p0 + pb_me;
   const bool valid_me = pencil_valid(g, p_me);
   z_setup<T>(L, a, tid);
   const cpx<double>* __restrict__ gtw = a.tw64;
-  const int tot = g.npr * ZPB;
   const double inv = 1.0 / g.npr;
   const bool pm = s.pmix != nullptr;
 
@@ -304,27 +305,19 @@ __global__ __launch_bounds__(ZNT) void k_z_stageB(ZArgs a, StageBArgs s) {
   pencil_k(g, valid_me ? p_me : 0, kxo, kyo, kxt, kyt, ix, iy);
   const double kh2 = kxo * kxo + kyo * kyo;
 
-  // 1. V* (owned elements) and the wall sums of B_z(V*_z - k~z s) and B_z(s)
-  cpx<double> V[3][OWN];
+  // 1. wall sums of B_z(V*_z - k~z s) and B_z(s)
   cpx<double> sb = zero<double>(), st = zero<double>(), s0 = zero<double>(),
               s1 = zero<double>();
-  const int lt = tid / ZPB;
-#pragma unroll
-  for (int r = 0; r < OWN; ++r) {
-    const int e = tid + r * ZNT;
-#pragma unroll
-    for (int i = 0; i < 3; ++i) V[i][r] = zero<double>();
-    if (e < tot && valid_me) {
-      const int l = lt + r * ZLS;
+  if (valid_me) {
+    for (int l = lt; l < g.npr; l += ZLS) {
       const long long gi = (long long)l * g.npen + p_me;
-#pragma unroll
-      for (int i = 0; i < 3; ++i) V[i][r] = s.vs[i][gi];
+      const cpx<double> V0 = s.vs[0][gi], V1 = s.vs[1][gi], V2 = s.vs[2][gi];
       const double kz = k_odd(l, g.npr, g.kzs);
       const double k2 = kh2 + kz * kz;
       cpx<double> sv = zero<double>();
-      if (k2 > 0.0) sv = (V[0][r] * kxo + V[1][r] * kyo + V[2][r] * kz) * (1.0 / k2);
-      const cpx<double> rz = V[2][r] - sv * kz;
-      // e^{+2 pi i l (nz-1)/N'} = conj(tw[l (nz-1) mod N'])
+      if (k2 > 0.0) sv = (V0 * kxo + V1 * kyo + V2 * kz) * (1.0 / k2);
+      const cpx<double> rz = V2 - sv * kz;
+      // e^{+2 pi i l (nz-1)/N'} = conj(root[l (nz-1) mod N'])
       const cpx<double> et = conj(gtw[(int)(((long long)l * (g.nz - 1)) % g.npr)]);
       sb = sb + rz;
       st = st + rz * et;
@@ -385,95 +378,64 @@ __global__ __launch_bounds__(ZNT) void k_z_stageB(ZArgs a, StageBArgs s) {
   const cpx<double> A = coef[pb_me * 5 + 0], B = coef[pb_me * 5 + 1], D = coef[pb_me * 5 + 2];
   const double gam = gam_s[pb_me];
 
-  // passes: 0 = F_z(e+ + i e-); 1 = pressure (optional); 2..7 = v_i, dv_i/dz
-  cpx<T>* Xo = L.X1;
-  for (int pass = 0; pass < 8; ++pass) {
-    if (pass == 1 && !pm) continue;
-    cpx<T>* in = L.X0;
-    if (pass == 0) {
-      for (int z = lt; z < g.nz; z += ZLS) {
-        const double zz = z * g.dz;
-        L.X0[z * ZPB + pb_me] =
-            (gam > 0.0) ? mk((T)exp(gam * (zz - g.lz)), (T)exp(-gam * zz)) : mk((T)1, (T)0);
-      }
-      __syncthreads();
-      z_extend<T>(L.X0, L.M, g.nz, g.C, g.d, tid);
-      __syncthreads();
-    } else if (pass == 1) {
-      in = Xo;
-    } else {
-      const int i = (pass - 2) >> 1, dz = (pass - 2) & 1;
-#pragma unroll
-      for (int r = 0; r < OWN; ++r) {
-        const int e = tid + r * ZNT;
-        if (e < tot) {
-          cpx<double> v = (i == 0) ? V[0][r] : ((i == 1) ? V[1][r] : V[2][r]);
-          if (dz) v = mul_i(v) * k_odd(lt + r * ZLS, g.npr, g.kzs);
-          L.X0[e] = cvt<T>(conj(v));
-        }
-      }
-      __syncthreads();
-    }
-    cpx<T>* other = (in == L.X0) ? L.X1 : L.X0;
-    const cpx<T>* R = fft_fwd<T, ZPB, BIG>(in, other, ZPB, 1, a.pl, L.tw, tid, ZNT);
-    if (pass == 0) {
-      // V = V* - k~ s - H^ in registers; store the continued state
-      Xo = (R == L.X0) ? L.X1 : L.X0;
-#pragma unroll
-      for (int r = 0; r < OWN; ++r) {
-        const int e = tid + r * ZNT;
-        if (e < tot && valid_me) {
-          const int l = lt + r * ZLS;
-          const int lm = (l == 0) ? 0 : g.npr - l;
-          const cpx<double> xl = cvt<double>(R[e]), xm = conj(cvt<double>(R[lm * ZPB + pb_me]));
-          const cpx<double> ep = (xl + xm) * 0.5;
-          const cpx<double> em = mul_mi(xl - xm) * 0.5;
-          const double kz = k_odd(l, g.npr, g.kzs);
-          const double k2 = kh2 + kz * kz;
-          cpx<double> sv = zero<double>();
-          if (k2 > 0.0) sv = (V[0][r] * kxo + V[1][r] * kyo + V[2][r] * kz) * (1.0 / k2);
-          cpx<double> hx = zero<double>(), hy = zero<double>(), hz;
-          if (gam > 0.0) {
-            const cpx<double> sym = A * ep + B * em;
-            hx = mul_i(sym) * kxo;
-            hy = mul_i(sym) * kyo;
-            hz = (A * ep - B * em) * gam;
-          } else {
-            hz = D * ep;
-          }
-          V[0][r] = V[0][r] - sv * kxo - hx;
-          V[1][r] = V[1][r] - sv * kyo - hy;
-          V[2][r] = V[2][r] - sv * kz - hz;
-          const long long gi = (long long)l * g.npen + p_me;
-#pragma unroll
-          for (int i = 0; i < 3; ++i) s.vout[i][gi] = V[i][r];
-          if (pm) Xo[e] = cvt<T>(conj(mul_mi(sv)));  // phi^I = -i s
-        } else if (e < tot && pm) {
-          Xo[e] = zero<T>();
-        }
-      }
-    } else if (pass == 1) {
-      // pressure in mixed space: (B_z(-i s) + phi^H) / c
-      if (valid_me)
-        for (int z = lt; z < g.nz; z += ZLS) {
-          const double zz = z * g.dz;
-          cpx<double> ph;
-          if (gam > 0.0)
-            ph = A * exp(gam * (zz - g.lz)) + B * exp(-gam * zz);
-          else
-            ph = D * zz;
-          s.pmix[(long long)z * g.npen + p_me] =
-              (conj(cvt<double>(R[z * ZPB + pb_me])) * inv + ph) * (1.0 / s.c);
-        }
-    } else {
-      const int i = (pass - 2) >> 1, dz = (pass - 2) & 1;
-      cpx<double>* __restrict__ dst = dz ? s.mdz[i] : s.mv[i];
-      if (valid_me)
-        for (int z = lt; z < g.nz; z += ZLS)
-          dst[(long long)z * g.npen + p_me] = conj(cvt<double>(R[z * ZPB + pb_me])) * inv;
-    }
-    __syncthreads();
+  // 3. F_z(e+ + i e-) (gamma = 0: F_z(1))
+  for (int z = lt; z < g.nz; z += ZLS) {
+    const double zz = z * g.dz;
+    L.X0[z * ZPB + pb_me] =
+        (gam > 0.0) ? mk((T)exp(gam * (zz - g.lz)), (T)exp(-gam * zz)) : mk((T)1, (T)0);
   }
+  __syncthreads();
+  z_extend<T>(L.X0, L.M, g.nz, g.C, g.d, tid);
+  __syncthreads();
+  const cpx<T>* R = fft_fwd<T, ZPB, BIG>(L.X0, L.X1, ZPB, 1, a.pl, L.tw, tid, ZNT);
+  cpx<T>* Xo = (R == L.X0) ? L.X1 : L.X0;
+  // 4. V = V* - k~ s - H^ (V* streamed again), store the continued state
+  for (int l = lt; l < g.npr; l += ZLS) {
+    const int e = l * ZPB + pb_me;
+    if (!valid_me) {
+      if (pm) Xo[e] = zero<T>();
+      continue;
+    }
+    const long long gi = (long long)l * g.npen + p_me;
+    const cpx<double> V0 = s.vs[0][gi], V1 = s.vs[1][gi], V2 = s.vs[2][gi];
+    const int lm = (l == 0) ? 0 : g.npr - l;
+    const cpx<double> xl = cvt<double>(R[e]), xm = conj(cvt<double>(R[lm * ZPB + pb_me]));
+    const cpx<double> ep = (xl + xm) * 0.5;
+    const cpx<double> em = mul_mi(xl - xm) * 0.5;
+    const double kz = k_odd(l, g.npr, g.kzs);
+    const double k2 = kh2 + kz * kz;
+    cpx<double> sv = zero<double>();
+    if (k2 > 0.0) sv = (V0 * kxo + V1 * kyo + V2 * kz) * (1.0 / k2);
+    cpx<double> hx = zero<double>(), hy = zero<double>(), hz;
+    if (gam > 0.0) {
+      const cpx<double> sym = A * ep + B * em;
+      hx = mul_i(sym) * kxo;
+      hy = mul_i(sym) * kyo;
+      hz = (A * ep - B * em) * gam;
+    } else {
+      hz = D * ep;
+    }
+    s.vout[0][gi] = V0 - sv * kxo - hx;
+    s.vout[1][gi] = V1 - sv * kyo - hy;
+    s.vout[2][gi] = V2 - sv * kz - hz;
+    if (pm) Xo[e] = cvt<T>(conj(mul_mi(sv)));  // phi^I = -i s, conjugated
+  }
+  if (!pm) return;
+  // 5. pressure in mixed space: (B_z(-i s) + phi^H) / c
+  __syncthreads();
+  const cpx<T>* P = fft_fwd<T, ZPB, BIG>(Xo, (Xo == L.X0) ? L.X1 : L.X0, ZPB, 1, a.pl, L.tw, tid,
+                                         ZNT);
+  if (valid_me)
+    for (int z = lt; z < g.nz; z += ZLS) {
+      const double zz = z * g.dz;
+      cpx<double> ph;
+      if (gam > 0.0)
+        ph = A * exp(gam * (zz - g.lz)) + B * exp(-gam * zz);
+      else
+        ph = D * zz;
+      s.pmix[(long long)z * g.npen + p_me] =
+          (conj(cvt<double>(P[z * ZPB + pb_me])) * inv + ph) * (1.0 / s.c);
+    }
 }
 
 // ---------------------------------------------------------------- fc_extend
@@ -507,7 +469,7 @@ __global__ __launch_bounds__(ZNT) void k_fc_derivative(ZArgs a, const double* __
   extern __shared__ __align__(16) char smem[];
   const int tid = threadIdx.x;
   const Geom& g = a.g;
-  const ZLds<double> L(smem, g);
+  const ZLds<double> L(smem, g, a.pl.tsize);
   z_setup<double>(L, a, tid);
   const long long q0 = (long long)blockIdx.x * ZPB;
   for (int e = tid; e < g.nz * ZPB; e += ZNT) {
@@ -568,7 +530,7 @@ int z_max_npr() { return 16 * ZNT / ZPB; }
 void launch_z_fwd(const ZArgs& a, bool big, const cpx<double>* src, cpx<double>* dst,
                   long long sfs, long long dfs, int nfields, int filter, hipStream_t st) {
   dim3 grid((unsigned)((a.g.npen + ZPB - 1) / ZPB), nfields);
-  const size_t sh = zshared_bytes<double>(a.g);
+  const size_t sh = zshared_bytes<double>(a.g, a.pl.tsize);
   if (big)
     FCNS_LAUNCH((k_z_fwd<double, true>), grid, dim3(ZNT), sh, st, a, src, dst, sfs, dfs, filter);
   else
@@ -579,7 +541,7 @@ void launch_z_back(const ZArgs& a, bool big, const cpx<double>* src, cpx<double>
                    cpx<double>* dzdst, long long sfs, long long mfs, int nfields,
                    hipStream_t st) {
   dim3 grid((unsigned)((a.g.npen + ZPB - 1) / ZPB), nfields);
-  const size_t sh = zshared_bytes<double>(a.g);
+  const size_t sh = zshared_bytes<double>(a.g, a.pl.tsize);
   const int own = pick_own(a.g.npr);
   if (big) {
     FCNS_OWN_SWITCH(own, FCNS_LAUNCH((k_z_back<double, true, OWN>), grid, dim3(ZNT), sh, st,
@@ -592,7 +554,7 @@ void launch_z_back(const ZArgs& a, bool big, const cpx<double>* src, cpx<double>
 
 void launch_z_stageA(const ZArgs& a, bool big, const StageAArgs& s, int nfields, hipStream_t st) {
   dim3 grid((unsigned)((a.g.npen + ZPB - 1) / ZPB), nfields);
-  const size_t sh = zshared_bytes<double>(a.g);
+  const size_t sh = zshared_bytes<double>(a.g, a.pl.tsize);
   const int own = pick_own(a.g.npr);
   if (big) {
     FCNS_OWN_SWITCH(own, FCNS_LAUNCH((k_z_stageA<double, true, OWN>), grid, dim3(ZNT), sh, st, a, s))
@@ -603,13 +565,11 @@ void launch_z_stageA(const ZArgs& a, bool big, const StageAArgs& s, int nfields,
 
 void launch_z_stageB(const ZArgs& a, bool big, const StageBArgs& s, hipStream_t st) {
   dim3 grid((unsigned)((a.g.npen + ZPB - 1) / ZPB), 1);
-  const size_t sh = zshared_bytes<double>(a.g);
-  const int own = pick_own(a.g.npr);
-  if (big) {
-    FCNS_OWN_SWITCH(own, FCNS_LAUNCH((k_z_stageB<double, true, OWN>), grid, dim3(ZNT), sh, st, a, s))
-  } else {
-    FCNS_OWN_SWITCH(own, FCNS_LAUNCH((k_z_stageB<double, false, OWN>), grid, dim3(ZNT), sh, st, a, s))
-  }
+  const size_t sh = zshared_bytes<double>(a.g, a.pl.tsize);
+  if (big)
+    FCNS_LAUNCH((k_z_stageB<double, true>), grid, dim3(ZNT), sh, st, a, s);
+  else
+    FCNS_LAUNCH((k_z_stageB<double, false>), grid, dim3(ZNT), sh, st, a, s);
 }
 
 void launch_fc_extend(const double* in, long long nlines, long long ips, long long ils, double* out,
@@ -626,13 +586,13 @@ void launch_fc_derivative(const ZArgs& a, bool big, const double* in, double* ou
                           hipStream_t st) {
   const long long nq = (nlines + 1) / 2;
   dim3 grid((unsigned)((nq + ZPB - 1) / ZPB));
-  const size_t sh = zshared_bytes<double>(a.g);
+  const size_t sh = zshared_bytes<double>(a.g, a.pl.tsize);
   if (big)
     FCNS_LAUNCH(k_fc_derivative<true>, grid, dim3(ZNT), sh, st, a, in, out, nlines, ps, ls, order);
   else
     FCNS_LAUNCH(k_fc_derivative<false>, grid, dim3(ZNT), sh, st, a, in, out, nlines, ps, ls, order);
 }
 
-size_t z_lds_bytes(const Geom& g) { return zshared_bytes<double>(g); }
+
 
 }  // namespace fcns
