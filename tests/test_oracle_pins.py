@@ -404,3 +404,92 @@ def test_wall_slip_second_order_in_dt():
         slips.append(math.sqrt(np.mean(v[0][0] ** 2) + np.mean(v[1][0] ** 2)))
     ratio = slips[0] / slips[1]
     assert 3.5 < ratio < 4.5, (slips, ratio)
+
+
+# ---------------------------------------------------------------- Rayleigh-Benard onset
+def _cheb(n):
+    # Chebyshev collocation points on [-1, 1] and the differentiation matrix
+    # (Trefethen, Spectral Methods in MATLAB, ch. 6)
+    x = np.cos(np.pi * np.arange(n + 1) / n)
+    c = np.r_[2.0, np.ones(n - 1), 2.0] * (-1.0) ** np.arange(n + 1)
+    dx = x[:, None] - x[None, :]
+    D = np.outer(c, 1.0 / c) / (dx + np.eye(n + 1))
+    return D - np.diag(D.sum(axis=1)), x
+
+
+def _rb_linear_mode(Ra, a, n=40):
+    """Leading eigenpair of the conductive state's linearisation, no-slip and
+    isothermal walls, Pr = 1, gamma = h = 1 (so nu = kappa = Ra^-1/2), for the
+    horizontal wavenumber a: with w, theta ~ exp(i a x + s t),
+    s (D^2 - a^2) w = nu (D^2 - a^2)^2 w - a^2 theta,
+    s theta = kappa (D^2 - a^2) theta + w,  w = Dw = theta = 0 at z = 0, 1.
+    An independent Chebyshev discretisation (boundary rows replace the
+    equations at the end points)."""
+    import scipy.linalg
+    D, x = _cheb(n)
+    z = (x + 1.0) / 2.0
+    Dz = 2.0 * D
+    m = n + 1
+    I = np.eye(m)
+    L = Dz @ Dz - a * a * I
+    nu = kap = Ra ** -0.5
+    A = np.zeros((2 * m, 2 * m))
+    B = np.zeros((2 * m, 2 * m))
+    A[:m, :m], A[:m, m:], B[:m, :m] = nu * L @ L, -a * a * I, L
+    A[m:, m:], A[m:, :m], B[m:, m:] = kap * L, I, I
+    zero = np.zeros(m)
+    for r, row in ((0, np.r_[I[0], zero]), (n, np.r_[I[n], zero]),
+                   (1, np.r_[Dz[0], zero]), (n - 1, np.r_[Dz[n], zero]),
+                   (m, np.r_[zero, I[0]]), (m + n, np.r_[zero, I[n]])):
+        A[r], B[r] = row, 0.0
+    ev, V = scipy.linalg.eig(A, B)
+    ok = np.isfinite(ev) & (np.abs(ev) < 1e3)    # drop the boundary rows' infinite ones
+    ev, V = ev[ok], V[:, ok]
+    k = int(np.argmax(ev.real))
+    return ev[k], V[:, k], z, Dz
+
+
+def test_linear_stability_solver_reproduces_textbook_onset():
+    # pins the eigen-solver used below: no-slip Rayleigh-Benard onset at
+    # a_c = 3.117 is Ra_c = 1707.76 (Chandrasekhar 1961), the value the
+    # Boussinesq runs of Sec. 7 are set against
+    lo, _, _, _ = _rb_linear_mode(1700.0, 3.117)
+    hi, _, _, _ = _rb_linear_mode(1716.0, 3.117)
+    assert abs(lo.imag) < 1e-9 and abs(hi.imag) < 1e-9       # stationary onset
+    assert lo.real < 0 < hi.real
+    ra_c = 1700.0 + 16.0 * (-lo.real) / (hi.real - lo.real)
+    assert abs(ra_c - 1707.76) < 0.2
+
+
+@pytest.mark.parametrize("Ra", [1500.0, 2500.0])
+def test_rayleigh_benard_onset_growth_rate(Ra):
+    # Sec. 7: the oracle's Boussinesq step started from the linear eigenmode
+    # of wavenumber a = pi (the 2:2:1 box's lowest, 0.8% from a_c) at small
+    # amplitude decays below onset and grows above it, at the rate of the
+    # independent linear solver (a wrong buoyancy sign gives oscillation, a
+    # dropped buoyancy term pure diffusion)
+    a, nx, ny, nz, dt, T = np.pi, 8, 2, 33, 5e-3, 2.0
+    s, V, zc, Dz = _rb_linear_mode(Ra, a)
+    m = len(zc)
+    w, th = V[:m].real, V[m:].real
+    cheb = np.polynomial.chebyshev
+    z = np.linspace(0.0, 1.0, nz)
+    interp = lambda f: cheb.chebval(2 * z - 1, cheb.chebfit(2 * zc - 1, f, m - 1))
+    sc = 1e-6 / np.abs(w).max()
+    wz, dwz, thz = interp(w) * sc, interp(Dz @ w) * sc, interp(th) * sc
+    xg = np.arange(nx) * 2.0 / nx
+    v = np.zeros((3, nz, ny, nx))
+    v[0] = (-dwz / a)[:, None, None] * np.sin(a * xg)      # continuity: a u = -Dw
+    v[2] = wz[:, None, None] * np.cos(a * xg)
+    theta = thz[:, None, None] * np.cos(a * xg) * np.ones((1, ny, 1))
+    nu = Ra ** -0.5
+    o = Oracle(Problem(nx=nx, ny=ny, nz=nz, lx=2.0, ly=2.0, lz=1.0, nu=nu, C=25,
+                       boussinesq=True, kappa=nu, gamma=1.0))
+    o.set_state(v, theta)
+    o.rk_step(dt, int(round(T / dt)))
+    v1, th1, _ = o.get_state()
+    rate = math.log(np.linalg.norm(th1) / np.linalg.norm(theta)) / T
+    rate_w = math.log(np.linalg.norm(v1[2]) / np.linalg.norm(v[2])) / T
+    assert (rate > 0) == (Ra > 1707.76)
+    assert abs(rate - s.real) < 1e-3 * abs(s.real)
+    assert abs(rate_w - s.real) < 1e-3 * abs(s.real)
