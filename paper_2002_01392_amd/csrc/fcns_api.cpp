@@ -257,7 +257,6 @@ extern "C" fcns_status fcns_create(const fcns_problem* prob, void* hip_stream, f
   const int npr = p.nz + p.fc_C;
   if (npr > z_max_npr()) return fail(nullptr, FCNS_EINVAL, "N' = nz + C must be <= 512");
 
-  if (const char* v = getenv("FCNS_XNL_VARIANT")) x_nl_variant = atoi(v);
   fcns_ctx* c = new fcns_ctx();
   c->prob = p;
   c->prob.fc_table = nullptr;
@@ -287,6 +286,10 @@ extern "C" fcns_status fcns_create(const fcns_problem* prob, void* hip_stream, f
       !make_plan(p.ny, c->ply, c->big_y, twy)) {
     delete c;
     return fail(nullptr, FCNS_EINVAL, "unsupported transform length (more than 12 radix stages)");
+  }
+  if (y_lds_bytes(p.ny, c->ply.tsize) > 160 * 1024) {
+    delete c;
+    return fail(nullptr, FCNS_EINVAL, "ny too large for the y pass (its lines must fit in LDS)");
   }
 
   // M_r = A_r Q_r^T in extended precision (App. B)

@@ -55,27 +55,23 @@ struct Codelet;
 
 template <typename T>
 struct Codelet<T, 2> {
-  __device__ __forceinline__ static void run(cpx<T>* v, cpx<T>* dst, int os, const cpx<T>*) {
-    dst[0] = v[0] + v[1];
-    dst[os] = v[0] - v[1];
+  __device__ __forceinline__ static void run(cpx<T>* v, const cpx<T>*) {
+    const cpx<T> a = v[0], b = v[1];
+    v[0] = a + b;
+    v[1] = a - b;
   }
 };
 
 template <typename T>
 struct Codelet<T, 4> {
-  __device__ __forceinline__ static void run(cpx<T>* v, cpx<T>* dst, int os, const cpx<T>*) {
-    cpx<T> a0 = v[0], a1 = v[1], a2 = v[2], a3 = v[3];
-    dft4_reg<T>(a0, a1, a2, a3);
-    dst[0] = a0;
-    dst[os] = a1;
-    dst[2 * os] = a2;
-    dst[3 * os] = a3;
+  __device__ __forceinline__ static void run(cpx<T>* v, const cpx<T>*) {
+    dft4_reg<T>(v[0], v[1], v[2], v[3]);
   }
 };
 
 template <typename T>
 struct Codelet<T, 8> {
-  __device__ __forceinline__ static void run(cpx<T>* v, cpx<T>* dst, int os, const cpx<T>*) {
+  __device__ __forceinline__ static void run(cpx<T>* v, const cpx<T>*) {
     // n = n1 + 4 n2: even outputs from a = x_n1 + x_n1+4, odd outputs from
     // b = (x_n1 - x_n1+4) w8^n1, w8 = exp(-i pi/4)
     const T h = T(0.70710678118654752440084436210484903928483593768847);
@@ -86,21 +82,23 @@ struct Codelet<T, 8> {
     b3 = mk((b3.y - b3.x) * h, -(b3.x + b3.y) * h);
     dft4_reg<T>(a0, a1, a2, a3);
     dft4_reg<T>(b0, b1, b2, b3);
-    dst[0] = a0;
-    dst[2 * os] = a1;
-    dst[4 * os] = a2;
-    dst[6 * os] = a3;
-    dst[os] = b0;
-    dst[3 * os] = b1;
-    dst[5 * os] = b2;
-    dst[7 * os] = b3;
+    v[0] = a0;
+    v[2] = a1;
+    v[4] = a2;
+    v[6] = a3;
+    v[1] = b0;
+    v[3] = b1;
+    v[5] = b2;
+    v[7] = b3;
   }
 };
 
-// Odd prime P in registers.  cw: the P roots exp(-2 pi i q / P).
+// Odd prime P in registers.  cw: the P roots exp(-2 pi i q / P).  The inputs
+// are consumed into the sums a and differences b before any output is
+// written back, so the transform runs in place.
 template <typename T, int P>
 struct CodeletOdd {
-  __device__ __forceinline__ static void run(cpx<T>* v, cpx<T>* dst, int os, const cpx<T>* cw) {
+  __device__ __forceinline__ static void run(cpx<T>* v, const cpx<T>* cw) {
     constexpr int H = (P - 1) / 2;
     cpx<T> a[H], b[H];
     const cpx<T> x0 = v[0];
@@ -111,7 +109,7 @@ struct CodeletOdd {
       b[q - 1] = v[q] - v[P - q];
       s = s + a[q - 1];
     }
-    dst[0] = s;
+    v[0] = s;
 #pragma unroll
     for (int k = 1; k <= H; ++k) {
       cpx<T> re = x0, im = zero<T>();
@@ -122,8 +120,8 @@ struct CodeletOdd {
         im = im + b[q - 1] * (-w.y);
       }
       // X_k = re - i im, X_{P-k} = re + i im
-      dst[k * os] = re + mul_mi(im);
-      dst[(P - k) * os] = re + mul_i(im);
+      v[k] = re + mul_mi(im);
+      v[P - k] = re + mul_i(im);
     }
   }
 };
@@ -143,8 +141,18 @@ __device__ __forceinline__ int fast_mod(int j, int ns, float rcp) {
   return r;
 }
 
+// Position of element i of line l: l * ls + es * i, or with PAD one spare
+// slot after every 8 elements, l * ls + es * (i + i / 8).  The padding makes
+// the stride-R stores of the first stage hit distinct LDS banks when lines
+// are contiguous (es = 1) or interleaved by fewer than 8 (es < 8); a padded
+// line of n points spans es * (n + n / 8) slots.
+template <bool PAD>
+__device__ __forceinline__ int lds_pos(int l, int i, int es, int ls) {
+  return l * ls + es * (PAD ? i + (i >> 3) : i);
+}
+
 // ---------------------------------------------------------------- one stage
-template <typename T, int R>
+template <typename T, int R, bool PAD>
 __device__ __forceinline__ void fft_stage(const cpx<T>* __restrict__ src, cpx<T>* __restrict__ dst,
                                           int L, int es, int ls, int n, int ns,
                                           const cpx<T>* __restrict__ tws,
@@ -155,21 +163,23 @@ __device__ __forceinline__ void fft_stage(const cpx<T>* __restrict__ src, cpx<T>
   for (int g = tid; g < nb; g += nt) {
     const int l = g % L, j = g / L;
     const int k = fast_mod(j, ns, rcp);
-    const cpx<T>* s = src + l * ls + j * es;
     cpx<T> v[R];
 #pragma unroll
-    for (int m = 0; m < R; ++m) v[m] = s[m * nr * es];
+    for (int m = 0; m < R; ++m) v[m] = src[lds_pos<PAD>(l, j + m * nr, es, ls)];
     if (ns > 1) {
 #pragma unroll
       for (int m = 1; m < R; ++m) v[m] = v[m] * tws[(m - 1) * ns + k];
     }
-    Codelet<T, R>::run(v, dst + l * ls + ((j - k) * R + k) * es, ns * es, cw);
+    Codelet<T, R>::run(v, cw);
+    const int o = (j - k) * R + k;
+#pragma unroll
+    for (int m = 0; m < R; ++m) dst[lds_pos<PAD>(l, o + m * ns, es, ls)] = v[m];
   }
 }
 
 // Any odd prime R at run time: twiddle the butterfly's own inputs in place in
 // src (no other thread reads them), then form each output pair from LDS.
-template <typename T>
+template <typename T, bool PAD>
 __device__ __forceinline__ void fft_stage_prime(cpx<T>* __restrict__ src, cpx<T>* __restrict__ dst,
                                                 int R, int L, int es, int ls, int n, int ns,
                                                 const cpx<T>* __restrict__ tws,
@@ -181,16 +191,15 @@ __device__ __forceinline__ void fft_stage_prime(cpx<T>* __restrict__ src, cpx<T>
   for (int g = tid; g < nb; g += nt) {
     const int l = g % L, j = g / L;
     const int k = fast_mod(j, ns, rcp);
-    cpx<T>* s = src + l * ls + j * es;
-    const int is = nr * es;
+    auto S = [&](int m) -> cpx<T>& { return src[lds_pos<PAD>(l, j + m * nr, es, ls)]; };
+    const int o = (j - k) * R + k;
+    auto D = [&](int m) -> cpx<T>& { return dst[lds_pos<PAD>(l, o + m * ns, es, ls)]; };
     if (ns > 1)
-      for (int m = 1; m < R; ++m) s[m * is] = s[m * is] * tws[(m - 1) * ns + k];
-    cpx<T>* d = dst + l * ls + ((j - k) * R + k) * es;
-    const int os = ns * es;
-    const cpx<T> x0 = s[0];
+      for (int m = 1; m < R; ++m) S(m) = S(m) * tws[(m - 1) * ns + k];
+    const cpx<T> x0 = S(0);
     cpx<T> sum = x0;
-    for (int q = 1; q <= H; ++q) sum = sum + s[q * is] + s[(R - q) * is];
-    d[0] = sum;
+    for (int q = 1; q <= H; ++q) sum = sum + S(q) + S(R - q);
+    D(0) = sum;
     for (int kk = 1; kk <= H; ++kk) {
       cpx<T> re = x0, im = zero<T>();
       int qk = 0;
@@ -198,12 +207,12 @@ __device__ __forceinline__ void fft_stage_prime(cpx<T>* __restrict__ src, cpx<T>
         qk += kk;
         if (qk >= R) qk -= R;
         const cpx<T> w = cw[qk];
-        const cpx<T> xa = s[q * is], xb = s[(R - q) * is];
+        const cpx<T> xa = S(q), xb = S(R - q);
         re = re + (xa + xb) * w.x;
         im = im + (xa - xb) * (-w.y);
       }
-      d[kk * os] = re + mul_mi(im);
-      d[(R - kk) * os] = re + mul_i(im);
+      D(kk) = re + mul_mi(im);
+      D(R - kk) = re + mul_i(im);
     }
   }
 }
@@ -214,8 +223,8 @@ __device__ __forceinline__ void fft_stage_prime(cpx<T>* __restrict__ src, cpx<T>
 // Returns the buffer holding the result.  All threads of the workgroup must
 // call it, after a barrier that makes the input visible; it synchronises
 // before returning.  BIG: also dispatch radix 29, 47 and the run-time
-// odd-prime stage.
-template <typename T, int L, bool BIG>
+// odd-prime stage.  PAD: padded line layout (lds_pos).
+template <typename T, int L, bool BIG, bool PAD = false>
 __device__ __forceinline__ cpx<T>* fft_fwd(cpx<T>* buf0, cpx<T>* buf1, int es, int ls,
                                            const FFTPlan& pl, const cpx<T>* __restrict__ tw,
                                            int tid, int nt) {
@@ -228,20 +237,20 @@ __device__ __forceinline__ cpx<T>* fft_fwd(cpx<T>* buf0, cpx<T>* buf1, int es, i
     const cpx<T>* tws = tw + (pl.toff[s] < 0 ? 0 : pl.toff[s]);
     const cpx<T>* cw = tw + (pl.coff[s] < 0 ? 0 : pl.coff[s]);
     switch (r) {
-      case 2: fft_stage<T, 2>(src, dst, L, es, ls, n, ns, tws, cw, tid, nt); break;
-      case 3: fft_stage<T, 3>(src, dst, L, es, ls, n, ns, tws, cw, tid, nt); break;
-      case 4: fft_stage<T, 4>(src, dst, L, es, ls, n, ns, tws, cw, tid, nt); break;
-      case 5: fft_stage<T, 5>(src, dst, L, es, ls, n, ns, tws, cw, tid, nt); break;
-      case 7: fft_stage<T, 7>(src, dst, L, es, ls, n, ns, tws, cw, tid, nt); break;
-      case 8: fft_stage<T, 8>(src, dst, L, es, ls, n, ns, tws, cw, tid, nt); break;
+      case 2: fft_stage<T, 2, PAD>(src, dst, L, es, ls, n, ns, tws, cw, tid, nt); break;
+      case 3: fft_stage<T, 3, PAD>(src, dst, L, es, ls, n, ns, tws, cw, tid, nt); break;
+      case 4: fft_stage<T, 4, PAD>(src, dst, L, es, ls, n, ns, tws, cw, tid, nt); break;
+      case 5: fft_stage<T, 5, PAD>(src, dst, L, es, ls, n, ns, tws, cw, tid, nt); break;
+      case 7: fft_stage<T, 7, PAD>(src, dst, L, es, ls, n, ns, tws, cw, tid, nt); break;
+      case 8: fft_stage<T, 8, PAD>(src, dst, L, es, ls, n, ns, tws, cw, tid, nt); break;
       default:
         if constexpr (BIG) {
           if (r == 29)
-            fft_stage<T, 29>(src, dst, L, es, ls, n, ns, tws, cw, tid, nt);
+            fft_stage<T, 29, PAD>(src, dst, L, es, ls, n, ns, tws, cw, tid, nt);
           else if (r == 47)
-            fft_stage<T, 47>(src, dst, L, es, ls, n, ns, tws, cw, tid, nt);
+            fft_stage<T, 47, PAD>(src, dst, L, es, ls, n, ns, tws, cw, tid, nt);
           else
-            fft_stage_prime<T>(src, dst, r, L, es, ls, n, ns, tws, cw, tid, nt);
+            fft_stage_prime<T, PAD>(src, dst, r, L, es, ls, n, ns, tws, cw, tid, nt);
         }
         break;
     }
@@ -252,6 +261,87 @@ __device__ __forceinline__ cpx<T>* fft_fwd(cpx<T>* buf0, cpx<T>* buf1, int es, i
     ns *= r;
   }
   return src;
+}
+
+// ---------------------------------------------------------------- compile-time plans
+// A transform length known at compile time: the radices (in the order the
+// host plan builder uses, so the twiddle table layout is the same), and with
+// them every stride, loop bound and modulus of a stage, which turns the index
+// arithmetic of the run-time engine into shifts and constants.  DynPlan<BIG>
+// selects the run-time engine instead.
+template <int... Rs>
+struct SPlan {
+  static constexpr bool dynamic = false;
+  static constexpr int n = (Rs * ... * 1);
+  static constexpr int nst = sizeof...(Rs);
+  static constexpr bool big = false;
+};
+
+template <bool BIG>
+struct DynPlan {
+  static constexpr bool dynamic = true;
+  static constexpr int n = 0;
+  static constexpr bool big = BIG;
+};
+
+template <typename T, int R, int NS, int N, int L, int NT, bool PAD>
+__device__ __forceinline__ void sfft_stage(const cpx<T>* __restrict__ src, cpx<T>* __restrict__ dst,
+                                           int es, int ls, const cpx<T>* __restrict__ tws,
+                                           const cpx<T>* __restrict__ cw, int tid) {
+  constexpr int NR = N / R;
+  constexpr int NB = L * NR;
+  constexpr int IT = (NB + NT - 1) / NT;
+#pragma unroll
+  for (int it = 0; it < IT; ++it) {
+    const int g = tid + it * NT;
+    if (NB % NT == 0 || g < NB) {
+      const int l = g % L, j = g / L;
+      const int k = j % NS;
+      cpx<T> v[R];
+#pragma unroll
+      for (int m = 0; m < R; ++m) v[m] = src[lds_pos<PAD>(l, j + m * NR, es, ls)];
+      if constexpr (NS > 1) {
+#pragma unroll
+        for (int m = 1; m < R; ++m) v[m] = v[m] * tws[(m - 1) * NS + k];
+      }
+      Codelet<T, R>::run(v, cw);
+      const int o = (j - k) * R + k;
+#pragma unroll
+      for (int m = 0; m < R; ++m) dst[lds_pos<PAD>(l, o + m * NS, es, ls)] = v[m];
+    }
+  }
+}
+
+template <typename T, int L, int NT, bool PAD, int N, int S, int NS, int R, int... Rest>
+__device__ __forceinline__ cpx<T>* sfft_from(cpx<T>* src, cpx<T>* dst, int es, int ls,
+                                             const FFTPlan& pl, const cpx<T>* __restrict__ tw,
+                                             int tid) {
+  const cpx<T>* tws = tw + (NS > 1 ? pl.toff[S] : 0);
+  const cpx<T>* cw = tw + ((R & 1) ? pl.coff[S] : 0);
+  sfft_stage<T, R, NS, N, L, NT, PAD>(src, dst, es, ls, tws, cw, tid);
+  __syncthreads();
+  if constexpr (sizeof...(Rest) == 0)
+    return dst;
+  else
+    return sfft_from<T, L, NT, PAD, N, S + 1, NS * R, Rest...>(dst, src, es, ls, pl, tw, tid);
+}
+
+template <typename T, int L, int NT, bool PAD, int... Rs>
+__device__ __forceinline__ cpx<T>* sfft(SPlan<Rs...>, cpx<T>* buf0, cpx<T>* buf1, int es, int ls,
+                                        const FFTPlan& pl, const cpx<T>* __restrict__ tw, int tid) {
+  return sfft_from<T, L, NT, PAD, SPlan<Rs...>::n, 0, 1, Rs...>(buf0, buf1, es, ls, pl, tw, tid);
+}
+
+// Forward FFT with plan FP (SPlan<...> or DynPlan<BIG>), NT threads; same
+// contract as fft_fwd.
+template <typename T, int L, int NT, bool PAD, class FP>
+__device__ __forceinline__ cpx<T>* fft_run(cpx<T>* buf0, cpx<T>* buf1, int es, int ls,
+                                           const FFTPlan& pl, const cpx<T>* __restrict__ tw,
+                                           int tid) {
+  if constexpr (FP::dynamic)
+    return fft_fwd<T, L, FP::big, PAD>(buf0, buf1, es, ls, pl, tw, tid, NT);
+  else
+    return sfft<T, L, NT, PAD>(FP{}, buf0, buf1, es, ls, pl, tw, tid);
 }
 
 }  // namespace fcns

@@ -3,6 +3,8 @@
 #include "fcns_common.hpp"
 #include "fft_lds.hpp"
 
+#include <initializer_list>
+
 namespace fcns {
 
 // z kernels: ZPB pencils per workgroup of ZNT threads
@@ -16,6 +18,15 @@ constexpr long long Y_GRID = 1024;  // persistent y workgroups per field
 // x kernels: XR rows per workgroup (XR/2 complex lines); nx <= XNT
 constexpr int XR = 8;
 constexpr int XNT = 512;
+
+// Does the run-time plan have exactly these radices (in this order)?
+inline bool plan_is(const FFTPlan& pl, std::initializer_list<int> rs) {
+  if (pl.nst != (int)rs.size()) return false;
+  int s = 0;
+  for (int r : rs)
+    if (pl.r[s++] != r) return false;
+  return true;
+}
 
 struct ZArgs {
   Geom g;
@@ -63,6 +74,7 @@ struct XArgs {
 };
 
 int z_max_npr();
+size_t y_lds_bytes(int ny, int tsize);  // LDS of one y-pass workgroup
 size_t z_lds_bytes(const Geom& g);
 
 // Dynamic LDS above 64 KiB needs an explicit per-kernel opt-in.
@@ -110,7 +122,6 @@ void launch_x_c2r(const XArgs& a, bool big, const cpx<double>* xy, double* phys,
 // field slots 3f, 3f+1, 3f+2; nl gets -(v.grad) q_f at slot f.
 void launch_x_nl(const XArgs& a, bool big, const cpx<double>* xyb, cpx<double>* nl,
                  long long fstride, long long nrows, int nfields, hipStream_t st);
-extern int x_nl_variant;  // tile shape of the x pass (tuning)
 
 // small helpers
 void launch_fill(cpx<double>* p, long long n, hipStream_t st);

@@ -12,21 +12,29 @@ namespace fcns {
 
 // ---------------------------------------------------------------- y pass
 // Lines q = plane * nkxp + kx; a tile is YL consecutive lines, staged in LDS
-// as X[ky * YL + l].  Each thread keeps one line of the tile (l = tid % YL,
+// interleaved (element ky of line l at lds_pos<true>(l, ky, YL, 1), y_span
+// slots per buffer).  Each thread keeps one line of the tile (l = tid % YL,
 // YNT being a multiple of YL) and the rows ky = tid / YL + r * YNT / YL.
 // Workgroups loop over tiles and load the next tile into registers before
 // transforming the current one, so the loads overlap the FFT.  mode 1
 // (inverse only): a second pass transforms i k~y times the input into dst2.
-template <typename T, bool BIG, int OWN>
+__host__ __device__ inline int y_span(int ny) { return YL * (ny + ny / 8 + 1); }
+
+size_t y_lds_bytes(int ny, int tsize) {
+  return ((size_t)tsize + 2 * (size_t)y_span(ny)) * sizeof(cpx<double>);
+}
+
+template <typename T, class FP, int OWN>
 __global__ __launch_bounds__(YNT) void k_y(YArgs a, const cpx<double>* src, cpx<double>* dst,
                                            cpx<double>* dst2, long long sfs, long long dfs,
                                            long long nlines, int inv, int mode) {
   extern __shared__ __align__(16) char smem[];
   const int tid = threadIdx.x;
-  const int ny = a.ny, nkx = a.nkx, nkxp = a.nkxp;
+  const int ny = FP::dynamic ? a.ny : FP::n;
+  const int nkx = a.nkx, nkxp = a.nkxp;
   cpx<T>* tw = reinterpret_cast<cpx<T>*>(smem);
   cpx<T>* X0 = tw + a.pl.tsize;
-  cpx<T>* X1 = X0 + ny * YL;
+  cpx<T>* X1 = X0 + y_span(ny);
   src += blockIdx.y * sfs;
   dst += blockIdx.y * dfs;
   if (mode == 1) dst2 += blockIdx.y * dfs;
@@ -71,18 +79,18 @@ __global__ __launch_bounds__(YNT) void k_y(YArgs a, const cpx<double>* src, cpx<
         if (ky < ny) {
           cpx<double> v = cur[r];
           if (pass == 1) v = mul_i(v) * k_odd(ky, ny, a.kys);
-          X0[ky * YL + l] = cvt<T>(inv ? conj(v) : v);
+          X0[lds_pos<true>(l, ky, YL, 1)] = cvt<T>(inv ? conj(v) : v);
         }
       }
       __syncthreads();
-      const cpx<T>* R = fft_fwd<T, YL, BIG>(X0, X1, YL, 1, a.pl, tw, tid, YNT);
+      const cpx<T>* R = fft_run<T, YL, YNT, true, FP>(X0, X1, YL, 1, a.pl, tw, tid);
       cpx<double>* out = pass ? dst2 : dst;
       if (ok) {
 #pragma unroll
         for (int r = 0; r < OWN; ++r) {
           const int ky = ky0 + r * KYS;
           if (ky < ny) {
-            const cpx<double> v = cvt<double>(R[ky * YL + l]);
+            const cpx<double> v = cvt<double>(R[lds_pos<true>(l, ky, YL, 1)]);
             out[base + (long long)ky * nkxp] = (inv ? conj(v) : v) * sc;
           }
         }
@@ -96,10 +104,14 @@ __global__ __launch_bounds__(YNT) void k_y(YArgs a, const cpx<double>* src, cpx<
 
 // ---------------------------------------------------------------- x helpers
 // Rows r0..r0+XR-1; two real rows (2a, 2a+1) share complex line a:
-// z[n] = x_2a[n] + i x_2a+1[n], staged in LDS line-contiguous as
-// X[a * ls + n] with the odd stride ls = nx + 1 (conflict-free banks for the
-// line-fastest thread mapping of the FFT).
+// z[n] = x_2a[n] + i x_2a+1[n], staged in LDS line-contiguous with the padded
+// layout of the FFT engine, element n of line a at xp(a, n) (line stride
+// x_ls(nx) = 4 mod 8 slots, so the lines interleaved by the thread mapping
+// fall on different banks).
 constexpr int XL = XR / 2;
+
+__host__ __device__ inline int x_ls(int nx) { return ((nx + nx / 8 + 7) / 8) * 8 + 4; }
+__device__ __forceinline__ int xp(int a, int n, int ls) { return lds_pos<true>(a, n, 1, ls); }
 
 // Pack the spectra A (row 2a), B (row 2a+1) of two real rows into the
 // conjugate of the full spectrum of z = x_2a + i x_2a+1 (ready for the inverse
@@ -127,8 +139,8 @@ __device__ __forceinline__ void x_pack_c2r(cpx<T>* X, int ls, const cpx<double>*
         B.y = 0.0;
       }
       // Z[k] = A + i B, Z[nx - k] = conj(A) + i conj(B); store conjugates
-      X[al * ls + k] = cvt<T>(conj(mk(A.x - B.y, A.y + B.x)));
-      if (k > 0 && 2 * k < nx) X[al * ls + nx - k] = cvt<T>(conj(mk(A.x + B.y, B.x - A.y)));
+      X[xp(al, k, ls)] = cvt<T>(conj(mk(A.x - B.y, A.y + B.x)));
+      if (k > 0 && 2 * k < nx) X[xp(al, nx - k, ls)] = cvt<T>(conj(mk(A.x + B.y, B.x - A.y)));
     }
   }
 }
@@ -143,8 +155,8 @@ __device__ __forceinline__ void x_unpack_r2c(const cpx<T>* X, int ls, cpx<double
   for (int al = 0; al < XL; ++al) {
     const long long ra = r0 + 2 * al, rb = ra + 1;
     for (int k = tid; k < nkx; k += XNT) {
-      const cpx<double> Z = cvt<double>(X[al * ls + k]);
-      const cpx<double> Zm = conj(cvt<double>(X[al * ls + ((k == 0) ? 0 : nx - k)]));
+      const cpx<double> Z = cvt<double>(X[xp(al, k, ls)]);
+      const cpx<double> Zm = conj(cvt<double>(X[xp(al, ((k == 0) ? 0 : nx - k), ls)]));
       if (ra < nrows) xy[ra * nkxp + k] = (Z + Zm) * 0.5;
       if (rb < nrows) xy[rb * nkxp + k] = mul_mi(Z - Zm) * 0.5;
     }
@@ -158,7 +170,7 @@ __global__ __launch_bounds__(XNT) void k_x_r2c(XArgs a, const double* __restrict
                                                long long xfs, long long nrows) {
   extern __shared__ __align__(16) char smem[];
   const int tid = threadIdx.x;
-  const int nx = a.nx, ls = nx + 1;
+  const int nx = a.nx, ls = x_ls(nx);
   cpx<T>* tw = reinterpret_cast<cpx<T>*>(smem);
   cpx<T>* X0 = tw + a.pl.tsize;
   cpx<T>* X1 = X0 + XL * ls;
@@ -172,10 +184,10 @@ __global__ __launch_bounds__(XNT) void k_x_r2c(XArgs a, const double* __restrict
   for (int rl = 0; rl < XR; ++rl) {
     const long long r = r0 + rl;
     for (int n = tid; n < nx; n += XNT)
-      Xs[2 * ((rl >> 1) * ls + n) + (rl & 1)] = (r < nrows) ? (T)phys[r * nx + n] : T(0);
+      Xs[2 * xp(rl >> 1, n, ls) + (rl & 1)] = (r < nrows) ? (T)phys[r * nx + n] : T(0);
   }
   __syncthreads();
-  const cpx<T>* R = fft_fwd<T, XL, BIG>(X0, X1, 1, ls, a.pl, tw, tid, XNT);
+  const cpx<T>* R = fft_fwd<T, XL, BIG, true>(X0, X1, 1, ls, a.pl, tw, tid, XNT);
   x_unpack_r2c<T>(R, ls, xy, r0, nrows, a, tid);
 }
 
@@ -185,7 +197,7 @@ __global__ __launch_bounds__(XNT) void k_x_c2r(XArgs a, const cpx<double>* __res
                                                long long pfs, long long nrows) {
   extern __shared__ __align__(16) char smem[];
   const int tid = threadIdx.x;
-  const int nx = a.nx, ls = nx + 1;
+  const int nx = a.nx, ls = x_ls(nx);
   cpx<T>* tw = reinterpret_cast<cpx<T>*>(smem);
   cpx<T>* X0 = tw + a.pl.tsize;
   cpx<T>* X1 = X0 + XL * ls;
@@ -196,14 +208,14 @@ __global__ __launch_bounds__(XNT) void k_x_c2r(XArgs a, const cpx<double>* __res
   const long long r0 = (long long)blockIdx.x * XR;
   x_pack_c2r<T>(X0, ls, xy, r0, nrows, a, false, tid);
   __syncthreads();
-  const cpx<T>* R = fft_fwd<T, XL, BIG>(X0, X1, 1, ls, a.pl, tw, tid, XNT);
+  const cpx<T>* R = fft_fwd<T, XL, BIG, true>(X0, X1, 1, ls, a.pl, tw, tid, XNT);
   const double sc = 1.0 / nx;
 #pragma unroll
   for (int al = 0; al < XL; ++al) {
     const long long ra = r0 + 2 * al, rb = ra + 1;
     for (int n = tid; n < nx; n += XNT) {
       // z = conj(R) / nx: row 2a = Re z, row 2a+1 = Im z
-      const cpx<T> z = R[al * ls + n];
+      const cpx<T> z = R[xp(al, n, ls)];
       if (ra < nrows) phys[ra * nx + n] = (double)z.x * sc;
       if (rb < nrows) phys[rb * nx + n] = -(double)z.y * sc;
     }
@@ -218,14 +230,16 @@ __global__ __launch_bounds__(XNT) void k_x_c2r(XArgs a, const cpx<double>* __res
 // A workgroup of NT threads owns spectral columns k = tid + c NT and physical
 // columns n = tid + c NT (c < CC, CC NT >= nx) of its RR rows; each thread
 // loads the next pass's spectral inputs while the current pass is transformed.
-template <typename T, bool BIG, int RR, int NT, int CC>
+template <typename T, class FP, int RR, int NT, int CC>
 __global__ __launch_bounds__(NT) void k_x_nl(XArgs a, const cpx<double>* __restrict__ xyb,
                                              cpx<double>* __restrict__ nl, long long fs,
                                              long long nrows, int nfields) {
   constexpr int LL = RR / 2;
   extern __shared__ __align__(16) char smem[];
   const int tid = threadIdx.x;
-  const int nx = a.nx, nkx = a.nkx, nkxp = a.nkxp, ls = nx + 1;
+  // with a compile-time plan every row length below is a constant
+  const int nx = FP::dynamic ? a.nx : FP::n;
+  const int nkx = nx / 2 + 1, nkxp = (nkx + 3) / 4 * 4, ls = x_ls(nx);
   cpx<T>* tw = reinterpret_cast<cpx<T>*>(smem);
   cpx<T>* X0 = tw + a.pl.tsize;
   cpx<T>* X1 = X0 + LL * ls;
@@ -278,8 +292,8 @@ __global__ __launch_bounds__(NT) void k_x_nl(XArgs a, const cpx<double>* __restr
               B.y = 0.0;
             }
             // Z[k] = A + i B, Z[nx - k] = conj(A) + i conj(B); stored conjugated
-            X0[al * ls + k] = cvt<T>(conj(mk(A.x - B.y, A.y + B.x)));
-            if (k > 0 && 2 * k < nx) X0[al * ls + nx - k] = cvt<T>(conj(mk(A.x + B.y, B.x - A.y)));
+            X0[xp(al, k, ls)] = cvt<T>(conj(mk(A.x - B.y, A.y + B.x)));
+            if (k > 0 && 2 * k < nx) X0[xp(al, nx - k, ls)] = cvt<T>(conj(mk(A.x + B.y, B.x - A.y)));
           }
         }
       }
@@ -290,7 +304,7 @@ __global__ __launch_bounds__(NT) void k_x_nl(XArgs a, const cpx<double>* __restr
         if (n < nx) {
 #pragma unroll
           for (int al = 0; al < LL; ++al)
-            X0[al * ls + n] = mk((T)acc[c][2 * al], (T)acc[c][2 * al + 1]);
+            X0[xp(al, n, ls)] = mk((T)acc[c][2 * al], (T)acc[c][2 * al + 1]);
         }
       }
     }
@@ -299,7 +313,7 @@ __global__ __launch_bounds__(NT) void k_x_nl(XArgs a, const cpx<double>* __restr
     if (pn < npass && slot(pn) < 0) ++pn;
     if (pn < npass) load(pn);
     __syncthreads();
-    const cpx<T>* R = fft_fwd<T, LL, BIG>(X0, X1, 1, ls, a.pl, tw, tid, NT);
+    const cpx<T>* R = fft_run<T, LL, NT, true, FP>(X0, X1, 1, ls, a.pl, tw, tid);
     if (!fwd) {
 #pragma unroll
       for (int c = 0; c < CC; ++c) {
@@ -308,7 +322,7 @@ __global__ __launch_bounds__(NT) void k_x_nl(XArgs a, const cpx<double>* __restr
         double v[RR];
 #pragma unroll
         for (int al = 0; al < LL; ++al) {
-          const cpx<T> z = R[al * ls + n];
+          const cpx<T> z = R[xp(al, n, ls)];
           v[2 * al] = (double)z.x * sc;
           v[2 * al + 1] = -(double)z.y * sc;
         }
@@ -335,8 +349,8 @@ __global__ __launch_bounds__(NT) void k_x_nl(XArgs a, const cpx<double>* __restr
         const long long ra = r0 + 2 * al, rb = ra + 1;
         cpx<double>* dst = nl + f * fs;
         for (int k = tid; k < nkx; k += NT) {
-          const cpx<double> Z = cvt<double>(R[al * ls + k]);
-          const cpx<double> Zm = conj(cvt<double>(R[al * ls + ((k == 0) ? 0 : nx - k)]));
+          const cpx<double> Z = cvt<double>(R[xp(al, k, ls)]);
+          const cpx<double> Zm = conj(cvt<double>(R[xp(al, ((k == 0) ? 0 : nx - k), ls)]));
           if (ra < nrows) dst[ra * nkxp + k] = (Z + Zm) * 0.5;
           if (rb < nrows) dst[rb * nkxp + k] = mul_mi(Z - Zm) * 0.5;
         }
@@ -377,16 +391,22 @@ void launch_y(const YArgs& a, bool big, bool inv, int mode, const cpx<double>* s
   const long long nlines = (long long)nplanes * a.nkxp;
   const long long ntiles = (nlines + YL - 1) / YL;
   dim3 grid((unsigned)(ntiles < Y_GRID ? ntiles : Y_GRID), nfields);
-  const size_t sh = ((size_t)a.pl.tsize + (size_t)a.ny * 2 * YL) * sizeof(cpx<double>);
+  const size_t sh = y_lds_bytes(a.ny, a.pl.tsize);
   const int need = (a.ny + YNT / YL - 1) / (YNT / YL);
   const int iv = inv ? 1 : 0;
-#define FCNS_Y(BIGV, OWNV)                                                                    \
-  FCNS_LAUNCH((k_y<double, BIGV, OWNV>), grid, dim3(YNT), sh, st, a, src, dst, dst2, sfs, \
+#define FCNS_Y(FPV, OWNV)                                                                    \
+  FCNS_LAUNCH((k_y<double, FPV, OWNV>), grid, dim3(YNT), sh, st, a, src, dst, dst2, sfs, \
                      dfs, nlines, iv, mode)
-  if (big) {
-    if (need <= 4) FCNS_Y(true, 4); else if (need <= 8) FCNS_Y(true, 8); else FCNS_Y(true, 16);
+  if (a.ny == 512 && plan_is(a.pl, {8, 8, 8})) {
+    using P512 = SPlan<8, 8, 8>;
+    FCNS_Y(P512, 8);
+  } else if (a.ny == 256 && plan_is(a.pl, {8, 8, 4})) {
+    using P256 = SPlan<8, 8, 4>;
+    FCNS_Y(P256, 4);
+  } else if (big) {
+    if (need <= 4) FCNS_Y(DynPlan<true>, 4); else if (need <= 8) FCNS_Y(DynPlan<true>, 8); else FCNS_Y(DynPlan<true>, 16);
   } else {
-    if (need <= 4) FCNS_Y(false, 4); else if (need <= 8) FCNS_Y(false, 8); else FCNS_Y(false, 16);
+    if (need <= 4) FCNS_Y(DynPlan<false>, 4); else if (need <= 8) FCNS_Y(DynPlan<false>, 8); else FCNS_Y(DynPlan<false>, 16);
   }
 #undef FCNS_Y
 }
@@ -394,7 +414,7 @@ void launch_y(const YArgs& a, bool big, bool inv, int mode, const cpx<double>* s
 void launch_x_r2c(const XArgs& a, bool big, const double* phys, cpx<double>* xy, long long pfs,
                   long long xfs, long long nrows, int nfields, hipStream_t st) {
   dim3 grid((unsigned)((nrows + XR - 1) / XR), nfields);
-  const size_t sh = ((size_t)a.pl.tsize + 2 * XL * (a.nx + 1)) * sizeof(cpx<double>);
+  const size_t sh = ((size_t)a.pl.tsize + 2 * XL * x_ls(a.nx)) * sizeof(cpx<double>);
   if (big)
     FCNS_LAUNCH((k_x_r2c<double, true>), grid, dim3(XNT), sh, st, a, phys, xy, pfs, xfs, nrows);
   else
@@ -404,33 +424,33 @@ void launch_x_r2c(const XArgs& a, bool big, const double* phys, cpx<double>* xy,
 void launch_x_c2r(const XArgs& a, bool big, const cpx<double>* xy, double* phys, long long xfs,
                   long long pfs, long long nrows, int nfields, hipStream_t st) {
   dim3 grid((unsigned)((nrows + XR - 1) / XR), nfields);
-  const size_t sh = ((size_t)a.pl.tsize + 2 * XL * (a.nx + 1)) * sizeof(cpx<double>);
+  const size_t sh = ((size_t)a.pl.tsize + 2 * XL * x_ls(a.nx)) * sizeof(cpx<double>);
   if (big)
     FCNS_LAUNCH((k_x_c2r<double, true>), grid, dim3(XNT), sh, st, a, xy, phys, xfs, pfs, nrows);
   else
     FCNS_LAUNCH((k_x_c2r<double, false>), grid, dim3(XNT), sh, st, a, xy, phys, xfs, pfs, nrows);
 }
 
-int x_nl_variant = 1;  // 0: 8 rows x 512 threads, 1: 4 rows x 256 threads (faster on gfx950)
-
-template <bool BIG, int RR, int NT, int CC>
+template <class FP, int RR, int NT, int CC>
 static void launch_x_nl_v(const XArgs& a, const cpx<double>* xyb, cpx<double>* nl, long long fs,
                           long long nrows, int nfields, hipStream_t st) {
   dim3 grid((unsigned)((nrows + RR - 1) / RR));
-  const size_t sh = ((size_t)a.pl.tsize + 2 * (RR / 2) * (a.nx + 1)) * sizeof(cpx<double>);
-  FCNS_LAUNCH((k_x_nl<double, BIG, RR, NT, CC>), grid, dim3(NT), sh, st, a, xyb, nl, fs, nrows,
+  const size_t sh = ((size_t)a.pl.tsize + 2 * (RR / 2) * x_ls(a.nx)) * sizeof(cpx<double>);
+  FCNS_LAUNCH((k_x_nl<double, FP, RR, NT, CC>), grid, dim3(NT), sh, st, a, xyb, nl, fs, nrows,
               nfields);
 }
 
+// 4 rows x 256 threads; compile-time plans for nx = 512 and 256
 void launch_x_nl(const XArgs& a, bool big, const cpx<double>* xyb, cpx<double>* nl,
                  long long fs, long long nrows, int nfields, hipStream_t st) {
-  if (x_nl_variant == 1) {
-    if (big) launch_x_nl_v<true, 4, 256, 2>(a, xyb, nl, fs, nrows, nfields, st);
-    else launch_x_nl_v<false, 4, 256, 2>(a, xyb, nl, fs, nrows, nfields, st);
-  } else {
-    if (big) launch_x_nl_v<true, 8, 512, 1>(a, xyb, nl, fs, nrows, nfields, st);
-    else launch_x_nl_v<false, 8, 512, 1>(a, xyb, nl, fs, nrows, nfields, st);
-  }
+  if (a.nx == 512 && plan_is(a.pl, {8, 8, 8}))
+    launch_x_nl_v<SPlan<8, 8, 8>, 4, 256, 2>(a, xyb, nl, fs, nrows, nfields, st);
+  else if (a.nx == 256 && plan_is(a.pl, {8, 8, 4}))
+    launch_x_nl_v<SPlan<8, 8, 4>, 4, 256, 1>(a, xyb, nl, fs, nrows, nfields, st);
+  else if (big)
+    launch_x_nl_v<DynPlan<true>, 4, 256, 2>(a, xyb, nl, fs, nrows, nfields, st);
+  else
+    launch_x_nl_v<DynPlan<false>, 4, 256, 2>(a, xyb, nl, fs, nrows, nfields, st);
 }
 
 void launch_fill(cpx<double>* p, long long n, hipStream_t st) {

@@ -129,7 +129,7 @@ __global__ __launch_bounds__(ZNT) void k_z_fwd(ZArgs a, const cpx<double>* __res
 
 // ---------------------------------------------------------------- z back
 // continued spectral -> mixed: B_z = R o IFFT (and B_z(i k~z .) into dzdst).
-template <typename T, bool BIG, int OWN>
+template <typename T, class FP, int OWN>
 __global__ __launch_bounds__(ZNT) void k_z_back(ZArgs a, const cpx<double>* __restrict__ src,
                                                 cpx<double>* __restrict__ dst,
                                                 cpx<double>* __restrict__ dzdst,
@@ -137,13 +137,14 @@ __global__ __launch_bounds__(ZNT) void k_z_back(ZArgs a, const cpx<double>* __re
   extern __shared__ __align__(16) char smem[];
   const int tid = threadIdx.x;
   const Geom& g = a.g;
+  const int npr = FP::dynamic ? g.npr : FP::n;
   const ZLds<T> L(smem, g, a.pl.tsize);
   src += blockIdx.y * sfs;
   dst += blockIdx.y * mfs;
   if (dzdst) dzdst += blockIdx.y * mfs;
   const long long p0 = (long long)blockIdx.x * ZPB;
   z_setup<T>(L, a, tid);
-  const int tot = g.npr * ZPB;
+  const int tot = npr * ZPB;
   const int pb = tid % ZPB, lt = tid / ZPB;
   const long long p = p0 + pb;
   const bool pv = pencil_valid(g, p);
@@ -151,9 +152,9 @@ __global__ __launch_bounds__(ZNT) void k_z_back(ZArgs a, const cpx<double>* __re
 #pragma unroll
   for (int r = 0; r < OWN; ++r) {
     const int l = lt + r * ZLS;
-    keep[r] = (pv && l < g.npr) ? src[(long long)l * g.npen + p] : zero<double>();
+    keep[r] = (pv && l < npr) ? src[(long long)l * g.npen + p] : zero<double>();
   }
-  const double inv = 1.0 / g.npr;
+  const double inv = 1.0 / npr;
   const int npass = dzdst ? 2 : 1;
   for (int pass = 0; pass < npass; ++pass) {
 #pragma unroll
@@ -161,12 +162,12 @@ __global__ __launch_bounds__(ZNT) void k_z_back(ZArgs a, const cpx<double>* __re
       const int e = tid + r * ZNT;
       if (e < tot) {
         cpx<double> v = keep[r];
-        if (pass == 1) v = mul_i(v) * k_odd(lt + r * ZLS, g.npr, g.kzs);
+        if (pass == 1) v = mul_i(v) * k_odd(lt + r * ZLS, npr, g.kzs);
         L.X0[e] = cvt<T>(conj(v));
       }
     }
     __syncthreads();
-    const cpx<T>* R = fft_fwd<T, ZPB, BIG>(L.X0, L.X1, ZPB, 1, a.pl, L.tw, tid, ZNT);
+    const cpx<T>* R = fft_run<T, ZPB, ZNT, false, FP>(L.X0, L.X1, ZPB, 1, a.pl, L.tw, tid);
     cpx<double>* __restrict__ out = pass ? dzdst : dst;
     if (pv)
       for (int z = lt; z < g.nz; z += ZLS)
@@ -181,11 +182,12 @@ __global__ __launch_bounds__(ZNT) void k_z_back(ZArgs a, const cpx<double>* __re
 //   N = sigma F_z(NL);  S = V^t + c (N - diff |k|^2 W);  v* = B_z S, plus the
 //   body force / buoyancy at the physical points, then the wall injection
 //   v*_par = c grad_par p_prev (theta = 0) and V* = F_z v*.
-template <typename T, bool BIG, int OWN>
+template <typename T, class FP, int OWN>
 __global__ __launch_bounds__(ZNT) void k_z_stageA(ZArgs a, StageAArgs s) {
   extern __shared__ __align__(16) char smem[];
   const int tid = threadIdx.x;
   const Geom& g = a.g;
+  const int npr = FP::dynamic ? g.npr : FP::n;
   const ZLds<T> L(smem, g, a.pl.tsize);
   const int f = blockIdx.y;
   const long long p0 = (long long)blockIdx.x * ZPB;
@@ -196,7 +198,7 @@ __global__ __launch_bounds__(ZNT) void k_z_stageA(ZArgs a, StageAArgs s) {
   const cpx<double>* __restrict__ buoy = s.buoy[f];
   const double c = s.c;
   const double diff = (f == 3) ? s.kappa : s.nu;
-  const double inv = 1.0 / g.npr;
+  const double inv = 1.0 / npr;
   const int pb = tid % ZPB, lt = tid / ZPB;
   const long long p = p0 + pb;
   const bool pv = pencil_valid(g, p);
@@ -214,7 +216,7 @@ __global__ __launch_bounds__(ZNT) void k_z_stageA(ZArgs a, StageAArgs s) {
   for (int r = 0; r < OWN; ++r) {
     const int l = lt + r * ZLS;
     const long long gi = (long long)l * g.npen + p;
-    const bool ok = pv && l < g.npr;
+    const bool ok = pv && l < npr;
     vtr[r] = ok ? vt[gi] : zero<double>();
     wr[r] = ok ? w[gi] : zero<double>();
   }
@@ -229,11 +231,11 @@ __global__ __launch_bounds__(ZNT) void k_z_stageA(ZArgs a, StageAArgs s) {
 #pragma unroll
       for (int r = 0; r < OWN; ++r) {
         const int l = lt + r * ZLS;
-        if (l < g.npr) {
+        if (l < npr) {
           const int e = l * ZPB + pb;
           cpx<double> S = zero<double>();
           if (pv) {
-            const double kzt = k_true(l, g.npr, g.kzs);
+            const double kzt = k_true(l, npr, g.kzs);
             const double k2 = kh2 + kzt * kzt;
             const double sig = a.sigz[l] * sxy;
             S = vtr[r] + (cvt<double>(R[e]) * sig - wr[r] * (diff * k2)) * c;
@@ -263,11 +265,11 @@ __global__ __launch_bounds__(ZNT) void k_z_stageA(ZArgs a, StageAArgs s) {
       z_extend<T>(L.X0, L.M, g.nz, g.C, g.d, tid);
       __syncthreads();
     }
-    R = fft_fwd<T, ZPB, BIG>(L.X0, L.X1, ZPB, 1, a.pl, L.tw, tid, ZNT);
+    R = fft_run<T, ZPB, ZNT, false, FP>(L.X0, L.X1, ZPB, 1, a.pl, L.tw, tid);
   }
   cpx<double>* __restrict__ out = s.out[f];
   if (pv)
-    for (int l = lt; l < g.npr; l += ZLS) out[(long long)l * g.npen + p] = cvt<double>(R[l * ZPB + pb]);
+    for (int l = lt; l < npr; l += ZLS) out[(long long)l * g.npen + p] = cvt<double>(R[l * ZPB + pb]);
 }
 
 // ---------------------------------------------------------------- stage B
@@ -283,13 +285,14 @@ __global__ __launch_bounds__(ZNT) void k_z_stageA(ZArgs a, StageAArgs s) {
 // line; F_z(e+ + i e-) splits into F_z e+ and F_z e- by conjugate symmetry.
 // V* is streamed twice (wall sums, then the update) instead of being held in
 // registers; the mixed v, dv/dz of the result come from k_z_back.
-template <typename T, bool BIG>
+template <typename T, class FP>
 __global__ __launch_bounds__(ZNT) void k_z_stageB(ZArgs a, StageBArgs s) {
   extern __shared__ __align__(16) char smem[];
   __shared__ cpx<double> coef[ZPB * 5];  // b, t, s0, s1 then A, B, D
   __shared__ double gam_s[ZPB];
   const int tid = threadIdx.x;
   const Geom& g = a.g;
+  const int npr = FP::dynamic ? g.npr : FP::n;
   const ZLds<T> L(smem, g, a.pl.tsize);
   const long long p0 = (long long)blockIdx.x * ZPB;
   const int pb_me = tid % ZPB, lt = tid / ZPB;
@@ -297,7 +300,7 @@ __global__ __launch_bounds__(ZNT) void k_z_stageB(ZArgs a, StageBArgs s) {
   const bool valid_me = pencil_valid(g, p_me);
   z_setup<T>(L, a, tid);
   const cpx<double>* __restrict__ gtw = a.tw64;
-  const double inv = 1.0 / g.npr;
+  const double inv = 1.0 / npr;
   const bool pm = s.pmix != nullptr;
 
   double kxo, kyo, kxt, kyt;
@@ -309,16 +312,16 @@ __global__ __launch_bounds__(ZNT) void k_z_stageB(ZArgs a, StageBArgs s) {
   cpx<double> sb = zero<double>(), st = zero<double>(), s0 = zero<double>(),
               s1 = zero<double>();
   if (valid_me) {
-    for (int l = lt; l < g.npr; l += ZLS) {
+    for (int l = lt; l < npr; l += ZLS) {
       const long long gi = (long long)l * g.npen + p_me;
       const cpx<double> V0 = s.vs[0][gi], V1 = s.vs[1][gi], V2 = s.vs[2][gi];
-      const double kz = k_odd(l, g.npr, g.kzs);
+      const double kz = k_odd(l, npr, g.kzs);
       const double k2 = kh2 + kz * kz;
       cpx<double> sv = zero<double>();
       if (k2 > 0.0) sv = (V0 * kxo + V1 * kyo + V2 * kz) * (1.0 / k2);
       const cpx<double> rz = V2 - sv * kz;
       // e^{+2 pi i l (nz-1)/N'} = conj(root[l (nz-1) mod N'])
-      const cpx<double> et = conj(gtw[(int)(((long long)l * (g.nz - 1)) % g.npr)]);
+      const cpx<double> et = conj(gtw[(int)(((long long)l * (g.nz - 1)) % npr)]);
       sb = sb + rz;
       st = st + rz * et;
       s0 = s0 + sv;
@@ -387,10 +390,10 @@ __global__ __launch_bounds__(ZNT) void k_z_stageB(ZArgs a, StageBArgs s) {
   __syncthreads();
   z_extend<T>(L.X0, L.M, g.nz, g.C, g.d, tid);
   __syncthreads();
-  const cpx<T>* R = fft_fwd<T, ZPB, BIG>(L.X0, L.X1, ZPB, 1, a.pl, L.tw, tid, ZNT);
+  const cpx<T>* R = fft_run<T, ZPB, ZNT, false, FP>(L.X0, L.X1, ZPB, 1, a.pl, L.tw, tid);
   cpx<T>* Xo = (R == L.X0) ? L.X1 : L.X0;
   // 4. V = V* - k~ s - H^ (V* streamed again), store the continued state
-  for (int l = lt; l < g.npr; l += ZLS) {
+  for (int l = lt; l < npr; l += ZLS) {
     const int e = l * ZPB + pb_me;
     if (!valid_me) {
       if (pm) Xo[e] = zero<T>();
@@ -398,11 +401,11 @@ __global__ __launch_bounds__(ZNT) void k_z_stageB(ZArgs a, StageBArgs s) {
     }
     const long long gi = (long long)l * g.npen + p_me;
     const cpx<double> V0 = s.vs[0][gi], V1 = s.vs[1][gi], V2 = s.vs[2][gi];
-    const int lm = (l == 0) ? 0 : g.npr - l;
+    const int lm = (l == 0) ? 0 : npr - l;
     const cpx<double> xl = cvt<double>(R[e]), xm = conj(cvt<double>(R[lm * ZPB + pb_me]));
     const cpx<double> ep = (xl + xm) * 0.5;
     const cpx<double> em = mul_mi(xl - xm) * 0.5;
-    const double kz = k_odd(l, g.npr, g.kzs);
+    const double kz = k_odd(l, npr, g.kzs);
     const double k2 = kh2 + kz * kz;
     cpx<double> sv = zero<double>();
     if (k2 > 0.0) sv = (V0 * kxo + V1 * kyo + V2 * kz) * (1.0 / k2);
@@ -423,8 +426,7 @@ __global__ __launch_bounds__(ZNT) void k_z_stageB(ZArgs a, StageBArgs s) {
   if (!pm) return;
   // 5. pressure in mixed space: (B_z(-i s) + phi^H) / c
   __syncthreads();
-  const cpx<T>* P = fft_fwd<T, ZPB, BIG>(Xo, (Xo == L.X0) ? L.X1 : L.X0, ZPB, 1, a.pl, L.tw, tid,
-                                         ZNT);
+  const cpx<T>* P = fft_run<T, ZPB, ZNT, false, FP>(Xo, (Xo == L.X0) ? L.X1 : L.X0, ZPB, 1, a.pl, L.tw, tid);
   if (valid_me)
     for (int z = lt; z < g.nz; z += ZLS) {
       const double zz = z * g.dz;
@@ -537,18 +539,25 @@ void launch_z_fwd(const ZArgs& a, bool big, const cpx<double>* src, cpx<double>*
     FCNS_LAUNCH((k_z_fwd<double, false>), grid, dim3(ZNT), sh, st, a, src, dst, sfs, dfs, filter);
 }
 
+// Compile-time plan for N' = 288 (nz = 257 with C = 31); other lengths run
+// the run-time engine.
+using P288 = SPlan<8, 4, 3, 3>;
+static bool z_static_288(const ZArgs& a) { return a.g.npr == 288 && plan_is(a.pl, {8, 4, 3, 3}); }
+
 void launch_z_back(const ZArgs& a, bool big, const cpx<double>* src, cpx<double>* dst,
                    cpx<double>* dzdst, long long sfs, long long mfs, int nfields,
                    hipStream_t st) {
   dim3 grid((unsigned)((a.g.npen + ZPB - 1) / ZPB), nfields);
   const size_t sh = zshared_bytes<double>(a.g, a.pl.tsize);
   const int own = pick_own(a.g.npr);
-  if (big) {
-    FCNS_OWN_SWITCH(own, FCNS_LAUNCH((k_z_back<double, true, OWN>), grid, dim3(ZNT), sh, st,
-                                            a, src, dst, dzdst, sfs, mfs))
+  if (z_static_288(a)) {
+    FCNS_LAUNCH((k_z_back<double, P288, 9>), grid, dim3(ZNT), sh, st, a, src, dst, dzdst, sfs, mfs);
+  } else if (big) {
+    FCNS_OWN_SWITCH(own, FCNS_LAUNCH((k_z_back<double, DynPlan<true>, OWN>), grid, dim3(ZNT), sh,
+                                     st, a, src, dst, dzdst, sfs, mfs))
   } else {
-    FCNS_OWN_SWITCH(own, FCNS_LAUNCH((k_z_back<double, false, OWN>), grid, dim3(ZNT), sh, st,
-                                            a, src, dst, dzdst, sfs, mfs))
+    FCNS_OWN_SWITCH(own, FCNS_LAUNCH((k_z_back<double, DynPlan<false>, OWN>), grid, dim3(ZNT), sh,
+                                     st, a, src, dst, dzdst, sfs, mfs))
   }
 }
 
@@ -556,20 +565,26 @@ void launch_z_stageA(const ZArgs& a, bool big, const StageAArgs& s, int nfields,
   dim3 grid((unsigned)((a.g.npen + ZPB - 1) / ZPB), nfields);
   const size_t sh = zshared_bytes<double>(a.g, a.pl.tsize);
   const int own = pick_own(a.g.npr);
-  if (big) {
-    FCNS_OWN_SWITCH(own, FCNS_LAUNCH((k_z_stageA<double, true, OWN>), grid, dim3(ZNT), sh, st, a, s))
+  if (z_static_288(a)) {
+    FCNS_LAUNCH((k_z_stageA<double, P288, 9>), grid, dim3(ZNT), sh, st, a, s);
+  } else if (big) {
+    FCNS_OWN_SWITCH(own, FCNS_LAUNCH((k_z_stageA<double, DynPlan<true>, OWN>), grid, dim3(ZNT), sh,
+                                     st, a, s))
   } else {
-    FCNS_OWN_SWITCH(own, FCNS_LAUNCH((k_z_stageA<double, false, OWN>), grid, dim3(ZNT), sh, st, a, s))
+    FCNS_OWN_SWITCH(own, FCNS_LAUNCH((k_z_stageA<double, DynPlan<false>, OWN>), grid, dim3(ZNT),
+                                     sh, st, a, s))
   }
 }
 
 void launch_z_stageB(const ZArgs& a, bool big, const StageBArgs& s, hipStream_t st) {
   dim3 grid((unsigned)((a.g.npen + ZPB - 1) / ZPB), 1);
   const size_t sh = zshared_bytes<double>(a.g, a.pl.tsize);
-  if (big)
-    FCNS_LAUNCH((k_z_stageB<double, true>), grid, dim3(ZNT), sh, st, a, s);
+  if (z_static_288(a))
+    FCNS_LAUNCH((k_z_stageB<double, P288>), grid, dim3(ZNT), sh, st, a, s);
+  else if (big)
+    FCNS_LAUNCH((k_z_stageB<double, DynPlan<true>>), grid, dim3(ZNT), sh, st, a, s);
   else
-    FCNS_LAUNCH((k_z_stageB<double, false>), grid, dim3(ZNT), sh, st, a, s);
+    FCNS_LAUNCH((k_z_stageB<double, DynPlan<false>>), grid, dim3(ZNT), sh, st, a, s);
 }
 
 void launch_fc_extend(const double* in, long long nlines, long long ips, long long ils, double* out,

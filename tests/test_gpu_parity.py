@@ -117,6 +117,23 @@ def test_rhs_nonlinear_parity(fcns, filtered, nx, ny, nz, C):
     assert rel_l2(nlt, rt) < 1e-11
 
 
+@pytest.mark.parametrize("nx,ny,nz,C,filtered", [(512, 512, 11, 25, True), (256, 256, 11, 25, False)])
+def test_rhs_nonlinear_compile_time_plans(fcns, nx, ny, nz, C, filtered):
+    # nx = ny = 512 and 256 take the x and y kernels built for those lengths
+    lx, ly, lz = 2.0, 2.0, 1.0
+    s = fcns.Solver(nx, ny, nz, lx, ly, lz, 0.01, d=5, C=C, boussinesq=True, kappa=0.01,
+                    gamma=1.0)
+    v = np.stack([W.smooth_field(nx, ny, nz, lx, ly, lz, 20 + i) for i in range(3)])
+    th = W.smooth_field(nx, ny, nz, lx, ly, lz, 30)
+    nlv, nlt = s.rhs_nonlinear(torch.from_numpy(v), torch.from_numpy(th), filtered)
+    torch.cuda.synchronize()
+    o = Oracle(Problem(nx=nx, ny=ny, nz=nz, lx=lx, ly=ly, lz=lz, nu=0.01, C=C,
+                       boussinesq=True, kappa=0.01, gamma=1.0))
+    rv, rt = o.rhs_nonlinear(v, th, filtered)
+    assert rel_l2(nlv, rv) < 1e-11
+    assert rel_l2(nlt, rt) < 1e-11
+
+
 # ------------------------------------------------------------------ projection
 @pytest.mark.parametrize("nx,ny,nz,C,c", [(16, 16, 33, 25, 0.5), (32, 24, 65, 31, 1e-3),
                                           (20, 36, 129, 31, 2.0)])
@@ -168,6 +185,17 @@ def test_rk_rayleigh_benard_small(fcns):
     assert rel_l2(th, rth) < 1e-11
     assert rel_l2(v, rv) < 1e-10
     assert rel_l2(p, rp) < 1e-9
+
+
+def test_rk_rayleigh_benard_compile_time_z_plan(fcns):
+    # nz = 257 with C = 31: N' = 288, the z kernels built for that length
+    w = W.rayleigh_benard(16, 8, 257, 1e6, C=31, dt=1e-3, steps=3, kmax=2, mmax=3,
+                          noise_rms=1e-2)
+    (v, th, p, gw), (rv, rth, rp, rg) = _run_pair(fcns, w, w.steps)
+    assert rel_l2(th, rth) < 1e-11
+    assert rel_l2(v, rv) < 1e-11
+    assert rel_l2(p, rp) < 1e-10
+    assert rel_l2(gw, rg) < 1e-10
 
 
 def test_rk_channel_big_prime_length(fcns):
