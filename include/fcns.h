@@ -61,7 +61,8 @@ typedef struct {
                            gradient, Sec. 6); 0 for none */
   int32_t boussinesq;   /* 1: also carry theta (Sec. 7) */
   double kappa, gamma;  /* thermal diffusivity and buoyancy rate (Boussinesq) */
-  int32_t rk_order;     /* o of the time-splitting RK (Sec. 4.4); only 2 */
+  int32_t rk_order;     /* o of the time-splitting RK (Sec. 4.4), 1..4; o = 1 is
+                           the forward-Euler splitting of Sec. 4.1 */
   double filter_beta;   /* exponential filter (Sec. 4.3); 0 -> 16 ln 10 */
   double filter_2p;     /* filter order 2p; 0 -> 100 */
   int32_t precision;    /* FCNS_FP64 (only mode implemented) */
@@ -116,7 +117,9 @@ fcns_status fcns_pressure_project(fcns_ctx* ctx, const double* v_star, double c,
 fcns_status fcns_set_state(fcns_ctx* ctx, const double* v, const double* theta);
 
 /* Advance nsteps steps of the o-stage time-splitting Runge-Kutta scheme of
- * Sec. 4.4 with time step dt (stage coefficients c_j = dt/(o-j+1)).
+ * Sec. 4.4 with time step dt (stage coefficients c_j = dt/(o-j+1); each stage
+ * injects the wall gradient of the previous stage's pressure, which for o = 1
+ * is the time-splitting Euler scheme of Sec. 4.1).
  * Asynchronous on the context stream. */
 fcns_status fcns_rk_step(fcns_ctx* ctx, double dt, int32_t nsteps);
 

@@ -94,7 +94,8 @@ class Solver:
 
     def __init__(self, nx, ny, nz, lx, ly, lz, nu, d=5, C=25, forcing_x=0.0,
                  boussinesq=False, kappa=0.0, gamma=0.0, keep_pressure=False,
-                 filter_beta=0.0, filter_2p=0.0, table=None, device="cuda:0", stream=None):
+                 filter_beta=0.0, filter_2p=0.0, rk_order=2, table=None, device="cuda:0",
+                 stream=None):
         import torch
         from . import fctable
 
@@ -109,12 +110,13 @@ class Solver:
         self._table = tab
         prob = FcnsProblem(nx, ny, nz, lx, ly, lz, d, C,
                            tab.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
-                           nu, forcing_x, int(bool(boussinesq)), kappa, gamma, 2,
+                           nu, forcing_x, int(bool(boussinesq)), kappa, gamma, int(rk_order),
                            filter_beta, filter_2p, FCNS_FP64, int(bool(keep_pressure)))
         self.shape = (nz, ny, nx)
         self.nx, self.ny, self.nz, self.d, self.C = nx, ny, nz, d, C
         self.npr = nz + C
         self.boussinesq = bool(boussinesq)
+        self.rk_order = int(rk_order)
         self.lx, self.ly, self.lz = lx, ly, lz
         h = ctypes.c_void_p()
         with torch.cuda.device(self.device):

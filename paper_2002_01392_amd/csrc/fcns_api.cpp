@@ -250,7 +250,7 @@ extern "C" fcns_status fcns_create(const fcns_problem* prob, void* hip_stream, f
     return fail(nullptr, FCNS_EINVAL, "need d >= 2, C >= 1 and nz >= 2d");
   if ((p.nz + p.fc_C) % 2) return fail(nullptr, FCNS_EINVAL, "nz + C must be even");
   if (!(p.lx > 0 && p.ly > 0 && p.lz > 0)) return fail(nullptr, FCNS_EINVAL, "box lengths must be > 0");
-  if (p.rk_order != 2) return fail(nullptr, FCNS_EINVAL, "only rk_order = 2 is implemented");
+  if (p.rk_order < 1 || p.rk_order > 4) return fail(nullptr, FCNS_EINVAL, "rk_order must be 1..4");
   if (p.precision != FCNS_FP64) return fail(nullptr, FCNS_EINVAL, "only FCNS_FP64 is implemented");
   if (!p.fc_table) return fail(nullptr, FCNS_EINVAL, "fc_table is NULL");
   if (p.nx > 512 || p.ny > 1024) return fail(nullptr, FCNS_EINVAL, "need nx <= 512 and ny <= 1024");

@@ -154,15 +154,15 @@ def test_pressure_project_parity(fcns, nx, ny, nz, C, c):
 
 
 # ------------------------------------------------------------------ time stepping
-def _run_pair(fcns, w, steps, keep_pressure=True):
+def _run_pair(fcns, w, steps, keep_pressure=True, rk_order=2):
     v0, th0 = w.initial_state()
-    s = fcns.Solver.from_workload(w, keep_pressure=keep_pressure)
+    s = fcns.Solver.from_workload(w, keep_pressure=keep_pressure, rk_order=rk_order)
     s.set_state(torch.from_numpy(v0), torch.from_numpy(th0) if th0 is not None else None)
     s.rk_step(w.dt, steps)
     v, th, p = s.get_state(pressure=keep_pressure)
     gw = s.get_wall_grad()
     torch.cuda.synchronize()
-    o = Oracle(Problem(**w.problem_kwargs()))
+    o = Oracle(Problem(**w.problem_kwargs(), rk_order=rk_order))
     o.set_state(v0, th0)
     o.rk_step(w.dt, steps)
     rv, rth, rp = o.get_state()
@@ -203,6 +203,24 @@ def test_rk_channel_big_prime_length(fcns):
     w = W.channel(16, 8, 257, 2000.0, d=5, C=25, dt=5e-4, steps=3, seed=9, noise_rms=0.05)
     (v, _, _, _), (rv, _, _, _) = _run_pair(fcns, w, w.steps, keep_pressure=False)
     assert rel_l2(v, rv) < 1e-11
+
+
+@pytest.mark.parametrize("order", [1, 3, 4])
+def test_rk_orders_channel(fcns, order):
+    # o = 1 (the Euler splitting of Sec. 4.1) and the o = 3, 4 stages of Sec. 4.4
+    w = W.get("channel_32x32x33")
+    (v, _, p, gw), (rv, _, rp, rg) = _run_pair(fcns, w, 5, rk_order=order)
+    assert rel_l2(v, rv) < 1e-11
+    assert rel_l2(p, rp) < 1e-10
+    assert rel_l2(gw, rg) < 1e-10
+
+
+def test_rk_order3_rayleigh_benard(fcns):
+    w = W.rayleigh_benard(32, 24, 33, 1e5, C=31, dt=2e-3, steps=4, kmax=3, mmax=3,
+                          noise_rms=1e-2)
+    (v, th, _, _), (rv, rth, _, _) = _run_pair(fcns, w, w.steps, rk_order=3)
+    assert rel_l2(th, rth) < 1e-11
+    assert rel_l2(v, rv) < 1e-10
 
 
 def test_rk_is_deterministic_and_restartable(fcns):
