@@ -76,30 +76,80 @@ def pass_model_bytes(w):
     return 14 * w.nfields * M + 3 * w.nfields * S
 
 
-def cpu_baseline(w, seconds_hint=20.0):
-    """The FP64 oracle (as it stands) on a bounded sample: one RK step of the
-    same workload parameters and wall-normal grid on a reduced horizontal
-    grid, BLAS limited to one thread (numpy's FFT is single-threaded)."""
+def cpu_baseline(w, steps=2):
+    """The FP64 oracle (as it stands) on a bounded sample: `steps` RK steps of
+    the same workload parameters and wall-normal grid on a reduced horizontal
+    grid (about 10-30 s on one core), BLAS limited to one thread (numpy's FFT
+    is single-threaded)."""
     import numpy as np
     from dataclasses import replace
     from threadpoolctl import threadpool_limits
 
     from oracle.ns import Oracle, Problem
-    nxs = max(16, min(w.nx, 128))
-    nys = max(16, min(w.ny, 128))
+    nxs = max(16, min(w.nx, 256))
+    nys = max(16, min(w.ny, 256))
     ws = replace(w, nx=nxs, ny=nys, lx=w.lx * nxs / w.nx, ly=w.ly * nys / w.ny)
     v0, th0 = ws.initial_state()
     with threadpool_limits(limits=1):
         o = Oracle(Problem(**ws.problem_kwargs()))
         o.set_state(v0, th0)
         t0 = time.perf_counter()
-        o.rk_step(ws.dt, 1)
+        o.rk_step(ws.dt, steps)
         el = time.perf_counter() - t0
     pts = ws.nx * ws.ny * ws.nz
-    return {"value": pts * 2 / el, "unit": UNIT, "cores": 1, "kind": "oracle",
-            "sample": (f"1 RK2 step (2 substeps) of {w.name}'s parameters, nz={w.nz}, C={w.C}, "
+    return {"value": pts * 2 * steps / el, "unit": UNIT, "cores": 1, "kind": "oracle",
+            "sample": (f"{steps} RK2 steps ({2 * steps} substeps) of {w.name}'s parameters, "
+                       f"nz={w.nz}, C={w.C}, "
                        f"on a {nxs}x{nys} horizontal grid (box scaled to keep dx, dy), "
                        f"{el:.1f} s, numpy FFT, BLAS 1 thread")}
+
+
+def precision_run(name="channel_256x256x257", steps=100, warmup=2):
+    """The mixed-precision step on the channel grid: rate of the FP64 and the
+    mixed step (same initial state, same number of steps), and the mixed
+    result's per-field relative L2 distance from the FP64 one (which matches
+    the FP64 oracle to 1e-11 in the parity tests)."""
+    import numpy as np
+    import torch
+
+    import workloads as W
+    from paper_2002_01392_amd import Solver
+
+    w = W.get(name)
+    v0, th0 = w.initial_state()
+    v0 = torch.from_numpy(v0)
+    out = {}
+    res = {}
+    for prec in ("fp64", "mixed"):
+        s = Solver.from_workload(w, keep_pressure=True, precision=prec)
+        s.set_state(v0)
+        s.rk_step(w.dt, warmup)
+        s.set_state(v0)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(s.stream)
+        s.rk_step(w.dt, steps)
+        e1.record(s.stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1)
+        v, _, pr = s.get_state(pressure=True)
+        torch.cuda.synchronize()
+        res[prec] = (v.cpu().numpy(), pr.cpu().numpy())
+        out[prec] = {"ms_per_step": ms / steps,
+                     "value": w.nx * w.ny * w.nz * 2 * steps / (ms / 1e3)}
+        s.close()
+        del s
+    (vd, pd), (vm, pm) = res["fp64"], res["mixed"]
+    rel = lambda a, b: float(np.linalg.norm(a - b) / np.linalg.norm(b))
+    err = {c: rel(vm[i], vd[i]) for i, c in enumerate("uvw")}
+    err["p"] = rel(pm, pd)
+    return {"workload": name, "steps": steps, "unit": UNIT,
+            "fp64": out["fp64"], "mixed": out["mixed"],
+            "speedup": out["fp64"]["ms_per_step"] / out["mixed"]["ms_per_step"],
+            "rel_l2_vs_fp64": err,
+            "note": "nonlinear term in FP32 (back transforms of the state, x and y FFTs, "
+                    "products, mixed-space arrays); FP64 state, FC extension, the "
+                    "transforms that form v*, and the projection"}
 
 
 def load_traffic(w, kernel, src_hash):
@@ -125,6 +175,8 @@ def main():
     ap.add_argument("--workload", default="rb_512x512x257")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--timing", type=int, default=1, help="event-time kernels in the timed region")
+    ap.add_argument("--no-mixed", action="store_true",
+                    help="skip the mixed-precision run on the channel grid")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one plain device copy of 1 GiB (counter calibration)")
     args = ap.parse_args()
@@ -209,6 +261,14 @@ def main():
                   "GBps": round(pm / (total_ms / 1e3 / substeps) / 1e9, 1),
                   "frac": round(pm / (total_ms / 1e3 / substeps) / 1e9 / HBM_PEAK_GBPS, 4)}
 
+    mixed = None
+    if not args.no_mixed:
+        s.close()
+        del s
+        torch.cuda.empty_cache()
+        print("[bench] mixed precision on the channel grid", file=sys.stderr, flush=True)
+        mixed = precision_run()
+
     cpu = None
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline (oracle)", file=sys.stderr, flush=True)
@@ -225,7 +285,7 @@ def main():
         "step_ms_p50": float(np.percentile(step_ms, 50)),
         "step_ms_p99": float(np.percentile(step_ms, 99)),
         "wall_s": wall, "state_finite": finite,
-        "roofline": roof, "pass_model": pass_model, "kernels": kernels,
+        "roofline": roof, "pass_model": pass_model, "kernels": kernels, "precision": mixed,
         "cpu_baseline": cpu, "kernel_source_hash": src_hash,
     }
     print(json.dumps(out))

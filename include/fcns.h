@@ -65,7 +65,16 @@ typedef struct {
                            the forward-Euler splitting of Sec. 4.1 */
   double filter_beta;   /* exponential filter (Sec. 4.3); 0 -> 16 ln 10 */
   double filter_2p;     /* filter order 2p; 0 -> 100 */
-  int32_t precision;    /* FCNS_FP64 (only mode implemented) */
+  int32_t precision;    /* FCNS_FP64, or FCNS_MIXED: rk_step evaluates the
+                           nonlinear term in FP32 (the back transforms of the
+                           state, the x and y FFTs, the products with FP32
+                           accumulation, and their mixed-space arrays), while
+                           the continued state, the FC extension (FP64 tables
+                           and sums), the transforms of the RK combine that form
+                           v*, and the pressure projection with its
+                           homogeneous correction stay FP64.  The standalone
+                           calls (fc_*, rhs_nonlinear, pressure_project,
+                           get/set_state) are FP64 in both. */
   int32_t keep_pressure;/* 1: rk_step also keeps the pressure of its last stage
                            (one extra mixed-space field write per step) */
 } fcns_problem;

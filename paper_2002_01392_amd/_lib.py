@@ -17,6 +17,7 @@ LIB_PATH = os.path.join(_PKG, "libfcns.so")
 
 FCNS_OK, FCNS_EINVAL, FCNS_ENOMEM, FCNS_EDEVICE, FCNS_ENONFINITE, FCNS_ESTATE = 0, -1, -2, -3, -4, -5
 FCNS_FP64, FCNS_MIXED = 0, 1
+_PRECISIONS = {"fp64": FCNS_FP64, "mixed": FCNS_MIXED}
 
 
 class FcnsProblem(ctypes.Structure):
@@ -94,8 +95,8 @@ class Solver:
 
     def __init__(self, nx, ny, nz, lx, ly, lz, nu, d=5, C=25, forcing_x=0.0,
                  boussinesq=False, kappa=0.0, gamma=0.0, keep_pressure=False,
-                 filter_beta=0.0, filter_2p=0.0, rk_order=2, table=None, device="cuda:0",
-                 stream=None):
+                 filter_beta=0.0, filter_2p=0.0, rk_order=2, precision="fp64", table=None,
+                 device="cuda:0", stream=None):
         import torch
         from . import fctable
 
@@ -111,12 +112,14 @@ class Solver:
         prob = FcnsProblem(nx, ny, nz, lx, ly, lz, d, C,
                            tab.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
                            nu, forcing_x, int(bool(boussinesq)), kappa, gamma, int(rk_order),
-                           filter_beta, filter_2p, FCNS_FP64, int(bool(keep_pressure)))
+                           filter_beta, filter_2p, _PRECISIONS[precision],
+                           int(bool(keep_pressure)))
         self.shape = (nz, ny, nx)
         self.nx, self.ny, self.nz, self.d, self.C = nx, ny, nz, d, C
         self.npr = nz + C
         self.boussinesq = bool(boussinesq)
         self.rk_order = int(rk_order)
+        self.precision = precision
         self.lx, self.ly, self.lz = lx, ly, lz
         h = ctypes.c_void_p()
         with torch.cuda.device(self.device):

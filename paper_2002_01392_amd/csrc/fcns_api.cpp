@@ -25,6 +25,10 @@ struct fcns_ctx {
   cpx<double>* twx = nullptr;
   cpx<double>* twy = nullptr;
   cpx<double>* rootz = nullptr; // N' roots of unity (wall sums)
+  bool mixed = false;           // FP32 transforms and mixed-space arrays in rk_step
+  cpx<float>* twz_f = nullptr;  // the plan tables rounded to FP32 (mixed precision)
+  cpx<float>* twx_f = nullptr;
+  cpx<float>* twy_f = nullptr;
   double* fcM = nullptr;
   double* sigx = nullptr;
   double* sigy = nullptr;
@@ -35,10 +39,10 @@ struct fcns_ctx {
   cpx<double>* P = nullptr;    // V^t (nf fields)
   cpx<double>* Q = nullptr;    // V^(j) (nf fields)
   cpx<double>* VS = nullptr;   // V* / scratch (nf fields)
-  cpx<double>* MV = nullptr;   // mixed v_f, dv_f/dz at slots 2f, 2f+1
+  cpx<double>* MV = nullptr;   // mixed v_f, dv_f/dz at slots 2f, 2f+1 (cpx<float> when mixed)
   cpx<double>* MVT = nullptr;  // scratch copy of MV for the standalone calls
-  cpx<double>* XYB = nullptr;  // (kx, y, z): q_f, dq_f/dy, dq_f/dz at 3f..3f+2
-  cpx<double>* NLB = nullptr;  // nonlinear term (nf fields)
+  cpx<double>* XYB = nullptr;  // (kx, y, z): q_f, dq_f/dy, dq_f/dz at 3f..3f+2 (rk_step: T)
+  cpx<double>* NLB = nullptr;  // nonlinear term (nf fields; rk_step: T)
   cpx<double>* PM = nullptr;   // mixed pressure
   cpx<double>* GW = nullptr;   // wall tangential gradient [2][2][npen]
   cpx<double>* GWT = nullptr;  // scratch wall gradient
@@ -198,17 +202,18 @@ static fcns_status alloc(fcns_ctx* c, cpx<double>** p, long long n) {
 static void free_all(fcns_ctx* c) {
   for (hipEvent_t e : c->evpool) (void)hipEventDestroy(e);
   c->evpool.clear();
-  void* ps[] = {c->twz, c->twx, c->twy, c->rootz, c->fcM, c->sigx, c->sigy, c->sigz, c->P, c->Q,
+  void* ps[] = {c->twz, c->twx, c->twy, c->twz_f, c->twx_f, c->twy_f, c->rootz, c->fcM, c->sigx, c->sigy, c->sigz, c->P, c->Q,
                 c->VS, c->MV, c->MVT, c->XYB, c->NLB, c->PM, c->GW, c->GWT};
   for (void* p : ps)
     if (p) (void)hipFree(p);
 }
 
-static ZArgs zargs(const fcns_ctx* c) {
+// f32: the twiddle table of the FP32 kernels
+static ZArgs zargs(const fcns_ctx* c, bool f32 = false) {
   ZArgs a;
   a.g = c->g;
   a.pl = c->plz;
-  a.tw = c->twz;
+  a.tw = f32 ? (const void*)c->twz_f : (const void*)c->twz;
   a.tw64 = c->rootz;
   a.fc = c->fcM;
   a.sigx = c->sigx;
@@ -216,17 +221,17 @@ static ZArgs zargs(const fcns_ctx* c) {
   a.sigz = c->sigz;
   return a;
 }
-static YArgs yargs(const fcns_ctx* c) {
+static YArgs yargs(const fcns_ctx* c, bool f32 = false) {
   YArgs a;
   a.ny = c->g.ny;
   a.nkx = c->g.nkx;
   a.nkxp = c->g.nkxp;
   a.kys = c->g.kys;
   a.pl = c->ply;
-  a.tw = c->twy;
+  a.tw = f32 ? (const void*)c->twy_f : (const void*)c->twy;
   return a;
 }
-static XArgs xargs(const fcns_ctx* c) {
+static XArgs xargs(const fcns_ctx* c, bool f32 = false) {
   XArgs a;
   a.nx = c->g.nx;
   a.nkx = c->g.nkx;
@@ -234,7 +239,7 @@ static XArgs xargs(const fcns_ctx* c) {
   a.ny = c->g.ny;
   a.kxs = c->g.kxs;
   a.pl = c->plx;
-  a.tw = c->twx;
+  a.tw = f32 ? (const void*)c->twx_f : (const void*)c->twx;
   return a;
 }
 
@@ -251,7 +256,8 @@ extern "C" fcns_status fcns_create(const fcns_problem* prob, void* hip_stream, f
   if ((p.nz + p.fc_C) % 2) return fail(nullptr, FCNS_EINVAL, "nz + C must be even");
   if (!(p.lx > 0 && p.ly > 0 && p.lz > 0)) return fail(nullptr, FCNS_EINVAL, "box lengths must be > 0");
   if (p.rk_order < 1 || p.rk_order > 4) return fail(nullptr, FCNS_EINVAL, "rk_order must be 1..4");
-  if (p.precision != FCNS_FP64) return fail(nullptr, FCNS_EINVAL, "only FCNS_FP64 is implemented");
+  if (p.precision != FCNS_FP64 && p.precision != FCNS_MIXED)
+    return fail(nullptr, FCNS_EINVAL, "precision must be FCNS_FP64 or FCNS_MIXED");
   if (!p.fc_table) return fail(nullptr, FCNS_EINVAL, "fc_table is NULL");
   if (p.nx > 512 || p.ny > 1024) return fail(nullptr, FCNS_EINVAL, "need nx <= 512 and ny <= 1024");
   const int npr = p.nz + p.fc_C;
@@ -262,6 +268,7 @@ extern "C" fcns_status fcns_create(const fcns_problem* prob, void* hip_stream, f
   c->prob.fc_table = nullptr;
   c->stream = (hipStream_t)hip_stream;
   c->nf = p.boussinesq ? 4 : 3;
+  c->mixed = p.precision == FCNS_MIXED;
   Geom& g = c->g;
   g.nx = p.nx;
   g.ny = p.ny;
@@ -287,7 +294,7 @@ extern "C" fcns_status fcns_create(const fcns_problem* prob, void* hip_stream, f
     delete c;
     return fail(nullptr, FCNS_EINVAL, "unsupported transform length (more than 12 radix stages)");
   }
-  if (y_lds_bytes(p.ny, c->ply.tsize) > 160 * 1024) {
+  if (y_lds_bytes(p.ny, c->ply.tsize, sizeof(cpx<double>)) > 160 * 1024) {
     delete c;
     return fail(nullptr, FCNS_EINVAL, "ny too large for the y pass (its lines must fit in LDS)");
   }
@@ -312,7 +319,23 @@ extern "C" fcns_status fcns_create(const fcns_problem* prob, void* hip_stream, f
   auto sx = filter_table(p.nx, g.nkx, true, beta, two_p);
   auto sy = filter_table(p.ny, p.ny, false, beta, two_p);
   auto sz = filter_table(npr, npr, false, beta, two_p);
+  auto to_f32 = [](const std::vector<cpx<double>>& t) {
+    std::vector<cpx<float>> o(t.size());
+    for (size_t i = 0; i < t.size(); ++i) o[i] = mk((float)t[i].x, (float)t[i].y);
+    return o;
+  };
   fcns_status st = FCNS_OK;
+  if (c->mixed) {
+    auto fz = to_f32(twz), fx = to_f32(twx), fy = to_f32(twy);
+    if ((st = upload(c, &c->twz_f, fz.data(), fz.size())) ||
+        (st = upload(c, &c->twx_f, fx.data(), fx.size())) ||
+        (st = upload(c, &c->twy_f, fy.data(), fy.size()))) {
+      g_create_err = c->err;
+      free_all(c);
+      delete c;
+      return st;
+    }
+  }
   if ((st = upload(c, &c->twz, twz.data(), twz.size())) ||
       (st = upload(c, &c->twx, twx.data(), twx.size())) ||
       (st = upload(c, &c->twy, twy.data(), twy.size())) ||
@@ -371,7 +394,7 @@ static void phys_to_mixed(fcns_ctx* c, const double* phys, int nfields, cpx<doub
   const long long pfs = (long long)g.nz * g.ny * g.nx;
   launch_x_r2c(xargs(c), c->big_x, phys, mixed, pfs, c->M, (long long)g.nz * g.ny, nfields,
                c->stream);
-  launch_y(yargs(c), c->big_y, false, 0, mixed, mixed, nullptr, c->M, c->M, g.nz, nfields,
+  launch_y<double>(yargs(c), c->big_y, false, 0, mixed, mixed, nullptr, c->M, c->M, g.nz, nfields,
            c->stream);
 }
 
@@ -381,33 +404,52 @@ static void mixed_to_phys(fcns_ctx* c, const cpx<double>* mixed, long long mstri
   const Geom& g = c->g;
   const long long plane = (long long)g.ny * g.nkxp;
   const long long xfs = (long long)nplanes * plane;
-  launch_y(yargs(c), c->big_y, true, 0, mixed, c->XYB, nullptr, mstride, xfs, nplanes, nfields,
+  launch_y<double>(yargs(c), c->big_y, true, 0, mixed, c->XYB, nullptr, mstride, xfs, nplanes, nfields,
            c->stream);
   launch_x_c2r(xargs(c), c->big_x, c->XYB, phys, xfs, (long long)nplanes * g.ny * g.nx,
                (long long)nplanes * g.ny, nfields, c->stream);
 }
 
 // nonlinear term of the fields whose mixed v_f, dv_f/dz are in mv (slots 2f,
-// 2f+1) into NLB (mixed if fwd_y, else (kx, y, z))
-static void nonlinear_from_mixed(fcns_ctx* c, const cpx<double>* mv, int nfields, bool fwd_y) {
+// 2f+1) into NLB (mixed if fwd_y, else (kx, y, z)); T is the transform and
+// storage type of MV / XYB / NLB.
+template <typename T>
+static void nonlinear_from_mixed(fcns_ctx* c, const cpx<T>* mv, int nfields, bool fwd_y) {
   const Geom& g = c->g;
   const long long M = c->M;
+  const bool f32 = sizeof(T) == sizeof(float);
+  cpx<T>* xyb = reinterpret_cast<cpx<T>*>(c->XYB);
+  cpx<T>* nlb = reinterpret_cast<cpx<T>*>(c->NLB);
   tbeg(c, T_YBACK_DY);
-  launch_y(yargs(c), c->big_y, true, 1, mv, c->XYB, c->XYB + M, 2 * M, 3 * M, g.nz, nfields,
-           c->stream);
+  launch_y<T>(yargs(c, f32), c->big_y, true, 1, mv, xyb, xyb + M, 2 * M, 3 * M, g.nz, nfields,
+              c->stream);
   tend(c);
   tbeg(c, T_YBACK_DZ);
-  launch_y(yargs(c), c->big_y, true, 0, mv + M, c->XYB + 2 * M, nullptr, 2 * M, 3 * M, g.nz,
-           nfields, c->stream);
+  launch_y<T>(yargs(c, f32), c->big_y, true, 0, mv + M, xyb + 2 * M, nullptr, 2 * M, 3 * M, g.nz,
+              nfields, c->stream);
   tend(c);
   tbeg(c, T_XNL);
-  launch_x_nl(xargs(c), c->big_x, c->XYB, c->NLB, M, (long long)g.nz * g.ny, nfields, c->stream);
+  launch_x_nl<T>(xargs(c, f32), c->big_x, xyb, nlb, M, (long long)g.nz * g.ny, nfields,
+                 c->stream);
   tend(c);
   if (fwd_y) {
     tbeg(c, T_YFWD);
-    launch_y(yargs(c), c->big_y, false, 0, c->NLB, c->NLB, nullptr, M, M, g.nz, nfields,
-             c->stream);
+    launch_y<T>(yargs(c, f32), c->big_y, false, 0, nlb, nlb, nullptr, M, M, g.nz, nfields,
+                c->stream);
     tend(c);
+  }
+}
+
+// the mixed v, dv/dz of the continued state src into MV, in the type the
+// rk_step pipeline reads (FP32 for a mixed-precision context)
+static void state_to_mv(fcns_ctx* c, const cpx<double>* src) {
+  if (c->mixed) {
+    cpx<float>* mv = reinterpret_cast<cpx<float>*>(c->MV);
+    launch_z_back<float>(zargs(c, true), c->big_z, src, mv, mv + c->M, c->S, 2 * c->M, c->nf,
+                         c->stream);
+  } else {
+    launch_z_back<double>(zargs(c), c->big_z, src, c->MV, c->MV + c->M, c->S, 2 * c->M, c->nf,
+                          c->stream);
   }
 }
 
@@ -441,7 +483,8 @@ static void mixed_to_state(fcns_ctx* c, const cpx<double>* mixed, int nfields, c
                            cpx<double>* mv) {
   launch_z_fwd(zargs(c), c->big_z, mixed, dst, c->M, c->S, nfields, 0, c->stream);
   if (mv)
-    launch_z_back(zargs(c), c->big_z, dst, mv, mv + c->M, c->S, 2 * c->M, nfields, c->stream);
+    launch_z_back<double>(zargs(c), c->big_z, dst, mv, mv + c->M, c->S, 2 * c->M, nfields,
+                          c->stream);
 }
 
 extern "C" fcns_status fcns_set_state(fcns_ctx* c, const double* v, const double* theta) {
@@ -450,7 +493,8 @@ extern "C" fcns_status fcns_set_state(fcns_ctx* c, const double* v, const double
   if (c->prob.boussinesq && !theta) return fail(c, FCNS_EINVAL, "theta required (Boussinesq)");
   phys_to_mixed(c, v, 3, c->XYB);
   if (c->nf == 4) phys_to_mixed(c, theta, 1, c->XYB + 3 * c->M);
-  mixed_to_state(c, c->XYB, c->nf, c->P, c->MV);
+  mixed_to_state(c, c->XYB, c->nf, c->P, nullptr);
+  state_to_mv(c, c->P);
   launch_fill(c->GW, 4 * c->g.npen, c->stream);
   fcns_status st = check_launch(c, "set_state");
   if (st == FCNS_OK) {
@@ -460,8 +504,14 @@ extern "C" fcns_status fcns_set_state(fcns_ctx* c, const double* v, const double
   return st;
 }
 
-// One RK stage j of o (Sec. 4.4), c = dt/(o-j+1).
+// One RK stage j of o (Sec. 4.4), c = dt/(o-j+1).  T: type of the transforms
+// and arrays of the nonlinear term (float in a mixed-precision context); the
+// continued state, the FC extension, stage A's transforms of the RK combine,
+// and the projection are FP64 throughout.
+template <typename T>
 static void rk_stage(fcns_ctx* c, int j, int o, double dt) {
+  const cpx<T>* mv = reinterpret_cast<const cpx<T>*>(c->MV);
+  const cpx<T>* nlb = reinterpret_cast<const cpx<T>*>(c->NLB);
   const Geom& g = c->g;
   const long long S = c->S, M = c->M;
   const int nf = c->nf;
@@ -469,19 +519,19 @@ static void rk_stage(fcns_ctx* c, int j, int o, double dt) {
   cpx<double>* W = (j == 1) ? c->P : c->Q;
   cpx<double>* OUT = (j == o) ? c->P : c->Q;
   // y-back, x-pass with products, y-fwd: nonlinear term in mixed space
-  nonlinear_from_mixed(c, c->MV, nf, true);
+  nonlinear_from_mixed<T>(c, mv, nf, true);
   // stage A: pressureless update, wall injection, FC re-extension
   StageAArgs A{};
   for (int f = 0; f < nf; ++f) {
-    A.nl[f] = c->NLB + f * M;
+    A.nl[f] = nlb + f * M;
     A.vt[f] = c->P + f * S;
     A.w[f] = W + f * S;
     A.out[f] = (f < 3) ? c->VS + f * S : OUT + f * S;
     A.buoy[f] = nullptr;
   }
   if (nf == 4) {
-    A.buoy[2] = c->MV + (2 * 3) * M;  // mixed theta of the previous stage
-    A.buoy[3] = c->MV + (2 * 2) * M;  // mixed w of the previous stage
+    A.buoy[2] = mv + (2 * 3) * M;  // mixed theta of the previous stage
+    A.buoy[3] = mv + (2 * 2) * M;  // mixed w of the previous stage
   }
   A.gwall = c->GW;
   A.c = cj;
@@ -490,7 +540,7 @@ static void rk_stage(fcns_ctx* c, int j, int o, double dt) {
   A.gamma = c->prob.gamma;
   A.forcing_sum = c->prob.forcing_x * (double)g.nx * (double)g.ny;
   tbeg(c, T_ZSTAGEA);
-  launch_z_stageA(zargs(c), c->big_z, A, nf, c->stream);
+  launch_z_stageA<T>(zargs(c), c->big_z, A, nf, c->stream);
   tend(c);
   // stage B: projection, next-stage wall gradient, mixed v and dv/dz
   StageBArgs B{};
@@ -506,7 +556,7 @@ static void rk_stage(fcns_ctx* c, int j, int o, double dt) {
   tend(c);
   // mixed v_f, dv_f/dz of the new state for the next stage's x/y passes
   tbeg(c, T_ZBACK);
-  launch_z_back(zargs(c), c->big_z, OUT, c->MV, c->MV + M, S, 2 * M, nf, c->stream);
+  state_to_mv(c, OUT);
   tend(c);
 }
 
@@ -516,7 +566,12 @@ extern "C" fcns_status fcns_rk_step(fcns_ctx* c, double dt, int32_t nsteps) {
   if (!(dt > 0.0) || nsteps < 0) return fail(c, FCNS_EINVAL, "need dt > 0 and nsteps >= 0");
   const int o = c->prob.rk_order;
   for (int n = 0; n < nsteps; ++n)
-    for (int j = 1; j <= o; ++j) rk_stage(c, j, o, dt);
+    for (int j = 1; j <= o; ++j) {
+      if (c->mixed)
+        rk_stage<float>(c, j, o, dt);
+      else
+        rk_stage<double>(c, j, o, dt);
+    }
   fcns_status st = check_launch(c, "rk_step");
   if (st == FCNS_OK && nsteps > 0 && c->prob.keep_pressure) c->has_pressure = true;
   return st;
@@ -530,7 +585,7 @@ extern "C" fcns_status fcns_get_state(fcns_ctx* c, double* v, double* theta, dou
   const long long M = c->M;
   if (v || theta) {
     // R IFFT of the continued state, then the inverse xy transforms
-    launch_z_back(zargs(c), c->big_z, c->P, c->MVT, nullptr, c->S, M, c->nf, c->stream);
+    launch_z_back<double>(zargs(c), c->big_z, c->P, c->MVT, nullptr, c->S, M, c->nf, c->stream);
     if (v) mixed_to_phys(c, c->MVT, M, 3, v, c->g.nz);
     if (theta && c->nf == 4) mixed_to_phys(c, c->MVT + 3 * M, M, 1, theta, c->g.nz);
   }
@@ -552,10 +607,10 @@ extern "C" fcns_status fcns_rhs_nonlinear(fcns_ctx* c, const double* v, const do
   phys_to_mixed(c, v, 3, c->XYB);
   if (theta) phys_to_mixed(c, theta, 1, c->XYB + 3 * M);
   mixed_to_state(c, c->XYB, nf, c->VS, c->MVT);
-  nonlinear_from_mixed(c, c->MVT, nf, filtered != 0);
+  nonlinear_from_mixed<double>(c, c->MVT, nf, filtered != 0);
   if (filtered) {
     launch_z_fwd(zargs(c), c->big_z, c->NLB, c->VS, M, c->S, nf, 1, c->stream);
-    launch_z_back(zargs(c), c->big_z, c->VS, c->NLB, nullptr, c->S, M, nf, c->stream);
+    launch_z_back<double>(zargs(c), c->big_z, c->VS, c->NLB, nullptr, c->S, M, nf, c->stream);
     mixed_to_phys(c, c->NLB, M, 3, nl_v, c->g.nz);
     if (theta) mixed_to_phys(c, c->NLB + 3 * M, M, 1, nl_theta, c->g.nz);
   } else {
@@ -586,7 +641,7 @@ extern "C" fcns_status fcns_pressure_project(fcns_ctx* c, const double* v_star, 
   B.pmix = nullptr;
   B.c = cj;
   launch_z_stageB(zargs(c), c->big_z, B, c->stream);
-  launch_z_back(zargs(c), c->big_z, c->VS, c->MVT, nullptr, S, M, 3, c->stream);
+  launch_z_back<double>(zargs(c), c->big_z, c->VS, c->MVT, nullptr, S, M, 3, c->stream);
   mixed_to_phys(c, c->MVT, M, 3, v_out, c->g.nz);
   if (gradp_wall) mixed_to_phys(c, c->GWT, 0, 1, gradp_wall, 4);
   return check_launch(c, "pressure_project");
@@ -628,7 +683,7 @@ extern "C" fcns_status fcns_set_spectral(fcns_ctx* c, const double* const* field
   } else {
     launch_fill(c->GW, 4 * c->g.npen, c->stream);
   }
-  launch_z_back(zargs(c), c->big_z, c->P, c->MV, c->MV + c->M, c->S, 2 * c->M, c->nf, c->stream);
+  state_to_mv(c, c->P);
   fcns_status st = check_launch(c, "set_spectral");
   if (st == FCNS_OK) {
     c->has_state = true;

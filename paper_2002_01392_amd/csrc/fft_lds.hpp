@@ -15,9 +15,9 @@
 // Codelets: radix 2, 4, 8 in closed form; odd primes use the symmetric form
 // of a prime-length DFT (a_q = x_q + x_{R-q}, b_q = x_q - x_{R-q}), which takes
 // (R-1)^2 real multiply-adds per pair of outputs instead of R^2 complex ones,
-// with cos and sin read at a wave-uniform index (LDS broadcast).  3, 5, 7, 29
-// and 47 are unrolled in registers; any other odd prime runs a compact loop
-// that reads its inputs from LDS.
+// with cos and sin read at a wave-uniform index (LDS broadcast).  3, 5 and 7
+// are unrolled in registers; larger odd primes run a stage that spreads each
+// butterfly's output pairs over the threads and reads its inputs from LDS.
 //
 // Twiddle table (built on the host, copied to LDS): for every stage with
 // ns > 1 the factors w^{m k}, stored [m-1][k] so that the lanes of a wave,
@@ -128,8 +128,6 @@ struct CodeletOdd {
 template <typename T> struct Codelet<T, 3> : CodeletOdd<T, 3> {};
 template <typename T> struct Codelet<T, 5> : CodeletOdd<T, 5> {};
 template <typename T> struct Codelet<T, 7> : CodeletOdd<T, 7> {};
-template <typename T> struct Codelet<T, 29> : CodeletOdd<T, 29> {};
-template <typename T> struct Codelet<T, 47> : CodeletOdd<T, 47> {};
 
 // j mod ns for 0 <= j < 2^24 without an integer division: the float quotient
 // is off by at most one, which the two corrections absorb.
@@ -177,8 +175,13 @@ __device__ __forceinline__ void fft_stage(const cpx<T>* __restrict__ src, cpx<T>
   }
 }
 
-// Any odd prime R at run time: twiddle the butterfly's own inputs in place in
-// src (no other thread reads them), then form each output pair from LDS.
+// Any odd prime R > 7 at run time, spread over the workgroup: a line of n
+// points has only n / R butterflies of this radix, too few to occupy the
+// threads, and one whole R-point DFT per thread would not fit in registers.
+// Phase 1 twiddles the inputs in place (one thread per butterfly input),
+// phase 2 gives each thread one output pair (X_k, X_{R-k}) (or X_0) of one
+// butterfly, read from LDS with the butterfly index fastest across lanes and
+// the root index wave-uniform.
 template <typename T, bool PAD>
 __device__ __forceinline__ void fft_stage_prime(cpx<T>* __restrict__ src, cpx<T>* __restrict__ dst,
                                                 int R, int L, int es, int ls, int n, int ns,
@@ -188,19 +191,29 @@ __device__ __forceinline__ void fft_stage_prime(cpx<T>* __restrict__ src, cpx<T>
   const int nb = L * nr;
   const int H = (R - 1) / 2;
   const float rcp = 1.0f / (float)ns;
-  for (int g = tid; g < nb; g += nt) {
-    const int l = g % L, j = g / L;
+  if (ns > 1) {
+    for (int g = tid; g < nb * (R - 1); g += nt) {
+      const int b = g % nb, m = 1 + g / nb;
+      const int l = b % L, j = b / L;
+      const int k = fast_mod(j, ns, rcp);
+      cpx<T>& x = src[lds_pos<PAD>(l, j + m * nr, es, ls)];
+      x = x * tws[(m - 1) * ns + k];
+    }
+    __syncthreads();
+  }
+  for (int g = tid; g < nb * (H + 1); g += nt) {
+    const int b = g % nb, kk = g / nb;
+    const int l = b % L, j = b / L;
     const int k = fast_mod(j, ns, rcp);
-    auto S = [&](int m) -> cpx<T>& { return src[lds_pos<PAD>(l, j + m * nr, es, ls)]; };
+    auto S = [&](int m) -> const cpx<T>& { return src[lds_pos<PAD>(l, j + m * nr, es, ls)]; };
     const int o = (j - k) * R + k;
     auto D = [&](int m) -> cpx<T>& { return dst[lds_pos<PAD>(l, o + m * ns, es, ls)]; };
-    if (ns > 1)
-      for (int m = 1; m < R; ++m) S(m) = S(m) * tws[(m - 1) * ns + k];
     const cpx<T> x0 = S(0);
-    cpx<T> sum = x0;
-    for (int q = 1; q <= H; ++q) sum = sum + S(q) + S(R - q);
-    D(0) = sum;
-    for (int kk = 1; kk <= H; ++kk) {
+    if (kk == 0) {
+      cpx<T> sum = x0;
+      for (int q = 1; q <= H; ++q) sum = sum + S(q) + S(R - q);
+      D(0) = sum;
+    } else {
       cpx<T> re = x0, im = zero<T>();
       int qk = 0;
       for (int q = 1; q <= H; ++q) {
@@ -222,8 +235,8 @@ __device__ __forceinline__ void fft_stage_prime(cpx<T>* __restrict__ src, cpx<T>
 // scratch of the same size; tw is the plan's twiddle table (in LDS).
 // Returns the buffer holding the result.  All threads of the workgroup must
 // call it, after a barrier that makes the input visible; it synchronises
-// before returning.  BIG: also dispatch radix 29, 47 and the run-time
-// odd-prime stage.  PAD: padded line layout (lds_pos).
+// before returning.  BIG: also dispatch the run-time stage for odd primes
+// above 7.  PAD: padded line layout (lds_pos).
 template <typename T, int L, bool BIG, bool PAD = false>
 __device__ __forceinline__ cpx<T>* fft_fwd(cpx<T>* buf0, cpx<T>* buf1, int es, int ls,
                                            const FFTPlan& pl, const cpx<T>* __restrict__ tw,
@@ -244,14 +257,7 @@ __device__ __forceinline__ cpx<T>* fft_fwd(cpx<T>* buf0, cpx<T>* buf1, int es, i
       case 7: fft_stage<T, 7, PAD>(src, dst, L, es, ls, n, ns, tws, cw, tid, nt); break;
       case 8: fft_stage<T, 8, PAD>(src, dst, L, es, ls, n, ns, tws, cw, tid, nt); break;
       default:
-        if constexpr (BIG) {
-          if (r == 29)
-            fft_stage<T, 29, PAD>(src, dst, L, es, ls, n, ns, tws, cw, tid, nt);
-          else if (r == 47)
-            fft_stage<T, 47, PAD>(src, dst, L, es, ls, n, ns, tws, cw, tid, nt);
-          else
-            fft_stage_prime<T, PAD>(src, dst, r, L, es, ls, n, ns, tws, cw, tid, nt);
-        }
+        if constexpr (BIG) fft_stage_prime<T, PAD>(src, dst, r, L, es, ls, n, ns, tws, cw, tid, nt);
         break;
     }
     __syncthreads();

@@ -39,12 +39,13 @@ struct ZArgs {
   const double* sigz;
 };
 
+// Mixed-space arrays (nl, buoy) hold cpx<T> of the kernel's transform type T.
 struct StageAArgs {
-  const cpx<double>* nl[4];   // mixed nonlinear term per field
+  const void* nl[4];          // mixed nonlinear term per field
   const cpx<double>* vt[4];   // continued state at t
   const cpx<double>* w[4];    // continued state of the previous stage
   cpx<double>* out[4];        // V* (velocity) or Theta^(j) (temperature)
-  const cpx<double>* buoy[4]; // mixed theta (for w) / w (for theta), or null
+  const void* buoy[4];        // mixed theta (for w) / w (for theta), or null
   const cpx<double>* gwall;   // [2 walls][2 comps][npen], p units
   double c;                   // stage coefficient c_j
   double nu, kappa, gamma;
@@ -74,7 +75,7 @@ struct XArgs {
 };
 
 int z_max_npr();
-size_t y_lds_bytes(int ny, int tsize);  // LDS of one y-pass workgroup
+size_t y_lds_bytes(int ny, int tsize, size_t elem);  // LDS of one y-pass workgroup
 size_t z_lds_bytes(const Geom& g);
 
 // Dynamic LDS above 64 KiB needs an explicit per-kernel opt-in.
@@ -92,9 +93,15 @@ inline void allow_lds(K kernel, size_t bytes) {
 
 void launch_z_fwd(const ZArgs& a, bool big, const cpx<double>* src, cpx<double>* dst,
                   long long sfs, long long dfs, int nfields, int filter, hipStream_t st);
-void launch_z_back(const ZArgs& a, bool big, const cpx<double>* src, cpx<double>* dst,
-                   cpx<double>* dzdst, long long sfstride, long long mfstride, int nfields,
-                   hipStream_t st);
+// T: transform type and mixed-space storage (double, or float for the mixed
+// precision step); the continued state is always double.  The ZArgs / YArgs /
+// XArgs twiddle table must be the one of type T.
+template <typename T>
+void launch_z_back(const ZArgs& a, bool big, const cpx<double>* src, cpx<T>* dst, cpx<T>* dzdst,
+                   long long sfstride, long long mfstride, int nfields, hipStream_t st);
+// stage A transforms in FP64 always (it forms V*, which the projection
+// needs to full precision); TM is the storage of its mixed-space inputs.
+template <typename TM>
 void launch_z_stageA(const ZArgs& a, bool big, const StageAArgs& s, int nfields, hipStream_t st);
 void launch_z_stageB(const ZArgs& a, bool big, const StageBArgs& s, hipStream_t st);
 void launch_fc_extend(const double* in, long long nlines, long long ips, long long ils, double* out,
@@ -107,9 +114,10 @@ void launch_fc_derivative(const ZArgs& a, bool big, const double* in, double* ou
 // y: lines are (plane, kx) pairs, element ky; arrays [nplanes][ny][nkxp].
 // mode 0: dst = FFT (inverse scaled by 1/ny); mode 1 (inverse only): also
 // dst2 = inverse FFT of i k~y times the input.
-void launch_y(const YArgs& a, bool big, bool inv, int mode, const cpx<double>* src,
-              cpx<double>* dst, cpx<double>* dst2, long long sfstride, long long dfstride,
-              int nplanes, int nfields, hipStream_t st);
+template <typename T>
+void launch_y(const YArgs& a, bool big, bool inv, int mode, const cpx<T>* src, cpx<T>* dst,
+              cpx<T>* dst2, long long sfstride, long long dfstride, int nplanes, int nfields,
+              hipStream_t st);
 // x: rows are (plane, y) pairs; physical rows of nx reals <-> nkx complex
 // (row stride nkxp).
 void launch_x_r2c(const XArgs& a, bool big, const double* phys, cpx<double>* xy,
@@ -120,8 +128,9 @@ void launch_x_c2r(const XArgs& a, bool big, const cpx<double>* xy, double* phys,
                   hipStream_t st);
 // fused c2r + products + r2c: xyb holds, per field f, q_f, dq_f/dy, dq_f/dz at
 // field slots 3f, 3f+1, 3f+2; nl gets -(v.grad) q_f at slot f.
-void launch_x_nl(const XArgs& a, bool big, const cpx<double>* xyb, cpx<double>* nl,
-                 long long fstride, long long nrows, int nfields, hipStream_t st);
+template <typename T>
+void launch_x_nl(const XArgs& a, bool big, const cpx<T>* xyb, cpx<T>* nl, long long fstride,
+                 long long nrows, int nfields, hipStream_t st);
 
 // small helpers
 void launch_fill(cpx<double>* p, long long n, hipStream_t st);

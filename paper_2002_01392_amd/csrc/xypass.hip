@@ -20,14 +20,14 @@ namespace fcns {
 // (inverse only): a second pass transforms i k~y times the input into dst2.
 __host__ __device__ inline int y_span(int ny) { return YL * (ny + ny / 8 + 1); }
 
-size_t y_lds_bytes(int ny, int tsize) {
-  return ((size_t)tsize + 2 * (size_t)y_span(ny)) * sizeof(cpx<double>);
+size_t y_lds_bytes(int ny, int tsize, size_t elem) {
+  return ((size_t)tsize + 2 * (size_t)y_span(ny)) * elem;
 }
 
 template <typename T, class FP, int OWN>
-__global__ __launch_bounds__(YNT) void k_y(YArgs a, const cpx<double>* src, cpx<double>* dst,
-                                           cpx<double>* dst2, long long sfs, long long dfs,
-                                           long long nlines, int inv, int mode) {
+__global__ __launch_bounds__(YNT) void k_y(YArgs a, const cpx<T>* src, cpx<T>* dst, cpx<T>* dst2,
+                                           long long sfs, long long dfs, long long nlines, int inv,
+                                           int mode) {
   extern __shared__ __align__(16) char smem[];
   const int tid = threadIdx.x;
   const int ny = FP::dynamic ? a.ny : FP::n;
@@ -43,9 +43,9 @@ __global__ __launch_bounds__(YNT) void k_y(YArgs a, const cpx<double>* src, cpx<
   const int l = tid % YL, ky0 = tid / YL;
   constexpr int KYS = YNT / YL;
   const long long ntiles = (nlines + YL - 1) / YL;
-  const double sc = inv ? 1.0 / ny : 1.0;
+  const T sc = inv ? T(1) / (T)ny : T(1);
   const int npass = (mode == 1) ? 2 : 1;
-  cpx<double> cur[OWN], nxt[OWN];
+  cpx<T> cur[OWN], nxt[OWN];
   long long t = blockIdx.x;
   auto line_base = [&](long long tt, bool& ok) {
     const long long q = tt * YL + l;
@@ -59,7 +59,7 @@ __global__ __launch_bounds__(YNT) void k_y(YArgs a, const cpx<double>* src, cpx<
 #pragma unroll
     for (int r = 0; r < OWN; ++r) {
       const int ky = ky0 + r * KYS;
-      cur[r] = (ok && ky < ny) ? src[base + (long long)ky * nkxp] : zero<double>();
+      cur[r] = (ok && ky < ny) ? src[base + (long long)ky * nkxp] : zero<T>();
     }
   }
   for (; t < ntiles; t += gridDim.x) {
@@ -70,27 +70,27 @@ __global__ __launch_bounds__(YNT) void k_y(YArgs a, const cpx<double>* src, cpx<
 #pragma unroll
     for (int r = 0; r < OWN; ++r) {
       const int ky = ky0 + r * KYS;
-      nxt[r] = (okn && ky < ny) ? src[basen + (long long)ky * nkxp] : zero<double>();
+      nxt[r] = (okn && ky < ny) ? src[basen + (long long)ky * nkxp] : zero<T>();
     }
     for (int pass = 0; pass < npass; ++pass) {
 #pragma unroll
       for (int r = 0; r < OWN; ++r) {
         const int ky = ky0 + r * KYS;
         if (ky < ny) {
-          cpx<double> v = cur[r];
-          if (pass == 1) v = mul_i(v) * k_odd(ky, ny, a.kys);
-          X0[lds_pos<true>(l, ky, YL, 1)] = cvt<T>(inv ? conj(v) : v);
+          cpx<T> v = cur[r];
+          if (pass == 1) v = mul_i(v) * (T)k_odd(ky, ny, a.kys);
+          X0[lds_pos<true>(l, ky, YL, 1)] = inv ? conj(v) : v;
         }
       }
       __syncthreads();
       const cpx<T>* R = fft_run<T, YL, YNT, true, FP>(X0, X1, YL, 1, a.pl, tw, tid);
-      cpx<double>* out = pass ? dst2 : dst;
+      cpx<T>* out = pass ? dst2 : dst;
       if (ok) {
 #pragma unroll
         for (int r = 0; r < OWN; ++r) {
           const int ky = ky0 + r * KYS;
           if (ky < ny) {
-            const cpx<double> v = cvt<double>(R[lds_pos<true>(l, ky, YL, 1)]);
+            const cpx<T> v = R[lds_pos<true>(l, ky, YL, 1)];
             out[base + (long long)ky * nkxp] = (inv ? conj(v) : v) * sc;
           }
         }
@@ -231,8 +231,8 @@ __global__ __launch_bounds__(XNT) void k_x_c2r(XArgs a, const cpx<double>* __res
 // columns n = tid + c NT (c < CC, CC NT >= nx) of its RR rows; each thread
 // loads the next pass's spectral inputs while the current pass is transformed.
 template <typename T, class FP, int RR, int NT, int CC>
-__global__ __launch_bounds__(NT) void k_x_nl(XArgs a, const cpx<double>* __restrict__ xyb,
-                                             cpx<double>* __restrict__ nl, long long fs,
+__global__ __launch_bounds__(NT) void k_x_nl(XArgs a, const cpx<T>* __restrict__ xyb,
+                                             cpx<T>* __restrict__ nl, long long fs,
                                              long long nrows, int nfields) {
   constexpr int LL = RR / 2;
   extern __shared__ __align__(16) char smem[];
@@ -246,10 +246,10 @@ __global__ __launch_bounds__(NT) void k_x_nl(XArgs a, const cpx<double>* __restr
   const cpx<T>* gtw = reinterpret_cast<const cpx<T>*>(a.tw);
   for (int i = tid; i < a.pl.tsize; i += NT) tw[i] = gtw[i];
   const long long r0 = (long long)blockIdx.x * RR;
-  const double sc = 1.0 / nx;
-  double U[3][CC][RR];
-  double acc[CC][RR];
-  cpx<double> in[CC][RR];
+  const T sc = T(1) / (T)nx;
+  T U[3][CC][RR];
+  T acc[CC][RR];
+  cpx<T> in[CC][RR];
   // source slot of c2r pass p (-1: forward pass)
   auto slot = [&](int p) {
     if (p < 3) return 3 * p;
@@ -259,13 +259,13 @@ __global__ __launch_bounds__(NT) void k_x_nl(XArgs a, const cpx<double>* __restr
   auto load = [&](int p) {
     const int sl = slot(p);
     if (sl < 0) return;
-    const cpx<double>* src = xyb + sl * fs;
+    const cpx<T>* src = xyb + sl * fs;
 #pragma unroll
     for (int c = 0; c < CC; ++c) {
       const int k = tid + c * NT;
 #pragma unroll
       for (int r = 0; r < RR; ++r)
-        in[c][r] = (k < nkx && r0 + r < nrows) ? src[(r0 + r) * nkxp + k] : zero<double>();
+        in[c][r] = (k < nkx && r0 + r < nrows) ? src[(r0 + r) * nkxp + k] : zero<T>();
     }
   };
   const int npass = 3 + 4 * nfields;
@@ -279,21 +279,21 @@ __global__ __launch_bounds__(NT) void k_x_nl(XArgs a, const cpx<double>* __restr
       for (int c = 0; c < CC; ++c) {
         const int k = tid + c * NT;
         if (k < nkx) {
-          const double kx = (2 * k == nx) ? 0.0 : a.kxs * k;
+          const T kx = (2 * k == nx) ? T(0) : (T)(a.kxs * k);
 #pragma unroll
           for (int al = 0; al < LL; ++al) {
-            cpx<double> A = in[c][2 * al], B = in[c][2 * al + 1];
+            cpx<T> A = in[c][2 * al], B = in[c][2 * al + 1];
             if (dx) {
               A = mul_i(A) * kx;
               B = mul_i(B) * kx;
             }
             if (k == 0 || 2 * k == nx) {
-              A.y = 0.0;
-              B.y = 0.0;
+              A.y = T(0);
+              B.y = T(0);
             }
             // Z[k] = A + i B, Z[nx - k] = conj(A) + i conj(B); stored conjugated
-            X0[xp(al, k, ls)] = cvt<T>(conj(mk(A.x - B.y, A.y + B.x)));
-            if (k > 0 && 2 * k < nx) X0[xp(al, nx - k, ls)] = cvt<T>(conj(mk(A.x + B.y, B.x - A.y)));
+            X0[xp(al, k, ls)] = conj(mk(A.x - B.y, A.y + B.x));
+            if (k > 0 && 2 * k < nx) X0[xp(al, nx - k, ls)] = conj(mk(A.x + B.y, B.x - A.y));
           }
         }
       }
@@ -304,7 +304,7 @@ __global__ __launch_bounds__(NT) void k_x_nl(XArgs a, const cpx<double>* __restr
         if (n < nx) {
 #pragma unroll
           for (int al = 0; al < LL; ++al)
-            X0[xp(al, n, ls)] = mk((T)acc[c][2 * al], (T)acc[c][2 * al + 1]);
+            X0[xp(al, n, ls)] = mk(acc[c][2 * al], acc[c][2 * al + 1]);
         }
       }
     }
@@ -319,12 +319,12 @@ __global__ __launch_bounds__(NT) void k_x_nl(XArgs a, const cpx<double>* __restr
       for (int c = 0; c < CC; ++c) {
         const int n = tid + c * NT;
         if (n >= nx) continue;
-        double v[RR];
+        T v[RR];
 #pragma unroll
         for (int al = 0; al < LL; ++al) {
           const cpx<T> z = R[xp(al, n, ls)];
-          v[2 * al] = (double)z.x * sc;
-          v[2 * al + 1] = -(double)z.y * sc;
+          v[2 * al] = z.x * sc;
+          v[2 * al + 1] = -z.y * sc;
         }
         if (pass < 3) {
 #pragma unroll
@@ -336,7 +336,7 @@ __global__ __launch_bounds__(NT) void k_x_nl(XArgs a, const cpx<double>* __restr
         } else {
 #pragma unroll
           for (int r = 0; r < RR; ++r) {
-            const double u = (kk == 0) ? U[0][c][r] : ((kk == 1) ? U[1][c][r] : U[2][c][r]);
+            const T u = (kk == 0) ? U[0][c][r] : ((kk == 1) ? U[1][c][r] : U[2][c][r]);
             if (kk == 0) acc[c][r] = -u * v[r];
             else acc[c][r] -= u * v[r];
           }
@@ -347,12 +347,12 @@ __global__ __launch_bounds__(NT) void k_x_nl(XArgs a, const cpx<double>* __restr
 #pragma unroll
       for (int al = 0; al < LL; ++al) {
         const long long ra = r0 + 2 * al, rb = ra + 1;
-        cpx<double>* dst = nl + f * fs;
+        cpx<T>* dst = nl + f * fs;
         for (int k = tid; k < nkx; k += NT) {
-          const cpx<double> Z = cvt<double>(R[xp(al, k, ls)]);
-          const cpx<double> Zm = conj(cvt<double>(R[xp(al, ((k == 0) ? 0 : nx - k), ls)]));
-          if (ra < nrows) dst[ra * nkxp + k] = (Z + Zm) * 0.5;
-          if (rb < nrows) dst[rb * nkxp + k] = mul_mi(Z - Zm) * 0.5;
+          const cpx<T> Z = R[xp(al, k, ls)];
+          const cpx<T> Zm = conj(R[xp(al, ((k == 0) ? 0 : nx - k), ls)]);
+          if (ra < nrows) dst[ra * nkxp + k] = (Z + Zm) * T(0.5);
+          if (rb < nrows) dst[rb * nkxp + k] = mul_mi(Z - Zm) * T(0.5);
         }
       }
     }
@@ -385,17 +385,18 @@ __global__ void k_sub_mean00(cpx<double>* pmix, long long npen, int nz) {
 }
 
 // ---------------------------------------------------------------- launchers
-void launch_y(const YArgs& a, bool big, bool inv, int mode, const cpx<double>* src,
-              cpx<double>* dst, cpx<double>* dst2, long long sfs, long long dfs, int nplanes,
-              int nfields, hipStream_t st) {
+template <typename T>
+void launch_y(const YArgs& a, bool big, bool inv, int mode, const cpx<T>* src, cpx<T>* dst,
+              cpx<T>* dst2, long long sfs, long long dfs, int nplanes, int nfields,
+              hipStream_t st) {
   const long long nlines = (long long)nplanes * a.nkxp;
   const long long ntiles = (nlines + YL - 1) / YL;
   dim3 grid((unsigned)(ntiles < Y_GRID ? ntiles : Y_GRID), nfields);
-  const size_t sh = y_lds_bytes(a.ny, a.pl.tsize);
+  const size_t sh = y_lds_bytes(a.ny, a.pl.tsize, sizeof(cpx<T>));
   const int need = (a.ny + YNT / YL - 1) / (YNT / YL);
   const int iv = inv ? 1 : 0;
 #define FCNS_Y(FPV, OWNV)                                                                    \
-  FCNS_LAUNCH((k_y<double, FPV, OWNV>), grid, dim3(YNT), sh, st, a, src, dst, dst2, sfs, \
+  FCNS_LAUNCH((k_y<T, FPV, OWNV>), grid, dim3(YNT), sh, st, a, src, dst, dst2, sfs, \
                      dfs, nlines, iv, mode)
   if (a.ny == 512 && plan_is(a.pl, {8, 8, 8})) {
     using P512 = SPlan<8, 8, 8>;
@@ -410,6 +411,10 @@ void launch_y(const YArgs& a, bool big, bool inv, int mode, const cpx<double>* s
   }
 #undef FCNS_Y
 }
+template void launch_y<double>(const YArgs&, bool, bool, int, const cpx<double>*, cpx<double>*,
+                               cpx<double>*, long long, long long, int, int, hipStream_t);
+template void launch_y<float>(const YArgs&, bool, bool, int, const cpx<float>*, cpx<float>*,
+                              cpx<float>*, long long, long long, int, int, hipStream_t);
 
 void launch_x_r2c(const XArgs& a, bool big, const double* phys, cpx<double>* xy, long long pfs,
                   long long xfs, long long nrows, int nfields, hipStream_t st) {
@@ -431,27 +436,32 @@ void launch_x_c2r(const XArgs& a, bool big, const cpx<double>* xy, double* phys,
     FCNS_LAUNCH((k_x_c2r<double, false>), grid, dim3(XNT), sh, st, a, xy, phys, xfs, pfs, nrows);
 }
 
-template <class FP, int RR, int NT, int CC>
-static void launch_x_nl_v(const XArgs& a, const cpx<double>* xyb, cpx<double>* nl, long long fs,
+template <typename T, class FP, int RR, int NT, int CC>
+static void launch_x_nl_v(const XArgs& a, const cpx<T>* xyb, cpx<T>* nl, long long fs,
                           long long nrows, int nfields, hipStream_t st) {
   dim3 grid((unsigned)((nrows + RR - 1) / RR));
-  const size_t sh = ((size_t)a.pl.tsize + 2 * (RR / 2) * x_ls(a.nx)) * sizeof(cpx<double>);
-  FCNS_LAUNCH((k_x_nl<double, FP, RR, NT, CC>), grid, dim3(NT), sh, st, a, xyb, nl, fs, nrows,
+  const size_t sh = ((size_t)a.pl.tsize + 2 * (RR / 2) * x_ls(a.nx)) * sizeof(cpx<T>);
+  FCNS_LAUNCH((k_x_nl<T, FP, RR, NT, CC>), grid, dim3(NT), sh, st, a, xyb, nl, fs, nrows,
               nfields);
 }
 
 // 4 rows x 256 threads; compile-time plans for nx = 512 and 256
-void launch_x_nl(const XArgs& a, bool big, const cpx<double>* xyb, cpx<double>* nl,
-                 long long fs, long long nrows, int nfields, hipStream_t st) {
+template <typename T>
+void launch_x_nl(const XArgs& a, bool big, const cpx<T>* xyb, cpx<T>* nl, long long fs,
+                 long long nrows, int nfields, hipStream_t st) {
   if (a.nx == 512 && plan_is(a.pl, {8, 8, 8}))
-    launch_x_nl_v<SPlan<8, 8, 8>, 4, 256, 2>(a, xyb, nl, fs, nrows, nfields, st);
+    launch_x_nl_v<T, SPlan<8, 8, 8>, 4, 256, 2>(a, xyb, nl, fs, nrows, nfields, st);
   else if (a.nx == 256 && plan_is(a.pl, {8, 8, 4}))
-    launch_x_nl_v<SPlan<8, 8, 4>, 4, 256, 1>(a, xyb, nl, fs, nrows, nfields, st);
+    launch_x_nl_v<T, SPlan<8, 8, 4>, 4, 256, 1>(a, xyb, nl, fs, nrows, nfields, st);
   else if (big)
-    launch_x_nl_v<DynPlan<true>, 4, 256, 2>(a, xyb, nl, fs, nrows, nfields, st);
+    launch_x_nl_v<T, DynPlan<true>, 4, 256, 2>(a, xyb, nl, fs, nrows, nfields, st);
   else
-    launch_x_nl_v<DynPlan<false>, 4, 256, 2>(a, xyb, nl, fs, nrows, nfields, st);
+    launch_x_nl_v<T, DynPlan<false>, 4, 256, 2>(a, xyb, nl, fs, nrows, nfields, st);
 }
+template void launch_x_nl<double>(const XArgs&, bool, const cpx<double>*, cpx<double>*, long long,
+                                  long long, int, hipStream_t);
+template void launch_x_nl<float>(const XArgs&, bool, const cpx<float>*, cpx<float>*, long long,
+                                 long long, int, hipStream_t);
 
 void launch_fill(cpx<double>* p, long long n, hipStream_t st) {
   const int nt = 256;

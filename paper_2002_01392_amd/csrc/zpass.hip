@@ -131,8 +131,8 @@ __global__ __launch_bounds__(ZNT) void k_z_fwd(ZArgs a, const cpx<double>* __res
 // continued spectral -> mixed: B_z = R o IFFT (and B_z(i k~z .) into dzdst).
 template <typename T, class FP, int OWN>
 __global__ __launch_bounds__(ZNT) void k_z_back(ZArgs a, const cpx<double>* __restrict__ src,
-                                                cpx<double>* __restrict__ dst,
-                                                cpx<double>* __restrict__ dzdst,
+                                                cpx<T>* __restrict__ dst,
+                                                cpx<T>* __restrict__ dzdst,
                                                 long long sfs, long long mfs) {
   extern __shared__ __align__(16) char smem[];
   const int tid = threadIdx.x;
@@ -168,21 +168,22 @@ __global__ __launch_bounds__(ZNT) void k_z_back(ZArgs a, const cpx<double>* __re
     }
     __syncthreads();
     const cpx<T>* R = fft_run<T, ZPB, ZNT, false, FP>(L.X0, L.X1, ZPB, 1, a.pl, L.tw, tid);
-    cpx<double>* __restrict__ out = pass ? dzdst : dst;
+    cpx<T>* __restrict__ out = pass ? dzdst : dst;
     if (pv)
       for (int z = lt; z < g.nz; z += ZLS)
-        out[(long long)z * g.npen + p] = conj(cvt<double>(R[z * ZPB + pb])) * inv;
+        out[(long long)z * g.npen + p] = conj(R[z * ZPB + pb]) * (T)inv;
     __syncthreads();
   }
 }
 
 // ---------------------------------------------------------------- stage A
-// One field per blockIdx.y (0..2 velocity, 3 temperature).  Sec. 4.4 steps
+// One field per blockIdx.y (0..2 velocity, 3 temperature); T: transform type,
+// TM: storage of the mixed-space inputs (NL, buoyancy).  Sec. 4.4 steps
 // 1-3 up to the FC-Gram transform of v*:
 //   N = sigma F_z(NL);  S = V^t + c (N - diff |k|^2 W);  v* = B_z S, plus the
 //   body force / buoyancy at the physical points, then the wall injection
 //   v*_par = c grad_par p_prev (theta = 0) and V* = F_z v*.
-template <typename T, class FP, int OWN>
+template <typename T, typename TM, class FP, int OWN>
 __global__ __launch_bounds__(ZNT) void k_z_stageA(ZArgs a, StageAArgs s) {
   extern __shared__ __align__(16) char smem[];
   const int tid = threadIdx.x;
@@ -192,10 +193,10 @@ __global__ __launch_bounds__(ZNT) void k_z_stageA(ZArgs a, StageAArgs s) {
   const int f = blockIdx.y;
   const long long p0 = (long long)blockIdx.x * ZPB;
   z_setup<T>(L, a, tid);
-  const cpx<double>* __restrict__ nl = s.nl[f];
+  const cpx<TM>* __restrict__ nl = reinterpret_cast<const cpx<TM>*>(s.nl[f]);
   const cpx<double>* __restrict__ vt = s.vt[f];
   const cpx<double>* __restrict__ w = s.w[f];
-  const cpx<double>* __restrict__ buoy = s.buoy[f];
+  const cpx<TM>* __restrict__ buoy = reinterpret_cast<const cpx<TM>*>(s.buoy[f]);
   const double c = s.c;
   const double diff = (f == 3) ? s.kappa : s.nu;
   const double inv = 1.0 / npr;
@@ -252,7 +253,7 @@ __global__ __launch_bounds__(ZNT) void k_z_stageA(ZArgs a, StageAArgs s) {
         if (pv) {
           v = conj(cvt<double>(R[e])) * inv;
           if (f == 0 && p == 0) v.x += c * s.forcing_sum;
-          if (buoy) v = v + buoy[(long long)z * g.npen + p] * (c * s.gamma);
+          if (buoy) v = v + cvt<double>(buoy[(long long)z * g.npen + p]) * (c * s.gamma);
           if (z == 0 || z == g.nz - 1) {
             const int wall = (z == 0) ? 0 : 1;
             if (f < 2) v = s.gwall[(wall * 2 + f) * g.npen + p] * c;
@@ -544,37 +545,45 @@ void launch_z_fwd(const ZArgs& a, bool big, const cpx<double>* src, cpx<double>*
 using P288 = SPlan<8, 4, 3, 3>;
 static bool z_static_288(const ZArgs& a) { return a.g.npr == 288 && plan_is(a.pl, {8, 4, 3, 3}); }
 
-void launch_z_back(const ZArgs& a, bool big, const cpx<double>* src, cpx<double>* dst,
-                   cpx<double>* dzdst, long long sfs, long long mfs, int nfields,
-                   hipStream_t st) {
+template <typename T>
+void launch_z_back(const ZArgs& a, bool big, const cpx<double>* src, cpx<T>* dst, cpx<T>* dzdst,
+                   long long sfs, long long mfs, int nfields, hipStream_t st) {
   dim3 grid((unsigned)((a.g.npen + ZPB - 1) / ZPB), nfields);
-  const size_t sh = zshared_bytes<double>(a.g, a.pl.tsize);
+  const size_t sh = zshared_bytes<T>(a.g, a.pl.tsize);
   const int own = pick_own(a.g.npr);
   if (z_static_288(a)) {
-    FCNS_LAUNCH((k_z_back<double, P288, 9>), grid, dim3(ZNT), sh, st, a, src, dst, dzdst, sfs, mfs);
+    FCNS_LAUNCH((k_z_back<T, P288, 9>), grid, dim3(ZNT), sh, st, a, src, dst, dzdst, sfs, mfs);
   } else if (big) {
-    FCNS_OWN_SWITCH(own, FCNS_LAUNCH((k_z_back<double, DynPlan<true>, OWN>), grid, dim3(ZNT), sh,
-                                     st, a, src, dst, dzdst, sfs, mfs))
+    FCNS_OWN_SWITCH(own, FCNS_LAUNCH((k_z_back<T, DynPlan<true>, OWN>), grid, dim3(ZNT), sh, st,
+                                     a, src, dst, dzdst, sfs, mfs))
   } else {
-    FCNS_OWN_SWITCH(own, FCNS_LAUNCH((k_z_back<double, DynPlan<false>, OWN>), grid, dim3(ZNT), sh,
-                                     st, a, src, dst, dzdst, sfs, mfs))
+    FCNS_OWN_SWITCH(own, FCNS_LAUNCH((k_z_back<T, DynPlan<false>, OWN>), grid, dim3(ZNT), sh, st,
+                                     a, src, dst, dzdst, sfs, mfs))
   }
 }
+template void launch_z_back<double>(const ZArgs&, bool, const cpx<double>*, cpx<double>*,
+                                    cpx<double>*, long long, long long, int, hipStream_t);
+template void launch_z_back<float>(const ZArgs&, bool, const cpx<double>*, cpx<float>*,
+                                   cpx<float>*, long long, long long, int, hipStream_t);
 
+template <typename TM>
 void launch_z_stageA(const ZArgs& a, bool big, const StageAArgs& s, int nfields, hipStream_t st) {
+  using T = double;
   dim3 grid((unsigned)((a.g.npen + ZPB - 1) / ZPB), nfields);
-  const size_t sh = zshared_bytes<double>(a.g, a.pl.tsize);
+  const size_t sh = zshared_bytes<T>(a.g, a.pl.tsize);
   const int own = pick_own(a.g.npr);
   if (z_static_288(a)) {
-    FCNS_LAUNCH((k_z_stageA<double, P288, 9>), grid, dim3(ZNT), sh, st, a, s);
+    FCNS_LAUNCH((k_z_stageA<T, TM, P288, 9>), grid, dim3(ZNT), sh, st, a, s);
   } else if (big) {
-    FCNS_OWN_SWITCH(own, FCNS_LAUNCH((k_z_stageA<double, DynPlan<true>, OWN>), grid, dim3(ZNT), sh,
+    FCNS_OWN_SWITCH(own, FCNS_LAUNCH((k_z_stageA<T, TM, DynPlan<true>, OWN>), grid, dim3(ZNT), sh,
                                      st, a, s))
   } else {
-    FCNS_OWN_SWITCH(own, FCNS_LAUNCH((k_z_stageA<double, DynPlan<false>, OWN>), grid, dim3(ZNT),
+    FCNS_OWN_SWITCH(own, FCNS_LAUNCH((k_z_stageA<T, TM, DynPlan<false>, OWN>), grid, dim3(ZNT),
                                      sh, st, a, s))
   }
 }
+template void launch_z_stageA<double>(const ZArgs&, bool, const StageAArgs&, int, hipStream_t);
+template void launch_z_stageA<float>(const ZArgs&, bool, const StageAArgs&, int, hipStream_t);
 
 void launch_z_stageB(const ZArgs& a, bool big, const StageBArgs& s, hipStream_t st) {
   dim3 grid((unsigned)((a.g.npen + ZPB - 1) / ZPB), 1);

@@ -1,0 +1,85 @@
+"""Mixed-precision step (nonlinear term in FP32: its transforms, products and
+mixed-space arrays; FP64 state, FC extension, the transforms that form v*,
+and the projection) against the FP64 oracle, per field.
+
+Stated bounds (relative L2 after the runs below): 2e-6 for the velocity and
+temperature, 2e-5 for the pressure.  FP32 rounding (6e-8 per operation,
+~1e-6 after the four transforms and the products) enters only through
+c * N, the nonlinear increment of each stage.
+"""
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle.ns import Oracle, Problem
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+TOL_FIELD = 2e-6
+TOL_P = 2e-5
+
+
+@pytest.fixture(scope="module")
+def fcns():
+    if not torch.cuda.is_available():
+        pytest.skip("no HIP device")
+    import paper_2002_01392_amd as P
+    P.load_library()
+    return P
+
+
+def rel_l2(a, b):
+    a = a.detach().cpu().numpy() if hasattr(a, "detach") else np.asarray(a)
+    b = np.asarray(b)
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+def _mixed_vs_oracle(fcns, w, steps):
+    v0, th0 = w.initial_state()
+    s = fcns.Solver.from_workload(w, keep_pressure=True, precision="mixed")
+    s.set_state(torch.from_numpy(v0), torch.from_numpy(th0) if th0 is not None else None)
+    s.rk_step(w.dt, steps)
+    v, th, p = s.get_state(pressure=True)
+    torch.cuda.synchronize()
+    o = Oracle(Problem(**w.problem_kwargs()))
+    o.set_state(v0, th0)
+    o.rk_step(w.dt, steps)
+    rv, rth, rp = o.get_state()
+    err = {c: rel_l2(v[i], rv[i]) for i, c in enumerate("uvw")}
+    err["p"] = rel_l2(p, rp)
+    if th is not None:
+        err["theta"] = rel_l2(th, rth)
+    print(w.name, steps, "steps, mixed vs FP64 oracle:", err)
+    return err
+
+
+def test_mixed_channel_small(fcns):
+    w = W.get("channel_32x32x33")
+    err = _mixed_vs_oracle(fcns, w, w.steps)
+    for c in "uvw":
+        assert err[c] < TOL_FIELD, err
+    assert err["p"] < TOL_P, err
+    # and it is really reduced precision: far from the FP64 agreement
+    assert max(err[c] for c in "uvw") > 1e-10
+
+
+def test_mixed_rayleigh_benard_small(fcns):
+    w = W.rayleigh_benard(32, 24, 33, 1e5, C=31, dt=2e-3, steps=8, kmax=3, mmax=3,
+                          noise_rms=1e-2)
+    err = _mixed_vs_oracle(fcns, w, w.steps)
+    for c in ("u", "v", "w", "theta"):
+        assert err[c] < TOL_FIELD, err
+    assert err["p"] < TOL_P, err
+
+
+@pytest.mark.parametrize("nx,ny,nz,C", [(256, 16, 257, 31), (16, 256, 17, 25)])
+def test_mixed_compile_time_plans(fcns, nx, ny, nz, C):
+    # nx = 256 / ny = 256 and N' = 288 take the compiled FP32 kernels
+    w = W.rayleigh_benard(nx, ny, nz, 1e6, C=C, dt=1e-3, steps=2, kmax=3, mmax=3,
+                          noise_rms=1e-2)
+    err = _mixed_vs_oracle(fcns, w, w.steps)
+    for c in ("u", "v", "w", "theta"):
+        assert err[c] < TOL_FIELD, err
+    assert err["p"] < TOL_P, err
