@@ -157,8 +157,63 @@ fcns_status fcns_timing_reset(fcns_ctx* ctx);
 fcns_status fcns_timing_report(fcns_ctx* ctx, int32_t max, int32_t* n, char* names,
                                int64_t* counts, double* ms);
 
-/* Sizes of the context: N' and the number of transported fields. */
+/* Sizes of the context: N' = nz + C. */
 int32_t fcns_npr(const fcns_ctx* ctx);
+
+/* Device bytes a context for this problem allocates (state, scratch and
+ * tables), without creating it.  HOST problem pointer. */
+fcns_status fcns_footprint(const fcns_problem* prob, int64_t* bytes);
+
+/* Replace the physical parameters of an existing context (viscosity,
+ * diffusivity, buoyancy rate, body force) so that a resident context can serve
+ * another problem of the same shape; takes effect for work enqueued after the
+ * call.  EINVAL for negative nu or kappa or non-finite values. */
+fcns_status fcns_set_params(fcns_ctx* ctx, double nu, double kappa, double gamma,
+                            double forcing_x);
+
+/* The hipStream_t the context enqueues on. */
+void* fcns_stream(const fcns_ctx* ctx);
+
+/* ------------------------------------------------------------------ serving
+ * A request loop over independent solves of different shapes (the batched
+ * serving of parameter sweeps).  A request is (problem, initial state,
+ * dt, nsteps).  Requests are admitted in arrival order, first fit, while
+ * fewer than max_active run and their device footprint (fcns_footprint plus
+ * a staging copy of the physical fields) fits in max_bytes together with the
+ * resident contexts; finished contexts stay resident and serve later
+ * requests of the same shape (fcns_set_params), idle ones are evicted least
+ * recently used when memory is needed.  Each context has its own
+ * non-blocking HIP stream, so admitted requests overlap on the device, and
+ * each request's result is the one a single-problem rk_step gives.  All
+ * calls from one host thread; progress happens only inside
+ * fcns_server_poll. */
+typedef struct fcns_server fcns_server;
+
+fcns_status fcns_server_create(int32_t max_active, int64_t max_bytes, fcns_server** out);
+/* HOST pointers: the problem (its fc_table), v0 [3][nz][ny][nx] and theta0
+ * [nz][ny][nx] (Boussinesq), all copied; *id identifies the request. */
+fcns_status fcns_server_submit(fcns_server* srv, const fcns_problem* prob, const double* v0,
+                               const double* theta0, double dt, int32_t nsteps, int64_t* id);
+/* Progress: collect finished requests, admit queued ones.  Outputs (nullable)
+ * are the queue length, the number running and the number finished so far. */
+fcns_status fcns_server_poll(fcns_server* srv, int32_t* n_queued, int32_t* n_active,
+                             int64_t* n_done);
+/* Seconds on the server's clock (steady, from fcns_server_create). */
+double fcns_server_now(const fcns_server* srv);
+/* Result of a finished request into HOST arrays v [3][nz][ny][nx] and theta
+ * (nullable); stats (HOST, nullable, 6 doubles): submit, admit and done times
+ * (server clock, s), mean, median and max step time (ms, HIP events on its
+ * stream).  ESTATE if not finished; ENONFINITE if the state blew up. */
+fcns_status fcns_server_result(fcns_server* srv, int64_t id, double* v, double* theta,
+                               double* stats);
+/* Per-step times (ms) of a finished request: up to max into ms (HOST). */
+fcns_status fcns_server_step_times(fcns_server* srv, int64_t id, int32_t max, float* ms,
+                                   int32_t* n);
+/* Forget a finished request. */
+fcns_status fcns_server_release(fcns_server* srv, int64_t id);
+/* Synchronize and free every context. */
+fcns_status fcns_server_destroy(fcns_server* srv);
+const char* fcns_server_last_error(const fcns_server* srv);
 
 /* Message for the last error on this context (or on creation when ctx is
  * NULL). */

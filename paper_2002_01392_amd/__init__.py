@@ -4,8 +4,11 @@ for one AMD Instinct MI355X (gfx950).
 The hot path (FC-Gram continuation, FFTs along the walled and periodic
 directions, spectral derivatives, advective products, pressure projection and
 the time-splitting Runge-Kutta stage) runs in the HIP kernels of libfcns.so
-behind the C ABI of include/fcns.h.  ``Solver`` is a thin ctypes binding.
+behind the C ABI of include/fcns.h.  ``Solver`` (one problem) and ``Server``
+(the request loop over many) are thin ctypes bindings.
 """
-from ._lib import FcnsError, Solver, load_library, problem_bytes  # noqa: F401
+from ._lib import (FcnsError, Server, Solver, footprint, load_library,  # noqa: F401
+                   make_problem, problem_bytes, workload_problem)
 
-__all__ = ["Solver", "FcnsError", "load_library", "problem_bytes"]
+__all__ = ["Solver", "Server", "FcnsError", "load_library", "problem_bytes", "make_problem",
+           "workload_problem", "footprint"]

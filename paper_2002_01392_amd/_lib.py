@@ -55,6 +55,20 @@ SIGNATURES = {
     "fcns_timing_reset": (ctypes.c_int, [_P]),
     "fcns_timing_report": (ctypes.c_int, [_P, _I32, ctypes.POINTER(_I32), _P, _P, _P]),
     "fcns_last_error": (ctypes.c_char_p, [_P]),
+    "fcns_footprint": (ctypes.c_int, [ctypes.POINTER(FcnsProblem), ctypes.POINTER(_I64)]),
+    "fcns_set_params": (ctypes.c_int, [_P, _D, _D, _D, _D]),
+    "fcns_stream": (_P, [_P]),
+    "fcns_server_create": (ctypes.c_int, [_I32, _I64, ctypes.POINTER(_P)]),
+    "fcns_server_submit": (ctypes.c_int, [_P, ctypes.POINTER(FcnsProblem), _P, _P, _D, _I32,
+                                          ctypes.POINTER(_I64)]),
+    "fcns_server_poll": (ctypes.c_int, [_P, ctypes.POINTER(_I32), ctypes.POINTER(_I32),
+                                        ctypes.POINTER(_I64)]),
+    "fcns_server_now": (_D, [_P]),
+    "fcns_server_result": (ctypes.c_int, [_P, _I64, _P, _P, _P]),
+    "fcns_server_step_times": (ctypes.c_int, [_P, _I64, _I32, _P, ctypes.POINTER(_I32)]),
+    "fcns_server_release": (ctypes.c_int, [_P, _I64]),
+    "fcns_server_destroy": (ctypes.c_int, [_P]),
+    "fcns_server_last_error": (ctypes.c_char_p, [_P]),
 }
 
 _lib = None
@@ -86,6 +100,114 @@ def _ptr(t):
     return ctypes.c_void_p(t.data_ptr()) if t is not None else None
 
 
+def make_problem(nx, ny, nz, lx, ly, lz, nu, d=5, C=25, forcing_x=0.0, boussinesq=False,
+                 kappa=0.0, gamma=0.0, keep_pressure=False, filter_beta=0.0, filter_2p=0.0,
+                 rk_order=2, precision="fp64", table=None):
+    """The fcns_problem struct and the FC table array it points to (keep the
+    array alive as long as the struct is used)."""
+    from . import fctable
+    tab = np.ascontiguousarray(table if table is not None else fctable.load(d, C),
+                               dtype=np.float64)
+    prob = FcnsProblem(nx, ny, nz, lx, ly, lz, d, C,
+                       tab.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                       nu, forcing_x, int(bool(boussinesq)), kappa, gamma, int(rk_order),
+                       filter_beta, filter_2p, _PRECISIONS[precision], int(bool(keep_pressure)))
+    return prob, tab
+
+
+def workload_problem(w, **kw):
+    return make_problem(w.nx, w.ny, w.nz, w.lx, w.ly, w.lz, w.nu, d=w.d, C=w.C,
+                        forcing_x=w.forcing_x, boussinesq=w.boussinesq, kappa=w.kappa,
+                        gamma=w.gamma, **kw)
+
+
+def footprint(prob):
+    lib = load_library()
+    b = ctypes.c_int64()
+    st = lib.fcns_footprint(ctypes.byref(prob), ctypes.byref(b))
+    if st != FCNS_OK:
+        raise FcnsError(st, "footprint")
+    return b.value
+
+
+class Server:
+    """The library's request loop (fcns_server_*): host numpy in and out."""
+
+    def __init__(self, max_active=8, max_bytes=64 << 30):
+        import torch
+        if not torch.cuda.is_available():
+            raise RuntimeError("no HIP device: the server runs only on the GPU")
+        self.lib = load_library()
+        h = ctypes.c_void_p()
+        st = self.lib.fcns_server_create(int(max_active), int(max_bytes), ctypes.byref(h))
+        if st != FCNS_OK:
+            raise FcnsError(st, "server_create")
+        self.srv = h
+        self.shapes = {}
+
+    def _check(self, st):
+        if st != FCNS_OK:
+            raise FcnsError(st, self.lib.fcns_server_last_error(self.srv).decode())
+
+    def submit(self, prob, v0, theta0, dt, nsteps):
+        v0 = np.ascontiguousarray(v0, dtype=np.float64)
+        th = None if theta0 is None else np.ascontiguousarray(theta0, dtype=np.float64)
+        rid = ctypes.c_int64()
+        self._check(self.lib.fcns_server_submit(
+            self.srv, ctypes.byref(prob), v0.ctypes.data_as(ctypes.c_void_p),
+            None if th is None else th.ctypes.data_as(ctypes.c_void_p), float(dt), int(nsteps),
+            ctypes.byref(rid)))
+        self.shapes[rid.value] = (v0.shape, None if th is None else th.shape)
+        return rid.value
+
+    def poll(self):
+        q, a, d = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int64()
+        self._check(self.lib.fcns_server_poll(self.srv, ctypes.byref(q), ctypes.byref(a),
+                                              ctypes.byref(d)))
+        return q.value, a.value, d.value
+
+    def now(self):
+        return self.lib.fcns_server_now(self.srv)
+
+    def result(self, rid):
+        vs, ts = self.shapes[rid]
+        v = np.empty(vs)
+        th = np.empty(ts) if ts is not None else None
+        stats = np.zeros(6)
+        st = self.lib.fcns_server_result(self.srv, rid, v.ctypes.data_as(ctypes.c_void_p),
+                                         None if th is None else th.ctypes.data_as(ctypes.c_void_p),
+                                         stats.ctypes.data_as(ctypes.c_void_p))
+        if st not in (FCNS_OK, FCNS_ENONFINITE):
+            self._check(st)
+        keys = ("t_submit", "t_admit", "t_done", "step_ms_mean", "step_ms_p50", "step_ms_max")
+        info = dict(zip(keys, stats.tolist()))
+        info["finite"] = st == FCNS_OK
+        return v, th, info
+
+    def step_times(self, rid, maxn=1 << 16):
+        ms = np.zeros(maxn, dtype=np.float32)
+        n = ctypes.c_int32()
+        self._check(self.lib.fcns_server_step_times(self.srv, rid, maxn,
+                                                    ms.ctypes.data_as(ctypes.c_void_p),
+                                                    ctypes.byref(n)))
+        return ms[:n.value].copy()
+
+    def release(self, rid):
+        self._check(self.lib.fcns_server_release(self.srv, rid))
+        self.shapes.pop(rid, None)
+
+    def close(self):
+        if getattr(self, "srv", None):
+            self.lib.fcns_server_destroy(self.srv)
+            self.srv = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
 class Solver:
     """One solver context on the current torch stream of `device`.
 
@@ -98,7 +220,6 @@ class Solver:
                  filter_beta=0.0, filter_2p=0.0, rk_order=2, precision="fp64", table=None,
                  device="cuda:0", stream=None):
         import torch
-        from . import fctable
 
         if not torch.cuda.is_available():
             raise RuntimeError("no HIP device: the solver runs only on the GPU")
@@ -106,14 +227,12 @@ class Solver:
         self.lib = load_library()
         self.device = torch.device(device)
         self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
-        tab = np.ascontiguousarray(table if table is not None else fctable.load(d, C),
-                                   dtype=np.float64)
+        prob, tab = make_problem(nx, ny, nz, lx, ly, lz, nu, d=d, C=C, forcing_x=forcing_x,
+                                 boussinesq=boussinesq, kappa=kappa, gamma=gamma,
+                                 keep_pressure=keep_pressure, filter_beta=filter_beta,
+                                 filter_2p=filter_2p, rk_order=rk_order, precision=precision,
+                                 table=table)
         self._table = tab
-        prob = FcnsProblem(nx, ny, nz, lx, ly, lz, d, C,
-                           tab.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
-                           nu, forcing_x, int(bool(boussinesq)), kappa, gamma, int(rk_order),
-                           filter_beta, filter_2p, _PRECISIONS[precision],
-                           int(bool(keep_pressure)))
         self.shape = (nz, ny, nx)
         self.nx, self.ny, self.nz, self.d, self.C = nx, ny, nz, d, C
         self.npr = nz + C
@@ -261,10 +380,10 @@ class Solver:
         self.stream.synchronize()
 
 
-def problem_bytes(nx, ny, nz, C, nfields):
-    """Device memory the context allocates (bytes)."""
-    nkx = nx // 2 + 1
-    S = (nz + C) * ny * nkx * 16
-    M = nz * ny * nkx * 16
-    return 3 * nfields * S + (2 + 2 + 3 + 1) * nfields * M + M + 8 * ny * nkx * 16
+def problem_bytes(nx, ny, nz, C, nfields, d=5):
+    """Device memory a context of this shape allocates (bytes), from the
+    library (no device needed)."""
+    prob, _tab = make_problem(nx, ny, nz, 1.0, 1.0, 1.0, 0.0, d=d, C=C,
+                              boussinesq=nfields == 4)
+    return footprint(prob)
 

@@ -1,6 +1,8 @@
 // Host side of the C ABI: problem validation, FFT plans, tables, buffers and
 // the sequence of kernel launches for each entry point.
 #include <math.h>
+
+#include <cmath>
 #include <stdio.h>
 #include <stdlib.h>
 #include <string.h>
@@ -386,6 +388,35 @@ extern "C" const char* fcns_last_error(const fcns_ctx* c) {
 }
 
 extern "C" int32_t fcns_npr(const fcns_ctx* c) { return c ? c->g.npr : 0; }
+
+extern "C" fcns_status fcns_footprint(const fcns_problem* p, int64_t* bytes) {
+  if (!p || !bytes) return FCNS_EINVAL;
+  if (p->nx < 4 || p->ny < 4 || p->nz < 2 || p->fc_C < 1) return FCNS_EINVAL;
+  const long long nkxp = ((long long)p->nx / 2 + 1 + 3) / 4 * 4;
+  const long long npen = nkxp * p->ny;
+  const long long S = (long long)(p->nz + p->fc_C) * npen, M = (long long)p->nz * npen;
+  const long long nf = p->boussinesq ? 4 : 3;
+  // P, Q, VS; MV, MVT, XYB, NLB, PM; GW, GWT (complex128), plus tables
+  const long long elems = 3 * nf * S + (2 * nf + 2 * nf + 3 * nf + nf + 1) * M + 8 * npen;
+  const long long tables = 16LL * (4LL * (p->nx + p->ny + p->nz + p->fc_C) + 4096) +
+                           8LL * p->fc_C * p->fc_d;
+  *bytes = (int64_t)(elems * 16 + tables);
+  return FCNS_OK;
+}
+
+extern "C" fcns_status fcns_set_params(fcns_ctx* c, double nu, double kappa, double gamma,
+                                       double forcing_x) {
+  if (!c) return FCNS_EINVAL;
+  if (!(nu >= 0.0) || !(kappa >= 0.0) || !std::isfinite(gamma) || !std::isfinite(forcing_x))
+    return fail(c, FCNS_EINVAL, "need nu, kappa >= 0 and finite gamma, forcing_x");
+  c->prob.nu = nu;
+  c->prob.kappa = kappa;
+  c->prob.gamma = gamma;
+  c->prob.forcing_x = forcing_x;
+  return FCNS_OK;
+}
+
+extern "C" void* fcns_stream(const fcns_ctx* c) { return c ? (void*)c->stream : nullptr; }
 
 // ---------------------------------------------------------------- pieces
 // physical fields (nfields consecutive [nz][ny][nx] arrays) -> mixed (kx, ky, z)

@@ -1,0 +1,415 @@
+// Serving engine: a request loop over independent solves of different grid
+// sizes.  Requests are admitted in arrival order as soon as a slot and device
+// memory allow (first fit: a request that does not fit yet does not block the
+// ones behind it), run on solver contexts that stay resident and are reused by
+// later requests of the same shape, and overlap on the device through one
+// non-blocking HIP stream per context.  Every step of every request is
+// bracketed by HIP events, so step latency under load is measured on the
+// device; request latency is measured on the host clock from submission to
+// the detection of the finished result.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <deque>
+#include <map>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "../../include/fcns.h"
+
+namespace {
+
+using Clock = std::chrono::steady_clock;
+
+struct PoolCtx {
+  fcns_ctx* ctx = nullptr;
+  hipStream_t stream = nullptr;
+  std::string key;
+  int64_t bytes = 0;        // device bytes held (solver + staging)
+  double* dphys = nullptr;  // device staging: 3 velocity fields then theta
+  double* hphys = nullptr;  // pinned host staging of the same size
+  int64_t npts = 0;         // points of one physical field
+  int nphys = 3;            // physical fields staged (3, or 4 with theta)
+  bool busy = false;
+  uint64_t last_used = 0;
+};
+
+enum { Q_QUEUED = 0, Q_RUNNING, Q_FINISHING, Q_DONE };
+
+struct Request {
+  int64_t id = 0;
+  fcns_problem prob{};
+  std::vector<double> table;
+  std::vector<double> v0, th0;
+  double dt = 0.0;
+  int nsteps = 0;
+  double t_submit = 0.0, t_admit = -1.0, t_done = -1.0;
+  int state = Q_QUEUED;
+  PoolCtx* pc = nullptr;
+  std::vector<hipEvent_t> ev;
+  hipEvent_t fin = nullptr;
+  std::vector<float> step_ms;
+  std::vector<double> v, th;
+  fcns_status status = FCNS_OK;
+  std::string err;
+};
+
+std::string shape_key(const fcns_problem& p, const std::vector<double>& table) {
+  char buf[512];
+  snprintf(buf, sizeof(buf), "%d %d %d %.17g %.17g %.17g %d %d %d %d %d %.17g %.17g", p.nx, p.ny,
+           p.nz, p.lx, p.ly, p.lz, p.fc_d, p.fc_C, p.boussinesq, p.rk_order, p.precision,
+           p.filter_beta, p.filter_2p);
+  // the continuation table is part of the shape (contexts copy it at create)
+  uint64_t h = 1469598103934665603ULL;
+  for (double x : table) {
+    uint64_t b;
+    memcpy(&b, &x, 8);
+    h = (h ^ b) * 1099511628211ULL;
+  }
+  return std::string(buf) + " " + std::to_string(h);
+}
+
+}  // namespace
+
+struct fcns_server {
+  int max_active = 1;
+  int64_t max_bytes = 0;
+  int64_t used_bytes = 0;
+  Clock::time_point t0;
+  std::vector<std::unique_ptr<PoolCtx>> pool;
+  std::map<int64_t, std::unique_ptr<Request>> reqs;
+  std::deque<int64_t> queue;
+  std::vector<int64_t> active;
+  int64_t next_id = 1;
+  int64_t n_done = 0;
+  uint64_t tick = 0;
+  std::string err;
+
+  double now() const { return std::chrono::duration<double>(Clock::now() - t0).count(); }
+};
+
+static fcns_status srv_fail(fcns_server* s, fcns_status st, const std::string& m) {
+  if (s) s->err = m;
+  return st;
+}
+
+static void destroy_pool_ctx(fcns_server* s, PoolCtx* pc) {
+  if (pc->ctx) fcns_destroy(pc->ctx);
+  if (pc->dphys) (void)hipFree(pc->dphys);
+  if (pc->hphys) (void)hipHostFree(pc->hphys);
+  if (pc->stream) (void)hipStreamDestroy(pc->stream);
+  s->used_bytes -= pc->bytes;
+}
+
+extern "C" fcns_status fcns_server_create(int32_t max_active, int64_t max_bytes,
+                                          fcns_server** out) {
+  if (!out) return FCNS_EINVAL;
+  *out = nullptr;
+  if (max_active < 1 || max_bytes <= 0) return FCNS_EINVAL;
+  fcns_server* s = new fcns_server();
+  s->max_active = max_active;
+  s->max_bytes = max_bytes;
+  s->t0 = Clock::now();
+  *out = s;
+  return FCNS_OK;
+}
+
+extern "C" double fcns_server_now(const fcns_server* s) { return s ? s->now() : 0.0; }
+
+extern "C" fcns_status fcns_server_submit(fcns_server* s, const fcns_problem* prob,
+                                          const double* v0, const double* theta0, double dt,
+                                          int32_t nsteps, int64_t* id) {
+  if (!s) return FCNS_EINVAL;
+  if (!prob || !v0 || !id || !prob->fc_table) return srv_fail(s, FCNS_EINVAL, "NULL argument");
+  if (prob->boussinesq && !theta0) return srv_fail(s, FCNS_EINVAL, "theta0 required");
+  if (!(dt > 0.0) || nsteps < 1) return srv_fail(s, FCNS_EINVAL, "need dt > 0 and nsteps >= 1");
+  int64_t need = 0;
+  if (fcns_footprint(prob, &need) != FCNS_OK) return srv_fail(s, FCNS_EINVAL, "bad problem");
+  auto r = std::make_unique<Request>();
+  r->id = s->next_id++;
+  r->prob = *prob;
+  const int d = prob->fc_d, C = prob->fc_C;
+  r->table.assign(prob->fc_table, prob->fc_table + (size_t)d * d + (size_t)C * d);
+  r->prob.fc_table = nullptr;
+  const size_t n = (size_t)prob->nx * prob->ny * prob->nz;
+  r->v0.assign(v0, v0 + 3 * n);
+  if (prob->boussinesq) r->th0.assign(theta0, theta0 + n);
+  r->dt = dt;
+  r->nsteps = nsteps;
+  r->t_submit = s->now();
+  *id = r->id;
+  s->queue.push_back(r->id);
+  s->reqs[r->id] = std::move(r);
+  return FCNS_OK;
+}
+
+// a free resident context of this shape, or a new one if memory allows
+// (evicting idle contexts of other shapes, least recently used first)
+static PoolCtx* acquire(fcns_server* s, Request& r, const std::string& key, fcns_status& st) {
+  st = FCNS_OK;
+  PoolCtx* best = nullptr;
+  for (auto& pc : s->pool)
+    if (!pc->busy && pc->key == key) {
+      best = pc.get();
+      break;
+    }
+  if (best) return best;
+  int64_t need = 0;
+  fcns_footprint(&r.prob, &need);
+  const int nphys = r.prob.boussinesq ? 4 : 3;
+  const int64_t npts = (int64_t)r.prob.nx * r.prob.ny * r.prob.nz;
+  need += (int64_t)nphys * npts * 8;
+  if (need > s->max_bytes) {
+    st = FCNS_ENOMEM;
+    return nullptr;
+  }
+  while (s->used_bytes + need > s->max_bytes) {
+    PoolCtx* victim = nullptr;
+    for (auto& pc : s->pool)
+      if (!pc->busy && (!victim || pc->last_used < victim->last_used)) victim = pc.get();
+    if (!victim) return nullptr;  // wait for a running request to finish
+    destroy_pool_ctx(s, victim);
+    s->pool.erase(std::find_if(s->pool.begin(), s->pool.end(),
+                               [&](const std::unique_ptr<PoolCtx>& p) { return p.get() == victim; }));
+  }
+  auto pc = std::make_unique<PoolCtx>();
+  pc->key = key;
+  pc->npts = npts;
+  pc->nphys = nphys;
+  if (hipStreamCreateWithFlags(&pc->stream, hipStreamNonBlocking) != hipSuccess) {
+    st = FCNS_EDEVICE;
+    return nullptr;
+  }
+  fcns_problem p = r.prob;
+  p.fc_table = r.table.data();
+  if ((st = fcns_create(&p, pc->stream, &pc->ctx)) != FCNS_OK) {
+    s->err = std::string("context: ") + fcns_last_error(nullptr);
+    (void)hipStreamDestroy(pc->stream);
+    return nullptr;
+  }
+  const size_t sb = (size_t)nphys * npts * sizeof(double);
+  if (hipMalloc((void**)&pc->dphys, sb) != hipSuccess ||
+      hipHostMalloc((void**)&pc->hphys, sb, hipHostMallocDefault) != hipSuccess) {
+    pc->bytes = 0;
+    destroy_pool_ctx(s, pc.get());
+    st = FCNS_ENOMEM;
+    return nullptr;
+  }
+  pc->bytes = need;
+  s->used_bytes += need;
+  s->pool.push_back(std::move(pc));
+  return s->pool.back().get();
+}
+
+static void finish_with_error(fcns_server* s, Request& r, fcns_status st, const std::string& m) {
+  r.status = st;
+  r.err = m;
+  r.state = Q_DONE;
+  r.t_done = s->now();
+  s->n_done++;
+}
+
+static fcns_status launch_request(fcns_server* s, Request& r) {
+  PoolCtx* pc = r.pc;
+  fcns_ctx* c = pc->ctx;
+  const size_t n = (size_t)pc->npts;
+  fcns_status st = fcns_set_params(c, r.prob.nu, r.prob.kappa, r.prob.gamma, r.prob.forcing_x);
+  if (st != FCNS_OK) return st;
+  memcpy(pc->hphys, r.v0.data(), 3 * n * sizeof(double));
+  if (pc->nphys == 4) memcpy(pc->hphys + 3 * n, r.th0.data(), n * sizeof(double));
+  if (hipMemcpyAsync(pc->dphys, pc->hphys, pc->nphys * n * sizeof(double),
+                     hipMemcpyHostToDevice, pc->stream) != hipSuccess)
+    return FCNS_EDEVICE;
+  if ((st = fcns_set_state(c, pc->dphys, pc->nphys == 4 ? pc->dphys + 3 * n : nullptr)) != FCNS_OK)
+    return st;
+  r.ev.assign(r.nsteps + 1, nullptr);
+  for (auto& e : r.ev)
+    if (hipEventCreate(&e) != hipSuccess) return FCNS_EDEVICE;
+  if (hipEventCreateWithFlags(&r.fin, hipEventDisableTiming) != hipSuccess) return FCNS_EDEVICE;
+  (void)hipEventRecord(r.ev[0], pc->stream);
+  for (int k = 1; k <= r.nsteps; ++k) {
+    if ((st = fcns_rk_step(c, r.dt, 1)) != FCNS_OK) return st;
+    (void)hipEventRecord(r.ev[k], pc->stream);
+  }
+  return FCNS_OK;
+}
+
+static void release_events(Request& r) {
+  for (auto e : r.ev)
+    if (e) (void)hipEventDestroy(e);
+  r.ev.clear();
+  if (r.fin) (void)hipEventDestroy(r.fin);
+  r.fin = nullptr;
+}
+
+extern "C" fcns_status fcns_server_poll(fcns_server* s, int32_t* n_queued, int32_t* n_active,
+                                        int64_t* n_done) {
+  if (!s) return FCNS_EINVAL;
+  // 1. progress of the admitted requests
+  for (size_t i = 0; i < s->active.size();) {
+    Request& r = *s->reqs[s->active[i]];
+    bool remove = false;
+    if (r.state == Q_RUNNING) {
+      const hipError_t q = hipEventQuery(r.ev.back());
+      if (q == hipSuccess) {
+        r.step_ms.resize(r.nsteps);
+        for (int k = 0; k < r.nsteps; ++k) {
+          float ms = 0.f;
+          (void)hipEventElapsedTime(&ms, r.ev[k], r.ev[k + 1]);
+          r.step_ms[k] = ms;
+        }
+        PoolCtx* pc = r.pc;
+        const size_t n = (size_t)pc->npts;
+        fcns_status st = fcns_get_state(pc->ctx, pc->dphys,
+                                        pc->nphys == 4 ? pc->dphys + 3 * n : nullptr, nullptr);
+        if (st == FCNS_OK &&
+            hipMemcpyAsync(pc->hphys, pc->dphys, pc->nphys * n * sizeof(double),
+                           hipMemcpyDeviceToHost, pc->stream) == hipSuccess &&
+            hipEventRecord(r.fin, pc->stream) == hipSuccess) {
+          r.state = Q_FINISHING;
+        } else {
+          finish_with_error(s, r, st == FCNS_OK ? FCNS_EDEVICE : st, "result copy failed");
+          remove = true;
+        }
+      } else if (q != hipErrorNotReady) {
+        finish_with_error(s, r, FCNS_EDEVICE, hipGetErrorString(q));
+        remove = true;
+      }
+    }
+    if (r.state == Q_FINISHING) {
+      const hipError_t q = hipEventQuery(r.fin);
+      if (q == hipSuccess) {
+        PoolCtx* pc = r.pc;
+        const size_t n = (size_t)pc->npts;
+        r.v.assign(pc->hphys, pc->hphys + 3 * n);
+        if (pc->nphys == 4) r.th.assign(pc->hphys + 3 * n, pc->hphys + 4 * n);
+        bool finite = true;
+        for (double x : r.v) finite = finite && std::isfinite(x);
+        r.status = finite ? FCNS_OK : FCNS_ENONFINITE;
+        r.state = Q_DONE;
+        r.t_done = s->now();
+        s->n_done++;
+        remove = true;
+      } else if (q != hipErrorNotReady) {
+        finish_with_error(s, r, FCNS_EDEVICE, hipGetErrorString(q));
+        remove = true;
+      }
+    }
+    if (remove) {
+      release_events(r);
+      if (r.pc) {
+        r.pc->busy = false;
+        r.pc->last_used = ++s->tick;
+        r.pc = nullptr;
+      }
+      r.v0.clear();
+      r.th0.clear();
+      s->active.erase(s->active.begin() + i);
+    } else {
+      ++i;
+    }
+  }
+  // 2. admission, first fit in arrival order
+  for (auto it = s->queue.begin(); it != s->queue.end() && (int)s->active.size() < s->max_active;) {
+    Request& r = *s->reqs[*it];
+    fcns_status st;
+    PoolCtx* pc = acquire(s, r, shape_key(r.prob, r.table), st);
+    if (!pc) {
+      if (st != FCNS_OK) {  // can never run: report it
+        finish_with_error(s, r, st, s->err.empty() ? "does not fit" : s->err);
+        it = s->queue.erase(it);
+      } else {
+        ++it;
+      }
+      continue;
+    }
+    pc->busy = true;
+    pc->last_used = ++s->tick;
+    r.pc = pc;
+    r.t_admit = s->now();
+    if ((st = launch_request(s, r)) != FCNS_OK) {
+      finish_with_error(s, r, st, fcns_last_error(pc->ctx));
+      release_events(r);
+      pc->busy = false;
+      r.pc = nullptr;
+    } else {
+      r.state = Q_RUNNING;
+      s->active.push_back(r.id);
+    }
+    it = s->queue.erase(it);
+  }
+  if (n_queued) *n_queued = (int32_t)s->queue.size();
+  if (n_active) *n_active = (int32_t)s->active.size();
+  if (n_done) *n_done = s->n_done;
+  return FCNS_OK;
+}
+
+extern "C" fcns_status fcns_server_result(fcns_server* s, int64_t id, double* v, double* theta,
+                                          double* stats) {
+  if (!s) return FCNS_EINVAL;
+  auto f = s->reqs.find(id);
+  if (f == s->reqs.end()) return srv_fail(s, FCNS_EINVAL, "unknown request");
+  Request& r = *f->second;
+  if (r.state != Q_DONE) return srv_fail(s, FCNS_ESTATE, "request not finished");
+  if (r.status != FCNS_OK && r.status != FCNS_ENONFINITE) return srv_fail(s, r.status, r.err);
+  if (v) memcpy(v, r.v.data(), r.v.size() * sizeof(double));
+  if (theta && !r.th.empty()) memcpy(theta, r.th.data(), r.th.size() * sizeof(double));
+  if (stats) {
+    std::vector<float> sm = r.step_ms;
+    std::sort(sm.begin(), sm.end());
+    double sum = 0.0;
+    for (float x : sm) sum += x;
+    const auto pct = [&](double q) {
+      if (sm.empty()) return 0.0;
+      const size_t k = (size_t)std::min<double>(sm.size() - 1, std::ceil(q * sm.size()) - 1);
+      return (double)sm[k];
+    };
+    stats[0] = r.t_submit;
+    stats[1] = r.t_admit;
+    stats[2] = r.t_done;
+    stats[3] = sm.empty() ? 0.0 : sum / sm.size();
+    stats[4] = pct(0.5);
+    stats[5] = sm.empty() ? 0.0 : (double)sm.back();
+  }
+  return r.status;
+}
+
+extern "C" fcns_status fcns_server_step_times(fcns_server* s, int64_t id, int32_t max, float* ms,
+                                              int32_t* n) {
+  if (!s || !n) return FCNS_EINVAL;
+  auto f = s->reqs.find(id);
+  if (f == s->reqs.end()) return srv_fail(s, FCNS_EINVAL, "unknown request");
+  const Request& r = *f->second;
+  if (r.state != Q_DONE) return srv_fail(s, FCNS_ESTATE, "request not finished");
+  const int k = std::min<int>(max, (int)r.step_ms.size());
+  if (ms) memcpy(ms, r.step_ms.data(), k * sizeof(float));
+  *n = k;
+  return FCNS_OK;
+}
+
+extern "C" fcns_status fcns_server_release(fcns_server* s, int64_t id) {
+  if (!s) return FCNS_EINVAL;
+  auto f = s->reqs.find(id);
+  if (f == s->reqs.end()) return FCNS_EINVAL;
+  if (f->second->state != Q_DONE) return srv_fail(s, FCNS_ESTATE, "request not finished");
+  s->reqs.erase(f);
+  return FCNS_OK;
+}
+
+extern "C" fcns_status fcns_server_destroy(fcns_server* s) {
+  if (!s) return FCNS_OK;
+  for (auto& pc : s->pool)
+    if (pc->stream) (void)hipStreamSynchronize(pc->stream);
+  for (auto& kv : s->reqs) release_events(*kv.second);
+  for (auto& pc : s->pool) destroy_pool_ctx(s, pc.get());
+  delete s;
+  return FCNS_OK;
+}
+
+extern "C" const char* fcns_server_last_error(const fcns_server* s) {
+  return s ? s->err.c_str() : "";
+}

@@ -61,3 +61,15 @@ def test_fc_tables_agree_with_the_independent_oracle_tables():
         assert np.abs(Q - Qo).max() < 1e-15
         assert np.abs(A - Ao).max() <= 1e-15 * np.abs(Ao).max()
         assert np.abs(A @ Q.T - Mo).max() < 1e-14 * np.abs(Mo).max()
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="libfcns.so not built")
+def test_footprint_counts_the_context_buffers():
+    # no device needed: the library computes it from the shape
+    from paper_2002_01392_amd import problem_bytes
+    b = problem_bytes(512, 512, 257, 31, 4)
+    nkxp = 260
+    S, M = 288 * 512 * nkxp * 16, 257 * 512 * nkxp * 16
+    W = 8 * 512 * nkxp * 16          # wall-gradient arrays
+    assert 12 * S + 33 * M + W <= b < 12 * S + 33 * M + W + (1 << 22)
+    assert problem_bytes(32, 32, 33, 31, 3) < problem_bytes(64, 64, 65, 31, 3)

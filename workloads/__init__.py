@@ -68,27 +68,30 @@ def solenoidal_noise(nx, ny, nz, lx, ly, lz, kmax, mmax, rms, seed):
     g = (z * (lz - z)) ** 2 / h ** 2
     gp = 2.0 * z * (lz - z) * (lz - 2.0 * z) / h ** 2
     modes = _mode_list(kmax)
-    v = np.zeros((3, nz, ny, nx))
-    for m in range(1, mmax + 1):
-        km = m * np.pi / lz
-        Zm = np.sin(km * z) * g
-        Zpm = km * np.cos(km * z) * g + np.sin(km * z) * gp
-        T = np.zeros((3, ny, nx))
-        Tx = np.zeros((3, ny, nx))
-        Ty = np.zeros((3, ny, nx))
-        for (p, q) in modes:
-            kx, ky = 2 * np.pi * p / lx, 2 * np.pi * q / ly
-            ph = kx * X + ky * Y
-            cs, sn = np.cos(ph), np.sin(ph)
-            for c in range(3):
-                a, b = r.standard_normal(2)
-                T[c] += a * cs + b * sn
-                Tx[c] += kx * (-a * sn + b * cs)
-                Ty[c] += ky * (-a * sn + b * cs)
-        # v = curl Psi with Psi_c = T_c(x, y) Z(z)
-        v[0] += Zm[:, None, None] * Ty[2][None] - Zpm[:, None, None] * T[1][None]
-        v[1] += Zpm[:, None, None] * T[0][None] - Zm[:, None, None] * Tx[2][None]
-        v[2] += Zm[:, None, None] * (Tx[1] - Ty[0])[None]
+    nm = len(modes)
+    kx = np.array([2 * np.pi * p / lx for (p, _) in modes])
+    ky = np.array([2 * np.pi * q / ly for (_, q) in modes])
+    ph = kx[:, None, None] * X[None] + ky[:, None, None] * Y[None]
+    H = np.cos(ph).reshape(nm, -1)          # horizontal harmonics (modes, ny*nx)
+    S = np.sin(ph).reshape(nm, -1)
+    # coefficients drawn in (m, mode, component, cos/sin) order
+    ab = r.standard_normal((mmax, nm, 3, 2))
+    A, B = ab[..., 0], ab[..., 1]            # (m, mode, c)
+    # T_c = sum a cs + b sn; its x and y derivatives, per m and component
+    T = np.einsum("mic,ip->mcp", A, H) + np.einsum("mic,ip->mcp", B, S)
+    Tx = np.einsum("mic,ip->mcp", B * kx[None, :, None], H) \
+        - np.einsum("mic,ip->mcp", A * kx[None, :, None], S)
+    Ty = np.einsum("mic,ip->mcp", B * ky[None, :, None], H) \
+        - np.einsum("mic,ip->mcp", A * ky[None, :, None], S)
+    km = np.arange(1, mmax + 1) * np.pi / lz
+    Zm = np.sin(km[:, None] * z[None]) * g[None]                       # (m, nz)
+    Zpm = km[:, None] * np.cos(km[:, None] * z[None]) * g[None] + np.sin(km[:, None] * z[None]) * gp[None]
+    # v = curl Psi with Psi_c = T_c(x, y) Z(z), summed over m
+    v = np.empty((3, nz, ny * nx))
+    v[0] = Zm.T @ Ty[:, 2] - Zpm.T @ T[:, 1]
+    v[1] = Zpm.T @ T[:, 0] - Zm.T @ Tx[:, 2]
+    v[2] = Zm.T @ (Tx[:, 1] - Ty[:, 0])
+    v = v.reshape(3, nz, ny, nx)
     cur = math.sqrt(float(np.mean(v ** 2)) * 3.0)
     return v * (rms / cur) if cur > 0 else v
 
@@ -100,13 +103,15 @@ def wall_vanishing_noise(nx, ny, nz, lx, ly, lz, kmax, mmax, rms, seed):
     x, y, z = grid(nx, ny, nz, lx, ly, lz)
     X, Y = np.meshgrid(x, y, indexing="xy")
     th = np.zeros((nz, ny, nx))
+    modes = _mode_list(kmax)
+    phs = [2 * np.pi * p / lx * X + 2 * np.pi * q / ly * Y for (p, q) in modes]
+    harm = [(np.cos(ph), np.sin(ph)) for ph in phs]
     for m in range(1, mmax + 1):
         Zm = np.sin(m * np.pi * z / lz)
         P = np.zeros((ny, nx))
-        for (p, q) in _mode_list(kmax):
-            ph = 2 * np.pi * p / lx * X + 2 * np.pi * q / ly * Y
+        for cs, sn in harm:
             a, b = r.standard_normal(2)
-            P += a * np.cos(ph) + b * np.sin(ph)
+            P += a * cs + b * sn
         P += r.standard_normal()  # horizontally uniform part
         th += Zm[:, None, None] * P[None]
     cur = math.sqrt(float(np.mean(th ** 2)))
@@ -264,7 +269,11 @@ def stable_dt(w: Workload, cap=1e-3):
 
 
 def serving_stream(n=64, rate=20.0, steps=20, seed=5, sides=SERVING_SIDES, C=31):
-    """List of (arrival_time_s, Workload) for the serving workload."""
+    """List of (arrival_time_s, Workload) for the serving workload: Poisson
+    arrivals, channel or Rayleigh-Benard with equal odds, side uniform over
+    `sides` (nz = side + 1, so N' = side + 32 with C = 31), Re uniform in
+    [500, 5000] or Ra log-uniform in [1e4, 1e8], perturbations with few modes
+    (|k| <= 2 channel, 4 Rayleigh-Benard) to keep input generation short."""
     r = rng(seed)
     t = 0.0
     out = []
@@ -274,11 +283,11 @@ def serving_stream(n=64, rate=20.0, steps=20, seed=5, sides=SERVING_SIDES, C=31)
         if r.random() < 0.5:
             re = float(r.uniform(500.0, 5000.0))
             w = channel(side, side, side + 1, re, d=5, C=C, steps=steps, seed=500 + i,
-                        name=f"req{i}_channel_{side}")
+                        name=f"req{i}_channel_{side}", kmax=2, mmax=2)
         else:
             ra = float(10 ** r.uniform(4.0, 8.0))
             w = rayleigh_benard(side, side, side + 1, ra, d=5, C=C, steps=steps,
-                                seed=500 + i, name=f"req{i}_rb_{side}")
+                                seed=500 + i, name=f"req{i}_rb_{side}", kmax=4, mmax=4)
         w = replace(w, dt=stable_dt(w))
         out.append((t, w))
     return out
