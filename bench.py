@@ -30,8 +30,12 @@ PROFILES = os.path.join(ROOT, "profiles")
 
 
 def kernel_source_hash():
+    """Hash of the device code and the host code that launches it (the serving
+    loop, which launches nothing itself, is left out)."""
     h = hashlib.sha256()
     for fn in sorted(os.listdir(CSRC)):
+        if fn == "fcns_server.cpp":
+            continue
         with open(os.path.join(CSRC, fn), "rb") as fh:
             h.update(fn.encode())
             h.update(fh.read())
@@ -152,6 +156,70 @@ def precision_run(name="channel_256x256x257", steps=100, warmup=2):
                     "transforms that form v*, and the projection"}
 
 
+def serving_run(max_active=8, max_bytes=64 << 30, n=64, rate=20.0, steps=20):
+    """The serving workload: n requests with Poisson arrivals at `rate`/s, each
+    a `steps`-step solve (channel or Rayleigh-Benard, side 32..192), served by
+    the library's request loop with up to max_active overlapping requests, and
+    the same arrivals served one at a time (max_active = 1) for comparison.
+    Inputs are generated before the clock starts; arrivals are replayed in
+    real time; latency = result detected - submission (host clock)."""
+    import numpy as np
+
+    import workloads as W
+    from paper_2002_01392_amd import Server, workload_problem
+
+    stream = W.serving_stream(n=n, rate=rate, steps=steps)
+    reqs = []
+    for t, w in stream:
+        v0, th0 = w.initial_state()
+        prob, tab = workload_problem(w)
+        reqs.append((t, w, prob, tab, v0, th0))
+
+    def run(slots, replay=True):
+        srv = Server(max_active=slots, max_bytes=max_bytes)
+        t0 = srv.now()
+        ids, k = [], 0
+        while True:
+            now = srv.now() - t0
+            while k < len(reqs) and (reqs[k][0] <= now or not replay):
+                _, w, prob, _tab, v0, th0 = reqs[k]
+                ids.append((srv.submit(prob, v0, th0, w.dt, w.steps), w))
+                k += 1
+            _, _, done = srv.poll()
+            if k == len(reqs) and done == len(reqs):
+                break
+        lat, step_ms, work, t_end, finite = [], [], 0, 0.0, True
+        for rid, w in ids:
+            _, _, info = srv.result(rid)
+            finite = finite and info["finite"]
+            lat.append(1e3 * (info["t_done"] - info["t_submit"]))
+            step_ms.extend(srv.step_times(rid).tolist())
+            work += w.nx * w.ny * w.nz * 2 * w.steps
+            t_end = max(t_end, info["t_done"] - t0)
+        srv.close()
+        t_first = reqs[0][0] if replay else 0.0
+        pct = lambda a, q: float(np.percentile(np.asarray(a), q))
+        return {"max_active": slots, "makespan_s": t_end - t_first,
+                "value": work / (t_end - t_first), "unit": UNIT,
+                "request_ms_p50": pct(lat, 50), "request_ms_p99": pct(lat, 99),
+                "step_ms_p50": pct(step_ms, 50), "step_ms_p99": pct(step_ms, 99),
+                "all_finite": finite}
+
+    seq = run(1)
+    bat = run(max_active)
+    # the same requests all submitted at once (offered load above capacity)
+    seq_sat = run(1, replay=False)
+    bat_sat = run(max_active, replay=False)
+    return {"requests": n, "rate_per_s": rate, "steps_each": steps,
+            "sides": list(W.SERVING_SIDES), "batched": bat, "sequential": seq,
+            "throughput_gain": bat["value"] / seq["value"],
+            "p99_request_gain": seq["request_ms_p99"] / bat["request_ms_p99"],
+            "saturated": {"batched": bat_sat, "sequential": seq_sat,
+                          "throughput_gain": bat_sat["value"] / seq_sat["value"],
+                          "p99_request_gain": seq_sat["request_ms_p99"]
+                          / bat_sat["request_ms_p99"]}}
+
+
 def load_traffic(w, kernel, src_hash):
     """HBM bytes per launch from the committed rocprofv3 PMC summary, if it was
     taken on the current kernel sources and workload."""
@@ -177,6 +245,7 @@ def main():
     ap.add_argument("--timing", type=int, default=1, help="event-time kernels in the timed region")
     ap.add_argument("--no-mixed", action="store_true",
                     help="skip the mixed-precision run on the channel grid")
+    ap.add_argument("--no-serving", action="store_true", help="skip the serving run")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one plain device copy of 1 GiB (counter calibration)")
     args = ap.parse_args()
@@ -262,12 +331,18 @@ def main():
                   "frac": round(pm / (total_ms / 1e3 / substeps) / 1e9 / HBM_PEAK_GBPS, 4)}
 
     mixed = None
+    s.close()
+    del s
+    torch.cuda.empty_cache()
     if not args.no_mixed:
-        s.close()
-        del s
-        torch.cuda.empty_cache()
         print("[bench] mixed precision on the channel grid", file=sys.stderr, flush=True)
         mixed = precision_run()
+
+    serving = None
+    if not args.no_serving:
+        print("[bench] serving: 64 requests, sequential then overlapped", file=sys.stderr,
+              flush=True)
+        serving = serving_run()
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -286,6 +361,7 @@ def main():
         "step_ms_p99": float(np.percentile(step_ms, 99)),
         "wall_s": wall, "state_finite": finite,
         "roofline": roof, "pass_model": pass_model, "kernels": kernels, "precision": mixed,
+        "serving": serving,
         "cpu_baseline": cpu, "kernel_source_hash": src_hash,
     }
     print(json.dumps(out))

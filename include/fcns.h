@@ -190,22 +190,25 @@ void* fcns_stream(const fcns_ctx* ctx);
 typedef struct fcns_server fcns_server;
 
 fcns_status fcns_server_create(int32_t max_active, int64_t max_bytes, fcns_server** out);
-/* HOST pointers: the problem (its fc_table), v0 [3][nz][ny][nx] and theta0
- * [nz][ny][nx] (Boussinesq), all copied; *id identifies the request. */
+/* HOST pointers.  The problem (and its fc_table) is copied.  v0
+ * [3][nz][ny][nx] and theta0 [nz][ny][nx] (Boussinesq) are read when the
+ * request is admitted, v_out and theta_out (same shapes) are written when it
+ * finishes: the caller keeps all four valid and v0, theta0 unchanged until
+ * then.  *id identifies the request. */
 fcns_status fcns_server_submit(fcns_server* srv, const fcns_problem* prob, const double* v0,
-                               const double* theta0, double dt, int32_t nsteps, int64_t* id);
+                               const double* theta0, double dt, int32_t nsteps, double* v_out,
+                               double* theta_out, int64_t* id);
 /* Progress: collect finished requests, admit queued ones.  Outputs (nullable)
  * are the queue length, the number running and the number finished so far. */
 fcns_status fcns_server_poll(fcns_server* srv, int32_t* n_queued, int32_t* n_active,
                              int64_t* n_done);
 /* Seconds on the server's clock (steady, from fcns_server_create). */
 double fcns_server_now(const fcns_server* srv);
-/* Result of a finished request into HOST arrays v [3][nz][ny][nx] and theta
- * (nullable); stats (HOST, nullable, 6 doubles): submit, admit and done times
- * (server clock, s), mean, median and max step time (ms, HIP events on its
- * stream).  ESTATE if not finished; ENONFINITE if the state blew up. */
-fcns_status fcns_server_result(fcns_server* srv, int64_t id, double* v, double* theta,
-                               double* stats);
+/* Status of a finished request (its state is then in v_out, theta_out);
+ * stats (HOST, nullable, 6 doubles): submit, admit and done times (server
+ * clock, s), mean, median and max step time (ms, HIP events on its stream).
+ * ESTATE if not finished; ENONFINITE if the state blew up. */
+fcns_status fcns_server_result(fcns_server* srv, int64_t id, double* stats);
 /* Per-step times (ms) of a finished request: up to max into ms (HOST). */
 fcns_status fcns_server_step_times(fcns_server* srv, int64_t id, int32_t max, float* ms,
                                    int32_t* n);

@@ -60,11 +60,11 @@ SIGNATURES = {
     "fcns_stream": (_P, [_P]),
     "fcns_server_create": (ctypes.c_int, [_I32, _I64, ctypes.POINTER(_P)]),
     "fcns_server_submit": (ctypes.c_int, [_P, ctypes.POINTER(FcnsProblem), _P, _P, _D, _I32,
-                                          ctypes.POINTER(_I64)]),
+                                          _P, _P, ctypes.POINTER(_I64)]),
     "fcns_server_poll": (ctypes.c_int, [_P, ctypes.POINTER(_I32), ctypes.POINTER(_I32),
                                         ctypes.POINTER(_I64)]),
     "fcns_server_now": (_D, [_P]),
-    "fcns_server_result": (ctypes.c_int, [_P, _I64, _P, _P, _P]),
+    "fcns_server_result": (ctypes.c_int, [_P, _I64, _P]),
     "fcns_server_step_times": (ctypes.c_int, [_P, _I64, _I32, _P, ctypes.POINTER(_I32)]),
     "fcns_server_release": (ctypes.c_int, [_P, _I64]),
     "fcns_server_destroy": (ctypes.c_int, [_P]),
@@ -143,7 +143,7 @@ class Server:
         if st != FCNS_OK:
             raise FcnsError(st, "server_create")
         self.srv = h
-        self.shapes = {}
+        self.arrays = {}   # per request: inputs and outputs the library reads / writes
 
     def _check(self, st):
         if st != FCNS_OK:
@@ -152,12 +152,14 @@ class Server:
     def submit(self, prob, v0, theta0, dt, nsteps):
         v0 = np.ascontiguousarray(v0, dtype=np.float64)
         th = None if theta0 is None else np.ascontiguousarray(theta0, dtype=np.float64)
+        vo = np.empty_like(v0)
+        tho = None if th is None else np.empty_like(th)
+        addr = lambda a: None if a is None else a.ctypes.data_as(ctypes.c_void_p)
         rid = ctypes.c_int64()
         self._check(self.lib.fcns_server_submit(
-            self.srv, ctypes.byref(prob), v0.ctypes.data_as(ctypes.c_void_p),
-            None if th is None else th.ctypes.data_as(ctypes.c_void_p), float(dt), int(nsteps),
-            ctypes.byref(rid)))
-        self.shapes[rid.value] = (v0.shape, None if th is None else th.shape)
+            self.srv, ctypes.byref(prob), addr(v0), addr(th), float(dt), int(nsteps), addr(vo),
+            addr(tho), ctypes.byref(rid)))
+        self.arrays[rid.value] = (v0, th, vo, tho)
         return rid.value
 
     def poll(self):
@@ -170,13 +172,9 @@ class Server:
         return self.lib.fcns_server_now(self.srv)
 
     def result(self, rid):
-        vs, ts = self.shapes[rid]
-        v = np.empty(vs)
-        th = np.empty(ts) if ts is not None else None
+        _, _, v, th = self.arrays[rid]
         stats = np.zeros(6)
-        st = self.lib.fcns_server_result(self.srv, rid, v.ctypes.data_as(ctypes.c_void_p),
-                                         None if th is None else th.ctypes.data_as(ctypes.c_void_p),
-                                         stats.ctypes.data_as(ctypes.c_void_p))
+        st = self.lib.fcns_server_result(self.srv, rid, stats.ctypes.data_as(ctypes.c_void_p))
         if st not in (FCNS_OK, FCNS_ENONFINITE):
             self._check(st)
         keys = ("t_submit", "t_admit", "t_done", "step_ms_mean", "step_ms_p50", "step_ms_max")
@@ -194,7 +192,7 @@ class Server:
 
     def release(self, rid):
         self._check(self.lib.fcns_server_release(self.srv, rid))
-        self.shapes.pop(rid, None)
+        self.arrays.pop(rid, None)
 
     def close(self):
         if getattr(self, "srv", None):

@@ -44,7 +44,10 @@ struct Request {
   int64_t id = 0;
   fcns_problem prob{};
   std::vector<double> table;
-  std::vector<double> v0, th0;
+  const double* v0 = nullptr;  // caller's host arrays (read at admission)
+  const double* th0 = nullptr;
+  double* v_out = nullptr;     // caller's host arrays (written when done)
+  double* th_out = nullptr;
   double dt = 0.0;
   int nsteps = 0;
   double t_submit = 0.0, t_admit = -1.0, t_done = -1.0;
@@ -53,7 +56,6 @@ struct Request {
   std::vector<hipEvent_t> ev;
   hipEvent_t fin = nullptr;
   std::vector<float> step_ms;
-  std::vector<double> v, th;
   fcns_status status = FCNS_OK;
   std::string err;
 };
@@ -122,10 +124,13 @@ extern "C" double fcns_server_now(const fcns_server* s) { return s ? s->now() : 
 
 extern "C" fcns_status fcns_server_submit(fcns_server* s, const fcns_problem* prob,
                                           const double* v0, const double* theta0, double dt,
-                                          int32_t nsteps, int64_t* id) {
+                                          int32_t nsteps, double* v_out, double* theta_out,
+                                          int64_t* id) {
   if (!s) return FCNS_EINVAL;
-  if (!prob || !v0 || !id || !prob->fc_table) return srv_fail(s, FCNS_EINVAL, "NULL argument");
-  if (prob->boussinesq && !theta0) return srv_fail(s, FCNS_EINVAL, "theta0 required");
+  if (!prob || !v0 || !v_out || !id || !prob->fc_table)
+    return srv_fail(s, FCNS_EINVAL, "NULL argument");
+  if (prob->boussinesq && (!theta0 || !theta_out))
+    return srv_fail(s, FCNS_EINVAL, "theta0 and theta_out required");
   if (!(dt > 0.0) || nsteps < 1) return srv_fail(s, FCNS_EINVAL, "need dt > 0 and nsteps >= 1");
   int64_t need = 0;
   if (fcns_footprint(prob, &need) != FCNS_OK) return srv_fail(s, FCNS_EINVAL, "bad problem");
@@ -135,9 +140,10 @@ extern "C" fcns_status fcns_server_submit(fcns_server* s, const fcns_problem* pr
   const int d = prob->fc_d, C = prob->fc_C;
   r->table.assign(prob->fc_table, prob->fc_table + (size_t)d * d + (size_t)C * d);
   r->prob.fc_table = nullptr;
-  const size_t n = (size_t)prob->nx * prob->ny * prob->nz;
-  r->v0.assign(v0, v0 + 3 * n);
-  if (prob->boussinesq) r->th0.assign(theta0, theta0 + n);
+  r->v0 = v0;
+  r->th0 = prob->boussinesq ? theta0 : nullptr;
+  r->v_out = v_out;
+  r->th_out = prob->boussinesq ? theta_out : nullptr;
   r->dt = dt;
   r->nsteps = nsteps;
   r->t_submit = s->now();
@@ -219,10 +225,12 @@ static fcns_status launch_request(fcns_server* s, Request& r) {
   const size_t n = (size_t)pc->npts;
   fcns_status st = fcns_set_params(c, r.prob.nu, r.prob.kappa, r.prob.gamma, r.prob.forcing_x);
   if (st != FCNS_OK) return st;
-  memcpy(pc->hphys, r.v0.data(), 3 * n * sizeof(double));
-  if (pc->nphys == 4) memcpy(pc->hphys + 3 * n, r.th0.data(), n * sizeof(double));
-  if (hipMemcpyAsync(pc->dphys, pc->hphys, pc->nphys * n * sizeof(double),
-                     hipMemcpyHostToDevice, pc->stream) != hipSuccess)
+  // straight from the caller's (pageable) arrays: the runtime stages the copy
+  if (hipMemcpyAsync(pc->dphys, r.v0, 3 * n * sizeof(double), hipMemcpyHostToDevice,
+                     pc->stream) != hipSuccess)
+    return FCNS_EDEVICE;
+  if (pc->nphys == 4 && hipMemcpyAsync(pc->dphys + 3 * n, r.th0, n * sizeof(double),
+                                       hipMemcpyHostToDevice, pc->stream) != hipSuccess)
     return FCNS_EDEVICE;
   if ((st = fcns_set_state(c, pc->dphys, pc->nphys == 4 ? pc->dphys + 3 * n : nullptr)) != FCNS_OK)
     return st;
@@ -285,10 +293,10 @@ extern "C" fcns_status fcns_server_poll(fcns_server* s, int32_t* n_queued, int32
       if (q == hipSuccess) {
         PoolCtx* pc = r.pc;
         const size_t n = (size_t)pc->npts;
-        r.v.assign(pc->hphys, pc->hphys + 3 * n);
-        if (pc->nphys == 4) r.th.assign(pc->hphys + 3 * n, pc->hphys + 4 * n);
+        memcpy(r.v_out, pc->hphys, 3 * n * sizeof(double));
+        if (pc->nphys == 4) memcpy(r.th_out, pc->hphys + 3 * n, n * sizeof(double));
         bool finite = true;
-        for (double x : r.v) finite = finite && std::isfinite(x);
+        for (size_t i = 0; i < 3 * n; ++i) finite = finite && std::isfinite(r.v_out[i]);
         r.status = finite ? FCNS_OK : FCNS_ENONFINITE;
         r.state = Q_DONE;
         r.t_done = s->now();
@@ -306,8 +314,6 @@ extern "C" fcns_status fcns_server_poll(fcns_server* s, int32_t* n_queued, int32
         r.pc->last_used = ++s->tick;
         r.pc = nullptr;
       }
-      r.v0.clear();
-      r.th0.clear();
       s->active.erase(s->active.begin() + i);
     } else {
       ++i;
@@ -348,16 +354,13 @@ extern "C" fcns_status fcns_server_poll(fcns_server* s, int32_t* n_queued, int32
   return FCNS_OK;
 }
 
-extern "C" fcns_status fcns_server_result(fcns_server* s, int64_t id, double* v, double* theta,
-                                          double* stats) {
+extern "C" fcns_status fcns_server_result(fcns_server* s, int64_t id, double* stats) {
   if (!s) return FCNS_EINVAL;
   auto f = s->reqs.find(id);
   if (f == s->reqs.end()) return srv_fail(s, FCNS_EINVAL, "unknown request");
   Request& r = *f->second;
   if (r.state != Q_DONE) return srv_fail(s, FCNS_ESTATE, "request not finished");
   if (r.status != FCNS_OK && r.status != FCNS_ENONFINITE) return srv_fail(s, r.status, r.err);
-  if (v) memcpy(v, r.v.data(), r.v.size() * sizeof(double));
-  if (theta && !r.th.empty()) memcpy(theta, r.th.data(), r.th.size() * sizeof(double));
   if (stats) {
     std::vector<float> sm = r.step_ms;
     std::sort(sm.begin(), sm.end());

@@ -1,12 +1,32 @@
-"""Write a short text summary of a rocprofv3 kernel-trace database.
+"""Short summaries of rocprofv3 output, written under profiles/.
 
-    python profiles/make_summary.py <results.db> <out.txt> "<command that made it>"
+Kernel-trace statistics (text):
+    python profiles/make_summary.py trace <results.db> <out.txt> "<command>"
+
+HBM traffic per launch from two counter runs (FETCH_SIZE, then WRITE_SIZE,
+both in KiB per dispatch), each scaled by what the same counter reads for the
+largest plain device copy in the run (a 1 GiB copy: it reads and writes
+exactly 1 GiB), one JSON file per kernel class:
+    python profiles/make_summary.py pmc <fetch.csv> <write.csv> <workload> \\
+        <kernel source hash> "<fetch command>" "<write command>"
 """
+import csv
+import json
+import os
 import sqlite3
+import statistics
 import sys
 
+HERE = os.path.dirname(os.path.abspath(__file__))
 
-def main(db, out, cmd):
+# kernel name prefix -> timing class of the library (the y kernel serves three
+# classes of equal traffic pattern; it is reported as one)
+CLASSES = {"fcns::k_x_nl<": "x_nl", "fcns::k_z_stageA<": "z_stageA",
+           "fcns::k_z_stageB<": "z_stageB", "fcns::k_z_back<": "z_back", "fcns::k_y<": "y"}
+COPY_BYTES = 1 << 30
+
+
+def trace(db, out, cmd):
     con = sqlite3.connect(db)
     rows = con.execute("select name, total_calls, total_duration, average, percentage "
                        "from top_kernels").fetchall()
@@ -15,8 +35,47 @@ def main(db, out, cmd):
         fh.write("# kernel | calls | total_ms | avg_ms | percent  (top_kernels view: durations in us)\n")
         for name, n, tot, avg, pct in rows:
             short = name.split("(")[0].replace("void ", "")
-            fh.write(f"{short} | {n} | {tot / 1e3:.1f} | {avg / 1e3:.2f} | {pct:.2f}\n")
+            fh.write(f"{short} | {n} | {tot / 1e3:.2f} | {avg / 1e3:.4f} | {pct:.2f}\n")
+
+
+def _per_dispatch(path, counter):
+    out = []
+    for r in csv.DictReader(open(path)):
+        if r["Counter_Name"] == counter:
+            out.append((r["Kernel_Name"], int(r["Grid_Size"]), float(r["Counter_Value"])))
+    return out
+
+
+def pmc(fetch_csv, write_csv, workload, src_hash, cmd_fetch, cmd_write):
+    fetch = _per_dispatch(fetch_csv, "FETCH_SIZE")
+    write = _per_dispatch(write_csv, "WRITE_SIZE")
+    cf = max(v for n, g, v in fetch if "copyBuffer" in n)
+    cw = max(v for n, g, v in write if "copyBuffer" in n)
+    kf = COPY_BYTES / (cf * 1024.0)
+    kw = COPY_BYTES / (cw * 1024.0)
+    for prefix, cls in CLASSES.items():
+        fv = [v for n, g, v in fetch if n.replace("void ", "").startswith(prefix)]
+        wv = [v for n, g, v in write if n.replace("void ", "").startswith(prefix)]
+        if not fv or not wv:
+            continue
+        # the median dispatch: the step's launches outnumber the set/get-state ones
+        fb = statistics.median(fv) * 1024.0 * kf
+        wb = statistics.median(wv) * 1024.0 * kw
+        rec = {"kernel_class": cls, "workload": workload, "source_hash": src_hash,
+               "hbm_bytes_per_launch": int(fb + wb), "read_bytes": int(fb),
+               "write_bytes": int(wb), "dispatches": len(fv),
+               "calibration": {"copy_bytes": COPY_BYTES, "fetch_kib": cf, "write_kib": cw,
+                               "fetch_factor": kf, "write_factor": kw},
+               "commands": [cmd_fetch, cmd_write]}
+        with open(os.path.join(HERE, f"pmc_{cls}_{workload}.json"), "w") as fh:
+            json.dump(rec, fh, indent=1)
+            fh.write("\n")
 
 
 if __name__ == "__main__":
-    main(*sys.argv[1:4])
+    if sys.argv[1] == "trace":
+        trace(*sys.argv[2:5])
+    elif sys.argv[1] == "pmc":
+        pmc(*sys.argv[2:8])
+    else:
+        raise SystemExit(__doc__)
