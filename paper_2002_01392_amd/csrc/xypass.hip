@@ -360,6 +360,183 @@ __global__ __launch_bounds__(NT) void k_x_nl(XArgs a, const cpx<T>* __restrict__
   }
 }
 
+// ---------------------------------------------------------------- x pass, 512-point rows
+// One wavefront per row (y, z), 8 points per lane: lane t holds index
+// t + 64 m (m = 0..7) of every transform, in and out.  The 512-point DFT is
+// split as n = n0 + 8 n1 + 64 n2, k = k0 + 8 k1 + 64 k2 (n0 + 8 n1 = t):
+//   a radix-8 DFT over n2 in registers, twiddle w64^(n1 k0);
+//   exchange so that lane n0 + 8 k0 holds n1 = 0..7, radix-8 over n1,
+//   twiddle w512^(n0 (k0 + 8 k1));
+//   exchange so that lane k0 + 8 k1 holds n0 = 0..7, radix-8 over n0,
+// which leaves X[t + 64 k2] in lane t.  The exchanges go through a padded
+// per-wave LDS buffer (conflict-free 16-byte accesses) and need only
+// wave-level ordering, no workgroup barrier.  Two real transforms share one
+// complex transform: z = a + i b (inverse from the spectra A, B; forward of two
+// nonlinear terms).
+constexpr int XW_WAVES = 4;        // waves (rows in flight) per workgroup
+constexpr int XW_BUF = 512 + 64;   // padded slots of one wave's exchange buffer
+
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Padded slots (one spare slot per 64 in exchange 1, per 8 in exchange 2 and
+// in the natural-order buffer): element 64 n0 + 8 k0 + n1 of exchange 1 sits
+// at 65 n0 + 8 k0 + n1, element 8 j + n0 of exchange 2 at 9 j + n0, element i
+// of the natural-order buffer at i + i / 8.  Written with the per-lane part
+// separate so that the per-register part is an instruction offset.
+__device__ __forceinline__ int xw_nat(int i) { return i + (i >> 3); }
+
+// Per-lane twiddles, stored [register][lane] in LDS (read at lane + offset):
+// tw[k0 - 1][t] = w64^(n1 k0) (k0 = 1..7), tw[7 + k1][t] = w512^(n0 (k0' + 8 k1))
+// with t = n0 + 8 n1 before exchange 1 and t = n0 + 8 k0' after it.
+constexpr int XW_TW = 15 * 64;
+
+template <typename T>
+__device__ __forceinline__ void wave_fft512(cpx<T> (&r)[8], cpx<T>* __restrict__ buf,
+                                            const cpx<T>* __restrict__ tw, int lane) {
+  const int n0 = lane & 7, hi = lane >> 3;  // hi = n1 before, k0 after exchange 1
+  Codelet<T, 8>::run(r, nullptr);
+#pragma unroll
+  for (int k0 = 1; k0 < 8; ++k0) r[k0] = r[k0] * tw[(k0 - 1) * 64 + lane];
+  cpx<T>* w1 = buf + 65 * n0 + hi;
+#pragma unroll
+  for (int k0 = 0; k0 < 8; ++k0) w1[8 * k0] = r[k0];
+  wave_sync();
+  const cpx<T>* r1 = buf + 65 * n0 + 8 * hi;
+#pragma unroll
+  for (int n1 = 0; n1 < 8; ++n1) r[n1] = r1[n1];
+  wave_sync();
+  Codelet<T, 8>::run(r, nullptr);
+#pragma unroll
+  for (int k1 = 0; k1 < 8; ++k1) r[k1] = r[k1] * tw[(7 + k1) * 64 + lane];
+  cpx<T>* w2 = buf + 9 * hi + n0;
+#pragma unroll
+  for (int k1 = 0; k1 < 8; ++k1) w2[72 * k1] = r[k1];
+  wave_sync();
+  const cpx<T>* r2 = buf + 9 * lane;
+#pragma unroll
+  for (int q = 0; q < 8; ++q) r[q] = r2[q];
+  wave_sync();
+  Codelet<T, 8>::run(r, nullptr);
+}
+
+// NL_f = -(u dq_f/dx + v dq_f/dy + w dq_f/dz) on rows of nx = 512 points.
+// Real quantities in order: u, v, w, then per field dq/dx, dq/dy, dq/dz;
+// consecutive pairs share one inverse transform, and the forward transform of
+// a pair of finished fields follows as soon as both are complete.
+template <typename T, int NF>
+__global__ __launch_bounds__(64 * XW_WAVES) void k_x_nl512(XArgs a, const cpx<T>* __restrict__ xyb,
+                                                           cpx<T>* __restrict__ nl, long long fs,
+                                                           long long nrows) {
+  constexpr int N = 512, NQ = 3 + 3 * NF, NP = (NQ + 1) / 2;
+  __shared__ cpx<T> tw[XW_TW];
+  __shared__ cpx<T> xbuf[XW_WAVES][XW_BUF];
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);  // wave-uniform
+  for (int e = tid; e < XW_TW; e += 64 * XW_WAVES) {
+    const int reg = e / 64, t = e % 64, n0 = t & 7, hi = t >> 3;
+    const int j = reg < 7 ? 8 * hi * (reg + 1) : n0 * (hi + 8 * (reg - 7));  // power of w512
+    double sn, cs;
+    sincospi(2.0 * j / N, &sn, &cs);
+    tw[e] = mk((T)cs, (T)(-sn));   // exp(-2 pi i j / 512)
+  }
+  __syncthreads();
+  cpx<T>* buf = xbuf[wv];
+  const int nkxp = a.nkxp;
+  const T kxs = (T)a.kxs;
+  const T sc = T(1) / T(N);
+  for (long long row = (long long)blockIdx.x * XW_WAVES + wv; row < nrows;
+       row += (long long)gridDim.x * XW_WAVES) {
+    T U[3][8];
+    T acc[NF][8];
+#pragma unroll
+    for (int p = 0; p < NP; ++p) {
+      // keep each pair's loads next to its transform (hoisting them all would
+      // multiply the live registers)
+      __builtin_amdgcn_sched_barrier(0);
+      // the two quantities of this pair (qb = NQ: none)
+      const int qa = 2 * p, qb = 2 * p + 1;
+      cpx<T> r[8];
+      auto src = [&](int q, bool& dx) -> const cpx<T>* {
+        dx = false;
+        if (q < 3) return xyb + (3 * q) * fs + row * nkxp;
+        const int f = (q - 3) / 3, d = (q - 3) % 3;
+        dx = d == 0;
+        return xyb + (3 * f + d) * fs + row * nkxp;
+      };
+      bool dxa, dxb = false;
+      const cpx<T>* pa = src(qa, dxa);
+      const cpx<T>* pb = qb < NQ ? src(qb, dxb) : nullptr;
+#pragma unroll
+      for (int m = 0; m < 8; ++m) {
+        const int k = lane + 64 * m;
+        const int kk = k <= N / 2 ? k : N - k;
+        cpx<T> A = pa[kk];
+        cpx<T> B = pb ? pb[kk] : zero<T>();
+        const T kx = (kk == N / 2) ? T(0) : kxs * (T)kk;
+        if (dxa) A = mul_i(A) * kx;
+        if (dxb) B = mul_i(B) * kx;
+        if (kk == 0 || kk == N / 2) {
+          A.y = T(0);
+          B.y = T(0);
+        }
+        // Z[k] = A + i B (k <= N/2), conj(A) + i conj(B) (k > N/2); inverse via conj
+        const cpx<T> Z = (k <= N / 2) ? mk(A.x - B.y, A.y + B.x) : mk(A.x + B.y, B.x - A.y);
+        r[m] = conj(Z);
+      }
+      wave_fft512<T>(r, buf, tw, lane);
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const int q = 2 * p + h;
+        if (q >= NQ) continue;
+#pragma unroll
+        for (int m = 0; m < 8; ++m) {
+          const T val = h == 0 ? r[m].x * sc : -r[m].y * sc;
+          if (q < 3) {
+            U[q][m] = val;
+          } else {
+            const int f = (q - 3) / 3, d = (q - 3) % 3;
+            if (d == 0)
+              acc[f][m] = -U[0][m] * val;
+            else
+              acc[f][m] -= U[d][m] * val;
+          }
+        }
+        // a pair of fields finished: forward transform and unpack
+        if (q >= 3 && (q - 3) % 3 == 2) {
+          const int f = (q - 3) / 3;
+          if (f % 2 == 1 || f == NF - 1) {
+            const int fa = f % 2 == 1 ? f - 1 : f;
+            const bool two = f % 2 == 1;
+            cpx<T> z[8];
+#pragma unroll
+            for (int m = 0; m < 8; ++m) z[m] = mk(acc[fa][m], two ? acc[fa + 1][m] : T(0));
+            wave_fft512<T>(z, buf, tw, lane);
+            cpx<T>* wn = buf + xw_nat(lane);
+#pragma unroll
+            for (int m = 0; m < 8; ++m) wn[72 * m] = z[m];
+            wave_sync();
+#pragma unroll
+            for (int m = 0; m < 5; ++m) {
+              const int k = lane + 64 * m;
+              if (k <= N / 2) {
+                const cpx<T> Zk = wn[72 * m];
+                const cpx<T> Zm = conj(buf[xw_nat((N - k) & (N - 1))]);
+                nl[fa * fs + row * nkxp + k] = (Zk + Zm) * T(0.5);
+                if (two) nl[(fa + 1) * fs + row * nkxp + k] = mul_mi(Zk - Zm) * T(0.5);
+              }
+            }
+            wave_sync();
+          }
+        }
+      }
+    }
+  }
+}
+
 // ---------------------------------------------------------------- helpers
 __global__ void k_fill(cpx<double>* p, long long n) {
   const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -449,7 +626,17 @@ static void launch_x_nl_v(const XArgs& a, const cpx<T>* xyb, cpx<T>* nl, long lo
 template <typename T>
 void launch_x_nl(const XArgs& a, bool big, const cpx<T>* xyb, cpx<T>* nl, long long fs,
                  long long nrows, int nfields, hipStream_t st) {
-  if (a.nx == 512 && plan_is(a.pl, {8, 8, 8}))
+  if (a.nx == 512) {
+    // one wavefront per row; enough workgroups to fill the chip several times
+    const long long need = (nrows + XW_WAVES - 1) / XW_WAVES;
+    dim3 grid((unsigned)(need < 4096 ? need : 4096));
+    if (nfields == 4)
+      hipLaunchKernelGGL((k_x_nl512<T, 4>), grid, dim3(64 * XW_WAVES), 0, st, a, xyb, nl, fs,
+                         nrows);
+    else
+      hipLaunchKernelGGL((k_x_nl512<T, 3>), grid, dim3(64 * XW_WAVES), 0, st, a, xyb, nl, fs,
+                         nrows);
+  } else if (a.nx == 512 && plan_is(a.pl, {8, 8, 8}))
     launch_x_nl_v<T, SPlan<8, 8, 8>, 4, 256, 2>(a, xyb, nl, fs, nrows, nfields, st);
   else if (a.nx == 256 && plan_is(a.pl, {8, 8, 4}))
     launch_x_nl_v<T, SPlan<8, 8, 4>, 4, 256, 1>(a, xyb, nl, fs, nrows, nfields, st);

@@ -134,6 +134,18 @@ def test_rhs_nonlinear_compile_time_plans(fcns, nx, ny, nz, C, filtered):
     assert rel_l2(nlt, rt) < 1e-11
 
 
+def test_rhs_nonlinear_velocity_only_512(fcns):
+    # three transported fields on 512-point rows
+    nx, ny, nz, C, lx, ly, lz = 512, 24, 17, 25, 2.0, 1.0, 1.0
+    s = fcns.Solver(nx, ny, nz, lx, ly, lz, 0.01, d=5, C=C)
+    v = np.stack([W.smooth_field(nx, ny, nz, lx, ly, lz, 50 + i, kmax=6) for i in range(3)])
+    nlv, _ = s.rhs_nonlinear(torch.from_numpy(v), None, False)
+    torch.cuda.synchronize()
+    o = Oracle(Problem(nx=nx, ny=ny, nz=nz, lx=lx, ly=ly, lz=lz, nu=0.01, C=C))
+    rv, _ = o.rhs_nonlinear(v, None, False)
+    assert rel_l2(nlv, rv) < 1e-11
+
+
 # ------------------------------------------------------------------ projection
 @pytest.mark.parametrize("nx,ny,nz,C,c", [(16, 16, 33, 25, 0.5), (32, 24, 65, 31, 1e-3),
                                           (20, 36, 129, 31, 2.0)])
