@@ -96,6 +96,88 @@ def solenoidal_noise(nx, ny, nz, lx, ly, lz, kmax, mmax, rms, seed):
     return v * (rms / cur) if cur > 0 else v
 
 
+def clamped_beam_lambdas(mmax):
+    """lambda_1..lambda_mmax of the Chandrasekhar-Reid functions g_m (App. A):
+    the roots of tanh(l/2) + tan(l/2) = 0 (m odd, even functions) and
+    coth(l/2) - cot(l/2) = 0 (m even, odd functions), which alternate and lie
+    near (m + 1/2) pi; found by bisection in FP64."""
+    out = []
+    for m in range(1, mmax + 1):
+        if m % 2:
+            f = lambda l: math.tanh(l / 2) + math.tan(l / 2)
+        else:
+            f = lambda l: 1.0 / math.tanh(l / 2) - 1.0 / math.tan(l / 2)
+        guess = (m + 0.5) * math.pi
+        lo, hi = guess - 0.3, guess + 0.3
+        flo = f(lo)
+        for _ in range(200):
+            mid = 0.5 * (lo + hi)
+            fm = f(mid)
+            if (fm < 0) == (flo < 0):
+                lo, flo = mid, fm
+            else:
+                hi = mid
+        out.append(0.5 * (lo + hi))
+    return out
+
+
+def _g_cr(m, lam, zp):
+    """g_m(z') and g_m'(z') of App. A (z' in [-1/2, 1/2])."""
+    if m % 2:
+        g = np.cosh(lam * zp) / math.cosh(lam / 2) - np.cos(lam * zp) / math.cos(lam / 2)
+        dg = lam * (np.sinh(lam * zp) / math.cosh(lam / 2) + np.sin(lam * zp) / math.cos(lam / 2))
+        d2 = lam ** 2 * (np.cosh(lam * zp) / math.cosh(lam / 2) + np.cos(lam * zp) / math.cos(lam / 2))
+    else:
+        g = np.sinh(lam * zp) / math.sinh(lam / 2) - np.sin(lam * zp) / math.sin(lam / 2)
+        dg = lam * (np.cosh(lam * zp) / math.sinh(lam / 2) - np.cos(lam * zp) / math.sin(lam / 2))
+        d2 = lam ** 2 * (np.sinh(lam * zp) / math.sinh(lam / 2) + np.sin(lam * zp) / math.sin(lam / 2))
+    return g, dg, d2
+
+
+def curl_eigen_noise(nx, ny, nz, lx, ly, lz, rms, seed, kh2=(4, 25), mrange=(2, 5)):
+    """Random solenoidal no-slip field of App. A: q = curl curl(phi z^) +
+    curl(psi z^) with phi = sum a exp(i(kx x + ky y)) g_m(z'), psi = sum b
+    exp(i(kx x + ky y)) sin(m pi (z' + 1/2)), z' = z/Lz - 1/2, over horizontal
+    mode numbers with kh2[0] <= n^2 + l^2 <= kh2[1] and mrange[0] <= m <=
+    mrange[1]; random phases, uniform random amplitudes decaying as k^-4 (a)
+    and k^-3 (b) with k^2 = kx^2 + ky^2 + (lambda_m / Lz)^2.  The mode numbers
+    count the box's fundamental wavenumbers (the paper's box is 2 pi wide).
+    Component form: q = (d2 phi/dxdz + dpsi/dy, d2 phi/dydz - dpsi/dx,
+    -(d2/dx2 + d2/dy2) phi).  Scaled to the requested rms."""
+    r = rng(seed)
+    x, y, z = grid(nx, ny, nz, lx, ly, lz)
+    X, Y = np.meshgrid(x, y, indexing="xy")
+    zp = z / lz - 0.5
+    lams = clamped_beam_lambdas(mrange[1])
+    nmax = int(math.isqrt(kh2[1]))
+    v = np.zeros((3, nz, ny, nx))
+    for n in range(-nmax, nmax + 1):
+        for l in range(0, nmax + 1):
+            if l == 0 and n < 0:
+                continue               # real field: one of each +-(n, l) pair
+            if not kh2[0] <= n * n + l * l <= kh2[1]:
+                continue
+            kx, ky = 2 * math.pi * n / lx, 2 * math.pi * l / ly
+            ph = kx * X + ky * Y
+            for m in range(mrange[0], mrange[1] + 1):
+                lam = lams[m - 1]
+                k = math.sqrt(kx * kx + ky * ky + (lam / lz) ** 2)
+                amp_a, pha, amp_b, phb = r.random(4)
+                a = amp_a * k ** -4
+                b = amp_b * k ** -3
+                g, dg, _ = _g_cr(m, lam, zp)
+                dgz = dg / lz
+                sz = np.sin(m * math.pi * (zp + 0.5))
+                ca, sa = np.cos(ph + 2 * math.pi * pha), np.sin(ph + 2 * math.pi * pha)
+                cb, sb = np.cos(ph + 2 * math.pi * phb), np.sin(ph + 2 * math.pi * phb)
+                # phi = a cos(ph + alpha) g(z), psi = b cos(ph + beta) sin(...)
+                v[0] += (-a * kx * sa)[None] * dgz[:, None, None] + (-b * ky * sb)[None] * sz[:, None, None]
+                v[1] += (-a * ky * sa)[None] * dgz[:, None, None] + (b * kx * sb)[None] * sz[:, None, None]
+                v[2] += (a * (kx * kx + ky * ky) * ca)[None] * g[:, None, None]
+    cur = math.sqrt(float(np.mean(v ** 2)) * 3.0)
+    return v * (rms / cur) if cur > 0 else v
+
+
 def wall_vanishing_noise(nx, ny, nz, lx, ly, lz, kmax, mmax, rms, seed):
     """Scalar band-limited field sum a T(x,y) sin(m pi z / Lz), |p|,|q| <= kmax,
     1 <= m <= mmax, zero at both walls, scaled to the requested rms."""
