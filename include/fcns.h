@@ -157,6 +157,29 @@ fcns_status fcns_timing_reset(fcns_ctx* ctx);
 fcns_status fcns_timing_report(fcns_ctx* ctx, int32_t max, int32_t* n, char* names,
                                int64_t* counts, double* ms);
 
+/* Flow diagnostics of the current state (synchronizes the stream).  out
+ * (HOST) receives up to nout of FCNS_NDIAG values, in this order:
+ *   0 kinetic energy, one half of the grid mean of |v|^2
+ *   1 grid mean of (div v)^2, the FC divergence (Sec. 6)
+ *   2, 3 wall means of u^2 + v^2 (slip) at z = 0 and z = Lz
+ *   4, 5 wall means of w^2 at z = 0 and z = Lz
+ *   6, 7 x-y mean of du/dz at z = 0 and z = Lz
+ *   8, 9 friction Reynolds number sqrt(nu |dU/dz|) (Lz/2) / nu at each wall
+ *   10, 11 Nusselt number 1 - (1/gamma) <d theta/dz>_xy at each wall
+ *         (Sec. 7; NaN without theta)
+ *   12 grid mean of theta^2 (0 without theta)
+ * Grid means are over the nx*ny*nz points; z derivatives are those of the
+ * continued state (B_z(i k~z V^)). */
+#define FCNS_NDIAG 13
+fcns_status fcns_diagnostics(fcns_ctx* ctx, double* out, int32_t nout);
+
+/* 1D spectra of field (0..2 velocity, 3 theta) at height index z (Sec. 6):
+ * ex[kx] (HOST, nx/2+1) = sum over ky of |q^(kx, ky)|^2 with the -kx half
+ * folded in, ey[ky] (HOST, ny, FFT order) = sum over all kx, both with q^
+ * normalised by nx ny so that each sums to the x-y mean of q^2 at z.
+ * Synchronizes the stream. */
+fcns_status fcns_spectra(fcns_ctx* ctx, int32_t field, int32_t z, double* ex, double* ey);
+
 /* Sizes of the context: N' = nz + C. */
 int32_t fcns_npr(const fcns_ctx* ctx);
 

@@ -56,6 +56,8 @@ SIGNATURES = {
     "fcns_timing_report": (ctypes.c_int, [_P, _I32, ctypes.POINTER(_I32), _P, _P, _P]),
     "fcns_last_error": (ctypes.c_char_p, [_P]),
     "fcns_footprint": (ctypes.c_int, [ctypes.POINTER(FcnsProblem), ctypes.POINTER(_I64)]),
+    "fcns_diagnostics": (ctypes.c_int, [_P, _P, _I32]),
+    "fcns_spectra": (ctypes.c_int, [_P, _I32, _I32, _P, _P]),
     "fcns_set_params": (ctypes.c_int, [_P, _D, _D, _D, _D]),
     "fcns_stream": (_P, [_P]),
     "fcns_server_create": (ctypes.c_int, [_I32, _I64, ctypes.POINTER(_P)]),
@@ -335,6 +337,24 @@ class Solver:
                                                    _ptr(gp)))
         self._keep = (vs,)
         return vo, gp
+
+    DIAG_NAMES = ("energy", "div2", "slip_bottom", "slip_top", "w2_bottom", "w2_top",
+                  "dudz_bottom", "dudz_top", "re_tau_bottom", "re_tau_top", "nu_bottom",
+                  "nu_top", "theta2")
+
+    def diagnostics(self):
+        out = np.zeros(len(self.DIAG_NAMES))
+        self._check(self.lib.fcns_diagnostics(self.ctx, out.ctypes.data_as(ctypes.c_void_p),
+                                              len(out)))
+        return dict(zip(self.DIAG_NAMES, out.tolist()))
+
+    def spectra(self, field, z):
+        ex = np.zeros(self.nx // 2 + 1)
+        ey = np.zeros(self.ny)
+        self._check(self.lib.fcns_spectra(self.ctx, int(field), int(z),
+                                          ex.ctypes.data_as(ctypes.c_void_p),
+                                          ey.ctypes.data_as(ctypes.c_void_p)))
+        return ex, ey
 
     def get_spectral(self, field):
         out = self.torch.empty((self.npr, self.ny, self.nx // 2 + 1), dtype=self.torch.complex128,

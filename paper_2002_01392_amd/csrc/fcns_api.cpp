@@ -48,6 +48,7 @@ struct fcns_ctx {
   cpx<double>* PM = nullptr;   // mixed pressure
   cpx<double>* GW = nullptr;   // wall tangential gradient [2][2][npen]
   cpx<double>* GWT = nullptr;  // scratch wall gradient
+  double* DG = nullptr;        // diagnostics: per-plane sums [nz][5], then spectra
   bool has_state = false;
   bool has_pressure = false;
   std::string err;
@@ -205,7 +206,7 @@ static void free_all(fcns_ctx* c) {
   for (hipEvent_t e : c->evpool) (void)hipEventDestroy(e);
   c->evpool.clear();
   void* ps[] = {c->twz, c->twx, c->twy, c->twz_f, c->twx_f, c->twy_f, c->rootz, c->fcM, c->sigx, c->sigy, c->sigz, c->P, c->Q,
-                c->VS, c->MV, c->MVT, c->XYB, c->NLB, c->PM, c->GW, c->GWT};
+                c->VS, c->MV, c->MVT, c->XYB, c->NLB, c->PM, c->GW, c->GWT, c->DG};
   for (void* p : ps)
     if (p) (void)hipFree(p);
 }
@@ -358,7 +359,9 @@ extern "C" fcns_status fcns_create(const fcns_problem* prob, void* hip_stream, f
       (st = alloc(c, &c->VS, nf * c->S)) || (st = alloc(c, &c->MV, 2 * nf * c->M)) ||
       (st = alloc(c, &c->MVT, 2 * nf * c->M)) || (st = alloc(c, &c->XYB, 3 * nf * c->M)) ||
       (st = alloc(c, &c->NLB, nf * c->M)) || (st = alloc(c, &c->PM, c->M)) ||
-      (st = alloc(c, &c->GW, 4 * g.npen)) || (st = alloc(c, &c->GWT, 4 * g.npen))) {
+      (st = alloc(c, &c->GW, 4 * g.npen)) || (st = alloc(c, &c->GWT, 4 * g.npen)) ||
+      (st = hipMalloc((void**)&c->DG, sizeof(double) * (5 * (size_t)p.nz + g.nkx + p.ny)) ==
+                    hipSuccess ? FCNS_OK : fail(c, FCNS_ENOMEM, "device allocation failed"))) {
     g_create_err = c->err;
     free_all(c);
     delete c;
@@ -676,6 +679,90 @@ extern "C" fcns_status fcns_pressure_project(fcns_ctx* c, const double* v_star, 
   mixed_to_phys(c, c->MVT, M, 3, v_out, c->g.nz);
   if (gradp_wall) mixed_to_phys(c, c->GWT, 0, 1, gradp_wall, 4);
   return check_launch(c, "pressure_project");
+}
+
+// ---------------------------------------------------------------- diagnostics
+extern "C" fcns_status fcns_diagnostics(fcns_ctx* c, double* out, int32_t nout) {
+  if (!c) return FCNS_EINVAL;
+  if (!c->has_state) return fail(c, FCNS_ESTATE, "diagnostics before set_state");
+  if (!out || nout < 0) return fail(c, FCNS_EINVAL, "NULL out");
+  const Geom& g = c->g;
+  const long long M = c->M;
+  launch_z_back<double>(zargs(c), c->big_z, c->P, c->MVT, c->MVT + M, c->S, 2 * M, c->nf,
+                        c->stream);
+  launch_diag_planes(g, c->MVT, M, c->nf, c->DG, c->stream);
+  fcns_status st = check_launch(c, "diagnostics");
+  if (st != FCNS_OK) return st;
+  std::vector<double> pl(5 * (size_t)g.nz);
+  cpx<double> corner[4] = {};  // (0,0) mode of du/dz, dtheta/dz at z = 0, Lz
+  const long long zt = (long long)(g.nz - 1) * g.npen;
+  const cpx<double>* dudz = c->MVT + M;
+  const cpx<double>* dtdz = c->MVT + 7 * M;
+  if ((st = check_hip(c, hipMemcpyAsync(pl.data(), c->DG, pl.size() * sizeof(double),
+                                        hipMemcpyDeviceToHost, c->stream), "diagnostics")) ||
+      (st = check_hip(c, hipMemcpyAsync(&corner[0], dudz, sizeof(cpx<double>),
+                                        hipMemcpyDeviceToHost, c->stream), "diagnostics")) ||
+      (st = check_hip(c, hipMemcpyAsync(&corner[1], dudz + zt, sizeof(cpx<double>),
+                                        hipMemcpyDeviceToHost, c->stream), "diagnostics")))
+    return st;
+  if (c->nf == 4 &&
+      ((st = check_hip(c, hipMemcpyAsync(&corner[2], dtdz, sizeof(cpx<double>),
+                                         hipMemcpyDeviceToHost, c->stream), "diagnostics")) ||
+       (st = check_hip(c, hipMemcpyAsync(&corner[3], dtdz + zt, sizeof(cpx<double>),
+                                         hipMemcpyDeviceToHost, c->stream), "diagnostics"))))
+    return st;
+  if ((st = check_hip(c, hipStreamSynchronize(c->stream), "diagnostics"))) return st;
+  const double nxy = (double)g.nx * g.ny, n2 = nxy * nxy;
+  double sum[5] = {0, 0, 0, 0, 0};
+  for (int z = 0; z < g.nz; ++z)
+    for (int q = 0; q < 5; ++q) sum[q] += pl[5 * z + q];
+  const double* b = &pl[0];
+  const double* t = &pl[5 * (size_t)(g.nz - 1)];
+  const double nu = c->prob.nu, delta = 0.5 * g.lz;
+  const double dub = corner[0].x / nxy, dut = corner[1].x / nxy;
+  double v[FCNS_NDIAG];
+  v[0] = 0.5 * (sum[0] + sum[1] + sum[2]) / n2 / g.nz;     // kinetic energy
+  v[1] = sum[4] / n2 / g.nz;                                // <(div v)^2>
+  v[2] = (b[0] + b[1]) / n2;                                // slip, bottom
+  v[3] = (t[0] + t[1]) / n2;                                // slip, top
+  v[4] = b[2] / n2;                                         // <w^2>, bottom
+  v[5] = t[2] / n2;                                         // <w^2>, top
+  v[6] = dub;                                               // <du/dz>, bottom
+  v[7] = dut;                                               // <du/dz>, top
+  v[8] = nu > 0 ? sqrt(nu * fabs(dub)) * delta / nu : 0.0;  // Re_tau, bottom
+  v[9] = nu > 0 ? sqrt(nu * fabs(dut)) * delta / nu : 0.0;  // Re_tau, top
+  if (c->nf == 4) {
+    v[10] = 1.0 - corner[2].x / nxy / c->prob.gamma;        // Nu, bottom
+    v[11] = 1.0 - corner[3].x / nxy / c->prob.gamma;        // Nu, top
+    v[12] = sum[3] / n2 / g.nz;                              // <theta^2>
+  } else {
+    v[10] = v[11] = NAN;
+    v[12] = 0.0;
+  }
+  for (int i = 0; i < nout && i < FCNS_NDIAG; ++i) out[i] = v[i];
+  return FCNS_OK;
+}
+
+extern "C" fcns_status fcns_spectra(fcns_ctx* c, int32_t field, int32_t z, double* ex,
+                                    double* ey) {
+  if (!c) return FCNS_EINVAL;
+  if (!c->has_state) return fail(c, FCNS_ESTATE, "spectra before set_state");
+  if (field < 0 || field >= c->nf || z < 0 || z >= c->g.nz || !ex || !ey)
+    return fail(c, FCNS_EINVAL, "bad field, height or NULL");
+  const Geom& g = c->g;
+  launch_z_back<double>(zargs(c), c->big_z, c->P + field * c->S, c->MVT, nullptr, c->S, c->M, 1,
+                        c->stream);
+  double* dex = c->DG + 5 * (size_t)g.nz;
+  double* dey = dex + g.nkx;
+  launch_spectra(g, c->MVT, z, dex, dey, c->stream);
+  fcns_status st = check_launch(c, "spectra");
+  if (st) return st;
+  if ((st = check_hip(c, hipMemcpyAsync(ex, dex, g.nkx * sizeof(double), hipMemcpyDeviceToHost,
+                                        c->stream), "spectra")) ||
+      (st = check_hip(c, hipMemcpyAsync(ey, dey, g.ny * sizeof(double), hipMemcpyDeviceToHost,
+                                        c->stream), "spectra")))
+    return st;
+  return check_hip(c, hipStreamSynchronize(c->stream), "spectra");
 }
 
 extern "C" fcns_status fcns_get_spectral(fcns_ctx* c, int32_t field, double* out) {

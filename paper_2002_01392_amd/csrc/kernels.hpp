@@ -132,6 +132,12 @@ template <typename T>
 void launch_x_nl(const XArgs& a, bool big, const cpx<T>* xyb, cpx<T>* nl, long long fstride,
                  long long nrows, int nfields, hipStream_t st);
 
+// diagnostics (mv: slots 2f = q_f, 2f+1 = dq_f/dz, stride ms)
+void launch_diag_planes(const Geom& g, const cpx<double>* mv, long long ms, int nf, double* out,
+                        hipStream_t st);
+void launch_spectra(const Geom& g, const cpx<double>* q, int z, double* ex, double* ey,
+                    hipStream_t st);
+
 // small helpers
 void launch_fill(cpx<double>* p, long long n, hipStream_t st);
 void launch_sub_mean00(cpx<double>* pmix, long long npen, int nz, double scale, hipStream_t st);

@@ -256,3 +256,55 @@ def test_rk_is_deterministic_and_restartable(fcns):
     torch.cuda.synchronize()
     assert torch.equal(va, vb)     # resume is bitwise identical
     assert torch.equal(va, vc)     # and so is a repeated run
+
+
+# ------------------------------------------------------------------ diagnostics
+def _diag_pair(fcns, w, steps):
+    from oracle.diagnostics import diagnostics, spectra
+    v0, th0 = w.initial_state()
+    s = fcns.Solver.from_workload(w)
+    s.set_state(torch.from_numpy(v0), torch.from_numpy(th0) if th0 is not None else None)
+    s.rk_step(w.dt, steps)
+    o = Oracle(Problem(**w.problem_kwargs()))
+    o.set_state(v0, th0)
+    o.rk_step(w.dt, steps)
+    return s, o, diagnostics, spectra
+
+
+@pytest.mark.parametrize("kind", ["channel", "rb"])
+def test_diagnostics_match_oracle(fcns, kind):
+    if kind == "channel":
+        w = W.channel(32, 24, 33, 2000.0, C=25, dt=1e-3, steps=4, seed=21, noise_rms=0.05)
+    else:
+        w = W.rayleigh_benard(32, 24, 33, 1e5, C=31, dt=2e-3, steps=4, kmax=3, mmax=3,
+                              noise_rms=1e-2)
+    s, o, diagnostics, spectra = _diag_pair(fcns, w, w.steps)
+    got = s.diagnostics()
+    ref = diagnostics(o)
+    # residues of cancellation (the FC divergence, the wall values) are
+    # compared as rms values against the velocity scale, the others relatively
+    vscale = np.sqrt(2 * ref["energy"])
+    kmax = np.pi * max(w.nx / w.lx, w.ny / w.ly, (w.nz - 1) / w.lz)
+    residue = {"div2": vscale * kmax, "slip_bottom": vscale, "slip_top": vscale,
+               "w2_bottom": vscale, "w2_top": vscale}
+    delta = w.lz / 2
+    for k, r in ref.items():
+        g = got[k]
+        if np.isnan(r):
+            assert np.isnan(g), k
+        elif k in residue:
+            assert abs(np.sqrt(g) - np.sqrt(r)) <= 1e-11 * residue[k], (k, g, r)
+        elif k.startswith("dudz"):
+            assert abs(g - r) <= 1e-11 * vscale * kmax, (k, g, r)
+        elif k.startswith("re_tau"):
+            # u_tau^2 = nu |dU/dz|
+            ut2 = lambda x: (x * w.nu / delta) ** 2
+            assert abs(ut2(g) - ut2(r)) <= 1e-11 * w.nu * vscale * kmax, (k, g, r)
+        elif k.startswith("nu_"):
+            assert abs(g - r) <= 1e-11 * max(1.0, abs(r)), (k, g, r)
+        else:
+            assert abs(g - r) <= 1e-11 * abs(r), (k, g, r)
+    for f in range(w.nfields):
+        ex, ey = s.spectra(f, 7)
+        rx, ry = spectra(o, f, 7)
+        assert rel_l2(ex, rx) < 1e-11 and rel_l2(ey, ry) < 1e-11
