@@ -220,6 +220,35 @@ def serving_run(max_active=8, max_bytes=64 << 30, n=64, rate=20.0, steps=20):
                           / bat_sat["request_ms_p99"]}}
 
 
+def graph_run(name="channel_32x32x33", steps=200, warmup=5):
+    """Launch-bound small problem: eager rk_step against the replayed HIP graph
+    of one step (same state, same steps)."""
+    import torch
+
+    import workloads as W
+    from paper_2002_01392_amd import Solver
+
+    w = W.get(name)
+    v0, th0 = w.initial_state()
+    out = {"workload": name, "steps": steps, "unit": UNIT}
+    for mode in ("eager", "graph"):
+        s = Solver.from_workload(w)
+        s.set_state(torch.from_numpy(v0))
+        run = s.rk_step if mode == "eager" else s.rk_graph
+        run(w.dt, warmup)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            run(w.dt, 1)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        out[mode] = {"ms_per_step": 1e3 * el / steps,
+                     "value": w.nx * w.ny * w.nz * 2 * steps / el}
+        s.close()
+    out["speedup"] = out["eager"]["ms_per_step"] / out["graph"]["ms_per_step"]
+    return out
+
+
 def load_traffic(w, kernel, src_hash):
     """HBM bytes per launch from the committed rocprofv3 PMC summary, if it was
     taken on the current kernel sources and workload."""
@@ -338,6 +367,9 @@ def main():
         print("[bench] mixed precision on the channel grid", file=sys.stderr, flush=True)
         mixed = precision_run()
 
+    print("[bench] HIP graph replay on the small channel", file=sys.stderr, flush=True)
+    graph = graph_run()
+
     serving = None
     if not args.no_serving:
         print("[bench] serving: 64 requests, sequential then overlapped", file=sys.stderr,
@@ -361,7 +393,7 @@ def main():
         "step_ms_p99": float(np.percentile(step_ms, 99)),
         "wall_s": wall, "state_finite": finite,
         "roofline": roof, "pass_model": pass_model, "kernels": kernels, "precision": mixed,
-        "serving": serving,
+        "serving": serving, "graph": graph,
         "cpu_baseline": cpu, "kernel_source_hash": src_hash,
     }
     print(json.dumps(out))

@@ -14,7 +14,8 @@
  *  - Pointers named in the signatures are DEVICE pointers unless a comment
  *    says HOST.  The caller owns every pointer it passes; the context copies
  *    what it keeps (the FC table) and owns all device state and scratch, which
- *    is allocated once by fcns_create.  No call below fcns_create allocates.
+ *    is allocated once by fcns_create.  No call below fcns_create allocates
+ *    device memory (fcns_rk_graph creates its graph object on first use).
  *  - Physical fields are float64 arrays [nz][ny][nx] (x fastest); a vector
  *    field is 3 such arrays back to back (x, y, z components).
  *  - All work is enqueued on the HIP stream given to fcns_create and is
@@ -131,6 +132,14 @@ fcns_status fcns_set_state(fcns_ctx* ctx, const double* v, const double* theta);
  * is the time-splitting Euler scheme of Sec. 4.1).
  * Asynchronous on the context stream. */
 fcns_status fcns_rk_step(fcns_ctx* ctx, double dt, int32_t nsteps);
+
+/* Same as fcns_rk_step, by replaying a HIP graph of one step.  The graph is
+ * captured on the first call and again whenever dt changes (capture
+ * synchronizes the stream and allocates the graph; replays allocate
+ * nothing), which removes the per-kernel launch cost of small problems.
+ * Results are bitwise those of fcns_rk_step.  Kernel timing does not cover
+ * graph replays. */
+fcns_status fcns_rk_graph(fcns_ctx* ctx, double dt, int32_t nsteps);
 
 /* Physical state.  theta (nullable) for Boussinesq contexts; p (nullable)
  * needs keep_pressure and at least one step, and is returned with zero mean. */

@@ -46,6 +46,7 @@ SIGNATURES = {
     "fcns_pressure_project": (ctypes.c_int, [_P, _P, _D, _P, _P]),
     "fcns_set_state": (ctypes.c_int, [_P, _P, _P]),
     "fcns_rk_step": (ctypes.c_int, [_P, _D, _I32]),
+    "fcns_rk_graph": (ctypes.c_int, [_P, _D, _I32]),
     "fcns_get_state": (ctypes.c_int, [_P, _P, _P, _P]),
     "fcns_get_spectral": (ctypes.c_int, [_P, _I32, _P]),
     "fcns_set_spectral": (ctypes.c_int, [_P, ctypes.POINTER(_P), _P]),
@@ -311,6 +312,9 @@ class Solver:
 
     def rk_step(self, dt, nsteps=1):
         self._check(self.lib.fcns_rk_step(self.ctx, float(dt), int(nsteps)))
+
+    def rk_graph(self, dt, nsteps=1):
+        self._check(self.lib.fcns_rk_graph(self.ctx, float(dt), int(nsteps)))
 
     def get_state(self, pressure=False):
         v = self._empty(3, *self.shape)

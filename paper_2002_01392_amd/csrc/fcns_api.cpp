@@ -49,6 +49,10 @@ struct fcns_ctx {
   cpx<double>* GW = nullptr;   // wall tangential gradient [2][2][npen]
   cpx<double>* GWT = nullptr;  // scratch wall gradient
   double* DG = nullptr;        // diagnostics: per-plane sums [nz][5], then spectra
+  // one RK step captured as a HIP graph (fcns_rk_graph), for one dt
+  hipStream_t cap_stream = nullptr;
+  hipGraphExec_t graph = nullptr;
+  double graph_dt = 0.0;
   bool has_state = false;
   bool has_pressure = false;
   std::string err;
@@ -203,6 +207,8 @@ static fcns_status alloc(fcns_ctx* c, cpx<double>** p, long long n) {
 }
 
 static void free_all(fcns_ctx* c) {
+  if (c->graph) (void)hipGraphExecDestroy(c->graph);
+  if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
   for (hipEvent_t e : c->evpool) (void)hipEventDestroy(e);
   c->evpool.clear();
   void* ps[] = {c->twz, c->twx, c->twy, c->twz_f, c->twx_f, c->twy_f, c->rootz, c->fcM, c->sigx, c->sigy, c->sigz, c->P, c->Q,
@@ -609,6 +615,62 @@ extern "C" fcns_status fcns_rk_step(fcns_ctx* c, double dt, int32_t nsteps) {
   fcns_status st = check_launch(c, "rk_step");
   if (st == FCNS_OK && nsteps > 0 && c->prob.keep_pressure) c->has_pressure = true;
   return st;
+}
+
+// Capture one step (all o stages) for this dt on a private stream; the graph
+// is replayed on the context stream.  The captured kernels are exactly those
+// of fcns_rk_step (no memory-set nodes: buffers are cleared by kernels).
+static fcns_status capture_step(fcns_ctx* c, double dt) {
+  if (c->graph) {
+    (void)hipGraphExecDestroy(c->graph);
+    c->graph = nullptr;
+  }
+  fcns_status st;
+  if (!c->cap_stream &&
+      (st = check_hip(c, hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking),
+                      "graph stream")))
+    return st;
+  // the captured work must follow what is already queued on the context stream
+  if ((st = check_hip(c, hipStreamSynchronize(c->stream), "graph capture"))) return st;
+  hipStream_t saved = c->stream;
+  const bool timing = c->timing;
+  c->timing = false;
+  c->stream = c->cap_stream;
+  hipGraph_t g = nullptr;
+  hipError_t e = hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeRelaxed);
+  if (e == hipSuccess) {
+    const int o = c->prob.rk_order;
+    for (int j = 1; j <= o; ++j) {
+      if (c->mixed)
+        rk_stage<float>(c, j, o, dt);
+      else
+        rk_stage<double>(c, j, o, dt);
+    }
+    const hipError_t e2 = hipStreamEndCapture(c->cap_stream, &g);
+    e = (e2 != hipSuccess) ? e2 : hipGetLastError();
+  }
+  c->stream = saved;
+  c->timing = timing;
+  if (e == hipSuccess) e = hipGraphInstantiate(&c->graph, g, nullptr, nullptr, 0);
+  if (g) (void)hipGraphDestroy(g);
+  if (e != hipSuccess) {
+    c->graph = nullptr;
+    return check_hip(c, e, "graph capture");
+  }
+  c->graph_dt = dt;
+  return FCNS_OK;
+}
+
+extern "C" fcns_status fcns_rk_graph(fcns_ctx* c, double dt, int32_t nsteps) {
+  if (!c) return FCNS_EINVAL;
+  if (!c->has_state) return fail(c, FCNS_ESTATE, "rk_graph before set_state");
+  if (!(dt > 0.0) || nsteps < 0) return fail(c, FCNS_EINVAL, "need dt > 0 and nsteps >= 0");
+  fcns_status st;
+  if ((!c->graph || c->graph_dt != dt) && (st = capture_step(c, dt))) return st;
+  for (int n = 0; n < nsteps; ++n)
+    if ((st = check_hip(c, hipGraphLaunch(c->graph, c->stream), "graph launch"))) return st;
+  if (nsteps > 0 && c->prob.keep_pressure) c->has_pressure = true;
+  return FCNS_OK;
 }
 
 extern "C" fcns_status fcns_get_state(fcns_ctx* c, double* v, double* theta, double* p) {
