@@ -275,6 +275,7 @@ def main():
     ap.add_argument("--no-mixed", action="store_true",
                     help="skip the mixed-precision run on the channel grid")
     ap.add_argument("--no-serving", action="store_true", help="skip the serving run")
+    ap.add_argument("--no-autotune", action="store_true", help="keep the default launch choices")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one plain device copy of 1 GiB (counter calibration)")
     args = ap.parse_args()
@@ -296,6 +297,10 @@ def main():
     s.set_state(torch.from_numpy(v0), torch.from_numpy(th0) if th0 is not None else None)
     del v0, th0
     torch.cuda.synchronize()
+    tuned = None
+    if not args.no_autotune:
+        print("[bench] autotune", file=sys.stderr, flush=True)
+        tuned = s.autotune()
     print(f"[bench] warmup {args.warmup} steps", file=sys.stderr, flush=True)
     s.rk_step(w.dt, args.warmup)
     torch.cuda.synchronize()
@@ -393,7 +398,7 @@ def main():
         "step_ms_p99": float(np.percentile(step_ms, 99)),
         "wall_s": wall, "state_finite": finite,
         "roofline": roof, "pass_model": pass_model, "kernels": kernels, "precision": mixed,
-        "serving": serving, "graph": graph,
+        "serving": serving, "graph": graph, "autotune": tuned,
         "cpu_baseline": cpu, "kernel_source_hash": src_hash,
     }
     print(json.dumps(out))

@@ -133,6 +133,16 @@ fcns_status fcns_set_state(fcns_ctx* ctx, const double* v, const double* theta);
  * Asynchronous on the context stream. */
 fcns_status fcns_rk_step(fcns_ctx* ctx, double dt, int32_t nsteps);
 
+/* Autotuner: times, on this context's own buffers and stream, the launch
+ * choices that depend on the shape -- the persistent grid of the y pass, the
+ * tiling of the x pass with products, and the radix order of the run-time z
+ * plan (a compiled plan is kept) -- and keeps the fastest of each for later
+ * calls.  Needs a state; leaves it unchanged (results of later steps stay
+ * within rounding of the untuned ones).  Synchronizes the stream; may
+ * reallocate the small z twiddle tables.  report (HOST, nullable) receives a
+ * one-line summary of the choices. */
+fcns_status fcns_autotune(fcns_ctx* ctx, char* report, int32_t report_len);
+
 /* Same as fcns_rk_step, by replaying a HIP graph of one step.  The graph is
  * captured on the first call and again whenever dt changes (capture
  * synchronizes the stream and allocates the graph; replays allocate

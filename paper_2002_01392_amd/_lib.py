@@ -47,6 +47,7 @@ SIGNATURES = {
     "fcns_set_state": (ctypes.c_int, [_P, _P, _P]),
     "fcns_rk_step": (ctypes.c_int, [_P, _D, _I32]),
     "fcns_rk_graph": (ctypes.c_int, [_P, _D, _I32]),
+    "fcns_autotune": (ctypes.c_int, [_P, ctypes.c_char_p, _I32]),
     "fcns_get_state": (ctypes.c_int, [_P, _P, _P, _P]),
     "fcns_get_spectral": (ctypes.c_int, [_P, _I32, _P]),
     "fcns_set_spectral": (ctypes.c_int, [_P, ctypes.POINTER(_P), _P]),
@@ -312,6 +313,12 @@ class Solver:
 
     def rk_step(self, dt, nsteps=1):
         self._check(self.lib.fcns_rk_step(self.ctx, float(dt), int(nsteps)))
+
+    def autotune(self):
+        """Pick the fastest launch choices for this shape; returns the summary."""
+        buf = ctypes.create_string_buffer(1024)
+        self._check(self.lib.fcns_autotune(self.ctx, buf, len(buf)))
+        return buf.value.decode()
 
     def rk_graph(self, dt, nsteps=1):
         self._check(self.lib.fcns_rk_graph(self.ctx, float(dt), int(nsteps)))

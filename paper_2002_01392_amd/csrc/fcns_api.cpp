@@ -7,6 +7,7 @@
 #include <stdlib.h>
 #include <string.h>
 
+#include <algorithm>
 #include <string>
 #include <vector>
 
@@ -53,6 +54,9 @@ struct fcns_ctx {
   hipStream_t cap_stream = nullptr;
   hipGraphExec_t graph = nullptr;
   double graph_dt = 0.0;
+  // autotuned launch choices (fcns_autotune)
+  int xvar = 0;
+  long long ygrid = 0;
   bool has_state = false;
   bool has_pressure = false;
   std::string err;
@@ -128,10 +132,7 @@ static fcns_status check_launch(fcns_ctx* c, const char* what) {
 // Also lays out the twiddle table: per stage with ns > 1 the factors
 // w^{m k} = exp(-2 pi i m k / (ns R)) as [m-1][k], and per odd-radix stage its
 // R roots exp(-2 pi i q / R).
-static bool make_plan(int n, FFTPlan& pl, bool& big, std::vector<cpx<double>>& table) {
-  memset(&pl, 0, sizeof(pl));
-  pl.n = n;
-  big = false;
+static std::vector<int> default_radices(int n) {
   int m = n;
   std::vector<int> rs;
   while (m % 8 == 0) { rs.push_back(8); m /= 8; }
@@ -142,7 +143,18 @@ static bool make_plan(int n, FFTPlan& pl, bool& big, std::vector<cpx<double>>& t
       rs.push_back(p);
       m /= p;
     }
-  if (m != 1 || (int)rs.size() > FFT_MAX_STAGES) return false;
+  if (m != 1) rs.clear();
+  return rs;
+}
+
+static bool make_plan_order(int n, const std::vector<int>& rs, FFTPlan& pl, bool& big,
+                            std::vector<cpx<double>>& table) {
+  memset(&pl, 0, sizeof(pl));
+  pl.n = n;
+  big = false;
+  long long prod = 1;
+  for (int r : rs) prod *= r;
+  if (rs.empty() || prod != n || (int)rs.size() > FFT_MAX_STAGES) return false;
   pl.nst = (int)rs.size();
   const long double pi = 3.141592653589793238462643383279502884L;
   auto root = [&](long long num, long long den) {
@@ -171,6 +183,10 @@ static bool make_plan(int n, FFTPlan& pl, bool& big, std::vector<cpx<double>>& t
   if (table.empty()) table.push_back(mk(1.0, 0.0));
   pl.tsize = (int)table.size();
   return true;
+}
+
+static bool make_plan(int n, FFTPlan& pl, bool& big, std::vector<cpx<double>>& table) {
+  return make_plan_order(n, default_radices(n), pl, big, table);
 }
 
 static std::vector<cpx<double>> roots(int n) {
@@ -238,6 +254,7 @@ static YArgs yargs(const fcns_ctx* c, bool f32 = false) {
   a.kys = c->g.kys;
   a.pl = c->ply;
   a.tw = f32 ? (const void*)c->twy_f : (const void*)c->twy;
+  a.grid = c->ygrid;
   return a;
 }
 static XArgs xargs(const fcns_ctx* c, bool f32 = false) {
@@ -249,6 +266,7 @@ static XArgs xargs(const fcns_ctx* c, bool f32 = false) {
   a.kxs = c->g.kxs;
   a.pl = c->plx;
   a.tw = f32 ? (const void*)c->twx_f : (const void*)c->twx;
+  a.variant = c->xvar;
   return a;
 }
 
@@ -671,6 +689,166 @@ extern "C" fcns_status fcns_rk_graph(fcns_ctx* c, double dt, int32_t nsteps) {
     if ((st = check_hip(c, hipGraphLaunch(c->graph, c->stream), "graph launch"))) return st;
   if (nsteps > 0 && c->prob.keep_pressure) c->has_pressure = true;
   return FCNS_OK;
+}
+
+// ---------------------------------------------------------------- autotuner
+// Mean duration (ms) of `reps` runs of f on the context stream.
+template <typename F>
+static float time_ms(fcns_ctx* c, F&& f, int reps) {
+  hipEvent_t a, b;
+  (void)hipEventCreate(&a);
+  (void)hipEventCreate(&b);
+  f();  // warm-up (also the first-use LDS opt-in)
+  (void)hipEventRecord(a, c->stream);
+  for (int i = 0; i < reps; ++i) f();
+  (void)hipEventRecord(b, c->stream);
+  (void)hipEventSynchronize(b);
+  float ms = 0.f;
+  (void)hipEventElapsedTime(&ms, a, b);
+  (void)hipEventDestroy(a);
+  (void)hipEventDestroy(b);
+  return ms / reps;
+}
+
+static fcns_status set_z_plan(fcns_ctx* c, const std::vector<int>& rs) {
+  FFTPlan pl;
+  bool big;
+  std::vector<cpx<double>> t;
+  if (!make_plan_order(c->g.npr, rs, pl, big, t)) return fail(c, FCNS_EINVAL, "bad z plan");
+  cpx<double>* d = nullptr;
+  cpx<float>* f = nullptr;
+  fcns_status st;
+  if ((st = upload(c, &d, t.data(), t.size()))) return st;
+  if (c->mixed) {
+    std::vector<cpx<float>> tf(t.size());
+    for (size_t i = 0; i < t.size(); ++i) tf[i] = mk((float)t[i].x, (float)t[i].y);
+    if ((st = upload(c, &f, tf.data(), tf.size()))) {
+      (void)hipFree(d);
+      return st;
+    }
+  }
+  (void)hipStreamSynchronize(c->stream);
+  (void)hipFree(c->twz);
+  if (c->twz_f) (void)hipFree(c->twz_f);
+  c->twz = d;
+  c->twz_f = f;
+  c->plz = pl;
+  c->big_z = big;
+  if (c->graph) {  // a captured step holds the old tables
+    (void)hipGraphExecDestroy(c->graph);
+    c->graph = nullptr;
+  }
+  return FCNS_OK;
+}
+
+extern "C" fcns_status fcns_autotune(fcns_ctx* c, char* report, int32_t report_len) {
+  if (!c) return FCNS_EINVAL;
+  if (!c->has_state) return fail(c, FCNS_ESTATE, "autotune before set_state");
+  const Geom& g = c->g;
+  const long long M = c->M;
+  const int nf = c->nf, reps = 3;
+  const bool f32 = c->mixed;
+  std::string rep;
+  char line[256];
+  // y pass: persistent grid size, timed on the three y passes of a stage
+  // (back with d/dy, back of dv/dz, forward of NL) on the state's fields
+  {
+    float best = 1e30f;
+    long long bg = Y_GRID;
+    auto ypasses = [&](auto* mv, auto* xy, auto* nlb, bool f) {
+      launch_y(yargs(c, f), c->big_y, true, 1, mv, xy, xy + M, 2 * M, 3 * M, g.nz, nf, c->stream);
+      launch_y(yargs(c, f), c->big_y, true, 0, mv + M, xy + 2 * M, decltype(xy)(nullptr), 2 * M,
+               3 * M, g.nz, nf, c->stream);
+      launch_y(yargs(c, f), c->big_y, false, 0, nlb, nlb, decltype(xy)(nullptr), M, M, g.nz, nf,
+               c->stream);
+    };
+    for (long long gsz : {256LL, 512LL, 1024LL, 2048LL, 4096LL}) {
+      c->ygrid = gsz;
+      const float ms = time_ms(c, [&] {
+        if (f32)
+          ypasses(reinterpret_cast<cpx<float>*>(c->MV), reinterpret_cast<cpx<float>*>(c->XYB),
+                  reinterpret_cast<cpx<float>*>(c->NLB), true);
+        else
+          ypasses(c->MV, c->XYB, c->NLB, false);
+      }, reps);
+      if (ms < best) {
+        best = ms;
+        bg = gsz;
+      }
+    }
+    c->ygrid = bg;
+    snprintf(line, sizeof(line), "y: grid %lld (%.3f ms); ", bg, best);
+    rep += line;
+  }
+  // x pass with products: kernel variant (inputs: the y pass just run)
+  {
+    float best = 1e30f;
+    int bv = 0;
+    for (int v : {0, 1, 2}) {
+      if (v == 2 && g.nx > 512) continue;
+      c->xvar = v;
+      const float ms = time_ms(c, [&] {
+        if (f32)
+          launch_x_nl<float>(xargs(c, true), c->big_x, reinterpret_cast<cpx<float>*>(c->XYB),
+                             reinterpret_cast<cpx<float>*>(c->NLB), M, (long long)g.nz * g.ny,
+                             nf, c->stream);
+        else
+          launch_x_nl<double>(xargs(c), c->big_x, c->XYB, c->NLB, M, (long long)g.nz * g.ny, nf,
+                              c->stream);
+      }, reps);
+      if (ms < best) {
+        best = ms;
+        bv = v;
+      }
+    }
+    c->xvar = bv;
+    snprintf(line, sizeof(line), "x: variant %d (%.3f ms); ", bv, best);
+    rep += line;
+  }
+  // z: radix order of a run-time plan, timed on the back-transform of the
+  // state (a compiled plan, when the length has one, is kept)
+  {
+    std::vector<int> rs = default_radices(g.npr);
+    const bool compiled = g.npr == 288 && rs == std::vector<int>{8, 4, 3, 3};
+    std::vector<int> best_rs = rs;
+    float best = 1e30f;
+    if (!compiled) {
+      std::vector<int> perm = rs;
+      std::sort(perm.begin(), perm.end());
+      int n = 0;
+      do {
+        fcns_status st = set_z_plan(c, perm);
+        if (st) return st;
+        const float ms = time_ms(c, [&] {
+          launch_z_back<double>(zargs(c), c->big_z, c->P, c->MVT, c->MVT + M, c->S, 2 * M, nf,
+                                c->stream);
+        }, reps);
+        if (ms < best) {
+          best = ms;
+          best_rs = perm;
+        }
+      } while (++n < 24 && std::next_permutation(perm.begin(), perm.end()));
+      fcns_status st = set_z_plan(c, best_rs);
+      if (st) return st;
+    }
+    rep += "z: radices";
+    for (int r : best_rs) rep += " " + std::to_string(r);
+    if (compiled) {
+      rep += " (compiled plan)";
+    } else {
+      snprintf(line, sizeof(line), " (%.3f ms)", best);
+      rep += line;
+    }
+  }
+  // the mixed-space fields of the state were overwritten only in scratch; the
+  // ones the next step reads are rebuilt from the state
+  state_to_mv(c, c->P);
+  fcns_status st = check_launch(c, "autotune");
+  if (report && report_len > 0) {
+    strncpy(report, rep.c_str(), (size_t)report_len - 1);
+    report[report_len - 1] = 0;
+  }
+  return st;
 }
 
 extern "C" fcns_status fcns_get_state(fcns_ctx* c, double* v, double* theta, double* p) {

@@ -65,6 +65,7 @@ struct YArgs {
   double kys;
   FFTPlan pl;        // ny-point plan (lines = YL, threads = YNT)
   const void* tw;    // ny twiddles
+  long long grid;    // persistent workgroups per field (0: Y_GRID)
 };
 
 struct XArgs {
@@ -72,6 +73,7 @@ struct XArgs {
   double kxs;
   FFTPlan pl;        // nx-point plan (lines = XR/2, threads = XNT)
   const void* tw;    // nx twiddles
+  int variant;       // x pass with products: 0 default, 1 tiled 4 rows x 256, 2 tiled 8 x 512
 };
 
 int z_max_npr();

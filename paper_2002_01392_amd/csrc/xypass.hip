@@ -568,7 +568,8 @@ void launch_y(const YArgs& a, bool big, bool inv, int mode, const cpx<T>* src, c
               hipStream_t st) {
   const long long nlines = (long long)nplanes * a.nkxp;
   const long long ntiles = (nlines + YL - 1) / YL;
-  dim3 grid((unsigned)(ntiles < Y_GRID ? ntiles : Y_GRID), nfields);
+  const long long yg = a.grid > 0 ? a.grid : Y_GRID;
+  dim3 grid((unsigned)(ntiles < yg ? ntiles : yg), nfields);
   const size_t sh = y_lds_bytes(a.ny, a.pl.tsize, sizeof(cpx<T>));
   const int need = (a.ny + YNT / YL - 1) / (YNT / YL);
   const int iv = inv ? 1 : 0;
@@ -622,11 +623,20 @@ static void launch_x_nl_v(const XArgs& a, const cpx<T>* xyb, cpx<T>* nl, long lo
               nfields);
 }
 
-// 4 rows x 256 threads; compile-time plans for nx = 512 and 256
+// nx = 512: one wavefront per row (variant 0) or the tiled kernel; other nx:
+// 4 rows x 256 threads (variant 0, 1) or 8 rows x 512 threads (variant 2),
+// with compile-time plans for 512 and 256
 template <typename T>
 void launch_x_nl(const XArgs& a, bool big, const cpx<T>* xyb, cpx<T>* nl, long long fs,
                  long long nrows, int nfields, hipStream_t st) {
-  if (a.nx == 512) {
+  if (a.variant == 2 && a.nx <= 512) {
+    if (a.nx == 512 && plan_is(a.pl, {8, 8, 8}))
+      launch_x_nl_v<T, SPlan<8, 8, 8>, 8, 512, 1>(a, xyb, nl, fs, nrows, nfields, st);
+    else if (big)
+      launch_x_nl_v<T, DynPlan<true>, 8, 512, 1>(a, xyb, nl, fs, nrows, nfields, st);
+    else
+      launch_x_nl_v<T, DynPlan<false>, 8, 512, 1>(a, xyb, nl, fs, nrows, nfields, st);
+  } else if (a.nx == 512 && a.variant == 0) {
     // one wavefront per row; enough workgroups to fill the chip several times
     const long long need = (nrows + XW_WAVES - 1) / XW_WAVES;
     dim3 grid((unsigned)(need < 4096 ? need : 4096));

@@ -308,3 +308,25 @@ def test_diagnostics_match_oracle(fcns, kind):
         ex, ey = s.spectra(f, 7)
         rx, ry = spectra(o, f, 7)
         assert rel_l2(ex, rx) < 1e-11 and rel_l2(ey, ry) < 1e-11
+
+
+# ------------------------------------------------------------------ autotuner
+@pytest.mark.parametrize("name", ["channel_32x32x33", "prime"])
+def test_autotuned_steps_keep_parity(fcns, name):
+    if name == "prime":   # run-time z plan 2 * 3 * 47: its radix orders are tried
+        w = W.channel(16, 8, 257, 2000.0, d=5, C=25, dt=5e-4, steps=3, seed=9, noise_rms=0.05)
+    else:
+        w = W.get(name)
+    v0, _ = w.initial_state()
+    s = fcns.Solver.from_workload(w)
+    s.set_state(torch.from_numpy(v0))
+    rep = s.autotune()
+    assert rep.startswith("y: grid") and "x: variant" in rep and "z: radices" in rep
+    s.rk_step(w.dt, w.steps)
+    v, _, _ = s.get_state()
+    torch.cuda.synchronize()
+    o = Oracle(Problem(**w.problem_kwargs()))
+    o.set_state(v0)
+    o.rk_step(w.dt, w.steps)
+    rv, _, _ = o.get_state()
+    assert rel_l2(v, rv) < 1e-11
