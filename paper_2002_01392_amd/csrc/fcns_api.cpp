@@ -57,6 +57,7 @@ struct fcns_ctx {
   // autotuned launch choices (fcns_autotune)
   int xvar = 0;
   long long ygrid = 0;
+  int ynopf = 0;
   bool has_state = false;
   bool has_pressure = false;
   std::string err;
@@ -255,6 +256,7 @@ static YArgs yargs(const fcns_ctx* c, bool f32 = false) {
   a.pl = c->ply;
   a.tw = f32 ? (const void*)c->twy_f : (const void*)c->twy;
   a.grid = c->ygrid;
+  a.noprefetch = c->ynopf;
   return a;
 }
 static XArgs xargs(const fcns_ctx* c, bool f32 = false) {
@@ -762,22 +764,28 @@ extern "C" fcns_status fcns_autotune(fcns_ctx* c, char* report, int32_t report_l
       launch_y(yargs(c, f), c->big_y, false, 0, nlb, nlb, decltype(xy)(nullptr), M, M, g.nz, nf,
                c->stream);
     };
-    for (long long gsz : {256LL, 512LL, 1024LL, 2048LL, 4096LL}) {
-      c->ygrid = gsz;
-      const float ms = time_ms(c, [&] {
-        if (f32)
-          ypasses(reinterpret_cast<cpx<float>*>(c->MV), reinterpret_cast<cpx<float>*>(c->XYB),
-                  reinterpret_cast<cpx<float>*>(c->NLB), true);
-        else
-          ypasses(c->MV, c->XYB, c->NLB, false);
-      }, reps);
-      if (ms < best) {
-        best = ms;
-        bg = gsz;
+    int bpf = 0;
+    for (int nopf : {0, 1})
+      for (long long gsz : {256LL, 512LL, 1024LL, 2048LL, 4096LL}) {
+        c->ygrid = gsz;
+        c->ynopf = nopf;
+        const float ms = time_ms(c, [&] {
+          if (f32)
+            ypasses(reinterpret_cast<cpx<float>*>(c->MV), reinterpret_cast<cpx<float>*>(c->XYB),
+                    reinterpret_cast<cpx<float>*>(c->NLB), true);
+          else
+            ypasses(c->MV, c->XYB, c->NLB, false);
+        }, reps);
+        if (ms < best) {
+          best = ms;
+          bg = gsz;
+          bpf = nopf;
+        }
       }
-    }
     c->ygrid = bg;
-    snprintf(line, sizeof(line), "y: grid %lld (%.3f ms); ", bg, best);
+    c->ynopf = bpf;
+    snprintf(line, sizeof(line), "y: grid %lld%s (%.3f ms); ", bg, bpf ? " no-prefetch" : "",
+             best);
     rep += line;
   }
   // x pass with products: kernel variant (inputs: the y pass just run)

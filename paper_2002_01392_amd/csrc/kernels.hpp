@@ -66,6 +66,7 @@ struct YArgs {
   FFTPlan pl;        // ny-point plan (lines = YL, threads = YNT)
   const void* tw;    // ny twiddles
   long long grid;    // persistent workgroups per field (0: Y_GRID)
+  int noprefetch;    // 1: load each tile when needed instead of one tile ahead
 };
 
 struct XArgs {

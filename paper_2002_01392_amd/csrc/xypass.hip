@@ -12,19 +12,23 @@ namespace fcns {
 
 // ---------------------------------------------------------------- y pass
 // Lines q = plane * nkxp + kx; a tile is YL consecutive lines, staged in LDS
-// interleaved (element ky of line l at lds_pos<true>(l, ky, YL, 1), y_span
-// slots per buffer).  Each thread keeps one line of the tile (l = tid % YL,
+// interleaved (element ky of line l at l + YL ky, y_span slots per buffer).  Each thread keeps one line of the tile (l = tid % YL,
 // YNT being a multiple of YL) and the rows ky = tid / YL + r * YNT / YL.
 // Workgroups loop over tiles and load the next tile into registers before
 // transforming the current one, so the loads overlap the FFT.  mode 1
 // (inverse only): a second pass transforms i k~y times the input into dst2.
-__host__ __device__ inline int y_span(int ny) { return YL * (ny + ny / 8 + 1); }
+// Lines are interleaved without padding: two workgroups of 512-point lines
+// (2 x 4 lines x 512 points x 2 buffers) then fit the 160 KB of LDS per CU,
+// which matters more than the 2-way bank conflicts of the first stage.
+__host__ __device__ inline int y_span(int ny) { return YL * ny; }
 
 size_t y_lds_bytes(int ny, int tsize, size_t elem) {
   return ((size_t)tsize + 2 * (size_t)y_span(ny)) * elem;
 }
 
-template <typename T, class FP, int OWN>
+// PF: load the next tile into registers while the current one is transformed
+// (more registers, fewer waves per SIMD) or load each tile when it is needed.
+template <typename T, class FP, int OWN, bool PF>
 __global__ __launch_bounds__(YNT) void k_y(YArgs a, const cpx<T>* src, cpx<T>* dst, cpx<T>* dst2,
                                            long long sfs, long long dfs, long long nlines, int inv,
                                            int mode) {
@@ -45,7 +49,7 @@ __global__ __launch_bounds__(YNT) void k_y(YArgs a, const cpx<T>* src, cpx<T>* d
   const long long ntiles = (nlines + YL - 1) / YL;
   const T sc = inv ? T(1) / (T)ny : T(1);
   const int npass = (mode == 1) ? 2 : 1;
-  cpx<T> cur[OWN], nxt[OWN];
+  cpx<T> cur[OWN], nxt[PF ? OWN : 1];
   long long t = blockIdx.x;
   auto line_base = [&](long long tt, bool& ok) {
     const long long q = tt * YL + l;
@@ -53,7 +57,7 @@ __global__ __launch_bounds__(YNT) void k_y(YArgs a, const cpx<T>* src, cpx<T>* d
     ok = q < nlines && kx < nkx;
     return ok ? pl * ny * nkxp + kx : 0;  // element ky at base + ky * nkxp
   };
-  {
+  if constexpr (PF) {
     bool ok;
     const long long base = line_base(t, ok);
 #pragma unroll
@@ -63,14 +67,22 @@ __global__ __launch_bounds__(YNT) void k_y(YArgs a, const cpx<T>* src, cpx<T>* d
     }
   }
   for (; t < ntiles; t += gridDim.x) {
-    bool ok, okn;
+    bool ok;
     const long long base = line_base(t, ok);
-    const long long tn = t + gridDim.x;
-    const long long basen = line_base(tn, okn);
+    if constexpr (PF) {
+      bool okn;
+      const long long basen = line_base(t + gridDim.x, okn);
 #pragma unroll
-    for (int r = 0; r < OWN; ++r) {
-      const int ky = ky0 + r * KYS;
-      nxt[r] = (okn && ky < ny) ? src[basen + (long long)ky * nkxp] : zero<T>();
+      for (int r = 0; r < OWN; ++r) {
+        const int ky = ky0 + r * KYS;
+        nxt[r] = (okn && ky < ny) ? src[basen + (long long)ky * nkxp] : zero<T>();
+      }
+    } else {
+#pragma unroll
+      for (int r = 0; r < OWN; ++r) {
+        const int ky = ky0 + r * KYS;
+        cur[r] = (ok && ky < ny) ? src[base + (long long)ky * nkxp] : zero<T>();
+      }
     }
     for (int pass = 0; pass < npass; ++pass) {
 #pragma unroll
@@ -79,26 +91,28 @@ __global__ __launch_bounds__(YNT) void k_y(YArgs a, const cpx<T>* src, cpx<T>* d
         if (ky < ny) {
           cpx<T> v = cur[r];
           if (pass == 1) v = mul_i(v) * (T)k_odd(ky, ny, a.kys);
-          X0[lds_pos<true>(l, ky, YL, 1)] = inv ? conj(v) : v;
+          X0[lds_pos<false>(l, ky, YL, 1)] = inv ? conj(v) : v;
         }
       }
       __syncthreads();
-      const cpx<T>* R = fft_run<T, YL, YNT, true, FP>(X0, X1, YL, 1, a.pl, tw, tid);
+      const cpx<T>* R = fft_run<T, YL, YNT, false, FP>(X0, X1, YL, 1, a.pl, tw, tid);
       cpx<T>* out = pass ? dst2 : dst;
       if (ok) {
 #pragma unroll
         for (int r = 0; r < OWN; ++r) {
           const int ky = ky0 + r * KYS;
           if (ky < ny) {
-            const cpx<T> v = R[lds_pos<true>(l, ky, YL, 1)];
+            const cpx<T> v = R[lds_pos<false>(l, ky, YL, 1)];
             out[base + (long long)ky * nkxp] = (inv ? conj(v) : v) * sc;
           }
         }
       }
       __syncthreads();
     }
+    if constexpr (PF) {
 #pragma unroll
-    for (int r = 0; r < OWN; ++r) cur[r] = nxt[r];
+      for (int r = 0; r < OWN; ++r) cur[r] = nxt[r];
+    }
   }
 }
 
@@ -574,8 +588,14 @@ void launch_y(const YArgs& a, bool big, bool inv, int mode, const cpx<T>* src, c
   const int need = (a.ny + YNT / YL - 1) / (YNT / YL);
   const int iv = inv ? 1 : 0;
 #define FCNS_Y(FPV, OWNV)                                                                    \
-  FCNS_LAUNCH((k_y<T, FPV, OWNV>), grid, dim3(YNT), sh, st, a, src, dst, dst2, sfs, \
-                     dfs, nlines, iv, mode)
+  do {                                                                                      \
+    if (a.noprefetch)                                                                       \
+      FCNS_LAUNCH((k_y<T, FPV, OWNV, false>), grid, dim3(YNT), sh, st, a, src, dst, dst2, sfs, \
+                  dfs, nlines, iv, mode);                                                   \
+    else                                                                                    \
+      FCNS_LAUNCH((k_y<T, FPV, OWNV, true>), grid, dim3(YNT), sh, st, a, src, dst, dst2, sfs,  \
+                  dfs, nlines, iv, mode);                                                   \
+  } while (0)
   if (a.ny == 512 && plan_is(a.pl, {8, 8, 8})) {
     using P512 = SPlan<8, 8, 8>;
     FCNS_Y(P512, 8);
