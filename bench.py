@@ -276,6 +276,7 @@ def main():
                     help="skip the mixed-precision run on the channel grid")
     ap.add_argument("--no-serving", action="store_true", help="skip the serving run")
     ap.add_argument("--no-autotune", action="store_true", help="keep the default launch choices")
+    ap.add_argument("--no-graph", action="store_true", help="skip the HIP graph comparison")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one plain device copy of 1 GiB (counter calibration)")
     args = ap.parse_args()
@@ -372,8 +373,10 @@ def main():
         print("[bench] mixed precision on the channel grid", file=sys.stderr, flush=True)
         mixed = precision_run()
 
-    print("[bench] HIP graph replay on the small channel", file=sys.stderr, flush=True)
-    graph = graph_run()
+    graph = None
+    if not args.no_graph:
+        print("[bench] HIP graph replay on the small channel", file=sys.stderr, flush=True)
+        graph = graph_run()
 
     serving = None
     if not args.no_serving:

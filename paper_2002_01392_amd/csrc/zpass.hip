@@ -313,7 +313,10 @@ __global__ __launch_bounds__(ZNT) void k_z_stageB(ZArgs a, StageBArgs s) {
   cpx<double> sb = zero<double>(), st = zero<double>(), s0 = zero<double>(),
               s1 = zero<double>();
   if (valid_me) {
-    for (int l = lt; l < npr; l += ZLS) {
+    // root index l (nz - 1) mod N', stepped with l
+    const int step = (int)(((long long)ZLS * (g.nz - 1)) % npr);
+    int ei = (int)(((long long)lt * (g.nz - 1)) % npr);
+    for (int l = lt; l < npr; l += ZLS, ei = (ei + step >= npr) ? ei + step - npr : ei + step) {
       const long long gi = (long long)l * g.npen + p_me;
       const cpx<double> V0 = s.vs[0][gi], V1 = s.vs[1][gi], V2 = s.vs[2][gi];
       const double kz = k_odd(l, npr, g.kzs);
@@ -322,7 +325,7 @@ __global__ __launch_bounds__(ZNT) void k_z_stageB(ZArgs a, StageBArgs s) {
       if (k2 > 0.0) sv = (V0 * kxo + V1 * kyo + V2 * kz) * (1.0 / k2);
       const cpx<double> rz = V2 - sv * kz;
       // e^{+2 pi i l (nz-1)/N'} = conj(root[l (nz-1) mod N'])
-      const cpx<double> et = conj(gtw[(int)(((long long)l * (g.nz - 1)) % npr)]);
+      const cpx<double> et = conj(gtw[ei]);
       sb = sb + rz;
       st = st + rz * et;
       s0 = s0 + sv;

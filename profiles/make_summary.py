@@ -21,7 +21,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 
 # kernel name prefix -> timing class of the library (the y kernel serves three
 # classes of equal traffic pattern; it is reported as one)
-CLASSES = {"fcns::k_x_nl<": "x_nl", "fcns::k_z_stageA<": "z_stageA",
+CLASSES = {"fcns::k_x_nl<": "x_nl", "fcns::k_x_nl512<": "x_nl", "fcns::k_z_stageA<": "z_stageA",
            "fcns::k_z_stageB<": "z_stageB", "fcns::k_z_back<": "z_back", "fcns::k_y<": "y"}
 COPY_BYTES = 1 << 30
 
@@ -54,11 +54,15 @@ def pmc(fetch_csv, write_csv, workload, src_hash, cmd_fetch, cmd_write):
     kf = COPY_BYTES / (cf * 1024.0)
     kw = COPY_BYTES / (cw * 1024.0)
     for prefix, cls in CLASSES.items():
-        fv = [v for n, g, v in fetch if n.replace("void ", "").startswith(prefix)]
-        wv = [v for n, g, v in write if n.replace("void ", "").startswith(prefix)]
-        if not fv or not wv:
+        fr = [(g, v) for n, g, v in fetch if n.replace("void ", "").startswith(prefix)]
+        wr = [(g, v) for n, g, v in write if n.replace("void ", "").startswith(prefix)]
+        if not fr or not wr:
             continue
-        # the median dispatch: the step's launches outnumber the set/get-state ones
+        # the dispatches of the largest grid (the workload's own launches), and
+        # among them the median
+        gmax = max(g for g, _ in fr)
+        fv = [v for g, v in fr if g == gmax]
+        wv = [v for g, v in wr if g == gmax]
         fb = statistics.median(fv) * 1024.0 * kf
         wb = statistics.median(wv) * 1024.0 * kw
         rec = {"kernel_class": cls, "workload": workload, "source_hash": src_hash,
