@@ -134,6 +134,8 @@ static fcns_status check_launch(fcns_ctx* c, const char* what) {
 // w^{m k} = exp(-2 pi i m k / (ns R)) as [m-1][k], and per odd-radix stage its
 // R roots exp(-2 pi i q / R).
 static std::vector<int> default_radices(int n) {
+  // 288 (nz = 257 with C = 31): two register codelets, two LDS passes
+  if (n == 288) return {16, 18};
   int m = n;
   std::vector<int> rs;
   while (m % 8 == 0) { rs.push_back(8); m /= 8; }
@@ -817,7 +819,7 @@ extern "C" fcns_status fcns_autotune(fcns_ctx* c, char* report, int32_t report_l
   // state (a compiled plan, when the length has one, is kept)
   {
     std::vector<int> rs = default_radices(g.npr);
-    const bool compiled = g.npr == 288 && rs == std::vector<int>{8, 4, 3, 3};
+    const bool compiled = g.npr == 288 && rs == std::vector<int>{16, 18};
     std::vector<int> best_rs = rs;
     float best = 1e30f;
     if (!compiled) {

@@ -12,7 +12,7 @@
 // transform (exp(-2 pi i jk/n), unnormalized) is provided: callers obtain the
 // inverse as conj(FFT(conj(x))) by conjugating in their own loads and stores.
 //
-// Codelets: radix 2, 4, 8 in closed form; odd primes use the symmetric form
+// Codelets: radix 2, 4, 8, 16 (4 x 4) and 18 (6 x 3) in closed form; odd primes use the symmetric form
 // of a prime-length DFT (a_q = x_q + x_{R-q}, b_q = x_q - x_{R-q}), which takes
 // (R-1)^2 real multiply-adds per pair of outputs instead of R^2 complex ones,
 // with cos and sin read at a wave-uniform index (LDS broadcast).  3, 5 and 7
@@ -90,6 +90,133 @@ struct Codelet<T, 8> {
     v[3] = b1;
     v[5] = b2;
     v[7] = b3;
+  }
+};
+
+// Roots w_N^m = cos(2 pi m / N) - i sin(2 pi m / N) of the composite codelets.
+struct Roots16 {
+  static constexpr double c[16] = {1.0, 0.9238795325112867561281832, 0.7071067811865475244008444,
+                                   0.38268343236508977172846, 0.0, -0.38268343236508977172846,
+                                   -0.7071067811865475244008444, -0.9238795325112867561281832,
+                                   -1.0, -0.9238795325112867561281832,
+                                   -0.7071067811865475244008444, -0.38268343236508977172846,
+                                   0.0, 0.38268343236508977172846, 0.7071067811865475244008444,
+                                   0.9238795325112867561281832};
+  static constexpr double s[16] = {0.0, 0.38268343236508977172846, 0.7071067811865475244008444,
+                                   0.9238795325112867561281832, 1.0, 0.9238795325112867561281832,
+                                   0.7071067811865475244008444, 0.38268343236508977172846, 0.0,
+                                   -0.38268343236508977172846, -0.7071067811865475244008444,
+                                   -0.9238795325112867561281832, -1.0,
+                                   -0.9238795325112867561281832, -0.7071067811865475244008444,
+                                   -0.38268343236508977172846};
+};
+struct Roots18 {
+  static constexpr double c[18] = {1.0, 0.9396926207859083840541093, 0.7660444431189780352023927,
+                                   0.5, 0.1736481776669303488517166, -0.1736481776669303488517166,
+                                   -0.5, -0.7660444431189780352023927, -0.9396926207859083840541093,
+                                   -1.0, -0.9396926207859083840541093, -0.7660444431189780352023927,
+                                   -0.5, -0.1736481776669303488517166, 0.1736481776669303488517166,
+                                   0.5, 0.7660444431189780352023927, 0.9396926207859083840541093};
+  static constexpr double s[18] = {0.0, 0.3420201433256687330440996, 0.6427876096865393263226434,
+                                   0.8660254037844386467637232, 0.984807753012208059366743,
+                                   0.984807753012208059366743, 0.8660254037844386467637232,
+                                   0.6427876096865393263226434, 0.3420201433256687330440996, 0.0,
+                                   -0.3420201433256687330440996, -0.6427876096865393263226434,
+                                   -0.8660254037844386467637232, -0.984807753012208059366743,
+                                   -0.984807753012208059366743, -0.8660254037844386467637232,
+                                   -0.6427876096865393263226434, -0.3420201433256687330440996};
+};
+
+// v (cos - i sin)
+template <typename T>
+__device__ __forceinline__ cpx<T> rot(const cpx<T>& v, double c, double s) {
+  return mk(v.x * (T)c + v.y * (T)s, v.y * (T)c - v.x * (T)s);
+}
+
+// 3-point DFT with constant roots (w3 = -1/2 - i sqrt(3)/2).
+template <typename T>
+__device__ __forceinline__ void dft3_reg(cpx<T>& a0, cpx<T>& a1, cpx<T>& a2) {
+  const T h = T(0.8660254037844386467637231707529361834714);
+  const cpx<T> sm = a1 + a2, df = a1 - a2;
+  const cpx<T> c = a0 - sm * T(0.5);
+  const cpx<T> r = mk(df.y * h, -df.x * h);  // -i sqrt(3)/2 (a1 - a2)
+  a0 = a0 + sm;
+  a1 = c + r;
+  a2 = c - r;
+}
+
+// 6-point DFT in place: 3-point DFTs of the even and odd samples, then
+// X_k = E_k + w6^k O_k, X_{k+3} = E_k - w6^k O_k.
+template <typename T>
+__device__ __forceinline__ void dft6_reg(cpx<T>* a) {
+  const double h = 0.8660254037844386467637231707529361834714;
+  cpx<T> e0 = a[0], e1 = a[2], e2 = a[4], o0 = a[1], o1 = a[3], o2 = a[5];
+  dft3_reg<T>(e0, e1, e2);
+  dft3_reg<T>(o0, o1, o2);
+  const cpx<T> t1 = rot(o1, 0.5, h), t2 = rot(o2, -0.5, h);
+  a[0] = e0 + o0;
+  a[3] = e0 - o0;
+  a[1] = e1 + t1;
+  a[4] = e1 - t1;
+  a[2] = e2 + t2;
+  a[5] = e2 - t2;
+}
+
+// Composite codelets by one Cooley-Tukey split N = N1 N2 (n = N2 n1 + n2,
+// k = k1 + N1 k2): N2 inner DFTs of length N1, twiddles w_N^(n2 k1), N1
+// outer DFTs of length N2; all in registers with constant roots.
+// 16 = 4 x 4
+template <typename T>
+struct Codelet<T, 16> {
+  __device__ __forceinline__ static void run(cpx<T>* v, const cpx<T>*) {
+    cpx<T> a[4][4];
+#pragma unroll
+    for (int n2 = 0; n2 < 4; ++n2) {
+#pragma unroll
+      for (int n1 = 0; n1 < 4; ++n1) a[n2][n1] = v[4 * n1 + n2];
+      dft4_reg<T>(a[n2][0], a[n2][1], a[n2][2], a[n2][3]);
+    }
+#pragma unroll
+    for (int n2 = 1; n2 < 4; ++n2)
+#pragma unroll
+      for (int k1 = 1; k1 < 4; ++k1)
+        a[n2][k1] = rot(a[n2][k1], Roots16::c[n2 * k1], Roots16::s[n2 * k1]);
+#pragma unroll
+    for (int k1 = 0; k1 < 4; ++k1) {
+      cpx<T> b0 = a[0][k1], b1 = a[1][k1], b2 = a[2][k1], b3 = a[3][k1];
+      dft4_reg<T>(b0, b1, b2, b3);
+      v[k1] = b0;
+      v[k1 + 4] = b1;
+      v[k1 + 8] = b2;
+      v[k1 + 12] = b3;
+    }
+  }
+};
+
+// 18 = 6 x 3
+template <typename T>
+struct Codelet<T, 18> {
+  __device__ __forceinline__ static void run(cpx<T>* v, const cpx<T>*) {
+    cpx<T> a[3][6];
+#pragma unroll
+    for (int n2 = 0; n2 < 3; ++n2) {
+#pragma unroll
+      for (int n1 = 0; n1 < 6; ++n1) a[n2][n1] = v[3 * n1 + n2];
+      dft6_reg<T>(a[n2]);
+    }
+#pragma unroll
+    for (int n2 = 1; n2 < 3; ++n2)
+#pragma unroll
+      for (int k1 = 1; k1 < 6; ++k1)
+        a[n2][k1] = rot(a[n2][k1], Roots18::c[n2 * k1], Roots18::s[n2 * k1]);
+#pragma unroll
+    for (int k1 = 0; k1 < 6; ++k1) {
+      cpx<T> b0 = a[0][k1], b1 = a[1][k1], b2 = a[2][k1];
+      dft3_reg<T>(b0, b1, b2);
+      v[k1] = b0;
+      v[k1 + 6] = b1;
+      v[k1 + 12] = b2;
+    }
   }
 };
 
@@ -256,6 +383,8 @@ __device__ __forceinline__ cpx<T>* fft_fwd(cpx<T>* buf0, cpx<T>* buf1, int es, i
       case 5: fft_stage<T, 5, PAD>(src, dst, L, es, ls, n, ns, tws, cw, tid, nt); break;
       case 7: fft_stage<T, 7, PAD>(src, dst, L, es, ls, n, ns, tws, cw, tid, nt); break;
       case 8: fft_stage<T, 8, PAD>(src, dst, L, es, ls, n, ns, tws, cw, tid, nt); break;
+      case 16: fft_stage<T, 16, PAD>(src, dst, L, es, ls, n, ns, tws, cw, tid, nt); break;
+      case 18: fft_stage<T, 18, PAD>(src, dst, L, es, ls, n, ns, tws, cw, tid, nt); break;
       default:
         if constexpr (BIG) fft_stage_prime<T, PAD>(src, dst, r, L, es, ls, n, ns, tws, cw, tid, nt);
         break;

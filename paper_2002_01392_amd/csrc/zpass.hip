@@ -545,8 +545,8 @@ void launch_z_fwd(const ZArgs& a, bool big, const cpx<double>* src, cpx<double>*
 
 // Compile-time plan for N' = 288 (nz = 257 with C = 31); other lengths run
 // the run-time engine.
-using P288 = SPlan<8, 4, 3, 3>;
-static bool z_static_288(const ZArgs& a) { return a.g.npr == 288 && plan_is(a.pl, {8, 4, 3, 3}); }
+using P288 = SPlan<16, 18>;
+static bool z_static_288(const ZArgs& a) { return a.g.npr == 288 && plan_is(a.pl, {16, 18}); }
 
 template <typename T>
 void launch_z_back(const ZArgs& a, bool big, const cpx<double>* src, cpx<T>* dst, cpx<T>* dzdst,
