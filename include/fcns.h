@@ -133,6 +133,15 @@ fcns_status fcns_set_state(fcns_ctx* ctx, const double* v, const double* theta);
  * Asynchronous on the context stream. */
 fcns_status fcns_rk_step(fcns_ctx* ctx, double dt, int32_t nsteps);
 
+/* Batched stepping of n independent contexts (HOST arrays of n context
+ * pointers, time steps and step counts): step k of every context is
+ * enqueued before step k + 1 of any, each on its own context stream, so
+ * problems of different shapes overlap on the device.  Each context's result
+ * is bitwise its own fcns_rk_step.  Contexts must not share a stream for
+ * the overlap (sharing is correct, only serial). */
+fcns_status fcns_batch_step(fcns_ctx* const* ctxs, int32_t n, const double* dts,
+                            const int32_t* nsteps);
+
 /* Autotuner: times, on this context's own buffers and stream, the launch
  * choices that depend on the shape -- the persistent grid of the y pass, the
  * tiling of the x pass with products, and the radix order of the run-time z

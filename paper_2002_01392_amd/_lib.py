@@ -48,6 +48,8 @@ SIGNATURES = {
     "fcns_rk_step": (ctypes.c_int, [_P, _D, _I32]),
     "fcns_rk_graph": (ctypes.c_int, [_P, _D, _I32]),
     "fcns_autotune": (ctypes.c_int, [_P, ctypes.c_char_p, _I32]),
+    "fcns_batch_step": (ctypes.c_int, [ctypes.POINTER(_P), _I32, ctypes.POINTER(_D),
+                                       ctypes.POINTER(_I32)]),
     "fcns_get_state": (ctypes.c_int, [_P, _P, _P, _P]),
     "fcns_get_spectral": (ctypes.c_int, [_P, _I32, _P]),
     "fcns_set_spectral": (ctypes.c_int, [_P, ctypes.POINTER(_P), _P]),
@@ -123,6 +125,19 @@ def workload_problem(w, **kw):
     return make_problem(w.nx, w.ny, w.nz, w.lx, w.ly, w.lz, w.nu, d=w.d, C=w.C,
                         forcing_x=w.forcing_x, boussinesq=w.boussinesq, kappa=w.kappa,
                         gamma=w.gamma, **kw)
+
+
+def batch_step(solvers, dts, nsteps):
+    """Step several solvers together (fcns_batch_step): their launches are
+    interleaved step by step, each on the solver's own stream."""
+    lib = load_library()
+    n = len(solvers)
+    ctxs = (_P * n)(*[s.ctx for s in solvers])
+    dt = (_D * n)(*[float(x) for x in dts])
+    ns = (_I32 * n)(*[int(x) for x in nsteps])
+    st = lib.fcns_batch_step(ctxs, n, dt, ns)
+    if st != FCNS_OK:
+        raise FcnsError(st, "batch_step")
 
 
 def footprint(prob):
@@ -272,17 +287,22 @@ class Solver:
         if st != FCNS_OK:
             raise FcnsError(st, self.lib.fcns_last_error(self.ctx).decode())
 
+    # Inputs are staged and outputs allocated on the solver's stream, so the
+    # library's work on that stream is ordered after the copies and the
+    # allocator keeps the buffers until that stream is done with them.
     def _dev(self, a, shape=None):
         t = self.torch
         if isinstance(a, np.ndarray):
             a = t.from_numpy(np.ascontiguousarray(a, dtype=np.float64))
-        a = a.to(device=self.device, dtype=t.float64).contiguous()
+        with t.cuda.stream(self.stream):
+            a = a.to(device=self.device, dtype=t.float64).contiguous()
         if shape is not None and tuple(a.shape) != tuple(shape):
             raise ValueError(f"expected shape {shape}, got {tuple(a.shape)}")
         return a
 
     def _empty(self, *shape):
-        return self.torch.empty(shape, dtype=self.torch.float64, device=self.device)
+        with self.torch.cuda.stream(self.stream):
+            return self.torch.empty(shape, dtype=self.torch.float64, device=self.device)
 
     # -- entry points ----------------------------------------------------------
     def fc_extend(self, lines):
@@ -367,22 +387,25 @@ class Solver:
                                           ey.ctypes.data_as(ctypes.c_void_p)))
         return ex, ey
 
+    def _cempty(self, *shape):
+        with self.torch.cuda.stream(self.stream):
+            return self.torch.empty(shape, dtype=self.torch.complex128, device=self.device)
+
     def get_spectral(self, field):
-        out = self.torch.empty((self.npr, self.ny, self.nx // 2 + 1), dtype=self.torch.complex128,
-                               device=self.device)
+        out = self._cempty(self.npr, self.ny, self.nx // 2 + 1)
         self._check(self.lib.fcns_get_spectral(self.ctx, int(field), _ptr(out)))
         return out
 
     def get_wall_grad(self):
-        out = self.torch.empty((2, 2, self.ny, self.nx // 2 + 1), dtype=self.torch.complex128,
-                               device=self.device)
+        out = self._cempty(2, 2, self.ny, self.nx // 2 + 1)
         self._check(self.lib.fcns_get_wall_grad(self.ctx, _ptr(out)))
         return out
 
     def set_spectral(self, fields, wall_grad=None):
-        fs = [f.to(self.device).contiguous() for f in fields]
+        with self.torch.cuda.stream(self.stream):
+            fs = [f.to(self.device).contiguous() for f in fields]
+            wg = wall_grad.to(self.device).contiguous() if wall_grad is not None else None
         arr = (ctypes.c_void_p * len(fs))(*[f.data_ptr() for f in fs])
-        wg = wall_grad.to(self.device).contiguous() if wall_grad is not None else None
         self._check(self.lib.fcns_set_spectral(self.ctx, arr, _ptr(wg)))
         self._keep = (fs, wg)
 

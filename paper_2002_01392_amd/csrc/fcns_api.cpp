@@ -861,6 +861,41 @@ extern "C" fcns_status fcns_autotune(fcns_ctx* c, char* report, int32_t report_l
   return st;
 }
 
+// Several problems stepped together: step k of every context is enqueued
+// before step k + 1 of any, each on its own context stream, so that the
+// problems overlap on the device; each context's work is exactly its
+// fcns_rk_step.
+extern "C" fcns_status fcns_batch_step(fcns_ctx* const* ctxs, int32_t n, const double* dts,
+                                       const int32_t* nsteps) {
+  if (n < 0 || (n > 0 && (!ctxs || !dts || !nsteps))) return FCNS_EINVAL;
+  int most = 0;
+  for (int i = 0; i < n; ++i) {
+    fcns_ctx* c = ctxs[i];
+    if (!c) return FCNS_EINVAL;
+    if (!c->has_state) return fail(c, FCNS_ESTATE, "batch_step before set_state");
+    if (!(dts[i] > 0.0) || nsteps[i] < 0) return fail(c, FCNS_EINVAL, "need dt > 0, nsteps >= 0");
+    most = nsteps[i] > most ? nsteps[i] : most;
+  }
+  for (int k = 0; k < most; ++k)
+    for (int i = 0; i < n; ++i) {
+      if (k >= nsteps[i]) continue;
+      fcns_ctx* c = ctxs[i];
+      const int o = c->prob.rk_order;
+      for (int j = 1; j <= o; ++j) {
+        if (c->mixed)
+          rk_stage<float>(c, j, o, dts[i]);
+        else
+          rk_stage<double>(c, j, o, dts[i]);
+      }
+    }
+  for (int i = 0; i < n; ++i) {
+    fcns_status st = check_launch(ctxs[i], "batch_step");
+    if (st) return st;
+    if (nsteps[i] > 0 && ctxs[i]->prob.keep_pressure) ctxs[i]->has_pressure = true;
+  }
+  return FCNS_OK;
+}
+
 extern "C" fcns_status fcns_get_state(fcns_ctx* c, double* v, double* theta, double* p) {
   if (!c) return FCNS_EINVAL;
   if (!c->has_state) return fail(c, FCNS_ESTATE, "get_state before set_state");

@@ -104,3 +104,26 @@ def test_server_rejects_a_request_larger_than_the_budget(fcns):
         srv.result(rid)
     assert e.value.code == -2
     srv.close()
+
+
+def test_batch_step_matches_single_solves(fcns):
+    # several shapes stepped together on their own streams: each result is
+    # bitwise its own rk_step
+    ws = _requests()[:5]
+    states = [w.initial_state() for w in ws]
+    streams = [torch.cuda.Stream() for _ in ws]
+    solvers = []
+    for w, (v0, th0), st in zip(ws, states, streams):
+        s = fcns.Solver.from_workload(w, stream=st)
+        s.set_state(torch.from_numpy(v0), torch.from_numpy(th0) if th0 is not None else None)
+        solvers.append(s)
+    torch.cuda.synchronize()
+    fcns.batch_step(solvers, [w.dt for w in ws], [w.steps for w in ws])
+    torch.cuda.synchronize()
+    for s, w, (v0, th0) in zip(solvers, ws, states):
+        v, th, _ = s.get_state()
+        torch.cuda.synchronize()
+        rv, rth = _alone(fcns, w, v0, th0)
+        assert np.array_equal(v.cpu().numpy(), rv), w.name
+        if th is not None:
+            assert np.array_equal(th.cpu().numpy(), rth), w.name
