@@ -284,9 +284,11 @@ __global__ __launch_bounds__(ZNT) void k_z_stageA(ZArgs a, StageAArgs s) {
 //   V = V* - k~ s - F_z H; next-stage wall gradient (k~ B_z s + H)_par / c.
 // The two exponentials are continued as the real and imaginary parts of one
 // line; F_z(e+ + i e-) splits into F_z e+ and F_z e- by conjugate symmetry.
-// V* is streamed twice (wall sums, then the update) instead of being held in
-// registers; the mixed v, dv/dz of the result come from k_z_back.
-template <typename T, class FP>
+// HOLD > 0 (compiled plans, N' <= HOLD * ZLS): V* is read once and held in
+// registers (HOLD rows per thread); HOLD = 0: V* is streamed twice (wall
+// sums, then the update).  The mixed v, dv/dz of the result come from
+// k_z_back.
+template <typename T, class FP, int HOLD>
 __global__ __launch_bounds__(ZNT) void k_z_stageB(ZArgs a, StageBArgs s) {
   extern __shared__ __align__(16) char smem[];
   __shared__ cpx<double> coef[ZPB * 5];  // b, t, s0, s1 then A, B, D
@@ -312,13 +314,38 @@ __global__ __launch_bounds__(ZNT) void k_z_stageB(ZArgs a, StageBArgs s) {
   // 1. wall sums of B_z(V*_z - k~z s) and B_z(s)
   cpx<double> sb = zero<double>(), st = zero<double>(), s0 = zero<double>(),
               s1 = zero<double>();
+  cpx<double> hv[3][HOLD > 0 ? HOLD : 1];
+  if (HOLD > 0) {
+#pragma unroll
+    for (int r = 0; r < HOLD; ++r) {
+      const int l = lt + r * ZLS;
+      const bool ok = valid_me && l < npr;
+      const long long gi = ok ? (long long)l * g.npen + p_me : 0;
+#pragma unroll
+      for (int i = 0; i < 3; ++i) hv[i][r] = s.vs[i][gi];
+      if (!ok)
+#pragma unroll
+        for (int i = 0; i < 3; ++i) hv[i][r] = zero<double>();
+    }
+  }
   if (valid_me) {
     // root index l (nz - 1) mod N', stepped with l
     const int step = (int)(((long long)ZLS * (g.nz - 1)) % npr);
     int ei = (int)(((long long)lt * (g.nz - 1)) % npr);
-    for (int l = lt; l < npr; l += ZLS, ei = (ei + step >= npr) ? ei + step - npr : ei + step) {
-      const long long gi = (long long)l * g.npen + p_me;
-      const cpx<double> V0 = s.vs[0][gi], V1 = s.vs[1][gi], V2 = s.vs[2][gi];
+#pragma unroll(HOLD > 0 ? HOLD : 1)
+    for (int l = lt, r = 0; l < npr; l += ZLS, ++r,
+             ei = (ei + step >= npr) ? ei + step - npr : ei + step) {
+      cpx<double> V0, V1, V2;
+      if (HOLD > 0) {
+        V0 = hv[0][r];
+        V1 = hv[1][r];
+        V2 = hv[2][r];
+      } else {
+        const long long gi = (long long)l * g.npen + p_me;
+        V0 = s.vs[0][gi];
+        V1 = s.vs[1][gi];
+        V2 = s.vs[2][gi];
+      }
       const double kz = k_odd(l, npr, g.kzs);
       const double k2 = kh2 + kz * kz;
       cpx<double> sv = zero<double>();
@@ -396,15 +423,25 @@ __global__ __launch_bounds__(ZNT) void k_z_stageB(ZArgs a, StageBArgs s) {
   __syncthreads();
   const cpx<T>* R = fft_run<T, ZPB, ZNT, false, FP>(L.X0, L.X1, ZPB, 1, a.pl, L.tw, tid);
   cpx<T>* Xo = (R == L.X0) ? L.X1 : L.X0;
-  // 4. V = V* - k~ s - H^ (V* streamed again), store the continued state
-  for (int l = lt; l < npr; l += ZLS) {
+  // 4. V = V* - k~ s - H^ (V* held or streamed again), store the continued state
+#pragma unroll(HOLD > 0 ? HOLD : 1)
+  for (int l = lt, r = 0; l < npr; l += ZLS, ++r) {
     const int e = l * ZPB + pb_me;
     if (!valid_me) {
       if (pm) Xo[e] = zero<T>();
       continue;
     }
     const long long gi = (long long)l * g.npen + p_me;
-    const cpx<double> V0 = s.vs[0][gi], V1 = s.vs[1][gi], V2 = s.vs[2][gi];
+    cpx<double> V0, V1, V2;
+    if (HOLD > 0) {
+      V0 = hv[0][r];
+      V1 = hv[1][r];
+      V2 = hv[2][r];
+    } else {
+      V0 = s.vs[0][gi];
+      V1 = s.vs[1][gi];
+      V2 = s.vs[2][gi];
+    }
     const int lm = (l == 0) ? 0 : npr - l;
     const cpx<double> xl = cvt<double>(R[e]), xm = conj(cvt<double>(R[lm * ZPB + pb_me]));
     const cpx<double> ep = (xl + xm) * 0.5;
@@ -592,11 +629,11 @@ void launch_z_stageB(const ZArgs& a, bool big, const StageBArgs& s, hipStream_t 
   dim3 grid((unsigned)((a.g.npen + ZPB - 1) / ZPB), 1);
   const size_t sh = zshared_bytes<double>(a.g, a.pl.tsize);
   if (z_static_288(a))
-    FCNS_LAUNCH((k_z_stageB<double, P288>), grid, dim3(ZNT), sh, st, a, s);
+    FCNS_LAUNCH((k_z_stageB<double, P288, 288 / ZLS>), grid, dim3(ZNT), sh, st, a, s);
   else if (big)
-    FCNS_LAUNCH((k_z_stageB<double, DynPlan<true>>), grid, dim3(ZNT), sh, st, a, s);
+    FCNS_LAUNCH((k_z_stageB<double, DynPlan<true>, 0>), grid, dim3(ZNT), sh, st, a, s);
   else
-    FCNS_LAUNCH((k_z_stageB<double, DynPlan<false>>), grid, dim3(ZNT), sh, st, a, s);
+    FCNS_LAUNCH((k_z_stageB<double, DynPlan<false>, 0>), grid, dim3(ZNT), sh, st, a, s);
 }
 
 void launch_fc_extend(const double* in, long long nlines, long long ips, long long ils, double* out,
