@@ -221,53 +221,64 @@ __global__ __launch_bounds__(ZNT) void k_z_stageA(ZArgs a, StageAArgs s) {
     vtr[r] = ok ? vt[gi] : zero<double>();
     wr[r] = ok ? w[gi] : zero<double>();
   }
-  for (int pass = 0; pass < 3; ++pass) {
-    if (pass == 0) {
-      // nonlinear term at the physical points (loaded above), continued
-      __syncthreads();
-      z_extend<T>(L.X0, L.M, g.nz, g.C, g.d, tid);
-      __syncthreads();
-    } else if (pass == 1) {
-      // S = V^t + c (sigma N - diff |k|^2 W), conjugated for the inverse
+  // 1. nonlinear term at the physical points (loaded above), continued,
+  // transformed
+  __syncthreads();
+  z_extend<T>(L.X0, L.M, g.nz, g.C, g.d, tid);
+  __syncthreads();
+  R = fft_run<T, ZPB, ZNT, false, FP>(L.X0, L.X1, ZPB, 1, a.pl, L.tw, tid);
+  // 2. S = V^t + c (sigma N - diff |k|^2 W), conjugated for the inverse
 #pragma unroll
-      for (int r = 0; r < OWN; ++r) {
-        const int l = lt + r * ZLS;
-        if (l < npr) {
-          const int e = l * ZPB + pb;
-          cpx<double> S = zero<double>();
-          if (pv) {
-            const double kzt = k_true(l, npr, g.kzs);
-            const double k2 = kh2 + kzt * kzt;
-            const double sig = a.sigz[l] * sxy;
-            S = vtr[r] + (cvt<double>(R[e]) * sig - wr[r] * (diff * k2)) * c;
-          }
-          L.X0[e] = cvt<T>(conj(S));
-        }
+  for (int r = 0; r < OWN; ++r) {
+    const int l = lt + r * ZLS;
+    if (l < npr) {
+      const int e = l * ZPB + pb;
+      cpx<double> S = zero<double>();
+      if (pv) {
+        const double kzt = k_true(l, npr, g.kzs);
+        const double k2 = kh2 + kzt * kzt;
+        const double sig = a.sigz[l] * sxy;
+        S = vtr[r] + (cvt<double>(R[e]) * sig - wr[r] * (diff * k2)) * c;
       }
-      __syncthreads();
-    } else {
-      // v* at the physical points: forcing, buoyancy, wall injection
-      for (int z = lt; z < g.nz; z += ZLS) {
-        const int e = z * ZPB + pb;
-        cpx<double> v = zero<double>();
-        if (pv) {
-          v = conj(cvt<double>(R[e])) * inv;
-          if (f == 0 && p == 0) v.x += c * s.forcing_sum;
-          if (buoy) v = v + cvt<double>(buoy[(long long)z * g.npen + p]) * (c * s.gamma);
-          if (z == 0 || z == g.nz - 1) {
-            const int wall = (z == 0) ? 0 : 1;
-            if (f < 2) v = s.gwall[(wall * 2 + f) * g.npen + p] * c;
-            if (f == 3) v = zero<double>();
-          }
-        }
-        L.X0[e] = cvt<T>(v);
-      }
-      __syncthreads();
-      z_extend<T>(L.X0, L.M, g.nz, g.C, g.d, tid);
-      __syncthreads();
+      L.X0[e] = cvt<T>(conj(S));
     }
-    R = fft_run<T, ZPB, ZNT, false, FP>(L.X0, L.X1, ZPB, 1, a.pl, L.tw, tid);
   }
+  // the buoyancy rows of this thread, in flight during the inverse transform
+  cpx<double> br[OWN];
+  if (buoy) {
+#pragma unroll
+    for (int r = 0; r < OWN; ++r) {
+      const int z = lt + r * ZLS;
+      br[r] = (pv && z < g.nz) ? cvt<double>(buoy[(long long)z * g.npen + p]) : zero<double>();
+    }
+  }
+  __syncthreads();
+  R = fft_run<T, ZPB, ZNT, false, FP>(L.X0, L.X1, ZPB, 1, a.pl, L.tw, tid);
+  // 3. v* at the physical points: forcing, buoyancy, wall injection;
+  // continued and transformed
+#pragma unroll
+  for (int r = 0; r < OWN; ++r) {
+    const int z = lt + r * ZLS;
+    if (z < g.nz) {
+      const int e = z * ZPB + pb;
+      cpx<double> v = zero<double>();
+      if (pv) {
+        v = conj(cvt<double>(R[e])) * inv;
+        if (f == 0 && p == 0) v.x += c * s.forcing_sum;
+        if (buoy) v = v + br[r] * (c * s.gamma);
+        if (z == 0 || z == g.nz - 1) {
+          const int wall = (z == 0) ? 0 : 1;
+          if (f < 2) v = s.gwall[(wall * 2 + f) * g.npen + p] * c;
+          if (f == 3) v = zero<double>();
+        }
+      }
+      L.X0[e] = cvt<T>(v);
+    }
+  }
+  __syncthreads();
+  z_extend<T>(L.X0, L.M, g.nz, g.C, g.d, tid);
+  __syncthreads();
+  R = fft_run<T, ZPB, ZNT, false, FP>(L.X0, L.X1, ZPB, 1, a.pl, L.tw, tid);
   cpx<double>* __restrict__ out = s.out[f];
   if (pv)
     for (int l = lt; l < npr; l += ZLS) out[(long long)l * g.npen + p] = cvt<double>(R[l * ZPB + pb]);
