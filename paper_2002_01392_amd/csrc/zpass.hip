@@ -213,6 +213,7 @@ __global__ __launch_bounds__(ZNT) void k_z_stageA(ZArgs a, StageAArgs s) {
     L.X0[z * ZPB + pb] = pv ? cvt<T>(nl[(long long)z * g.npen + p]) : zero<T>();
   // the continued state of this pencil, in flight during the first transform
   cpx<double> vtr[OWN], wr[OWN];
+  double sgr[OWN];
 #pragma unroll
   for (int r = 0; r < OWN; ++r) {
     const int l = lt + r * ZLS;
@@ -220,6 +221,7 @@ __global__ __launch_bounds__(ZNT) void k_z_stageA(ZArgs a, StageAArgs s) {
     const bool ok = pv && l < npr;
     vtr[r] = ok ? vt[gi] : zero<double>();
     wr[r] = ok ? w[gi] : zero<double>();
+    sgr[r] = ok ? a.sigz[l] : 0.0;
   }
   // 1. nonlinear term at the physical points (loaded above), continued,
   // transformed
@@ -237,13 +239,14 @@ __global__ __launch_bounds__(ZNT) void k_z_stageA(ZArgs a, StageAArgs s) {
       if (pv) {
         const double kzt = k_true(l, npr, g.kzs);
         const double k2 = kh2 + kzt * kzt;
-        const double sig = a.sigz[l] * sxy;
+        const double sig = sgr[r] * sxy;
         S = vtr[r] + (cvt<double>(R[e]) * sig - wr[r] * (diff * k2)) * c;
       }
       L.X0[e] = cvt<T>(conj(S));
     }
   }
-  // the buoyancy rows of this thread, in flight during the inverse transform
+  // the buoyancy rows and wall values of this thread, in flight during the
+  // inverse transform
   cpx<double> br[OWN];
   if (buoy) {
 #pragma unroll
@@ -251,6 +254,12 @@ __global__ __launch_bounds__(ZNT) void k_z_stageA(ZArgs a, StageAArgs s) {
       const int z = lt + r * ZLS;
       br[r] = (pv && z < g.nz) ? cvt<double>(buoy[(long long)z * g.npen + p]) : zero<double>();
     }
+  }
+  const bool has_w0 = lt == 0, has_w1 = (g.nz - 1) % ZLS == lt;
+  cpx<double> gw0 = zero<double>(), gw1 = zero<double>();
+  if (pv && f < 2) {
+    if (has_w0) gw0 = s.gwall[(0 * 2 + f) * g.npen + p];
+    if (has_w1) gw1 = s.gwall[(1 * 2 + f) * g.npen + p];
   }
   __syncthreads();
   R = fft_run<T, ZPB, ZNT, false, FP>(L.X0, L.X1, ZPB, 1, a.pl, L.tw, tid);
@@ -267,8 +276,7 @@ __global__ __launch_bounds__(ZNT) void k_z_stageA(ZArgs a, StageAArgs s) {
         if (f == 0 && p == 0) v.x += c * s.forcing_sum;
         if (buoy) v = v + br[r] * (c * s.gamma);
         if (z == 0 || z == g.nz - 1) {
-          const int wall = (z == 0) ? 0 : 1;
-          if (f < 2) v = s.gwall[(wall * 2 + f) * g.npen + p] * c;
+          if (f < 2) v = ((z == 0) ? gw0 : gw1) * c;
           if (f == 3) v = zero<double>();
         }
       }
