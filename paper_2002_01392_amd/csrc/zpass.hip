@@ -207,22 +207,39 @@ __global__ __launch_bounds__(ZNT) void k_z_stageA(ZArgs a, StageAArgs s) {
   int ix, iy;
   pencil_k(g, pv ? p : 0, kxo, kyo, kxt, kyt, ix, iy);
   const double kh2 = kxt * kxt + kyt * kyt;
-  const double sxy = a.sigy[iy] * a.sigx[ix];
   cpx<T>* R = L.X0;
-  for (int z = lt; z < g.nz; z += ZLS)
-    L.X0[z * ZPB + pb] = pv ? cvt<T>(nl[(long long)z * g.npen + p]) : zero<T>();
-  // the continued state of this pencil, in flight during the first transform
+  // All of this thread's loads before the first transform are issued before
+  // any is waited for: the nonlinear term's rows (rows past nz and invalid
+  // pencils read an in-bounds slot that is then discarded), then the
+  // continued state and filter factors, in flight during the transform.
+  cpx<TM> nr[OWN];
+  const long long pc = pv ? p : 0;
+#pragma unroll
+  for (int r = 0; r < OWN; ++r) {
+    const int z = min(lt + r * ZLS, g.nz - 1);
+    nr[r] = nl[(long long)z * g.npen + pc];
+  }
+  // keep these loads ahead of the ones below (loads complete in order, so a
+  // later one issued first would hold up the LDS writes of these rows)
+  __builtin_amdgcn_sched_barrier(0);
   cpx<double> vtr[OWN], wr[OWN];
   double sgr[OWN];
 #pragma unroll
   for (int r = 0; r < OWN; ++r) {
-    const int l = lt + r * ZLS;
-    const long long gi = (long long)l * g.npen + p;
-    const bool ok = pv && l < npr;
-    vtr[r] = ok ? vt[gi] : zero<double>();
-    wr[r] = ok ? w[gi] : zero<double>();
-    sgr[r] = ok ? a.sigz[l] : 0.0;
+    const int l = min(lt + r * ZLS, npr - 1);  // rows past N' are never used
+    const long long gi = (long long)l * g.npen + pc;
+    vtr[r] = vt[gi];
+    wr[r] = w[gi];
+    sgr[r] = a.sigz[l];
   }
+  // (rows z >= nz store zero to a continuation row, rewritten by the
+  // extension after the barrier, so that no load is tied to a branch)
+#pragma unroll
+  for (int r = 0; r < OWN; ++r) {
+    const int z = lt + r * ZLS;
+    L.X0[min(z, npr - 1) * ZPB + pb] = (pv && z < g.nz) ? cvt<T>(nr[r]) : zero<T>();
+  }
+  const double sxy = a.sigy[iy] * a.sigx[ix];
   // 1. nonlinear term at the physical points (loaded above), continued,
   // transformed
   __syncthreads();
@@ -333,24 +350,25 @@ __global__ __launch_bounds__(ZNT) void k_z_stageB(ZArgs a, StageBArgs s) {
   // 1. wall sums of B_z(V*_z - k~z s) and B_z(s)
   cpx<double> sb = zero<double>(), st = zero<double>(), s0 = zero<double>(),
               s1 = zero<double>();
-  cpx<double> hv[3][HOLD > 0 ? HOLD : 1];
+  // root index l (nz - 1) mod N', stepped with l
+  const int step = (int)(((long long)ZLS * (g.nz - 1)) % npr);
+  const int ei0 = (int)(((long long)lt * (g.nz - 1)) % npr);
+  // HOLD > 0: the roots of this thread's rows and V* itself, all loads issued
+  // together (rows of an invalid pencil read pencil 0 and are never used)
+  cpx<double> hv[3][HOLD > 0 ? HOLD : 1], etr[HOLD > 0 ? HOLD : 1];
   if (HOLD > 0) {
 #pragma unroll
+    for (int r = 0, ei = ei0; r < HOLD; ++r, ei = (ei + step >= npr) ? ei + step - npr : ei + step)
+      etr[r] = conj(gtw[ei]);
+#pragma unroll
     for (int r = 0; r < HOLD; ++r) {
-      const int l = lt + r * ZLS;
-      const bool ok = valid_me && l < npr;
-      const long long gi = ok ? (long long)l * g.npen + p_me : 0;
+      const long long gi = valid_me ? (long long)(lt + r * ZLS) * g.npen + p_me : 0;
 #pragma unroll
       for (int i = 0; i < 3; ++i) hv[i][r] = s.vs[i][gi];
-      if (!ok)
-#pragma unroll
-        for (int i = 0; i < 3; ++i) hv[i][r] = zero<double>();
     }
   }
   if (valid_me) {
-    // root index l (nz - 1) mod N', stepped with l
-    const int step = (int)(((long long)ZLS * (g.nz - 1)) % npr);
-    int ei = (int)(((long long)lt * (g.nz - 1)) % npr);
+    int ei = ei0;
 #pragma unroll(HOLD > 0 ? HOLD : 1)
     for (int l = lt, r = 0; l < npr; l += ZLS, ++r,
              ei = (ei + step >= npr) ? ei + step - npr : ei + step) {
@@ -371,7 +389,7 @@ __global__ __launch_bounds__(ZNT) void k_z_stageB(ZArgs a, StageBArgs s) {
       if (k2 > 0.0) sv = (V0 * kxo + V1 * kyo + V2 * kz) * (1.0 / k2);
       const cpx<double> rz = V2 - sv * kz;
       // e^{+2 pi i l (nz-1)/N'} = conj(root[l (nz-1) mod N'])
-      const cpx<double> et = conj(gtw[ei]);
+      const cpx<double> et = (HOLD > 0) ? etr[r] : conj(gtw[ei]);
       sb = sb + rz;
       st = st + rz * et;
       s0 = s0 + sv;
