@@ -44,6 +44,52 @@ size_t zshared_bytes(const Geom& g, int tsize) {
          2 * nx * sizeof(cpx<T>);
 }
 
+// Tables into LDS, in two halves so that a kernel can issue its own first
+// loads in between: load() issues the global reads, store() writes LDS.  Up
+// to 2 * ZNT entries each (the twiddle table always, as it has fewer than
+// N' + 64 entries) the reads are all issued before any is waited for;
+// larger continuation tables are copied by a loop inside store().
+template <typename T>
+struct ZTables {
+  cpx<T> t0, t1;
+  double m0, m1;
+};
+
+__device__ __forceinline__ bool ztab_fast(const ZArgs& a) {
+  return a.pl.tsize <= 2 * ZNT && a.g.C * a.g.d <= 2 * ZNT;
+}
+
+template <typename T>
+__device__ __forceinline__ ZTables<T> ztab_load(const ZArgs& a, int tid) {
+  ZTables<T> t{};
+  if (ztab_fast(a)) {
+    const cpx<T>* gtw = reinterpret_cast<const cpx<T>*>(a.tw);
+    const int nt = a.pl.tsize, nm = a.g.C * a.g.d;
+    t.t0 = gtw[min(tid, nt - 1)];
+    t.t1 = gtw[min(tid + ZNT, nt - 1)];
+    t.m0 = a.fc[min(tid, nm - 1)];
+    t.m1 = a.fc[min(tid + ZNT, nm - 1)];
+  }
+  return t;
+}
+
+template <typename T>
+__device__ __forceinline__ void ztab_store(const ZTables<T> t, const ZLds<T>& s, const ZArgs& a,
+                                           int tid) {
+  const int nt = a.pl.tsize, nm = a.g.C * a.g.d;
+  if (ztab_fast(a)) {
+    if (tid < nt) s.tw[tid] = t.t0;
+    if (tid + ZNT < nt) s.tw[tid + ZNT] = t.t1;
+    if (tid < nm) s.M[tid] = t.m0;
+    if (tid + ZNT < nm) s.M[tid + ZNT] = t.m1;
+    return;
+  }
+  const cpx<T>* gtw = reinterpret_cast<const cpx<T>*>(a.tw);
+  for (int i = tid; i < nt; i += ZNT) s.tw[i] = gtw[i];
+  for (int i = tid; i < nm; i += ZNT) s.M[i] = a.fc[i];
+}
+
+// The plain copy loop (measured faster than the split form for k_z_back).
 template <typename T>
 __device__ __forceinline__ void z_setup(const ZLds<T>& s, const ZArgs& a, int tid) {
   const cpx<T>* gtw = reinterpret_cast<const cpx<T>*>(a.tw);
@@ -192,7 +238,7 @@ __global__ __launch_bounds__(ZNT) void k_z_stageA(ZArgs a, StageAArgs s) {
   const ZLds<T> L(smem, g, a.pl.tsize);
   const int f = blockIdx.y;
   const long long p0 = (long long)blockIdx.x * ZPB;
-  z_setup<T>(L, a, tid);
+  const ZTables<T> tab = ztab_load<T>(a, tid);
   const cpx<TM>* __restrict__ nl = reinterpret_cast<const cpx<TM>*>(s.nl[f]);
   const cpx<double>* __restrict__ vt = s.vt[f];
   const cpx<double>* __restrict__ w = s.w[f];
@@ -234,6 +280,7 @@ __global__ __launch_bounds__(ZNT) void k_z_stageA(ZArgs a, StageAArgs s) {
   }
   // (rows z >= nz store zero to a continuation row, rewritten by the
   // extension after the barrier, so that no load is tied to a branch)
+  ztab_store<T>(tab, L, a, tid);
 #pragma unroll
   for (int r = 0; r < OWN; ++r) {
     const int z = lt + r * ZLS;
@@ -337,7 +384,7 @@ __global__ __launch_bounds__(ZNT) void k_z_stageB(ZArgs a, StageBArgs s) {
   const int pb_me = tid % ZPB, lt = tid / ZPB;
   const long long p_me = p0 + pb_me;
   const bool valid_me = pencil_valid(g, p_me);
-  z_setup<T>(L, a, tid);
+  const ZTables<T> tab = ztab_load<T>(a, tid);
   const cpx<double>* __restrict__ gtw = a.tw64;
   const double inv = 1.0 / npr;
   const bool pm = s.pmix != nullptr;
@@ -367,6 +414,7 @@ __global__ __launch_bounds__(ZNT) void k_z_stageB(ZArgs a, StageBArgs s) {
       for (int i = 0; i < 3; ++i) hv[i][r] = s.vs[i][gi];
     }
   }
+  ztab_store<T>(tab, L, a, tid);
   if (valid_me) {
     int ei = ei0;
 #pragma unroll(HOLD > 0 ? HOLD : 1)
