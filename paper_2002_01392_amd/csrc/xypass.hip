@@ -49,6 +49,7 @@ __global__ __launch_bounds__(YNT) void k_y(YArgs a, const cpx<T>* src, cpx<T>* d
   const long long ntiles = (nlines + YL - 1) / YL;
   const T sc = inv ? T(1) / (T)ny : T(1);
   const int npass = (mode == 1) ? 2 : 1;
+  cpx<T> cur[OWN], nxt[PF ? OWN : 1];
   long long t = blockIdx.x;
   auto line_base = [&](long long tt, bool& ok) {
     const long long q = tt * YL + l;
@@ -56,23 +57,33 @@ __global__ __launch_bounds__(YNT) void k_y(YArgs a, const cpx<T>* src, cpx<T>* d
     ok = q < nlines && kx < nkx;
     return ok ? pl * ny * nkxp + kx : 0;  // element ky at base + ky * nkxp
   };
-  // Loads are unconditional (a line outside the array reads line 0, rows past
-  // ny read row ny - 1): every line transforms on its own and only valid
-  // lines are stored, so no value needs zeroing, and zeroing a register a
-  // load is still writing would wait for that load.
-  auto load = [&](long long tt, cpx<T>(&v)[OWN]) {
+  if constexpr (PF) {
     bool ok;
-    const long long base = line_base(tt, ok);
+    const long long base = line_base(t, ok);
 #pragma unroll
     for (int r = 0; r < OWN; ++r) {
-      const int ky = min(ky0 + r * KYS, ny - 1);
-      v[r] = src[base + (long long)ky * nkxp];
+      const int ky = ky0 + r * KYS;
+      cur[r] = (ok && ky < ny) ? src[base + (long long)ky * nkxp] : zero<T>();
     }
-  };
-  // one tile: transform(s) of the values in cur, results stored
-  auto tile = [&](long long tt, const cpx<T>(&cur)[OWN]) {
+  }
+  for (; t < ntiles; t += gridDim.x) {
     bool ok;
-    const long long base = line_base(tt, ok);
+    const long long base = line_base(t, ok);
+    if constexpr (PF) {
+      bool okn;
+      const long long basen = line_base(t + gridDim.x, okn);
+#pragma unroll
+      for (int r = 0; r < OWN; ++r) {
+        const int ky = ky0 + r * KYS;
+        nxt[r] = (okn && ky < ny) ? src[basen + (long long)ky * nkxp] : zero<T>();
+      }
+    } else {
+#pragma unroll
+      for (int r = 0; r < OWN; ++r) {
+        const int ky = ky0 + r * KYS;
+        cur[r] = (ok && ky < ny) ? src[base + (long long)ky * nkxp] : zero<T>();
+      }
+    }
     for (int pass = 0; pass < npass; ++pass) {
 #pragma unroll
       for (int r = 0; r < OWN; ++r) {
@@ -98,27 +109,9 @@ __global__ __launch_bounds__(YNT) void k_y(YArgs a, const cpx<T>* src, cpx<T>* d
       }
       __syncthreads();
     }
-  };
-  const long long G = gridDim.x;
-  if constexpr (PF) {
-    // two register buffers in turn (no copy between them, which would wait
-    // for the loads in flight): the next tile loads while this one transforms
-    // (a load past the last tile reads line 0 and is never used: issuing it
-    // unconditionally keeps the wait for the current tile's loads exact)
-    cpx<T> ba[OWN], bb[OWN];
-    load(t, ba);
-    for (; t < ntiles; t += 2 * G) {
-      load(t + G, bb);
-      tile(t, ba);
-      if (t + G >= ntiles) break;
-      load(t + 2 * G, ba);
-      tile(t + G, bb);
-    }
-  } else {
-    cpx<T> cur[OWN];
-    for (; t < ntiles; t += G) {
-      load(t, cur);
-      tile(t, cur);
+    if constexpr (PF) {
+#pragma unroll
+      for (int r = 0; r < OWN; ++r) cur[r] = nxt[r];
     }
   }
 }
@@ -488,27 +481,22 @@ __global__ __launch_bounds__(64 * XW_WAVES) void k_x_nl512(XArgs a, const cpx<T>
         dx = d == 0;
         return xyb + (3 * f + d) * fs + row * nkxp;
       };
-      // (whether the pair has a second quantity is known once p is unrolled;
-      // testing a pointer instead would leave branches between the loads)
-      const bool hasb = qb < NQ;
       bool dxa, dxb = false;
       const cpx<T>* pa = src(qa, dxa);
-      const cpx<T>* pb = src(hasb ? qb : qa, dxb);
-      if (!hasb) dxb = false;
+      const cpx<T>* pb = qb < NQ ? src(qb, dxb) : nullptr;
 #pragma unroll
       for (int m = 0; m < 8; ++m) {
         const int k = lane + 64 * m;
         const int kk = k <= N / 2 ? k : N - k;
         cpx<T> A = pa[kk];
-        cpx<T> B = hasb ? pb[kk] : zero<T>();
+        cpx<T> B = pb ? pb[kk] : zero<T>();
         const T kx = (kk == N / 2) ? T(0) : kxs * (T)kk;
         if (dxa) A = mul_i(A) * kx;
         if (dxb) B = mul_i(B) * kx;
-        // (selects, not a branch: a branch here would wait for the loads
-        // issued so far before the rest of the pair's loads go out)
-        const bool real = kk == 0 || kk == N / 2;
-        A.y = real ? T(0) : A.y;
-        B.y = real ? T(0) : B.y;
+        if (kk == 0 || kk == N / 2) {
+          A.y = T(0);
+          B.y = T(0);
+        }
         // Z[k] = A + i B (k <= N/2), conj(A) + i conj(B) (k > N/2); inverse via conj
         const cpx<T> Z = (k <= N / 2) ? mk(A.x - B.y, A.y + B.x) : mk(A.x + B.y, B.x - A.y);
         r[m] = conj(Z);
