@@ -134,8 +134,6 @@ static fcns_status check_launch(fcns_ctx* c, const char* what) {
 // w^{m k} = exp(-2 pi i m k / (ns R)) as [m-1][k], and per odd-radix stage its
 // R roots exp(-2 pi i q / R).
 static std::vector<int> default_radices(int n) {
-  // 288 (nz = 257 with C = 31): two register codelets, two LDS passes
-  if (n == 288) return {16, 18};
   int m = n;
   std::vector<int> rs;
   while (m % 8 == 0) { rs.push_back(8); m /= 8; }
@@ -190,6 +188,14 @@ static bool make_plan_order(int n, const std::vector<int>& rs, FFTPlan& pl, bool
 
 static bool make_plan(int n, FFTPlan& pl, bool& big, std::vector<cpx<double>>& table) {
   return make_plan_order(n, default_radices(n), pl, big, table);
+}
+
+// The z plan: 288 (nz = 257 with C = 31) runs the compiled 16 x 18 transform
+// (two register codelets, two LDS passes); radices 16 and 18 exist only
+// there, never in a run-time plan.
+static std::vector<int> z_radices(int n) {
+  if (n == 288) return {16, 18};
+  return default_radices(n);
 }
 
 static std::vector<cpx<double>> roots(int n) {
@@ -320,7 +326,7 @@ extern "C" fcns_status fcns_create(const fcns_problem* prob, void* hip_stream, f
   g.kzs = 2.0 * M_PI / g.lzp;
 
   std::vector<cpx<double>> twz, twx, twy;
-  if (!make_plan(npr, c->plz, c->big_z, twz) || !make_plan(p.nx, c->plx, c->big_x, twx) ||
+  if (!make_plan_order(npr, z_radices(npr), c->plz, c->big_z, twz) || !make_plan(p.nx, c->plx, c->big_x, twx) ||
       !make_plan(p.ny, c->ply, c->big_y, twy)) {
     delete c;
     return fail(nullptr, FCNS_EINVAL, "unsupported transform length (more than 12 radix stages)");
@@ -818,7 +824,7 @@ extern "C" fcns_status fcns_autotune(fcns_ctx* c, char* report, int32_t report_l
   // z: radix order of a run-time plan, timed on the back-transform of the
   // state (a compiled plan, when the length has one, is kept)
   {
-    std::vector<int> rs = default_radices(g.npr);
+    std::vector<int> rs = z_radices(g.npr);
     const bool compiled = g.npr == 288 && rs == std::vector<int>{16, 18};
     std::vector<int> best_rs = rs;
     float best = 1e30f;

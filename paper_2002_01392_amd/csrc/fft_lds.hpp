@@ -383,8 +383,6 @@ __device__ __forceinline__ cpx<T>* fft_fwd(cpx<T>* buf0, cpx<T>* buf1, int es, i
       case 5: fft_stage<T, 5, PAD>(src, dst, L, es, ls, n, ns, tws, cw, tid, nt); break;
       case 7: fft_stage<T, 7, PAD>(src, dst, L, es, ls, n, ns, tws, cw, tid, nt); break;
       case 8: fft_stage<T, 8, PAD>(src, dst, L, es, ls, n, ns, tws, cw, tid, nt); break;
-      case 16: fft_stage<T, 16, PAD>(src, dst, L, es, ls, n, ns, tws, cw, tid, nt); break;
-      case 18: fft_stage<T, 18, PAD>(src, dst, L, es, ls, n, ns, tws, cw, tid, nt); break;
       default:
         if constexpr (BIG) fft_stage_prime<T, PAD>(src, dst, r, L, es, ls, n, ns, tws, cw, tid, nt);
         break;

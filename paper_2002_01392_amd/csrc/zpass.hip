@@ -139,7 +139,7 @@ __device__ __forceinline__ bool pencil_valid(const Geom& g, long long p) {
 
 // ---------------------------------------------------------------- z forward
 // mixed -> continued spectral: F_z = FFT_N' o E (times the filter if asked).
-template <typename T, bool BIG>
+template <typename T, class FP>
 __global__ __launch_bounds__(ZNT) void k_z_fwd(ZArgs a, const cpx<double>* __restrict__ src,
                                                cpx<double>* __restrict__ dst, long long sfs,
                                                long long dfs, int filter) {
@@ -159,7 +159,7 @@ __global__ __launch_bounds__(ZNT) void k_z_fwd(ZArgs a, const cpx<double>* __res
   __syncthreads();
   z_extend<T>(L.X0, L.M, g.nz, g.C, g.d, tid);
   __syncthreads();
-  const cpx<T>* R = fft_fwd<T, ZPB, BIG>(L.X0, L.X1, ZPB, 1, a.pl, L.tw, tid, ZNT);
+  const cpx<T>* R = fft_run<T, ZPB, ZNT, false, FP>(L.X0, L.X1, ZPB, 1, a.pl, L.tw, tid);
   if (!pv) return;
   double sxy = 1.0;
   if (filter) {
@@ -590,7 +590,7 @@ __global__ __launch_bounds__(256) void k_fc_extend(const double* __restrict__ in
 // Two real lines per complex line (line 2q real part, 2q+1 imaginary part):
 // the multipliers i k~z (Nyquist zeroed) and -kz^2 map real lines to real
 // lines, so the packed transform differentiates both at once.
-template <bool BIG>
+template <class FP>
 __global__ __launch_bounds__(ZNT) void k_fc_derivative(ZArgs a, const double* __restrict__ in,
                                                        double* __restrict__ out, long long nlines,
                                                        long long ps, long long ls, int order) {
@@ -626,7 +626,7 @@ __global__ __launch_bounds__(ZNT) void k_fc_derivative(ZArgs a, const double* __
       }
       __syncthreads();
     }
-    R = fft_fwd<double, ZPB, BIG>(L.X0, L.X1, ZPB, 1, a.pl, L.tw, tid, ZNT);
+    R = fft_run<double, ZPB, ZNT, false, FP>(L.X0, L.X1, ZPB, 1, a.pl, L.tw, tid);
   }
   const double inv = 1.0 / g.npr;
   for (int e = tid; e < g.nz * ZPB; e += ZNT) {
@@ -655,20 +655,25 @@ int z_max_npr() { return 16 * ZNT / ZPB; }
     default: { constexpr int OWN = 16; CALL; } break; \
   }
 
-void launch_z_fwd(const ZArgs& a, bool big, const cpx<double>* src, cpx<double>* dst,
-                  long long sfs, long long dfs, int nfields, int filter, hipStream_t st) {
-  dim3 grid((unsigned)((a.g.npen + ZPB - 1) / ZPB), nfields);
-  const size_t sh = zshared_bytes<double>(a.g, a.pl.tsize);
-  if (big)
-    FCNS_LAUNCH((k_z_fwd<double, true>), grid, dim3(ZNT), sh, st, a, src, dst, sfs, dfs, filter);
-  else
-    FCNS_LAUNCH((k_z_fwd<double, false>), grid, dim3(ZNT), sh, st, a, src, dst, sfs, dfs, filter);
-}
-
 // Compile-time plan for N' = 288 (nz = 257 with C = 31); other lengths run
 // the run-time engine.
 using P288 = SPlan<16, 18>;
 static bool z_static_288(const ZArgs& a) { return a.g.npr == 288 && plan_is(a.pl, {16, 18}); }
+
+void launch_z_fwd(const ZArgs& a, bool big, const cpx<double>* src, cpx<double>* dst,
+                  long long sfs, long long dfs, int nfields, int filter, hipStream_t st) {
+  dim3 grid((unsigned)((a.g.npen + ZPB - 1) / ZPB), nfields);
+  const size_t sh = zshared_bytes<double>(a.g, a.pl.tsize);
+  if (z_static_288(a))
+    FCNS_LAUNCH((k_z_fwd<double, P288>), grid, dim3(ZNT), sh, st, a, src, dst, sfs, dfs, filter);
+  else if (big)
+    FCNS_LAUNCH((k_z_fwd<double, DynPlan<true>>), grid, dim3(ZNT), sh, st, a, src, dst, sfs, dfs,
+                filter);
+  else
+    FCNS_LAUNCH((k_z_fwd<double, DynPlan<false>>), grid, dim3(ZNT), sh, st, a, src, dst, sfs, dfs,
+                filter);
+}
+
 
 template <typename T>
 void launch_z_back(const ZArgs& a, bool big, const cpx<double>* src, cpx<T>* dst, cpx<T>* dzdst,
@@ -736,10 +741,14 @@ void launch_fc_derivative(const ZArgs& a, bool big, const double* in, double* ou
   const long long nq = (nlines + 1) / 2;
   dim3 grid((unsigned)((nq + ZPB - 1) / ZPB));
   const size_t sh = zshared_bytes<double>(a.g, a.pl.tsize);
-  if (big)
-    FCNS_LAUNCH(k_fc_derivative<true>, grid, dim3(ZNT), sh, st, a, in, out, nlines, ps, ls, order);
+  if (z_static_288(a))
+    FCNS_LAUNCH(k_fc_derivative<P288>, grid, dim3(ZNT), sh, st, a, in, out, nlines, ps, ls, order);
+  else if (big)
+    FCNS_LAUNCH(k_fc_derivative<DynPlan<true>>, grid, dim3(ZNT), sh, st, a, in, out, nlines, ps, ls,
+                order);
   else
-    FCNS_LAUNCH(k_fc_derivative<false>, grid, dim3(ZNT), sh, st, a, in, out, nlines, ps, ls, order);
+    FCNS_LAUNCH(k_fc_derivative<DynPlan<false>>, grid, dim3(ZNT), sh, st, a, in, out, nlines, ps, ls,
+                order);
 }
 
 

@@ -101,8 +101,10 @@ def test_state_round_trip_and_spectrum(fcns, nx, ny, nz, C):
 
 # ------------------------------------------------------------------ nonlinear term
 @pytest.mark.parametrize("filtered", [False, True])
-@pytest.mark.parametrize("nx,ny,nz,C", [(16, 16, 33, 25), (32, 24, 65, 31)])
+@pytest.mark.parametrize("nx,ny,nz,C", [(16, 16, 33, 25), (32, 24, 65, 31), (16, 288, 17, 25)])
 def test_rhs_nonlinear_parity(fcns, filtered, nx, ny, nz, C):
+    # ny = 288: the length of the compiled z plan, here run by the run-time
+    # y engine (radices 8 4 3 3)
     lx, ly, lz = 2.0, 2.0, 1.0
     s = fcns.Solver(nx, ny, nz, lx, ly, lz, 0.01, d=5, C=C, boussinesq=True, kappa=0.01,
                     gamma=1.0)
