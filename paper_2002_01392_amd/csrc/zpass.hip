@@ -101,8 +101,8 @@ __device__ __forceinline__ void z_setup(const ZLds<T>& s, const ZArgs& a, int ti
 // (Sec. 3 continuation formula; App. B block form A f = A_l Q_l^T f_l +
 // A_r Q_r^T f_r with M = A Q^T).
 template <typename T>
-__device__ __forceinline__ void z_extend(cpx<T>* X, const double* __restrict__ M, int nz, int C,
-                                         int d, int tid) {
+__device__ __forceinline__ void z_extend_fma(cpx<T>* X, const double* __restrict__ M, int nz, int C,
+                                             int d, int tid) {
   for (int e = tid; e < C * ZPB; e += ZNT) {
     const int i = e / ZPB, pb = e % ZPB;
     double ar = 0.0, ai = 0.0;
@@ -120,6 +120,61 @@ __device__ __forceinline__ void z_extend(cpx<T>* X, const double* __restrict__ M
     }
     X[(nz + i) * ZPB + pb] = mk((T)ar, (T)ai);
   }
+}
+
+// The same continuation on the matrix cores: per workgroup the C x 2d matrix
+// [M_r | M_l] times the 2d x 16 boundary values of its 8 pencils (real and
+// imaginary parts as separate columns), as 2 row tiles x 3 k-steps of
+// v_mfma_f64_16x16x4f64, one row tile per wavefront (C <= 32, d <= 6; rows and
+// k-steps past C and 2d are zero).  Lane l supplies A[i][k] and B[k][j] with
+// i, j = l % 16 and k = l / 16, and receives D[l / 16 + 4 r][l % 16],
+// r = 0..3.  Accumulation is FP64 throughout.
+typedef double zv4d __attribute__((ext_vector_type(4)));
+static_assert(ZPB == 8, "the MFMA extension maps 8 pencils x (re, im) onto 16 columns");
+
+__device__ __forceinline__ bool z_extend_mfma_ok(int C, int d) { return C <= 32 && d <= 6; }
+
+__device__ __forceinline__ void z_extend_mfma(cpx<double>* X, const double* __restrict__ M, int nz,
+                                              int C, int d, int tid) {
+  // wavefront t (t = 0, 1) computes row tile t
+  if (tid >= 128) return;
+  const int t = tid >> 6, l = tid & 63, col = l % 16, kq = l / 16;
+  const int pb = col >> 1, part = col & 1;
+  const double* Xd = reinterpret_cast<const double*>(X);
+  const int i = 16 * t + col;
+  zv4d acc = {0, 0, 0, 0};
+#pragma unroll
+  for (int s = 0; s < 3; ++s) {
+    const int k = 4 * s + kq;
+    // B[k][col]: the right boundary rows nz-d..nz-1, then the left rows 0..d-1
+    double b = 0.0, a = 0.0;
+    if (k < d) b = Xd[2 * ((nz - d + k) * ZPB + pb) + part];
+    else if (k < 2 * d) b = Xd[2 * ((k - d) * ZPB + pb) + part];
+    if (i < C) {
+      if (k < d) a = M[i * d + k];
+      else if (k < 2 * d) a = M[(C - 1 - i) * d + (d - 1 - (k - d))];
+    }
+    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
+  }
+  double* Xw = reinterpret_cast<double*>(X);
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const int io = 16 * t + kq + 4 * r;
+    if (io < C) Xw[2 * ((nz + io) * ZPB + pb) + part] = acc[r];
+  }
+}
+
+// FP64 lines take the matrix-core form where it applies.
+template <typename T>
+__device__ __forceinline__ void z_extend(cpx<T>* X, const double* __restrict__ M, int nz, int C,
+                                         int d, int tid) {
+  if constexpr (sizeof(T) == sizeof(double)) {
+    if (z_extend_mfma_ok(C, d)) {
+      z_extend_mfma(X, M, nz, C, d, tid);
+      return;
+    }
+  }
+  z_extend_fma<T>(X, M, nz, C, d, tid);
 }
 
 __device__ __forceinline__ void pencil_k(const Geom& g, long long p, double& kx_o, double& ky_o,
