@@ -3,6 +3,11 @@
 Kernel-trace statistics (text):
     python profiles/make_summary.py trace <results.db> <out.txt> "<command>"
 
+MFMA use per kernel class from one counter run (SQ_INSTS_VALU_MFMA_F64,
+SQ_INSTS_VALU_MFMA_MOPS_F64, SQ_VALU_MFMA_BUSY_CYCLES, GRBM_GUI_ACTIVE;
+utilisation = busy cycles / (active cycles x SIMDs), FP64 MFMA peak 78.6 TF/s):
+    python profiles/make_summary.py mfma <counters.csv> <out.txt> <simds> "<command>"
+
 HBM traffic per launch from two counter runs (FETCH_SIZE, then WRITE_SIZE,
 both in KiB per dispatch), each scaled by what the same counter reads for the
 largest plain device copy in the run (a 1 GiB copy: it reads and writes
@@ -10,6 +15,7 @@ exactly 1 GiB), one JSON file per kernel class:
     python profiles/make_summary.py pmc <fetch.csv> <write.csv> <workload> \\
         <kernel source hash> "<fetch command>" "<write command>"
 """
+import collections
 import csv
 import json
 import os
@@ -76,10 +82,38 @@ def pmc(fetch_csv, write_csv, workload, src_hash, cmd_fetch, cmd_write):
             fh.write("\n")
 
 
+def mfma(path, out, simds, cmd):
+    simds = int(simds)
+    rows = collections.defaultdict(lambda: collections.defaultdict(list))
+    for r in csv.DictReader(open(path)):
+        name = r["Kernel_Name"].replace("void ", "")
+        cls = next((c for pre, c in CLASSES.items() if name.startswith(pre)), None)
+        if cls is None:
+            continue
+        rows[(cls, int(r["Grid_Size"]))][r["Counter_Name"]].append(float(r["Counter_Value"]))
+    with open(out, "w") as fh:
+        fh.write(f"# rocprofv3 --pmc MFMA summary (FC extension on the matrix cores)\n# command: {cmd}\n")
+        fh.write("# class | dispatches | MFMA F64 insts / dispatch | MFMA FP64 flop / dispatch | "
+                 "MFMA busy %  (median over the dispatches of the largest grid)\n")
+        best = {}
+        for (cls, grid), d in rows.items():
+            if cls not in best or grid > best[cls][0]:
+                best[cls] = (grid, d)
+        for cls, (grid, d) in sorted(best.items()):
+            med = {k: statistics.median(v) for k, v in d.items()}
+            n = len(next(iter(d.values())))
+            flop = med.get("SQ_INSTS_VALU_MFMA_MOPS_F64", 0.0) * 512
+            util = 100.0 * med.get("SQ_VALU_MFMA_BUSY_CYCLES", 0.0) / max(
+                med.get("GRBM_GUI_ACTIVE", 1.0) * simds, 1.0)
+            fh.write(f"{cls} | {n} | {med.get('SQ_INSTS_VALU_MFMA_F64', 0):.0f} | {flop:.3e} | {util:.3f}\n")
+
+
 if __name__ == "__main__":
     if sys.argv[1] == "trace":
         trace(*sys.argv[2:5])
     elif sys.argv[1] == "pmc":
         pmc(*sys.argv[2:8])
+    elif sys.argv[1] == "mfma":
+        mfma(*sys.argv[2:6])
     else:
         raise SystemExit(__doc__)
