@@ -270,9 +270,21 @@ __global__ __launch_bounds__(ZNT) void k_z_back(ZArgs a, const cpx<double>* __re
     __syncthreads();
     const cpx<T>* R = fft_run<T, ZPB, ZNT, false, FP>(L.X0, L.X1, ZPB, 1, a.pl, L.tw, tid);
     cpx<T>* __restrict__ out = pass ? dzdst : dst;
-    if (pv)
-      for (int z = lt; z < g.nz; z += ZLS)
-        out[(long long)z * g.npen + p] = conj(R[z * ZPB + pb]) * (T)inv;
+    if (pv) {
+      if constexpr (!FP::dynamic) {
+        // compiled plans: LDS reads first (rows up to N' - 1 are in the
+        // buffer), then the stores
+        cpx<T> ov[OWN];
+#pragma unroll
+        for (int r = 0; r < OWN; ++r) ov[r] = R[min(lt + r * ZLS, npr - 1) * ZPB + pb];
+#pragma unroll
+        for (int r = 0; r < OWN; ++r)
+          if (lt + r * ZLS < g.nz) out[(long long)(lt + r * ZLS) * g.npen + p] = conj(ov[r]) * (T)inv;
+      } else {
+        for (int z = lt; z < g.nz; z += ZLS)
+          out[(long long)z * g.npen + p] = conj(R[z * ZPB + pb]) * (T)inv;
+      }
+    }
     __syncthreads();
   }
 }
@@ -406,9 +418,22 @@ __global__ __launch_bounds__(ZNT) void k_z_stageA(ZArgs a, StageAArgs s) {
   z_extend<T>(L.X0, L.M, g.nz, g.C, g.d, tid);
   __syncthreads();
   R = fft_run<T, ZPB, ZNT, false, FP>(L.X0, L.X1, ZPB, 1, a.pl, L.tw, tid);
+  // compiled plans: all of this thread's LDS reads first, then the stores
+  // (the rolled loop waits for each read in turn; it measured faster on the
+  // small run-time-plan grids)
   cpx<double>* __restrict__ out = s.out[f];
-  if (pv)
-    for (int l = lt; l < npr; l += ZLS) out[(long long)l * g.npen + p] = cvt<double>(R[l * ZPB + pb]);
+  if (pv) {
+    if constexpr (!FP::dynamic) {
+      cpx<double> ov[OWN];
+#pragma unroll
+      for (int r = 0; r < OWN; ++r) ov[r] = cvt<double>(R[min(lt + r * ZLS, npr - 1) * ZPB + pb]);
+#pragma unroll
+      for (int r = 0; r < OWN; ++r)
+        if (lt + r * ZLS < npr) out[(long long)(lt + r * ZLS) * g.npen + p] = ov[r];
+    } else {
+      for (int l = lt; l < npr; l += ZLS) out[(long long)l * g.npen + p] = cvt<double>(R[l * ZPB + pb]);
+    }
+  }
 }
 
 // ---------------------------------------------------------------- stage B
