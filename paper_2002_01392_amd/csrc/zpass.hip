@@ -6,9 +6,10 @@
 // [nz][ny][nkxp], continued spectral (kx, ky, kz) fields are [N'][ny][nkxp],
 // with the kx row padded to nkxp (a multiple of 4, so that 4-line tiles of
 // the y pass are 64-byte aligned).  A pencil is one (kx, ky) pair,
-// p = ky * nkxp + kx; slots with kx >= nkx are padding and never touched.  A workgroup owns ZPB consecutive pencils
-// and stages their lines in LDS as X[l * ZPB + pb] (pencil index fastest), so
-// every global row access is ZPB consecutive complex values.
+// p = ky * nkxp + kx; slots with kx >= nkx are padding and never touched.  A
+// workgroup owns ZPB consecutive pencils and stages their lines in LDS as
+// X[l * ZPB + pb] (pencil index fastest), so every global row access is ZPB
+// consecutive complex values.
 //
 // Inverse transforms use IFFT(y) = conj(FFT(conj(y))) / N' with the
 // conjugations folded into the surrounding loads and stores.
