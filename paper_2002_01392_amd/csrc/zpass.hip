@@ -297,7 +297,7 @@ __global__ __launch_bounds__(ZNT) void k_z_back(ZArgs a, const cpx<double>* __re
 //   N = sigma F_z(NL);  S = V^t + c (N - diff |k|^2 W);  v* = B_z S, plus the
 //   body force / buoyancy at the physical points, then the wall injection
 //   v*_par = c grad_par p_prev (theta = 0) and V* = F_z v*.
-template <typename T, typename TM, class FP, int OWN>
+template <typename T, typename TM, class FP, int OWN, bool WV>
 __global__ __launch_bounds__(ZNT) void k_z_stageA(ZArgs a, StageAArgs s) {
   extern __shared__ __align__(16) char smem[];
   const int tid = threadIdx.x;
@@ -336,6 +336,7 @@ __global__ __launch_bounds__(ZNT) void k_z_stageA(ZArgs a, StageAArgs s) {
   // keep these loads ahead of the ones below (loads complete in order, so a
   // later one issued first would hold up the LDS writes of these rows)
   __builtin_amdgcn_sched_barrier(0);
+  // (WV: W is V^t itself, as at the first RK stage; it is not loaded twice)
   cpx<double> vtr[OWN], wr[OWN];
   double sgr[OWN];
 #pragma unroll
@@ -343,7 +344,7 @@ __global__ __launch_bounds__(ZNT) void k_z_stageA(ZArgs a, StageAArgs s) {
     const int l = min(lt + r * ZLS, npr - 1);  // rows past N' are never used
     const long long gi = (long long)l * g.npen + pc;
     vtr[r] = vt[gi];
-    wr[r] = w[gi];
+    if constexpr (!WV) wr[r] = w[gi];
     sgr[r] = a.sigz[l];
   }
   // (rows z >= nz store zero to a continuation row, rewritten by the
@@ -372,7 +373,7 @@ __global__ __launch_bounds__(ZNT) void k_z_stageA(ZArgs a, StageAArgs s) {
         const double kzt = k_true(l, npr, g.kzs);
         const double k2 = kh2 + kzt * kzt;
         const double sig = sgr[r] * sxy;
-        S = vtr[r] + (cvt<double>(R[e]) * sig - wr[r] * (diff * k2)) * c;
+        S = vtr[r] + (cvt<double>(R[e]) * sig - (WV ? vtr[r] : wr[r]) * (diff * k2)) * c;
       }
       L.X0[e] = cvt<T>(conj(S));
     }
@@ -784,13 +785,18 @@ void launch_z_stageA(const ZArgs& a, bool big, const StageAArgs& s, int nfields,
   const size_t sh = zshared_bytes<T>(a.g, a.pl.tsize);
   const int own = pick_own(a.g.npr);
   if (z_static_288(a)) {
-    FCNS_LAUNCH((k_z_stageA<T, TM, P288, 9>), grid, dim3(ZNT), sh, st, a, s);
+    bool wv = true;  // W is V^t for every field (the first RK stage)
+    for (int f = 0; f < nfields; ++f) wv = wv && s.w[f] == s.vt[f];
+    if (wv)
+      FCNS_LAUNCH((k_z_stageA<T, TM, P288, 9, true>), grid, dim3(ZNT), sh, st, a, s);
+    else
+      FCNS_LAUNCH((k_z_stageA<T, TM, P288, 9, false>), grid, dim3(ZNT), sh, st, a, s);
   } else if (big) {
-    FCNS_OWN_SWITCH(own, FCNS_LAUNCH((k_z_stageA<T, TM, DynPlan<true>, OWN>), grid, dim3(ZNT), sh,
-                                     st, a, s))
-  } else {
-    FCNS_OWN_SWITCH(own, FCNS_LAUNCH((k_z_stageA<T, TM, DynPlan<false>, OWN>), grid, dim3(ZNT),
+    FCNS_OWN_SWITCH(own, FCNS_LAUNCH((k_z_stageA<T, TM, DynPlan<true>, OWN, false>), grid, dim3(ZNT),
                                      sh, st, a, s))
+  } else {
+    FCNS_OWN_SWITCH(own, FCNS_LAUNCH((k_z_stageA<T, TM, DynPlan<false>, OWN, false>), grid,
+                                     dim3(ZNT), sh, st, a, s))
   }
 }
 template void launch_z_stageA<double>(const ZArgs&, bool, const StageAArgs&, int, hipStream_t);
