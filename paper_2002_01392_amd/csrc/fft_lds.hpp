@@ -305,10 +305,69 @@ __device__ __forceinline__ void fft_stage(const cpx<T>* __restrict__ src, cpx<T>
 // Any odd prime R > 7 at run time, spread over the workgroup: a line of n
 // points has only n / R butterflies of this radix, too few to occupy the
 // threads, and one whole R-point DFT per thread would not fit in registers.
-// Phase 1 twiddles the inputs in place (one thread per butterfly input),
-// phase 2 gives each thread one output pair (X_k, X_{R-k}) (or X_0) of one
-// butterfly, read from LDS with the butterfly index fastest across lanes and
-// the root index wave-uniform.
+// Phase 1 twiddles the inputs in place (one thread per butterfly input);
+// phase 2 gives each work item PG consecutive output pairs (X_k, X_{R-k}) of
+// one butterfly (the first group also X_0), so that each input is read from
+// LDS once per PG pairs.  The butterfly index is fastest across lanes, so the
+// roots cw[q k mod R] are read at wave-uniform addresses.  PG = 6 where the
+// stage has enough butterflies to keep half the workgroup busy, else one
+// pair per item (small lines, e.g. 58 = 2 x 29, would otherwise idle most
+// threads).
+template <typename T, bool PAD, int PG>
+__device__ __forceinline__ void prime_outputs(const cpx<T>* __restrict__ src,
+                                              cpx<T>* __restrict__ dst, int R, int L, int es,
+                                              int ls, int nr, int ns, float rcp,
+                                              const cpx<T>* __restrict__ cw, int tid, int nt) {
+  const int nb = L * nr;
+  const int H = (R - 1) / 2;
+  const int ngrp = (H + PG - 1) / PG;
+  for (int g = tid; g < nb * (ngrp + (PG == 1 ? 1 : 0)); g += nt) {
+    const int b = g % nb, grp = g / nb;
+    const int l = b % L, j = b / L;
+    const int k = fast_mod(j, ns, rcp);
+    auto S = [&](int m) -> const cpx<T>& { return src[lds_pos<PAD>(l, j + m * nr, es, ls)]; };
+    const int o = (j - k) * R + k;
+    auto D = [&](int m) -> cpx<T>& { return dst[lds_pos<PAD>(l, o + m * ns, es, ls)]; };
+    // PG = 1: item 0 of a butterfly is X_0 alone, item kk the pair kk
+    const int k0 = (PG == 1) ? grp : 1 + grp * PG;
+    const bool dc = (PG == 1) ? grp == 0 : grp == 0;
+    const cpx<T> x0 = S(0);
+    cpx<T> sum = x0, re[PG], im[PG];
+    int qk[PG];
+#pragma unroll
+    for (int i = 0; i < PG; ++i) {
+      re[i] = x0;
+      im[i] = zero<T>();
+      qk[i] = 0;
+    }
+    for (int q = 1; q <= H; ++q) {
+      const cpx<T> xa = S(q), xb = S(R - q);
+      const cpx<T> ps = xa + xb, ms = xa - xb;
+      sum = sum + ps;
+      if (PG == 1 && k0 == 0) continue;
+#pragma unroll
+      for (int i = 0; i < PG; ++i) {
+        qk[i] += k0 + i;
+        if (qk[i] >= R) qk[i] -= R;
+        const cpx<T> w = cw[qk[i]];
+        re[i] = re[i] + ps * w.x;
+        im[i] = im[i] + ms * (-w.y);
+      }
+    }
+    if (dc) D(0) = sum;
+#pragma unroll
+    for (int i = 0; i < PG; ++i) {
+      const int kk = k0 + i;
+      if (kk >= 1 && kk <= H) {
+        D(kk) = re[i] + mul_mi(im[i]);
+        D(R - kk) = re[i] + mul_i(im[i]);
+      }
+    }
+  }
+}
+
+constexpr int PRIME_PG = 6;
+
 template <typename T, bool PAD>
 __device__ __forceinline__ void fft_stage_prime(cpx<T>* __restrict__ src, cpx<T>* __restrict__ dst,
                                                 int R, int L, int es, int ls, int n, int ns,
@@ -316,7 +375,6 @@ __device__ __forceinline__ void fft_stage_prime(cpx<T>* __restrict__ src, cpx<T>
                                                 const cpx<T>* __restrict__ cw, int tid, int nt) {
   const int nr = n / R;
   const int nb = L * nr;
-  const int H = (R - 1) / 2;
   const float rcp = 1.0f / (float)ns;
   if (ns > 1) {
     for (int g = tid; g < nb * (R - 1); g += nt) {
@@ -328,33 +386,11 @@ __device__ __forceinline__ void fft_stage_prime(cpx<T>* __restrict__ src, cpx<T>
     }
     __syncthreads();
   }
-  for (int g = tid; g < nb * (H + 1); g += nt) {
-    const int b = g % nb, kk = g / nb;
-    const int l = b % L, j = b / L;
-    const int k = fast_mod(j, ns, rcp);
-    auto S = [&](int m) -> const cpx<T>& { return src[lds_pos<PAD>(l, j + m * nr, es, ls)]; };
-    const int o = (j - k) * R + k;
-    auto D = [&](int m) -> cpx<T>& { return dst[lds_pos<PAD>(l, o + m * ns, es, ls)]; };
-    const cpx<T> x0 = S(0);
-    if (kk == 0) {
-      cpx<T> sum = x0;
-      for (int q = 1; q <= H; ++q) sum = sum + S(q) + S(R - q);
-      D(0) = sum;
-    } else {
-      cpx<T> re = x0, im = zero<T>();
-      int qk = 0;
-      for (int q = 1; q <= H; ++q) {
-        qk += kk;
-        if (qk >= R) qk -= R;
-        const cpx<T> w = cw[qk];
-        const cpx<T> xa = S(q), xb = S(R - q);
-        re = re + (xa + xb) * w.x;
-        im = im + (xa - xb) * (-w.y);
-      }
-      D(kk) = re + mul_mi(im);
-      D(R - kk) = re + mul_i(im);
-    }
-  }
+  const int H = (R - 1) / 2;
+  if (2 * nb * ((H + PRIME_PG - 1) / PRIME_PG) >= nt)
+    prime_outputs<T, PAD, PRIME_PG>(src, dst, R, L, es, ls, nr, ns, rcp, cw, tid, nt);
+  else
+    prime_outputs<T, PAD, 1>(src, dst, R, L, es, ls, nr, ns, rcp, cw, tid, nt);
 }
 
 // ---------------------------------------------------------------- driver
