@@ -56,8 +56,10 @@ struct fcns_ctx {
   double graph_dt = 0.0;
   // autotuned launch choices (fcns_autotune)
   int xvar = 0;
-  long long ygrid = 0;
+  long long ygrid = 0;   // y launches of one transform per tile
   int ynopf = 0;
+  long long ygrid1 = 0;  // y back with d/dy (two transforms per tile)
+  int ynopf1 = 0;
   bool has_state = false;
   bool has_pressure = false;
   std::string err;
@@ -255,7 +257,7 @@ static ZArgs zargs(const fcns_ctx* c, bool f32 = false) {
   a.sigz = c->sigz;
   return a;
 }
-static YArgs yargs(const fcns_ctx* c, bool f32 = false) {
+static YArgs yargs(const fcns_ctx* c, bool f32 = false, bool dy = false) {
   YArgs a;
   a.ny = c->g.ny;
   a.nkx = c->g.nkx;
@@ -263,8 +265,8 @@ static YArgs yargs(const fcns_ctx* c, bool f32 = false) {
   a.kys = c->g.kys;
   a.pl = c->ply;
   a.tw = f32 ? (const void*)c->twy_f : (const void*)c->twy;
-  a.grid = c->ygrid;
-  a.noprefetch = c->ynopf;
+  a.grid = dy ? c->ygrid1 : c->ygrid;
+  a.noprefetch = dy ? c->ynopf1 : c->ynopf;
   return a;
 }
 static XArgs xargs(const fcns_ctx* c, bool f32 = false) {
@@ -489,7 +491,7 @@ static void nonlinear_from_mixed(fcns_ctx* c, const cpx<T>* mv, int nfields, boo
   cpx<T>* xyb = reinterpret_cast<cpx<T>*>(c->XYB);
   cpx<T>* nlb = reinterpret_cast<cpx<T>*>(c->NLB);
   tbeg(c, T_YBACK_DY);
-  launch_y<T>(yargs(c, f32), c->big_y, true, 1, mv, xyb, xyb + M, 2 * M, 3 * M, g.nz, nfields,
+  launch_y<T>(yargs(c, f32, true), c->big_y, true, 1, mv, xyb, xyb + M, 2 * M, 3 * M, g.nz, nfields,
               c->stream);
   tend(c);
   tbeg(c, T_YBACK_DZ);
@@ -760,40 +762,59 @@ extern "C" fcns_status fcns_autotune(fcns_ctx* c, char* report, int32_t report_l
   const bool f32 = c->mixed;
   std::string rep;
   char line[256];
-  // y pass: persistent grid size, timed on the three y passes of a stage
-  // (back with d/dy, back of dv/dz, forward of NL) on the state's fields
+  // y pass: persistent grid size and prefetch, chosen separately for the back
+  // transform with d/dy (two transforms per tile) and for the two launches of
+  // one transform per tile (back of dv/dz, forward of NL), on the state's
+  // fields
   {
-    float best = 1e30f;
-    long long bg = Y_GRID;
-    auto ypasses = [&](auto* mv, auto* xy, auto* nlb, bool f) {
-      launch_y(yargs(c, f), c->big_y, true, 1, mv, xy, xy + M, 2 * M, 3 * M, g.nz, nf, c->stream);
+    auto pass_dy = [&](auto* mv, auto* xy, bool f) {
+      launch_y(yargs(c, f, true), c->big_y, true, 1, mv, xy, xy + M, 2 * M, 3 * M, g.nz, nf,
+               c->stream);
+    };
+    auto pass_one = [&](auto* mv, auto* xy, auto* nlb, bool f) {
       launch_y(yargs(c, f), c->big_y, true, 0, mv + M, xy + 2 * M, decltype(xy)(nullptr), 2 * M,
                3 * M, g.nz, nf, c->stream);
       launch_y(yargs(c, f), c->big_y, false, 0, nlb, nlb, decltype(xy)(nullptr), M, M, g.nz, nf,
                c->stream);
     };
-    int bpf = 0;
+    float best1 = 1e30f, best0 = 1e30f;
+    long long bg1 = Y_GRID, bg0 = Y_GRID;
+    int bpf1 = 0, bpf0 = 0;
     for (int nopf : {0, 1})
       for (long long gsz : {256LL, 512LL, 1024LL, 2048LL, 4096LL}) {
-        c->ygrid = gsz;
-        c->ynopf = nopf;
-        const float ms = time_ms(c, [&] {
+        c->ygrid = c->ygrid1 = gsz;
+        c->ynopf = c->ynopf1 = nopf;
+        const float ms1 = time_ms(c, [&] {
           if (f32)
-            ypasses(reinterpret_cast<cpx<float>*>(c->MV), reinterpret_cast<cpx<float>*>(c->XYB),
-                    reinterpret_cast<cpx<float>*>(c->NLB), true);
+            pass_dy(reinterpret_cast<cpx<float>*>(c->MV), reinterpret_cast<cpx<float>*>(c->XYB),
+                    true);
           else
-            ypasses(c->MV, c->XYB, c->NLB, false);
+            pass_dy(c->MV, c->XYB, false);
         }, reps);
-        if (ms < best) {
-          best = ms;
-          bg = gsz;
-          bpf = nopf;
+        const float ms0 = time_ms(c, [&] {
+          if (f32)
+            pass_one(reinterpret_cast<cpx<float>*>(c->MV), reinterpret_cast<cpx<float>*>(c->XYB),
+                     reinterpret_cast<cpx<float>*>(c->NLB), true);
+          else
+            pass_one(c->MV, c->XYB, c->NLB, false);
+        }, reps);
+        if (ms1 < best1) {
+          best1 = ms1;
+          bg1 = gsz;
+          bpf1 = nopf;
+        }
+        if (ms0 < best0) {
+          best0 = ms0;
+          bg0 = gsz;
+          bpf0 = nopf;
         }
       }
-    c->ygrid = bg;
-    c->ynopf = bpf;
-    snprintf(line, sizeof(line), "y: grid %lld%s (%.3f ms); ", bg, bpf ? " no-prefetch" : "",
-             best);
+    c->ygrid1 = bg1;
+    c->ynopf1 = bpf1;
+    c->ygrid = bg0;
+    c->ynopf = bpf0;
+    snprintf(line, sizeof(line), "y: grid %lld%s (%.3f ms), with d/dy %lld%s (%.3f ms); ", bg0,
+             bpf0 ? " no-prefetch" : "", best0, bg1, bpf1 ? " no-prefetch" : "", best1);
     rep += line;
   }
   // x pass with products: kernel variant (inputs: the y pass just run)

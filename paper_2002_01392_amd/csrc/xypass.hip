@@ -50,7 +50,19 @@ __global__ __launch_bounds__(YNT) void k_y(YArgs a, const cpx<T>* src, cpx<T>* d
   const T sc = inv ? T(1) / (T)ny : T(1);
   const int npass = (mode == 1) ? 2 : 1;
   cpx<T> cur[OWN], nxt[PF ? OWN : 1];
+  // XCD-aware tile order: workgroups are dispatched to the 8 XCDs in turn
+  // (workgroup b on XCD b % 8), and a tile is 4 kx columns, half of a
+  // 128-byte line, so neighbouring tiles share lines.  Each round of G tiles
+  // is cut into chunks of 64; in a chunk, XCD x takes the run of 8 tiles
+  // 8x .. 8x + 7, one per workgroup of that XCD, so that neighbours meet
+  // their shared lines in one L2 and a partial last round still spreads
+  // over all XCDs.
+  const long long G = gridDim.x;
   long long t = blockIdx.x;
+  if (G % 64 == 0) {
+    const int j = blockIdx.x / 8, x = blockIdx.x % 8;
+    t = (long long)(j / 8) * 64 + x * 8 + j % 8;
+  }
   auto line_base = [&](long long tt, bool& ok) {
     const long long q = tt * YL + l;
     const long long pl = q / nkxp, kx = q - pl * nkxp;
