@@ -453,8 +453,12 @@ __device__ __forceinline__ void wave_fft512(cpx<T> (&r)[8], cpx<T>* __restrict__
 // Real quantities in order: u, v, w, then per field dq/dx, dq/dy, dq/dz;
 // consecutive pairs share one inverse transform, and the forward transform of
 // a pair of finished fields follows as soon as both are complete.
+// The generic schedule (quantities in the order u, v, w, then dq/dx, dq/dy,
+// dq/dz per field, paired as they come; the value slots are read twice),
+// kept for three fields, where the one-read schedule below needs more
+// registers than two waves per SIMD allow.
 template <typename T, int NF>
-__global__ __launch_bounds__(64 * XW_WAVES) void k_x_nl512(XArgs a, const cpx<T>* __restrict__ xyb,
+__global__ __launch_bounds__(64 * XW_WAVES) void k_x_nl512_q(XArgs a, const cpx<T>* __restrict__ xyb,
                                                            cpx<T>* __restrict__ nl, long long fs,
                                                            long long nrows) {
   constexpr int N = 512, NQ = 3 + 3 * NF, NP = (NQ + 1) / 2;
@@ -560,6 +564,116 @@ __global__ __launch_bounds__(64 * XW_WAVES) void k_x_nl512(XArgs a, const cpx<T>
         }
       }
     }
+  }
+}
+
+template <typename T, int NF>
+__global__ __launch_bounds__(64 * XW_WAVES) void k_x_nl512(XArgs a, const cpx<T>* __restrict__ xyb,
+                                                           cpx<T>* __restrict__ nl, long long fs,
+                                                           long long nrows) {
+  // Four fields: pairs of real quantities per complex transform, each
+  // spectral slot read once: (u, du/dx), (v, dv/dx), (w, dw/dx) from one
+  // load each (the x derivative is i k~x times the same coefficients), then
+  // (dq_f/dy, dq_f/dz) for f = 0..2, and for theta (dq/dx, dq/dy), (dq/dz).
+  // NL_f = -(u dq_f/dx + v dq_f/dy + w dq_f/dz) accumulates in that order
+  // as soon as u is known; each pair of finished fields is transformed
+  // forward together.
+  static_assert(NF == 4, "three fields use k_x_nl512_q");
+  constexpr int N = 512, NP = 8;
+  __shared__ cpx<T> tw[XW_TW];
+  __shared__ cpx<T> xbuf[XW_WAVES][XW_BUF];
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);  // wave-uniform
+  for (int e = tid; e < XW_TW; e += 64 * XW_WAVES) {
+    const int reg = e / 64, t = e % 64, n0 = t & 7, hi = t >> 3;
+    const int j = reg < 7 ? 8 * hi * (reg + 1) : n0 * (hi + 8 * (reg - 7));  // power of w512
+    double sn, cs;
+    sincospi(2.0 * j / N, &sn, &cs);
+    tw[e] = mk((T)cs, (T)(-sn));   // exp(-2 pi i j / 512)
+  }
+  __syncthreads();
+  cpx<T>* buf = xbuf[wv];
+  const int nkxp = a.nkxp;
+  const T kxs = (T)a.kxs;
+  const T sc = T(1) / T(N);
+  // forward transform of two finished fields (fb < 0: one) and unpack
+  auto forward = [&](long long row, T (&fa_)[8], T (&fb_)[8], int fa, bool two) {
+    cpx<T> z[8];
+#pragma unroll
+    for (int m = 0; m < 8; ++m) z[m] = mk(fa_[m], two ? fb_[m] : T(0));
+    wave_fft512<T>(z, buf, tw, lane);
+    cpx<T>* wn = buf + xw_nat(lane);
+#pragma unroll
+    for (int m = 0; m < 8; ++m) wn[72 * m] = z[m];
+    wave_sync();
+#pragma unroll
+    for (int m = 0; m < 5; ++m) {
+      const int k = lane + 64 * m;
+      if (k <= N / 2) {
+        const cpx<T> Zk = wn[72 * m];
+        const cpx<T> Zm = conj(buf[xw_nat((N - k) & (N - 1))]);
+        nl[fa * fs + row * nkxp + k] = (Zk + Zm) * T(0.5);
+        if (two) nl[(fa + 1) * fs + row * nkxp + k] = mul_mi(Zk - Zm) * T(0.5);
+      }
+    }
+    wave_sync();
+  };
+  for (long long row = (long long)blockIdx.x * XW_WAVES + wv; row < nrows;
+       row += (long long)gridDim.x * XW_WAVES) {
+    T U[3][8];
+    T acc[NF][8];
+#pragma unroll
+    for (int p = 0; p < NP; ++p) {
+      // keep each pair's loads next to its transform (hoisting them all would
+      // multiply the live registers)
+      __builtin_amdgcn_sched_barrier(0);
+      // slot of A; B: the x derivative of A (p < 3), another slot, or none
+      const int slotA = p < 3 ? 3 * p : p < 6 ? 3 * (p - 3) + 1 : (p == 6 ? 9 : 11);
+      const bool dxA = p == 6;
+      const bool sameB = p < 3;
+      const bool hasB = p < 7;
+      const int slotB = p < 3 ? slotA : p < 6 ? 3 * (p - 3) + 2 : 10;
+      const cpx<T>* pa = xyb + slotA * fs + row * nkxp;
+      const cpx<T>* pb = xyb + slotB * fs + row * nkxp;
+      cpx<T> r[8];
+#pragma unroll
+      for (int m = 0; m < 8; ++m) {
+        const int k = lane + 64 * m;
+        const int kk = k <= N / 2 ? k : N - k;
+        const T kx = (kk == N / 2) ? T(0) : kxs * (T)kk;
+        cpx<T> A = pa[kk];
+        cpx<T> B = sameB ? mul_i(A) * kx : (hasB ? pb[kk] : zero<T>());
+        if (dxA) A = mul_i(A) * kx;
+        if (kk == 0 || kk == N / 2) {
+          A.y = T(0);
+          B.y = T(0);
+        }
+        // Z[k] = A + i B (k <= N/2), conj(A) + i conj(B) (k > N/2); inverse via conj
+        const cpx<T> Z = (k <= N / 2) ? mk(A.x - B.y, A.y + B.x) : mk(A.x + B.y, B.x - A.y);
+        r[m] = conj(Z);
+      }
+      wave_fft512<T>(r, buf, tw, lane);
+#pragma unroll
+      for (int m = 0; m < 8; ++m) {
+        const T va = r[m].x * sc, vb = -r[m].y * sc;
+        if (p < 3) {
+          U[p][m] = va;
+          acc[p][m] = -U[0][m] * vb;        // -u dq_p/dx (U[0] set by pair 0)
+        } else if (p < 6) {
+          acc[p - 3][m] -= U[1][m] * va;    // -v dq/dy
+          acc[p - 3][m] -= U[2][m] * vb;    // -w dq/dz
+        } else if (p == 6) {
+          acc[3][m] = -U[0][m] * va;
+          acc[3][m] -= U[1][m] * vb;
+        } else {
+          acc[3][m] -= U[2][m] * va;
+        }
+      }
+      if (p == 4) forward(row, acc[0], acc[1], 0, true);
+      if (p == 7) forward(row, acc[2], acc[3], 2, true);
+    }
+    // (the next row's loads stay behind this row's last transform)
+    __builtin_amdgcn_sched_barrier(0);
   }
 }
 
@@ -676,7 +790,7 @@ void launch_x_nl(const XArgs& a, bool big, const cpx<T>* xyb, cpx<T>* nl, long l
       hipLaunchKernelGGL((k_x_nl512<T, 4>), grid, dim3(64 * XW_WAVES), 0, st, a, xyb, nl, fs,
                          nrows);
     else
-      hipLaunchKernelGGL((k_x_nl512<T, 3>), grid, dim3(64 * XW_WAVES), 0, st, a, xyb, nl, fs,
+      hipLaunchKernelGGL((k_x_nl512_q<T, 3>), grid, dim3(64 * XW_WAVES), 0, st, a, xyb, nl, fs,
                          nrows);
   } else if (a.nx == 512 && plan_is(a.pl, {8, 8, 8}))
     launch_x_nl_v<T, SPlan<8, 8, 8>, 4, 256, 2>(a, xyb, nl, fs, nrows, nfields, st);

@@ -27,7 +27,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 
 # kernel name prefix -> timing class of the library (the y kernel serves three
 # classes of equal traffic pattern; it is reported as one)
-CLASSES = {"fcns::k_x_nl<": "x_nl", "fcns::k_x_nl512<": "x_nl", "fcns::k_z_stageA<": "z_stageA",
+CLASSES = {"fcns::k_x_nl<": "x_nl", "fcns::k_x_nl512<": "x_nl", "fcns::k_x_nl512_q<": "x_nl", "fcns::k_z_stageA<": "z_stageA",
            "fcns::k_z_stageB<": "z_stageB", "fcns::k_z_back<": "z_back", "fcns::k_y<": "y"}
 COPY_BYTES = 1 << 30
 
@@ -65,12 +65,14 @@ def pmc(fetch_csv, write_csv, workload, src_hash, cmd_fetch, cmd_write):
         if not fr or not wr:
             continue
         # the dispatches of the largest grid (the workload's own launches), and
-        # among them the median
+        # among them the mean (launches of one class may differ, e.g. the first
+        # RK stage reads one state array less; the roofline's rate is a mean
+        # over launches too)
         gmax = max(g for g, _ in fr)
         fv = [v for g, v in fr if g == gmax]
         wv = [v for g, v in wr if g == gmax]
-        fb = statistics.median(fv) * 1024.0 * kf
-        wb = statistics.median(wv) * 1024.0 * kw
+        fb = statistics.mean(fv) * 1024.0 * kf
+        wb = statistics.mean(wv) * 1024.0 * kw
         rec = {"kernel_class": cls, "workload": workload, "source_hash": src_hash,
                "hbm_bytes_per_launch": int(fb + wb), "read_bytes": int(fb),
                "write_bytes": int(wb), "dispatches": len(fv),
