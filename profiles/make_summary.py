@@ -52,6 +52,18 @@ def _per_dispatch(path, counter):
     return out
 
 
+def _per_launch(rows):
+    """Median per kernel name (template variants of a class differ, e.g. the
+    first RK stage's stage A reads one state array less; a median keeps
+    the odd dispatch outside the step out), then the mean over the names
+    weighted by their dispatches."""
+    by = collections.defaultdict(list)
+    for n, v in rows:
+        by[n].append(v)
+    tot = sum(len(v) for v in by.values())
+    return sum(statistics.median(v) * len(v) for v in by.values()) / tot
+
+
 def pmc(fetch_csv, write_csv, workload, src_hash, cmd_fetch, cmd_write):
     fetch = _per_dispatch(fetch_csv, "FETCH_SIZE")
     write = _per_dispatch(write_csv, "WRITE_SIZE")
@@ -60,19 +72,17 @@ def pmc(fetch_csv, write_csv, workload, src_hash, cmd_fetch, cmd_write):
     kf = COPY_BYTES / (cf * 1024.0)
     kw = COPY_BYTES / (cw * 1024.0)
     for prefix, cls in CLASSES.items():
-        fr = [(g, v) for n, g, v in fetch if n.replace("void ", "").startswith(prefix)]
-        wr = [(g, v) for n, g, v in write if n.replace("void ", "").startswith(prefix)]
+        fr = [(n, g, v) for n, g, v in fetch if n.replace("void ", "").startswith(prefix)]
+        wr = [(n, g, v) for n, g, v in write if n.replace("void ", "").startswith(prefix)]
         if not fr or not wr:
             continue
-        # the dispatches of the largest grid (the workload's own launches), and
-        # among them the mean (launches of one class may differ, e.g. the first
-        # RK stage reads one state array less; the roofline's rate is a mean
-        # over launches too)
-        gmax = max(g for g, _ in fr)
-        fv = [v for g, v in fr if g == gmax]
-        wv = [v for g, v in wr if g == gmax]
-        fb = statistics.mean(fv) * 1024.0 * kf
-        wb = statistics.mean(wv) * 1024.0 * kw
+        # the dispatches of the largest grid (the workload's own launches),
+        # per launch as in _per_launch
+        gmax = max(g for _, g, _ in fr)
+        fv = [(n, v) for n, g, v in fr if g == gmax]
+        wv = [(n, v) for n, g, v in wr if g == gmax]
+        fb = _per_launch(fv) * 1024.0 * kf
+        wb = _per_launch(wv) * 1024.0 * kw
         rec = {"kernel_class": cls, "workload": workload, "source_hash": src_hash,
                "hbm_bytes_per_launch": int(fb + wb), "read_bytes": int(fb),
                "write_bytes": int(wb), "dispatches": len(fv),
