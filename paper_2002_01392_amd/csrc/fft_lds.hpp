@@ -309,7 +309,7 @@ __device__ __forceinline__ void fft_stage(const cpx<T>* __restrict__ src, cpx<T>
 // phase 2 gives each work item PG consecutive output pairs (X_k, X_{R-k}) of
 // one butterfly (the first group also X_0), so that each input is read from
 // LDS once per PG pairs.  The butterfly index is fastest across lanes, so the
-// roots cw[q k mod R] are read at wave-uniform addresses.  PG = 6 where the
+// roots cw[q k mod R] are read at wave-uniform addresses.  PG = 5 where the
 // stage has enough butterflies to keep half the workgroup busy, else one
 // pair per item (small lines, e.g. 58 = 2 x 29, would otherwise idle most
 // threads).
@@ -366,7 +366,7 @@ __device__ __forceinline__ void prime_outputs(const cpx<T>* __restrict__ src,
   }
 }
 
-constexpr int PRIME_PG = 6;
+constexpr int PRIME_PG = 5;
 
 template <typename T, bool PAD>
 __device__ __forceinline__ void fft_stage_prime(cpx<T>* __restrict__ src, cpx<T>* __restrict__ dst,
