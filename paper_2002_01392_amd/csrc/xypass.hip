@@ -386,21 +386,30 @@ __global__ __launch_bounds__(NT) void k_x_nl(XArgs a, const cpx<T>* __restrict__
   }
 }
 
-// ---------------------------------------------------------------- x pass, 512-point rows
-// One wavefront per row (y, z), 8 points per lane: lane t holds index
-// t + 64 m (m = 0..7) of every transform, in and out.  The 512-point DFT is
-// split as n = n0 + 8 n1 + 64 n2, k = k0 + 8 k1 + 64 k2 (n0 + 8 n1 = t):
+// ---------------------------------------------------------------- x pass, wave-level rows
+// Rows of N = 512 or 256 points with 8 points per lane: a row occupies
+// S = N / 8 lanes (one row per wavefront at 512, two at 256), and lane t of a
+// row (t < S) holds index t + S m (m = 0..7) of every transform, in and out.
+//
+// N = 512 = 8 x 8 x 8: n = n0 + 8 n1 + 64 n2, k = k0 + 8 k1 + 64 k2 (t = n0 + 8 n1):
 //   a radix-8 DFT over n2 in registers, twiddle w64^(n1 k0);
 //   exchange so that lane n0 + 8 k0 holds n1 = 0..7, radix-8 over n1,
 //   twiddle w512^(n0 (k0 + 8 k1));
 //   exchange so that lane k0 + 8 k1 holds n0 = 0..7, radix-8 over n0,
-// which leaves X[t + 64 k2] in lane t.  The exchanges go through a padded
-// per-wave LDS buffer (conflict-free 16-byte accesses) and need only
-// wave-level ordering, no workgroup barrier.  Two real transforms share one
-// complex transform: z = a + i b (inverse from the spectra A, B; forward of two
-// nonlinear terms).
-constexpr int XW_WAVES = 4;        // waves (rows in flight) per workgroup
-constexpr int XW_BUF = 512 + 64;   // padded slots of one wave's exchange buffer
+// which leaves X[t + 64 k2] in lane t.
+// N = 256 = 8 x 32: n = t + 32 m, k = a + 8 b:
+//   a radix-8 DFT over m in registers, twiddle w256^(t a);
+//   the eight 32-point DFTs over t = t0 + 4 t1 (b = j1 + 8 j0): exchange so
+//   that lane t0 + 4 a holds t1 = 0..7, radix-8 over t1, twiddle w32^(t0 j1);
+//   exchange so that lane L holds t0 = 0..3 of c = a + 8 j1 = L and L + 32,
+//   two radix-4 DFTs over t0,
+// which leaves X[c + 64 j0] = X[L + 32 (h + 2 j0)] (c = L + 32 h) in lane L.
+// The exchanges go through a padded per-row LDS buffer (conflict-free
+// 16-byte accesses) and need only wave-level ordering, no workgroup barrier.
+// Two real transforms share one complex transform: z = a + i b (inverse from
+// the spectra A, B; forward of two nonlinear terms).
+constexpr int XW_WAVES = 4;        // waves per workgroup
+constexpr int XW_BUF = 512 + 64;   // padded slots of one wave's exchange buffer(s)
 
 __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -408,17 +417,37 @@ __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// Padded slots (one spare slot per 64 in exchange 1, per 8 in exchange 2 and
-// in the natural-order buffer): element 64 n0 + 8 k0 + n1 of exchange 1 sits
-// at 65 n0 + 8 k0 + n1, element 8 j + n0 of exchange 2 at 9 j + n0, element i
-// of the natural-order buffer at i + i / 8.  Written with the per-lane part
-// separate so that the per-register part is an instruction offset.
+// Padded slots, written with the per-lane part separate so that the
+// per-register part is an instruction offset.  N = 512: element
+// 64 n0 + 8 k0 + n1 of exchange 1 sits at 65 n0 + 8 k0 + n1, element
+// 8 j + n0 of exchange 2 at 9 j + n0.  N = 256: element (a, t) of exchange 1
+// at 36 a + t, element (c, t0) of exchange 2 at 4 c + c / 4 + t0.  Both: element
+// i of the natural-order buffer at i + i / 8.
 __device__ __forceinline__ int xw_nat(int i) { return i + (i >> 3); }
 
-// Per-lane twiddles, stored [register][lane] in LDS (read at lane + offset):
-// tw[k0 - 1][t] = w64^(n1 k0) (k0 = 1..7), tw[7 + k1][t] = w512^(n0 (k0' + 8 k1))
-// with t = n0 + 8 n1 before exchange 1 and t = n0 + 8 k0' after it.
+// Per-lane twiddles, stored [register][t] in LDS (read at t + offset).
+// N = 512: tw[k0 - 1][t] = w64^(n1 k0) (k0 = 1..7) with t = n0 + 8 n1, and
+// tw[7 + k1][t] = w512^(n0 (k0' + 8 k1)) with t = n0 + 8 k0'.
+// N = 256: tw[a - 1][t] = w256^(t a) (a = 1..7), tw[6 + j1][t] = w32^(t0 j1)
+// (j1 = 1..7) with t = t0 + 4 a.
 constexpr int XW_TW = 15 * 64;
+
+template <typename T, int N>
+__device__ __forceinline__ void xw_twiddles(cpx<T>* tw, int tid) {
+  constexpr int S = N / 8, NTW = (N == 512 ? 15 : 14) * S;
+  static_assert(NTW <= XW_TW, "twiddle table");
+  for (int e = tid; e < NTW; e += 64 * XW_WAVES) {
+    const int reg = e / S, t = e % S;
+    int j;  // power of wN
+    if (N == 512)
+      j = reg < 7 ? 8 * (t >> 3) * (reg + 1) : (t & 7) * ((t >> 3) + 8 * (reg - 7));
+    else
+      j = reg < 7 ? t * (reg + 1) : 8 * (t & 3) * (reg - 6);
+    double sn, cs;
+    sincospi(2.0 * j / N, &sn, &cs);
+    tw[e] = mk((T)cs, (T)(-sn));   // exp(-2 pi i j / N)
+  }
+}
 
 template <typename T>
 __device__ __forceinline__ void wave_fft512(cpx<T> (&r)[8], cpx<T>* __restrict__ buf,
@@ -449,37 +478,109 @@ __device__ __forceinline__ void wave_fft512(cpx<T> (&r)[8], cpx<T>* __restrict__
   Codelet<T, 8>::run(r, nullptr);
 }
 
-// NL_f = -(u dq_f/dx + v dq_f/dy + w dq_f/dz) on rows of nx = 512 points.
-// Real quantities in order: u, v, w, then per field dq/dx, dq/dy, dq/dz;
-// consecutive pairs share one inverse transform, and the forward transform of
-// a pair of finished fields follows as soon as both are complete.
-// The generic schedule (quantities in the order u, v, w, then dq/dx, dq/dy,
-// dq/dz per field, paired as they come; the value slots are read twice),
-// kept for three fields, where the one-read schedule below needs more
-// registers than two waves per SIMD allow.
-template <typename T, int NF>
-__global__ __launch_bounds__(64 * XW_WAVES) void k_x_nl512_q(XArgs a, const cpx<T>* __restrict__ xyb,
+template <typename T>
+__device__ __forceinline__ void wave_fft256(cpx<T> (&r)[8], cpx<T>* __restrict__ buf,
+                                            const cpx<T>* __restrict__ tw, int t) {
+  Codelet<T, 8>::run(r, nullptr);
+#pragma unroll
+  for (int a = 1; a < 8; ++a) r[a] = r[a] * tw[(a - 1) * 32 + t];
+  cpx<T>* w1 = buf + t;
+#pragma unroll
+  for (int a = 0; a < 8; ++a) w1[36 * a] = r[a];
+  wave_sync();
+  const int t0 = t & 3, a = t >> 2;  // the lane's (t0, a) after exchange 1
+  const cpx<T>* r1 = buf + 36 * a + t0;
+#pragma unroll
+  for (int t1 = 0; t1 < 8; ++t1) r[t1] = r1[4 * t1];
+  wave_sync();
+  Codelet<T, 8>::run(r, nullptr);
+#pragma unroll
+  for (int j1 = 1; j1 < 8; ++j1) r[j1] = r[j1] * tw[(6 + j1) * 32 + t];
+  // c = a + 8 j1: 4 c + c / 4 + t0 = (4 a + a / 4 + t0) + 34 j1
+  cpx<T>* w2 = buf + 4 * a + (a >> 2) + t0;
+#pragma unroll
+  for (int j1 = 0; j1 < 8; ++j1) w2[34 * j1] = r[j1];
+  wave_sync();
+  // c = t + 32 h: 4 c + c / 4 = (4 t + t / 4) + 136 h
+  const cpx<T>* r2 = buf + 4 * t + (t >> 2);
+  cpx<T> q[8];
+#pragma unroll
+  for (int i = 0; i < 8; ++i) q[i] = r2[136 * (i >> 2) + (i & 3)];
+  wave_sync();
+  dft4_reg<T>(q[0], q[1], q[2], q[3]);
+  dft4_reg<T>(q[4], q[5], q[6], q[7]);
+  // q[4 h + j0] = X[t + 32 (h + 2 j0)]
+#pragma unroll
+  for (int m = 0; m < 8; ++m) r[m] = q[4 * (m & 1) + (m >> 1)];
+}
+
+template <typename T, int N>
+__device__ __forceinline__ void wave_fft(cpx<T> (&r)[8], cpx<T>* __restrict__ buf,
+                                         const cpx<T>* __restrict__ tw, int t) {
+  if constexpr (N == 512)
+    wave_fft512<T>(r, buf, tw, t);
+  else
+    wave_fft256<T>(r, buf, tw, t);
+}
+
+// Forward transform of two finished real fields (b: none when !two), unpacked
+// into the r2c spectra of rows `row` of fields fa and fa + 1; nothing is
+// stored for a row past the end (valid false).
+template <typename T, int N>
+__device__ __forceinline__ void xw_forward(cpx<T> (&z)[8], cpx<T>* __restrict__ buf,
+                                           const cpx<T>* __restrict__ tw, int t,
+                                           cpx<T>* __restrict__ nl, long long fs, long long row,
+                                           int nkxp, int fa, bool two, bool valid) {
+  constexpr int S = N / 8, SN = S + S / 8;  // SN: natural-order slots per register
+  wave_fft<T, N>(z, buf, tw, t);
+  cpx<T>* wn = buf + xw_nat(t);
+#pragma unroll
+  for (int m = 0; m < 8; ++m) wn[SN * m] = z[m];
+  wave_sync();
+#pragma unroll
+  for (int m = 0; m < 5; ++m) {
+    const int k = t + S * m;
+    if (k <= N / 2 && valid) {
+      const cpx<T> Zk = wn[SN * m];
+      const cpx<T> Zm = conj(buf[xw_nat((N - k) & (N - 1))]);
+      nl[fa * fs + row * nkxp + k] = (Zk + Zm) * T(0.5);
+      if (two) nl[(fa + 1) * fs + row * nkxp + k] = mul_mi(Zk - Zm) * T(0.5);
+    }
+  }
+  wave_sync();
+}
+
+// NL_f = -(u dq_f/dx + v dq_f/dy + w dq_f/dz) on rows of N points.
+// The generic schedule: real quantities in the order u, v, w, then per field
+// dq/dx, dq/dy, dq/dz, consecutive pairs sharing one inverse transform (the
+// value slots are read twice), and the forward transform of a pair of
+// finished fields as soon as both are complete.  Used for three fields, where
+// the one-read schedule below needs more registers than two waves per SIMD
+// allow.
+template <typename T, int NF, int N>
+__global__ __launch_bounds__(64 * XW_WAVES) void k_x_nlw_q(XArgs a, const cpx<T>* __restrict__ xyb,
                                                            cpx<T>* __restrict__ nl, long long fs,
                                                            long long nrows) {
-  constexpr int N = 512, NQ = 3 + 3 * NF, NP = (NQ + 1) / 2;
+  constexpr int NQ = 3 + 3 * NF, NP = (NQ + 1) / 2;
+  constexpr int S = N / 8, RPW = 64 / S;  // lanes per row, rows per wave
   __shared__ cpx<T> tw[XW_TW];
   __shared__ cpx<T> xbuf[XW_WAVES][XW_BUF];
   const int tid = threadIdx.x, lane = tid & 63;
   const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);  // wave-uniform
-  for (int e = tid; e < XW_TW; e += 64 * XW_WAVES) {
-    const int reg = e / 64, t = e % 64, n0 = t & 7, hi = t >> 3;
-    const int j = reg < 7 ? 8 * hi * (reg + 1) : n0 * (hi + 8 * (reg - 7));  // power of w512
-    double sn, cs;
-    sincospi(2.0 * j / N, &sn, &cs);
-    tw[e] = mk((T)cs, (T)(-sn));   // exp(-2 pi i j / 512)
-  }
+  xw_twiddles<T, N>(tw, tid);
   __syncthreads();
-  cpx<T>* buf = xbuf[wv];
+  const int t = lane % S, half = lane / S;
+  cpx<T>* buf = xbuf[wv] + half * (XW_BUF / RPW);
   const int nkxp = a.nkxp;
   const T kxs = (T)a.kxs;
   const T sc = T(1) / T(N);
-  for (long long row = (long long)blockIdx.x * XW_WAVES + wv; row < nrows;
-       row += (long long)gridDim.x * XW_WAVES) {
+  for (long long rw = (long long)blockIdx.x * XW_WAVES + wv; rw * RPW < nrows;
+       rw += (long long)gridDim.x * XW_WAVES) {
+    // a row past the end (second row of the last wave) computes on a copy of
+    // the last row and stores nothing
+    const long long row0 = rw * RPW + half;
+    const bool valid = RPW == 1 || row0 < nrows;
+    const long long row = valid ? row0 : nrows - 1;
     T U[3][8];
     T acc[NF][8];
 #pragma unroll
@@ -502,7 +603,7 @@ __global__ __launch_bounds__(64 * XW_WAVES) void k_x_nl512_q(XArgs a, const cpx<
       const cpx<T>* pb = qb < NQ ? src(qb, dxb) : nullptr;
 #pragma unroll
       for (int m = 0; m < 8; ++m) {
-        const int k = lane + 64 * m;
+        const int k = t + S * m;
         const int kk = k <= N / 2 ? k : N - k;
         cpx<T> A = pa[kk];
         cpx<T> B = pb ? pb[kk] : zero<T>();
@@ -517,7 +618,7 @@ __global__ __launch_bounds__(64 * XW_WAVES) void k_x_nl512_q(XArgs a, const cpx<
         const cpx<T> Z = (k <= N / 2) ? mk(A.x - B.y, A.y + B.x) : mk(A.x + B.y, B.x - A.y);
         r[m] = conj(Z);
       }
-      wave_fft512<T>(r, buf, tw, lane);
+      wave_fft<T, N>(r, buf, tw, t);
 #pragma unroll
       for (int h = 0; h < 2; ++h) {
         const int q = 2 * p + h;
@@ -544,22 +645,7 @@ __global__ __launch_bounds__(64 * XW_WAVES) void k_x_nl512_q(XArgs a, const cpx<
             cpx<T> z[8];
 #pragma unroll
             for (int m = 0; m < 8; ++m) z[m] = mk(acc[fa][m], two ? acc[fa + 1][m] : T(0));
-            wave_fft512<T>(z, buf, tw, lane);
-            cpx<T>* wn = buf + xw_nat(lane);
-#pragma unroll
-            for (int m = 0; m < 8; ++m) wn[72 * m] = z[m];
-            wave_sync();
-#pragma unroll
-            for (int m = 0; m < 5; ++m) {
-              const int k = lane + 64 * m;
-              if (k <= N / 2) {
-                const cpx<T> Zk = wn[72 * m];
-                const cpx<T> Zm = conj(buf[xw_nat((N - k) & (N - 1))]);
-                nl[fa * fs + row * nkxp + k] = (Zk + Zm) * T(0.5);
-                if (two) nl[(fa + 1) * fs + row * nkxp + k] = mul_mi(Zk - Zm) * T(0.5);
-              }
-            }
-            wave_sync();
+            xw_forward<T, N>(z, buf, tw, t, nl, fs, row, nkxp, fa, two, valid);
           }
         }
       }
@@ -567,10 +653,10 @@ __global__ __launch_bounds__(64 * XW_WAVES) void k_x_nl512_q(XArgs a, const cpx<
   }
 }
 
-template <typename T, int NF>
-__global__ __launch_bounds__(64 * XW_WAVES) void k_x_nl512(XArgs a, const cpx<T>* __restrict__ xyb,
-                                                           cpx<T>* __restrict__ nl, long long fs,
-                                                           long long nrows) {
+template <typename T, int NF, int N>
+__global__ __launch_bounds__(64 * XW_WAVES) void k_x_nlw(XArgs a, const cpx<T>* __restrict__ xyb,
+                                                         cpx<T>* __restrict__ nl, long long fs,
+                                                         long long nrows) {
   // Four fields: pairs of real quantities per complex transform, each
   // spectral slot read once: (u, du/dx), (v, dv/dx), (w, dw/dx) from one
   // load each (the x derivative is i k~x times the same coefficients), then
@@ -578,48 +664,27 @@ __global__ __launch_bounds__(64 * XW_WAVES) void k_x_nl512(XArgs a, const cpx<T>
   // NL_f = -(u dq_f/dx + v dq_f/dy + w dq_f/dz) accumulates in that order
   // as soon as u is known; each pair of finished fields is transformed
   // forward together.
-  static_assert(NF == 4, "three fields use k_x_nl512_q");
-  constexpr int N = 512, NP = 8;
+  static_assert(NF == 4, "three fields use k_x_nlw_q");
+  constexpr int NP = 8;
+  constexpr int S = N / 8, RPW = 64 / S;  // lanes per row, rows per wave
   __shared__ cpx<T> tw[XW_TW];
   __shared__ cpx<T> xbuf[XW_WAVES][XW_BUF];
   const int tid = threadIdx.x, lane = tid & 63;
   const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);  // wave-uniform
-  for (int e = tid; e < XW_TW; e += 64 * XW_WAVES) {
-    const int reg = e / 64, t = e % 64, n0 = t & 7, hi = t >> 3;
-    const int j = reg < 7 ? 8 * hi * (reg + 1) : n0 * (hi + 8 * (reg - 7));  // power of w512
-    double sn, cs;
-    sincospi(2.0 * j / N, &sn, &cs);
-    tw[e] = mk((T)cs, (T)(-sn));   // exp(-2 pi i j / 512)
-  }
+  xw_twiddles<T, N>(tw, tid);
   __syncthreads();
-  cpx<T>* buf = xbuf[wv];
+  const int t = lane % S, half = lane / S;
+  cpx<T>* buf = xbuf[wv] + half * (XW_BUF / RPW);
   const int nkxp = a.nkxp;
   const T kxs = (T)a.kxs;
   const T sc = T(1) / T(N);
-  // forward transform of two finished fields (fb < 0: one) and unpack
-  auto forward = [&](long long row, T (&fa_)[8], T (&fb_)[8], int fa, bool two) {
-    cpx<T> z[8];
-#pragma unroll
-    for (int m = 0; m < 8; ++m) z[m] = mk(fa_[m], two ? fb_[m] : T(0));
-    wave_fft512<T>(z, buf, tw, lane);
-    cpx<T>* wn = buf + xw_nat(lane);
-#pragma unroll
-    for (int m = 0; m < 8; ++m) wn[72 * m] = z[m];
-    wave_sync();
-#pragma unroll
-    for (int m = 0; m < 5; ++m) {
-      const int k = lane + 64 * m;
-      if (k <= N / 2) {
-        const cpx<T> Zk = wn[72 * m];
-        const cpx<T> Zm = conj(buf[xw_nat((N - k) & (N - 1))]);
-        nl[fa * fs + row * nkxp + k] = (Zk + Zm) * T(0.5);
-        if (two) nl[(fa + 1) * fs + row * nkxp + k] = mul_mi(Zk - Zm) * T(0.5);
-      }
-    }
-    wave_sync();
-  };
-  for (long long row = (long long)blockIdx.x * XW_WAVES + wv; row < nrows;
-       row += (long long)gridDim.x * XW_WAVES) {
+  for (long long rw = (long long)blockIdx.x * XW_WAVES + wv; rw * RPW < nrows;
+       rw += (long long)gridDim.x * XW_WAVES) {
+    // a row past the end (second row of the last wave) computes on a copy of
+    // the last row and stores nothing
+    const long long row0 = rw * RPW + half;
+    const bool valid = RPW == 1 || row0 < nrows;
+    const long long row = valid ? row0 : nrows - 1;
     T U[3][8];
     T acc[NF][8];
 #pragma unroll
@@ -638,7 +703,7 @@ __global__ __launch_bounds__(64 * XW_WAVES) void k_x_nl512(XArgs a, const cpx<T>
       cpx<T> r[8];
 #pragma unroll
       for (int m = 0; m < 8; ++m) {
-        const int k = lane + 64 * m;
+        const int k = t + S * m;
         const int kk = k <= N / 2 ? k : N - k;
         const T kx = (kk == N / 2) ? T(0) : kxs * (T)kk;
         cpx<T> A = pa[kk];
@@ -652,7 +717,7 @@ __global__ __launch_bounds__(64 * XW_WAVES) void k_x_nl512(XArgs a, const cpx<T>
         const cpx<T> Z = (k <= N / 2) ? mk(A.x - B.y, A.y + B.x) : mk(A.x + B.y, B.x - A.y);
         r[m] = conj(Z);
       }
-      wave_fft512<T>(r, buf, tw, lane);
+      wave_fft<T, N>(r, buf, tw, t);
 #pragma unroll
       for (int m = 0; m < 8; ++m) {
         const T va = r[m].x * sc, vb = -r[m].y * sc;
@@ -669,8 +734,18 @@ __global__ __launch_bounds__(64 * XW_WAVES) void k_x_nl512(XArgs a, const cpx<T>
           acc[3][m] -= U[2][m] * va;
         }
       }
-      if (p == 4) forward(row, acc[0], acc[1], 0, true);
-      if (p == 7) forward(row, acc[2], acc[3], 2, true);
+      if (p == 4) {
+        cpx<T> z[8];
+#pragma unroll
+        for (int m = 0; m < 8; ++m) z[m] = mk(acc[0][m], acc[1][m]);
+        xw_forward<T, N>(z, buf, tw, t, nl, fs, row, nkxp, 0, true, valid);
+      }
+      if (p == 7) {
+        cpx<T> z[8];
+#pragma unroll
+        for (int m = 0; m < 8; ++m) z[m] = mk(acc[2][m], acc[3][m]);
+        xw_forward<T, N>(z, buf, tw, t, nl, fs, row, nkxp, 2, true, valid);
+      }
     }
     // (the next row's loads stay behind this row's last transform)
     __builtin_amdgcn_sched_barrier(0);
@@ -769,8 +844,8 @@ static void launch_x_nl_v(const XArgs& a, const cpx<T>* xyb, cpx<T>* nl, long lo
               nfields);
 }
 
-// nx = 512: one wavefront per row (variant 0) or the tiled kernel; other nx:
-// 4 rows x 256 threads (variant 0, 1) or 8 rows x 512 threads (variant 2),
+// nx = 512 and 256: wave-level rows (variant 0) or the tiled kernels; other
+// nx: 4 rows x 256 threads (variant 0, 1) or 8 rows x 512 threads (variant 2),
 // with compile-time plans for 512 and 256
 template <typename T>
 void launch_x_nl(const XArgs& a, bool big, const cpx<T>* xyb, cpx<T>* nl, long long fs,
@@ -782,16 +857,19 @@ void launch_x_nl(const XArgs& a, bool big, const cpx<T>* xyb, cpx<T>* nl, long l
       launch_x_nl_v<T, DynPlan<true>, 8, 512, 1>(a, xyb, nl, fs, nrows, nfields, st);
     else
       launch_x_nl_v<T, DynPlan<false>, 8, 512, 1>(a, xyb, nl, fs, nrows, nfields, st);
-  } else if (a.nx == 512 && a.variant == 0) {
-    // one wavefront per row; enough workgroups to fill the chip several times
-    const long long need = (nrows + XW_WAVES - 1) / XW_WAVES;
+  } else if ((a.nx == 512 || a.nx == 256) && a.variant == 0) {
+    // wave-level rows; enough workgroups to fill the chip several times
+    const long long rpw = 64 / (a.nx / 8);
+    const long long need = (nrows + rpw * XW_WAVES - 1) / (rpw * XW_WAVES);
     dim3 grid((unsigned)(need < 4096 ? need : 4096));
-    if (nfields == 4)
-      hipLaunchKernelGGL((k_x_nl512<T, 4>), grid, dim3(64 * XW_WAVES), 0, st, a, xyb, nl, fs,
-                         nrows);
+    if (a.nx == 512 && nfields == 4)
+      FCNS_LAUNCH((k_x_nlw<T, 4, 512>), grid, dim3(64 * XW_WAVES), 0, st, a, xyb, nl, fs, nrows);
+    else if (a.nx == 512)
+      FCNS_LAUNCH((k_x_nlw_q<T, 3, 512>), grid, dim3(64 * XW_WAVES), 0, st, a, xyb, nl, fs, nrows);
+    else if (nfields == 4)
+      FCNS_LAUNCH((k_x_nlw<T, 4, 256>), grid, dim3(64 * XW_WAVES), 0, st, a, xyb, nl, fs, nrows);
     else
-      hipLaunchKernelGGL((k_x_nl512_q<T, 3>), grid, dim3(64 * XW_WAVES), 0, st, a, xyb, nl, fs,
-                         nrows);
+      FCNS_LAUNCH((k_x_nlw_q<T, 3, 256>), grid, dim3(64 * XW_WAVES), 0, st, a, xyb, nl, fs, nrows);
   } else if (a.nx == 512 && plan_is(a.pl, {8, 8, 8}))
     launch_x_nl_v<T, SPlan<8, 8, 8>, 4, 256, 2>(a, xyb, nl, fs, nrows, nfields, st);
   else if (a.nx == 256 && plan_is(a.pl, {8, 8, 4}))

@@ -27,8 +27,9 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 
 # kernel name prefix -> timing class of the library (the y kernel serves three
 # classes of equal traffic pattern; it is reported as one)
-CLASSES = {"fcns::k_x_nl<": "x_nl", "fcns::k_x_nl512<": "x_nl", "fcns::k_x_nl512_q<": "x_nl", "fcns::k_z_stageA<": "z_stageA",
-           "fcns::k_z_stageB<": "z_stageB", "fcns::k_z_back<": "z_back", "fcns::k_y<": "y"}
+CLASSES = {"fcns::k_x_nl<": "x_nl", "fcns::k_x_nlw<": "x_nl", "fcns::k_x_nlw_q<": "x_nl",
+           "fcns::k_z_stageA<": "z_stageA", "fcns::k_z_stageB<": "z_stageB",
+           "fcns::k_z_back<": "z_back", "fcns::k_y<": "y"}
 COPY_BYTES = 1 << 30
 
 

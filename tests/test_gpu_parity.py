@@ -148,6 +148,25 @@ def test_rhs_nonlinear_velocity_only_512(fcns):
     assert rel_l2(nlv, rv) < 1e-11
 
 
+@pytest.mark.parametrize("boussinesq", [False, True])
+def test_rhs_nonlinear_wave_rows_256_partial(fcns, boussinesq):
+    # 256-point rows, two per wavefront and eight per workgroup: 17 x 10 rows
+    # leave the last workgroup one wavefront with rows and three without
+    nx, ny, nz, C, lx, ly, lz = 256, 10, 17, 25, 2.0, 1.0, 1.0
+    kw = dict(boussinesq=True, kappa=0.01, gamma=1.0) if boussinesq else {}
+    s = fcns.Solver(nx, ny, nz, lx, ly, lz, 0.01, d=5, C=C, **kw)
+    v = np.stack([W.smooth_field(nx, ny, nz, lx, ly, lz, 60 + i, kmax=6) for i in range(3)])
+    th = W.smooth_field(nx, ny, nz, lx, ly, lz, 64, kmax=6) if boussinesq else None
+    nlv, nlt = s.rhs_nonlinear(torch.from_numpy(v),
+                               torch.from_numpy(th) if boussinesq else None, False)
+    torch.cuda.synchronize()
+    o = Oracle(Problem(nx=nx, ny=ny, nz=nz, lx=lx, ly=ly, lz=lz, nu=0.01, C=C, **kw))
+    rv, rt = o.rhs_nonlinear(v, th, False)
+    assert rel_l2(nlv, rv) < 1e-11
+    if boussinesq:
+        assert rel_l2(nlt, rt) < 1e-11
+
+
 # ------------------------------------------------------------------ projection
 @pytest.mark.parametrize("nx,ny,nz,C,c", [(16, 16, 33, 25, 0.5), (32, 24, 65, 31, 1e-3),
                                           (20, 36, 129, 31, 2.0)])
