@@ -8,6 +8,8 @@
 // into loads and stores.
 #include "kernels.hpp"
 
+#include <type_traits>
+
 namespace fcns {
 
 // ---------------------------------------------------------------- y pass
@@ -46,6 +48,8 @@ __global__ __launch_bounds__(YNT) void k_y(YArgs a, const cpx<T>* src, cpx<T>* d
   for (int i = tid; i < a.pl.tsize; i += YNT) tw[i] = gtw[i];
   const int l = tid % YL, ky0 = tid / YL;
   constexpr int KYS = YNT / YL;
+  // the 512-point compiled plan keeps its first and last stages in registers
+  constexpr bool RE = std::is_same<FP, SPlan<8, 8, 8>>::value && OWN == 8 && KYS == 64;
   const long long ntiles = (nlines + YL - 1) / YL;
   const T sc = inv ? T(1) / (T)ny : T(1);
   const int npass = (mode == 1) ? 2 : 1;
@@ -97,6 +101,41 @@ __global__ __launch_bounds__(YNT) void k_y(YArgs a, const cpx<T>* src, cpx<T>* d
       }
     }
     for (int pass = 0; pass < npass; ++pass) {
+      if constexpr (RE) {
+        // 512 = 8 x 8 x 8 with one butterfly per thread in every stage: the
+        // first stage's inputs are this thread's rows ky0 + 64 m (its DFT
+        // over m needs no twiddles), and so are the last stage's outputs.
+        // Only the middle stage goes through LDS: two barriers per
+        // transform.  Reuse of X0 / X1 by the next transform is ordered by
+        // these barriers (a thread writes X0 only after the barrier that
+        // ends every read of it, and X1 only after the next one).
+        cpx<T> v[8];
+#pragma unroll
+        for (int m = 0; m < 8; ++m) {
+          cpx<T> x = cur[m];
+          if (pass == 1) x = mul_i(x) * (T)k_odd(ky0 + 64 * m, 512, a.kys);
+          v[m] = inv ? conj(x) : x;
+        }
+        Codelet<T, 8>::run(v, nullptr);
+#pragma unroll
+        for (int m = 0; m < 8; ++m) X0[lds_pos<false>(l, 8 * ky0 + m, YL, 1)] = v[m];
+        __syncthreads();
+        sfft_stage<T, 8, 8, 512, YL, YNT, false>(X0, X1, YL, 1, tw + a.pl.toff[1], nullptr, tid);
+        __syncthreads();
+        const cpx<T>* tws = tw + a.pl.toff[2];
+#pragma unroll
+        for (int m = 0; m < 8; ++m) v[m] = X1[lds_pos<false>(l, ky0 + 64 * m, YL, 1)];
+#pragma unroll
+        for (int m = 1; m < 8; ++m) v[m] = v[m] * tws[(m - 1) * 64 + ky0];
+        Codelet<T, 8>::run(v, nullptr);
+        cpx<T>* out = pass ? dst2 : dst;
+        if (ok) {
+#pragma unroll
+          for (int m = 0; m < 8; ++m)
+            out[base + (long long)(ky0 + 64 * m) * nkxp] = (inv ? conj(v[m]) : v[m]) * sc;
+        }
+        continue;
+      }
 #pragma unroll
       for (int r = 0; r < OWN; ++r) {
         const int ky = ky0 + r * KYS;
