@@ -1,18 +1,18 @@
 """Short summaries of rocprofv3 output, written under profiles/.
 
 Kernel-trace statistics (text):
-    python profiles/make_summary.py trace <results.db> <out.txt> "<command>"
+    python -m paper_2002_01392_amd.profsummary trace <results.db> <out.txt> "<command>"
 
 MFMA use per kernel class from one counter run (SQ_INSTS_VALU_MFMA_F64,
 SQ_INSTS_VALU_MFMA_MOPS_F64, SQ_VALU_MFMA_BUSY_CYCLES, GRBM_GUI_ACTIVE;
 utilisation = busy cycles / (active cycles x SIMDs), FP64 MFMA peak 78.6 TF/s):
-    python profiles/make_summary.py mfma <counters.csv> <out.txt> <simds> "<command>"
+    python -m paper_2002_01392_amd.profsummary mfma <counters.csv> <out.txt> <simds> "<command>"
 
 HBM traffic per launch from two counter runs (FETCH_SIZE, then WRITE_SIZE,
 both in KiB per dispatch), each scaled by what the same counter reads for the
 largest plain device copy in the run (a 1 GiB copy: it reads and writes
 exactly 1 GiB), one JSON file per kernel class:
-    python profiles/make_summary.py pmc <fetch.csv> <write.csv> <workload> \\
+    python -m paper_2002_01392_amd.profsummary pmc <fetch.csv> <write.csv> <workload> \\
         <kernel source hash> "<fetch command>" "<write command>"
 """
 import collections
@@ -23,7 +23,8 @@ import sqlite3
 import statistics
 import sys
 
-HERE = os.path.dirname(os.path.abspath(__file__))
+# summaries go to the repository's profiles/ folder
+HERE = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "profiles")
 
 # kernel name prefix -> timing class of the library (the y kernel serves three
 # classes of equal traffic pattern; it is reported as one)
