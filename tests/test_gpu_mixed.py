@@ -74,9 +74,11 @@ def test_mixed_rayleigh_benard_small(fcns):
     assert err["p"] < TOL_P, err
 
 
-@pytest.mark.parametrize("nx,ny,nz,C", [(256, 16, 257, 31), (16, 256, 17, 25)])
+@pytest.mark.parametrize("nx,ny,nz,C", [(256, 16, 257, 31), (16, 256, 17, 25), (512, 16, 17, 25),
+                                         (16, 512, 17, 25)])
 def test_mixed_compile_time_plans(fcns, nx, ny, nz, C):
-    # nx = 256 / ny = 256 and N' = 288 take the compiled FP32 kernels
+    # nx = 256, 512 (wave-level x rows), ny = 256, 512 and N' = 288 take the
+    # compiled FP32 kernels
     w = W.rayleigh_benard(nx, ny, nz, 1e6, C=C, dt=1e-3, steps=2, kmax=3, mmax=3,
                           noise_rms=1e-2)
     err = _mixed_vs_oracle(fcns, w, w.steps)
