@@ -178,6 +178,10 @@ fcns_status fcns_get_wall_grad(fcns_ctx* ctx, double* out);
  * context stream (small extra launch latency).  Classes: y_back_dy,
  * y_back_dz, x_nl, y_fwd, z_stageA, z_stageB, z_back. */
 fcns_status fcns_set_timing(fcns_ctx* ctx, int32_t enable);
+/* The same for a subset: bit i of mask enables class i (in the order above;
+ * 0 disables timing).  Bits beyond the last class: FCNS_EINVAL.  Fewer
+ * events perturb the step less. */
+fcns_status fcns_set_timing_mask(fcns_ctx* ctx, int32_t mask);
 fcns_status fcns_timing_reset(fcns_ctx* ctx);
 /* Synchronizes the stream, then fills up to max classes: names (HOST,
  * 32 chars each, NUL-terminated), counts (HOST, launches) and ms (HOST,

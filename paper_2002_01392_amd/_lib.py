@@ -56,6 +56,7 @@ SIGNATURES = {
     "fcns_get_wall_grad": (ctypes.c_int, [_P, _P]),
     "fcns_npr": (ctypes.c_int32, [_P]),
     "fcns_set_timing": (ctypes.c_int, [_P, _I32]),
+    "fcns_set_timing_mask": (ctypes.c_int, [_P, _I32]),
     "fcns_timing_reset": (ctypes.c_int, [_P]),
     "fcns_timing_report": (ctypes.c_int, [_P, _I32, ctypes.POINTER(_I32), _P, _P, _P]),
     "fcns_last_error": (ctypes.c_char_p, [_P]),
@@ -409,8 +410,19 @@ class Solver:
         self._check(self.lib.fcns_set_spectral(self.ctx, arr, _ptr(wg)))
         self._keep = (fs, wg)
 
-    def set_timing(self, enable=True):
-        self._check(self.lib.fcns_set_timing(self.ctx, int(bool(enable))))
+    TIMING_CLASSES = ("y_back_dy", "y_back_dz", "x_nl", "y_fwd", "z_stageA", "z_stageB",
+                      "z_back")
+
+    def set_timing(self, enable=True, classes=None):
+        """Event-time rk_step's kernels: every class, or only those named in
+        `classes` (fewer events perturb the step less)."""
+        if classes is None or not enable:
+            self._check(self.lib.fcns_set_timing(self.ctx, int(bool(enable))))
+            return
+        mask = 0
+        for nm in classes:
+            mask |= 1 << self.TIMING_CLASSES.index(nm)
+        self._check(self.lib.fcns_set_timing_mask(self.ctx, mask))
 
     def timing_reset(self):
         self._check(self.lib.fcns_timing_reset(self.ctx))

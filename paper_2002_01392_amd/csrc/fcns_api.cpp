@@ -63,8 +63,10 @@ struct fcns_ctx {
   bool has_state = false;
   bool has_pressure = false;
   std::string err;
-  // kernel timing (HIP events around every rk_step launch)
+  // kernel timing (HIP events around the rk_step launches of the classes in
+  // tmask, bit i = class i)
   bool timing = false;
+  uint32_t tmask = 0;
   std::vector<hipEvent_t> evpool;
   size_t evnext = 0;
   struct Rec {
@@ -97,7 +99,8 @@ static void timing_flush(fcns_ctx* c) {
 }
 
 static void tbeg(fcns_ctx* c, int cls) {
-  if (!c->timing) return;
+  c->cur.cls = -1;
+  if (!c->timing || !((c->tmask >> cls) & 1u)) return;
   if (c->evnext + 2 > c->evpool.size()) timing_flush(c);
   c->cur.cls = cls;
   c->cur.a = c->evpool[c->evnext++];
@@ -105,7 +108,7 @@ static void tbeg(fcns_ctx* c, int cls) {
 }
 
 static void tend(fcns_ctx* c) {
-  if (!c->timing) return;
+  if (!c->timing || c->cur.cls < 0) return;
   c->cur.b = c->evpool[c->evnext++];
   (void)hipEventRecord(c->cur.b, c->stream);
   c->recs.push_back(c->cur);
@@ -1132,16 +1135,22 @@ extern "C" fcns_status fcns_get_wall_grad(fcns_ctx* c, double* out) {
 }
 
 // ---------------------------------------------------------------- timing
-extern "C" fcns_status fcns_set_timing(fcns_ctx* c, int32_t enable) {
+extern "C" fcns_status fcns_set_timing_mask(fcns_ctx* c, int32_t mask) {
   if (!c) return FCNS_EINVAL;
-  if (enable && c->evpool.empty()) {
+  if (mask & ~((1 << T_NCLS) - 1)) return fail(c, FCNS_EINVAL, "timing mask names no class");
+  if (mask && c->evpool.empty()) {
     c->evpool.resize(4096);
     for (auto& e : c->evpool)
       if (hipEventCreate(&e) != hipSuccess) return fail(c, FCNS_EDEVICE, "hipEventCreate failed");
   }
-  if (!enable) timing_flush(c);
-  c->timing = enable != 0;
+  timing_flush(c);
+  c->timing = mask != 0;
+  c->tmask = (uint32_t)mask;
   return FCNS_OK;
+}
+
+extern "C" fcns_status fcns_set_timing(fcns_ctx* c, int32_t enable) {
+  return fcns_set_timing_mask(c, enable ? (1 << T_NCLS) - 1 : 0);
 }
 
 extern "C" fcns_status fcns_timing_reset(fcns_ctx* c) {

@@ -279,6 +279,37 @@ def test_rk_is_deterministic_and_restartable(fcns):
     assert torch.equal(va, vc)     # and so is a repeated run
 
 
+def test_kernel_timing_classes_and_mask(fcns):
+    # every class, then one class only; the step's results do not depend on it
+    w = W.get("channel_32x32x33")
+    v0, _ = w.initial_state()
+    a = fcns.Solver.from_workload(w)
+    a.set_state(torch.from_numpy(v0))
+    a.set_timing(True)
+    a.timing_reset()
+    a.rk_step(w.dt, 2)
+    rep = a.timing_report()
+    assert set(rep) == set(a.TIMING_CLASSES)
+    assert all(n == 4 for n, _ in rep.values()), rep   # one launch per substep
+    assert all(ms > 0 for _, ms in rep.values()), rep
+    a.set_timing(True, classes=["z_stageA"])
+    a.timing_reset()
+    a.rk_step(w.dt, 3)
+    rep = a.timing_report()
+    assert rep["z_stageA"][0] == 6
+    assert all(n == 0 for k, (n, _) in rep.items() if k != "z_stageA"), rep
+    with pytest.raises(fcns.FcnsError):
+        a._check(a.lib.fcns_set_timing_mask(a.ctx, 1 << len(a.TIMING_CLASSES)))
+    a.set_timing(False)
+    va, _, _ = a.get_state()
+    b = fcns.Solver.from_workload(w)
+    b.set_state(torch.from_numpy(v0))
+    b.rk_step(w.dt, 5)
+    vb, _, _ = b.get_state()
+    torch.cuda.synchronize()
+    assert torch.equal(va, vb)
+
+
 # ------------------------------------------------------------------ diagnostics
 def _diag_pair(fcns, w, steps):
     from oracle.diagnostics import diagnostics, spectra
