@@ -23,6 +23,7 @@ import math
 
 import numpy as np
 
+from . import fft as dft
 from .ns import Oracle
 
 NAMES = ("energy", "div2", "slip_bottom", "slip_top", "w2_bottom", "w2_top",
@@ -68,7 +69,7 @@ def spectra(o: Oracle, field, z):
     v, th, _ = o.get_state()
     a = th if field == 3 else v[field]
     nx, ny = o.p.nx, o.p.ny
-    f = np.fft.fft2(a[z]) / (nx * ny)          # [ky][kx], all kx
+    f = dft.fft(dft.fft(a[z], -1), -2) / (nx * ny)   # [ky][kx], all kx
     e = np.abs(f) ** 2
     ex = np.zeros(nx // 2 + 1)
     for m in range(nx):

@@ -22,6 +22,7 @@ from __future__ import annotations
 
 import numpy as np
 
+from . import fft as dft
 from .fc_table import fc_tables
 
 
@@ -39,7 +40,7 @@ class FCGram:
         self.Mr = Mr
         self.Ml = Mr[::-1, ::-1].copy()           # J M_r J
         n = self.np_
-        lbar = np.fft.fftfreq(n, d=1.0 / n)       # signed integer index
+        lbar = dft.signed_index(n)                # signed integer index
         self.kz = 2.0 * np.pi * lbar / self.lzp    # true wavenumbers
         self.kz_odd = self.kz.copy()
         if n % 2 == 0:
@@ -56,11 +57,11 @@ class FCGram:
 
     def fwd(self, f):
         """F_z = FFT o E along axis 0 (unnormalized)."""
-        return np.fft.fft(self.extend(f), axis=0)
+        return dft.fft(self.extend(f), 0)
 
     def back(self, fh):
         """B_z = R o IFFT along axis 0."""
-        return np.fft.ifft(fh, axis=0)[: self.nz]
+        return dft.ifft(fh, 0)[: self.nz]
 
     def kz_shape(self, ndim, odd=True):
         k = self.kz_odd if odd else self.kz

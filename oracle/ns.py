@@ -50,6 +50,7 @@ from dataclasses import dataclass
 
 import numpy as np
 
+from . import fft as dft
 from .fcgram import FCGram
 
 BETA_DEFAULT = 16.0 * math.log(10.0)
@@ -77,7 +78,7 @@ class Problem:
 
 
 def _signed(n):
-    return np.fft.fftfreq(n, d=1.0 / n)
+    return dft.signed_index(n)
 
 
 class Oracle:
@@ -126,10 +127,10 @@ class Oracle:
 
     # -- transforms -----------------------------------------------------------
     def Fxy(self, a):
-        return np.fft.fft(np.fft.rfft(a, axis=-1), axis=-2)
+        return dft.fft(dft.rfft(a, -1), -2)
 
     def Bxy(self, m):
-        return np.fft.irfft(np.fft.ifft(m, axis=-2), n=self.p.nx, axis=-1)
+        return dft.irfft(dft.ifft(m, -2), self.p.nx, -1)
 
     def Fz(self, m):
         return self.fc.fwd(m)
@@ -275,15 +276,19 @@ class Oracle:
         nlt = NL[3] if theta is not None else None
         return nlv, nlt
 
-    def pressure_project(self, v_star, c):
+    def pressure_project(self, v_star, c, pressure=False):
         """Project a physical v* (no BC injection).  Returns the physical
         projected velocity and the wall tangential pressure gradient
-        [2 walls][2 comps][Ny][Nx] in p units."""
+        [2 walls][2 comps][Ny][Nx] in p units; with ``pressure`` also the
+        physical pressure phi / c (phi^I + phi^H of Sec. 4.2) with zero mean."""
         Vs = [self.to_spec(v_star[i]) for i in range(3)]
-        V_new, G, _ = self.project(Vs, c)
+        V_new, G, phi = self.project(Vs, c)
         v = np.stack([self.to_phys(V) for V in V_new])
-        gp = np.fft.irfft(np.fft.ifft(G, axis=-2), n=self.p.nx, axis=-1)
-        return v, gp
+        gp = dft.irfft(dft.ifft(G, -2), self.p.nx, -1)
+        if not pressure:
+            return v, gp
+        pres = self.Bxy(phi / c)
+        return v, gp, pres - pres.mean()
 
     # -- diagnostics used by the pins ------------------------------------------
     def divergence(self, V):
