@@ -42,7 +42,8 @@ typedef enum {
   FCNS_ENOMEM = -2,     /* device allocation failed in fcns_create */
   FCNS_EDEVICE = -3,    /* a HIP call or kernel launch failed */
   FCNS_ENONFINITE = -4, /* a non-finite value was found in the state */
-  FCNS_ESTATE = -5      /* call out of order (e.g. rk_step before set_state) */
+  FCNS_ESTATE = -5,     /* call out of order (e.g. rk_step before set_state) */
+  FCNS_ECANCELED = -6   /* a served request was cancelled */
 } fcns_status;
 
 enum { FCNS_FP64 = 0, FCNS_MIXED = 1 };
@@ -130,15 +131,36 @@ fcns_status fcns_set_state(fcns_ctx* ctx, const double* v, const double* theta);
  * Sec. 4.4 with time step dt (stage coefficients c_j = dt/(o-j+1); each stage
  * injects the wall gradient of the previous stage's pressure, which for o = 1
  * is the time-splitting Euler scheme of Sec. 4.1).
- * Asynchronous on the context stream. */
+ * Every stage checks the new state (all fields, theta included) for NaN and
+ * infinity on the device (a flag raised by the z back transform of the
+ * stage).  In the default check mode FCNS_CHECK_SYNC the call waits for its
+ * steps and returns FCNS_ENONFINITE when the flag is up; the state is then
+ * undefined and stays flagged until set_state / set_spectral.  In
+ * FCNS_CHECK_DEFERRED the call is asynchronous on the context stream and
+ * fcns_check_finite reports later; FCNS_CHECK_OFF skips the report. */
 fcns_status fcns_rk_step(fcns_ctx* ctx, double dt, int32_t nsteps);
+
+enum { FCNS_CHECK_OFF = 0, FCNS_CHECK_SYNC = 1, FCNS_CHECK_DEFERRED = 2 };
+/* Select how rk_step, rk_graph and batch_step report a non-finite state
+ * (see fcns_rk_step).  EINVAL for an unknown mode. */
+fcns_status fcns_set_finite_check(fcns_ctx* ctx, int32_t mode);
+/* Synchronize the context stream and return FCNS_ENONFINITE if a step
+ * enqueued so far left a non-finite state (FCNS_OK otherwise). */
+fcns_status fcns_check_finite(fcns_ctx* ctx);
+/* The host copy of the flag as of the last completed rk_step call, without
+ * synchronizing (1: non-finite; valid once the work of that call is done,
+ * e.g. after an event recorded behind it has completed). */
+int32_t fcns_nonfinite_flag(const fcns_ctx* ctx);
 
 /* Batched stepping of n independent contexts (HOST arrays of n context
  * pointers, time steps and step counts): step k of every context is
  * enqueued before step k + 1 of any, each on its own context stream, so
  * problems of different shapes overlap on the device.  Each context's result
- * is bitwise its own fcns_rk_step.  Contexts must not share a stream for
- * the overlap (sharing is correct, only serial). */
+ * is bitwise its own fcns_rk_step, and each reports a non-finite state in its
+ * own check mode (FCNS_ENONFINITE is returned if any context in
+ * FCNS_CHECK_SYNC mode has one; fcns_last_error of that context says so).
+ * Contexts must not share a stream for the overlap (sharing is correct, only
+ * serial). */
 fcns_status fcns_batch_step(fcns_ctx* const* ctxs, int32_t n, const double* dts,
                             const int32_t* nsteps);
 
@@ -239,9 +261,12 @@ void* fcns_stream(const fcns_ctx* ctx);
  * requests of the same shape (fcns_set_params), idle ones are evicted least
  * recently used when memory is needed.  Each context has its own
  * non-blocking HIP stream, so admitted requests overlap on the device, and
- * each request's result is the one a single-problem rk_step gives.  All
- * calls from one host thread; progress happens only inside
- * fcns_server_poll. */
+ * each request's result is the one a single-problem rk_step gives.  Steps
+ * are enqueued a few at a time as earlier ones complete, and each step's
+ * non-finite flag is read as it completes: a request whose state blows up
+ * stops there and finishes with FCNS_ENONFINITE (its outputs not written),
+ * without affecting the others.  All calls from one host thread; progress
+ * happens only inside fcns_server_poll. */
 typedef struct fcns_server fcns_server;
 
 fcns_status fcns_server_create(int32_t max_active, int64_t max_bytes, fcns_server** out);
@@ -262,11 +287,18 @@ double fcns_server_now(const fcns_server* srv);
 /* Status of a finished request (its state is then in v_out, theta_out);
  * stats (HOST, nullable, 6 doubles): submit, admit and done times (server
  * clock, s), mean, median and max step time (ms, HIP events on its stream).
- * ESTATE if not finished; ENONFINITE if the state blew up. */
+ * ESTATE if not finished; ENONFINITE if the state blew up; ECANCELED if
+ * cancelled. */
 fcns_status fcns_server_result(fcns_server* srv, int64_t id, double* stats);
 /* Per-step times (ms) of a finished request: up to max into ms (HOST). */
 fcns_status fcns_server_step_times(fcns_server* srv, int64_t id, int32_t max, float* ms,
                                    int32_t* n);
+/* Cancel a request: a queued one finishes at once, a running one after the
+ * steps already on the device (no more are enqueued); either way its result
+ * is FCNS_ECANCELED and v_out, theta_out are not written.  Other requests
+ * are unaffected.  EINVAL for an unknown id; FCNS_OK (no effect) when the
+ * request has already finished. */
+fcns_status fcns_server_cancel(fcns_server* srv, int64_t id);
 /* Forget a finished request. */
 fcns_status fcns_server_release(fcns_server* srv, int64_t id);
 /* Synchronize and free every context. */

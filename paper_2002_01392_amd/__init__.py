@@ -9,6 +9,8 @@ behind the C ABI of include/fcns.h.  ``Solver`` (one problem) and ``Server``
 """
 from ._lib import (FcnsError, Server, Solver, batch_step, footprint,  # noqa: F401
                    load_library, make_problem, problem_bytes, workload_problem)
+from ._lib import (FCNS_ECANCELED, FCNS_EDEVICE, FCNS_EINVAL, FCNS_ENOMEM,  # noqa: F401
+                   FCNS_ENONFINITE, FCNS_ESTATE, FCNS_OK)
 
 __all__ = ["Solver", "Server", "FcnsError", "load_library", "problem_bytes", "make_problem",
            "workload_problem", "footprint", "batch_step"]

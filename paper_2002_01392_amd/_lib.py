@@ -16,6 +16,8 @@ _PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_PKG, "libfcns.so")
 
 FCNS_OK, FCNS_EINVAL, FCNS_ENOMEM, FCNS_EDEVICE, FCNS_ENONFINITE, FCNS_ESTATE = 0, -1, -2, -3, -4, -5
+FCNS_ECANCELED = -6
+FCNS_CHECK_OFF, FCNS_CHECK_SYNC, FCNS_CHECK_DEFERRED = 0, 1, 2
 FCNS_FP64, FCNS_MIXED = 0, 1
 _PRECISIONS = {"fp64": FCNS_FP64, "mixed": FCNS_MIXED}
 
@@ -47,6 +49,9 @@ SIGNATURES = {
     "fcns_set_state": (ctypes.c_int, [_P, _P, _P]),
     "fcns_rk_step": (ctypes.c_int, [_P, _D, _I32]),
     "fcns_rk_graph": (ctypes.c_int, [_P, _D, _I32]),
+    "fcns_set_finite_check": (ctypes.c_int, [_P, _I32]),
+    "fcns_check_finite": (ctypes.c_int, [_P]),
+    "fcns_nonfinite_flag": (ctypes.c_int32, [_P]),
     "fcns_autotune": (ctypes.c_int, [_P, ctypes.c_char_p, _I32]),
     "fcns_batch_step": (ctypes.c_int, [ctypes.POINTER(_P), _I32, ctypes.POINTER(_D),
                                        ctypes.POINTER(_I32)]),
@@ -74,6 +79,7 @@ SIGNATURES = {
     "fcns_server_result": (ctypes.c_int, [_P, _I64, _P]),
     "fcns_server_step_times": (ctypes.c_int, [_P, _I64, _I32, _P, ctypes.POINTER(_I32)]),
     "fcns_server_release": (ctypes.c_int, [_P, _I64]),
+    "fcns_server_cancel": (ctypes.c_int, [_P, _I64]),
     "fcns_server_destroy": (ctypes.c_int, [_P]),
     "fcns_server_last_error": (ctypes.c_char_p, [_P]),
 }
@@ -195,12 +201,16 @@ class Server:
         _, _, v, th = self.arrays[rid]
         stats = np.zeros(6)
         st = self.lib.fcns_server_result(self.srv, rid, stats.ctypes.data_as(ctypes.c_void_p))
-        if st not in (FCNS_OK, FCNS_ENONFINITE):
+        if st not in (FCNS_OK, FCNS_ENONFINITE, FCNS_ECANCELED):
             self._check(st)
         keys = ("t_submit", "t_admit", "t_done", "step_ms_mean", "step_ms_p50", "step_ms_max")
         info = dict(zip(keys, stats.tolist()))
         info["finite"] = st == FCNS_OK
+        info["status"] = st
         return v, th, info
+
+    def cancel(self, rid):
+        self._check(self.lib.fcns_server_cancel(self.srv, rid))
 
     def step_times(self, rid, maxn=1 << 16):
         ms = np.zeros(maxn, dtype=np.float32)
@@ -334,6 +344,15 @@ class Solver:
 
     def rk_step(self, dt, nsteps=1):
         self._check(self.lib.fcns_rk_step(self.ctx, float(dt), int(nsteps)))
+
+    def set_finite_check(self, mode):
+        """"off", "sync" (rk_step waits and raises on a non-finite state) or
+        "deferred" (check_finite reports)."""
+        modes = {"off": FCNS_CHECK_OFF, "sync": FCNS_CHECK_SYNC, "deferred": FCNS_CHECK_DEFERRED}
+        self._check(self.lib.fcns_set_finite_check(self.ctx, modes[mode]))
+
+    def check_finite(self):
+        self._check(self.lib.fcns_check_finite(self.ctx))
 
     def autotune(self):
         """Pick the fastest launch choices for this shape; returns the summary."""

@@ -50,6 +50,11 @@ struct fcns_ctx {
   cpx<double>* GW = nullptr;   // wall tangential gradient [2][2][npen]
   cpx<double>* GWT = nullptr;  // scratch wall gradient
   double* DG = nullptr;        // diagnostics: per-plane sums [nz][5], then spectra
+  // non-finite check of the state: a device flag set by the z back transform
+  // of every stage, copied after each rk_step call into pinned host memory
+  int* dflag = nullptr;
+  int* hflag = nullptr;
+  int check_mode = FCNS_CHECK_SYNC;
   // one RK step captured as a HIP graph (fcns_rk_graph), for one dt
   hipStream_t cap_stream = nullptr;
   hipGraphExec_t graph = nullptr;
@@ -242,9 +247,10 @@ static void free_all(fcns_ctx* c) {
   for (hipEvent_t e : c->evpool) (void)hipEventDestroy(e);
   c->evpool.clear();
   void* ps[] = {c->twz, c->twx, c->twy, c->twz_f, c->twx_f, c->twy_f, c->rootz, c->fcM, c->sigx, c->sigy, c->sigz, c->P, c->Q,
-                c->VS, c->MV, c->MVT, c->XYB, c->NLB, c->PM, c->GW, c->GWT, c->DG};
+                c->VS, c->MV, c->MVT, c->XYB, c->NLB, c->PM, c->GW, c->GWT, c->DG, c->dflag};
   for (void* p : ps)
     if (p) (void)hipFree(p);
+  if (c->hflag) (void)hipHostFree(c->hflag);
 }
 
 // f32: the twiddle table of the FP32 kernels
@@ -258,6 +264,7 @@ static ZArgs zargs(const fcns_ctx* c, bool f32 = false) {
   a.sigx = c->sigx;
   a.sigy = c->sigy;
   a.sigz = c->sigz;
+  a.nonfinite = nullptr;
   return a;
 }
 static YArgs yargs(const fcns_ctx* c, bool f32 = false, bool dy = false) {
@@ -400,13 +407,18 @@ extern "C" fcns_status fcns_create(const fcns_problem* prob, void* hip_stream, f
       (st = alloc(c, &c->NLB, nf * c->M)) || (st = alloc(c, &c->PM, c->M)) ||
       (st = alloc(c, &c->GW, 4 * g.npen)) || (st = alloc(c, &c->GWT, 4 * g.npen)) ||
       (st = hipMalloc((void**)&c->DG, sizeof(double) * (5 * (size_t)p.nz + g.nkx + p.ny)) ==
-                    hipSuccess ? FCNS_OK : fail(c, FCNS_ENOMEM, "device allocation failed"))) {
+                    hipSuccess ? FCNS_OK : fail(c, FCNS_ENOMEM, "device allocation failed")) ||
+      (st = alloc(c, reinterpret_cast<cpx<double>**>(&c->dflag), 1)) ||
+      (st = hipHostMalloc((void**)&c->hflag, sizeof(int), hipHostMallocDefault) == hipSuccess
+                ? FCNS_OK : fail(c, FCNS_ENOMEM, "pinned host allocation failed"))) {
     g_create_err = c->err;
     free_all(c);
     delete c;
     return st;
   }
   launch_fill(c->GW, 4 * g.npen, c->stream);
+  launch_fill(reinterpret_cast<cpx<double>*>(c->dflag), 1, c->stream);
+  *c->hflag = 0;
   if ((st = check_launch(c, "fill")) != FCNS_OK) {
     g_create_err = c->err;
     free_all(c);
@@ -514,16 +526,39 @@ static void nonlinear_from_mixed(fcns_ctx* c, const cpx<T>* mv, int nfields, boo
 }
 
 // the mixed v, dv/dz of the continued state src into MV, in the type the
-// rk_step pipeline reads (FP32 for a mixed-precision context)
-static void state_to_mv(fcns_ctx* c, const cpx<double>* src) {
+// rk_step pipeline reads (FP32 for a mixed-precision context); check: the
+// transform also raises the context's non-finite flag
+static void state_to_mv(fcns_ctx* c, const cpx<double>* src, bool check = false) {
+  ZArgs a = zargs(c, c->mixed);
+  if (check) a.nonfinite = c->dflag;
   if (c->mixed) {
     cpx<float>* mv = reinterpret_cast<cpx<float>*>(c->MV);
-    launch_z_back<float>(zargs(c, true), c->big_z, src, mv, mv + c->M, c->S, 2 * c->M, c->nf,
-                         c->stream);
+    launch_z_back<float>(a, c->big_z, src, mv, mv + c->M, c->S, 2 * c->M, c->nf, c->stream);
   } else {
-    launch_z_back<double>(zargs(c), c->big_z, src, c->MV, c->MV + c->M, c->S, 2 * c->M, c->nf,
+    launch_z_back<double>(a, c->big_z, src, c->MV, c->MV + c->M, c->S, 2 * c->M, c->nf,
                           c->stream);
   }
+}
+
+// a new state: the device flag cleared, and its host copy once the stream
+// gets there
+static void clear_flag(fcns_ctx* c) {
+  launch_fill(reinterpret_cast<cpx<double>*>(c->dflag), 1, c->stream);
+  (void)hipMemcpyAsync(c->hflag, c->dflag, sizeof(int), hipMemcpyDeviceToHost, c->stream);
+}
+
+// After the steps of one call: the flag into pinned host memory; in the
+// synchronous mode wait for it and report a non-finite state.
+static fcns_status finish_steps(fcns_ctx* c, const char* what) {
+  fcns_status st = check_launch(c, what);
+  if (st != FCNS_OK || c->check_mode == FCNS_CHECK_OFF) return st;
+  if ((st = check_hip(c, hipMemcpyAsync(c->hflag, c->dflag, sizeof(int), hipMemcpyDeviceToHost,
+                                        c->stream), what)))
+    return st;
+  if (c->check_mode != FCNS_CHECK_SYNC) return FCNS_OK;
+  if ((st = check_hip(c, hipStreamSynchronize(c->stream), what))) return st;
+  if (*c->hflag) return fail(c, FCNS_ENONFINITE, "non-finite value in the state after a step");
+  return FCNS_OK;
 }
 
 // ---------------------------------------------------------------- entry points
@@ -569,6 +604,7 @@ extern "C" fcns_status fcns_set_state(fcns_ctx* c, const double* v, const double
   mixed_to_state(c, c->XYB, c->nf, c->P, nullptr);
   state_to_mv(c, c->P);
   launch_fill(c->GW, 4 * c->g.npen, c->stream);
+  clear_flag(c);
   fcns_status st = check_launch(c, "set_state");
   if (st == FCNS_OK) {
     c->has_state = true;
@@ -627,9 +663,10 @@ static void rk_stage(fcns_ctx* c, int j, int o, double dt) {
   tbeg(c, T_ZSTAGEB);
   launch_z_stageB(zargs(c), c->big_z, B, c->stream);
   tend(c);
-  // mixed v_f, dv_f/dz of the new state for the next stage's x/y passes
+  // mixed v_f, dv_f/dz of the new state for the next stage's x/y passes,
+  // with the non-finite check of the state
   tbeg(c, T_ZBACK);
-  state_to_mv(c, OUT);
+  state_to_mv(c, OUT, true);
   tend(c);
 }
 
@@ -645,9 +682,28 @@ extern "C" fcns_status fcns_rk_step(fcns_ctx* c, double dt, int32_t nsteps) {
       else
         rk_stage<double>(c, j, o, dt);
     }
-  fcns_status st = check_launch(c, "rk_step");
-  if (st == FCNS_OK && nsteps > 0 && c->prob.keep_pressure) c->has_pressure = true;
-  return st;
+  if (nsteps > 0 && c->prob.keep_pressure) c->has_pressure = true;
+  return finish_steps(c, "rk_step");
+}
+
+extern "C" fcns_status fcns_set_finite_check(fcns_ctx* c, int32_t mode) {
+  if (!c) return FCNS_EINVAL;
+  if (mode != FCNS_CHECK_OFF && mode != FCNS_CHECK_SYNC && mode != FCNS_CHECK_DEFERRED)
+    return fail(c, FCNS_EINVAL, "unknown check mode");
+  c->check_mode = mode;
+  return FCNS_OK;
+}
+
+extern "C" fcns_status fcns_check_finite(fcns_ctx* c) {
+  if (!c) return FCNS_EINVAL;
+  fcns_status st = check_hip(c, hipStreamSynchronize(c->stream), "check_finite");
+  if (st != FCNS_OK) return st;
+  if (*c->hflag) return fail(c, FCNS_ENONFINITE, "non-finite value in the state after a step");
+  return FCNS_OK;
+}
+
+extern "C" int32_t fcns_nonfinite_flag(const fcns_ctx* c) {
+  return (c && c->hflag) ? *c->hflag : 0;
 }
 
 // Capture one step (all o stages) for this dt on a private stream; the graph
@@ -703,7 +759,7 @@ extern "C" fcns_status fcns_rk_graph(fcns_ctx* c, double dt, int32_t nsteps) {
   for (int n = 0; n < nsteps; ++n)
     if ((st = check_hip(c, hipGraphLaunch(c->graph, c->stream), "graph launch"))) return st;
   if (nsteps > 0 && c->prob.keep_pressure) c->has_pressure = true;
-  return FCNS_OK;
+  return finish_steps(c, "rk_graph");
 }
 
 // ---------------------------------------------------------------- autotuner
@@ -918,12 +974,14 @@ extern "C" fcns_status fcns_batch_step(fcns_ctx* const* ctxs, int32_t n, const d
           rk_stage<double>(c, j, o, dts[i]);
       }
     }
+  fcns_status worst = FCNS_OK;
   for (int i = 0; i < n; ++i) {
-    fcns_status st = check_launch(ctxs[i], "batch_step");
-    if (st) return st;
     if (nsteps[i] > 0 && ctxs[i]->prob.keep_pressure) ctxs[i]->has_pressure = true;
+    fcns_status st = finish_steps(ctxs[i], "batch_step");
+    if (st == FCNS_ENONFINITE && worst == FCNS_OK) worst = st;
+    else if (st != FCNS_OK && st != FCNS_ENONFINITE) return st;
   }
-  return FCNS_OK;
+  return worst;
 }
 
 extern "C" fcns_status fcns_get_state(fcns_ctx* c, double* v, double* theta, double* p) {
@@ -1117,6 +1175,7 @@ extern "C" fcns_status fcns_set_spectral(fcns_ctx* c, const double* const* field
     launch_fill(c->GW, 4 * c->g.npen, c->stream);
   }
   state_to_mv(c, c->P);
+  clear_flag(c);
   fcns_status st = check_launch(c, "set_spectral");
   if (st == FCNS_OK) {
     c->has_state = true;

@@ -3,10 +3,13 @@
 // memory allow (first fit: a request that does not fit yet does not block the
 // ones behind it), run on solver contexts that stay resident and are reused by
 // later requests of the same shape, and overlap on the device through one
-// non-blocking HIP stream per context.  Every step of every request is
-// bracketed by HIP events, so step latency under load is measured on the
-// device; request latency is measured on the host clock from submission to
-// the detection of the finished result.
+// non-blocking HIP stream per context.  A running request keeps up to
+// kLookahead steps enqueued; each poll collects the completed ones (their
+// non-finite flag included) and tops the queue up, so a cancelled or
+// blown-up request stops within a few steps and frees its slot.  Every step
+// of every request is bracketed by HIP events, so step latency under load is
+// measured on the device; request latency is measured on the host clock from
+// submission to the detection of the finished result.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -40,6 +43,9 @@ struct PoolCtx {
 
 enum { Q_QUEUED = 0, Q_RUNNING, Q_FINISHING, Q_DONE };
 
+// steps of one request on its stream ahead of the host
+constexpr int kLookahead = 3;
+
 struct Request {
   int64_t id = 0;
   fcns_problem prob{};
@@ -50,6 +56,10 @@ struct Request {
   double* th_out = nullptr;
   double dt = 0.0;
   int nsteps = 0;
+  int enq = 0;               // steps enqueued
+  int done_steps = 0;        // steps known complete
+  bool cancel = false;       // stop enqueuing; finish as ECANCELED
+  bool nonfinite = false;    // a completed step left a non-finite state
   double t_submit = 0.0, t_admit = -1.0, t_done = -1.0;
   int state = Q_QUEUED;
   PoolCtx* pc = nullptr;
@@ -197,6 +207,8 @@ static PoolCtx* acquire(fcns_server* s, Request& r, const std::string& key, fcns
     (void)hipStreamDestroy(pc->stream);
     return nullptr;
   }
+  // rk_step stays asynchronous; the flag is read as each step completes
+  (void)fcns_set_finite_check(pc->ctx, FCNS_CHECK_DEFERRED);
   const size_t sb = (size_t)nphys * npts * sizeof(double);
   if (hipMalloc((void**)&pc->dphys, sb) != hipSuccess ||
       hipHostMalloc((void**)&pc->hphys, sb, hipHostMallocDefault) != hipSuccess) {
@@ -239,9 +251,17 @@ static fcns_status launch_request(fcns_server* s, Request& r) {
     if (hipEventCreate(&e) != hipSuccess) return FCNS_EDEVICE;
   if (hipEventCreateWithFlags(&r.fin, hipEventDisableTiming) != hipSuccess) return FCNS_EDEVICE;
   (void)hipEventRecord(r.ev[0], pc->stream);
-  for (int k = 1; k <= r.nsteps; ++k) {
-    if ((st = fcns_rk_step(c, r.dt, 1)) != FCNS_OK) return st;
-    (void)hipEventRecord(r.ev[k], pc->stream);
+  r.enq = r.done_steps = 0;
+  return FCNS_OK;
+}
+
+// Keep up to kLookahead steps of a running request on its stream.
+static fcns_status top_up(Request& r) {
+  while (!r.cancel && !r.nonfinite && r.enq < r.nsteps && r.enq - r.done_steps < kLookahead) {
+    fcns_status st = fcns_rk_step(r.pc->ctx, r.dt, 1);
+    if (st != FCNS_OK) return st;
+    if (hipEventRecord(r.ev[r.enq + 1], r.pc->stream) != hipSuccess) return FCNS_EDEVICE;
+    r.enq++;
   }
   return FCNS_OK;
 }
@@ -262,30 +282,48 @@ extern "C" fcns_status fcns_server_poll(fcns_server* s, int32_t* n_queued, int32
     Request& r = *s->reqs[s->active[i]];
     bool remove = false;
     if (r.state == Q_RUNNING) {
-      const hipError_t q = hipEventQuery(r.ev.back());
-      if (q == hipSuccess) {
-        r.step_ms.resize(r.nsteps);
-        for (int k = 0; k < r.nsteps; ++k) {
+      hipError_t q = hipSuccess;
+      while (r.done_steps < r.enq && (q = hipEventQuery(r.ev[r.done_steps + 1])) == hipSuccess)
+        r.done_steps++;
+      // the flag is sticky until set_state, so its latest host copy covers
+      // every step completed so far
+      if (r.done_steps > 0 && fcns_nonfinite_flag(r.pc->ctx)) r.nonfinite = true;
+      fcns_status st = FCNS_OK;
+      if (q != hipSuccess && q != hipErrorNotReady) {
+        finish_with_error(s, r, FCNS_EDEVICE, hipGetErrorString(q));
+        remove = true;
+      } else if ((st = top_up(r)) != FCNS_OK) {
+        finish_with_error(s, r, st, fcns_last_error(r.pc->ctx));
+        remove = true;
+      } else if (r.done_steps == r.enq) {
+        // nothing of this request is left on the device
+        r.step_ms.resize(r.done_steps);
+        for (int k = 0; k < r.done_steps; ++k) {
           float ms = 0.f;
           (void)hipEventElapsedTime(&ms, r.ev[k], r.ev[k + 1]);
           r.step_ms[k] = ms;
         }
-        PoolCtx* pc = r.pc;
-        const size_t n = (size_t)pc->npts;
-        fcns_status st = fcns_get_state(pc->ctx, pc->dphys,
-                                        pc->nphys == 4 ? pc->dphys + 3 * n : nullptr, nullptr);
-        if (st == FCNS_OK &&
-            hipMemcpyAsync(pc->hphys, pc->dphys, pc->nphys * n * sizeof(double),
-                           hipMemcpyDeviceToHost, pc->stream) == hipSuccess &&
-            hipEventRecord(r.fin, pc->stream) == hipSuccess) {
-          r.state = Q_FINISHING;
-        } else {
-          finish_with_error(s, r, st == FCNS_OK ? FCNS_EDEVICE : st, "result copy failed");
+        if (r.cancel) {
+          finish_with_error(s, r, FCNS_ECANCELED, "cancelled");
           remove = true;
+        } else if (r.nonfinite) {
+          finish_with_error(s, r, FCNS_ENONFINITE, "non-finite state");
+          remove = true;
+        } else {
+          PoolCtx* pc = r.pc;
+          const size_t n = (size_t)pc->npts;
+          st = fcns_get_state(pc->ctx, pc->dphys, pc->nphys == 4 ? pc->dphys + 3 * n : nullptr,
+                              nullptr);
+          if (st == FCNS_OK &&
+              hipMemcpyAsync(pc->hphys, pc->dphys, pc->nphys * n * sizeof(double),
+                             hipMemcpyDeviceToHost, pc->stream) == hipSuccess &&
+              hipEventRecord(r.fin, pc->stream) == hipSuccess) {
+            r.state = Q_FINISHING;
+          } else {
+            finish_with_error(s, r, st == FCNS_OK ? FCNS_EDEVICE : st, "result copy failed");
+            remove = true;
+          }
         }
-      } else if (q != hipErrorNotReady) {
-        finish_with_error(s, r, FCNS_EDEVICE, hipGetErrorString(q));
-        remove = true;
       }
     }
     if (r.state == Q_FINISHING) {
@@ -295,9 +333,8 @@ extern "C" fcns_status fcns_server_poll(fcns_server* s, int32_t* n_queued, int32
         const size_t n = (size_t)pc->npts;
         memcpy(r.v_out, pc->hphys, 3 * n * sizeof(double));
         if (pc->nphys == 4) memcpy(r.th_out, pc->hphys + 3 * n, n * sizeof(double));
-        bool finite = true;
-        for (size_t i = 0; i < 3 * n; ++i) finite = finite && std::isfinite(r.v_out[i]);
-        r.status = finite ? FCNS_OK : FCNS_ENONFINITE;
+        // every step's state passed the device check (all fields)
+        r.status = FCNS_OK;
         r.state = Q_DONE;
         r.t_done = s->now();
         s->n_done++;
@@ -342,6 +379,12 @@ extern "C" fcns_status fcns_server_poll(fcns_server* s, int32_t* n_queued, int32
       release_events(r);
       pc->busy = false;
       r.pc = nullptr;
+    } else if ((st = top_up(r)) != FCNS_OK) {
+      finish_with_error(s, r, st, fcns_last_error(pc->ctx));
+      (void)hipStreamSynchronize(pc->stream);
+      release_events(r);
+      pc->busy = false;
+      r.pc = nullptr;
     } else {
       r.state = Q_RUNNING;
       s->active.push_back(r.id);
@@ -360,7 +403,8 @@ extern "C" fcns_status fcns_server_result(fcns_server* s, int64_t id, double* st
   if (f == s->reqs.end()) return srv_fail(s, FCNS_EINVAL, "unknown request");
   Request& r = *f->second;
   if (r.state != Q_DONE) return srv_fail(s, FCNS_ESTATE, "request not finished");
-  if (r.status != FCNS_OK && r.status != FCNS_ENONFINITE) return srv_fail(s, r.status, r.err);
+  if (r.status != FCNS_OK && r.status != FCNS_ENONFINITE && r.status != FCNS_ECANCELED)
+    return srv_fail(s, r.status, r.err);
   if (stats) {
     std::vector<float> sm = r.step_ms;
     std::sort(sm.begin(), sm.end());
@@ -391,6 +435,20 @@ extern "C" fcns_status fcns_server_step_times(fcns_server* s, int64_t id, int32_
   const int k = std::min<int>(max, (int)r.step_ms.size());
   if (ms) memcpy(ms, r.step_ms.data(), k * sizeof(float));
   *n = k;
+  return FCNS_OK;
+}
+
+extern "C" fcns_status fcns_server_cancel(fcns_server* s, int64_t id) {
+  if (!s) return FCNS_EINVAL;
+  auto f = s->reqs.find(id);
+  if (f == s->reqs.end()) return srv_fail(s, FCNS_EINVAL, "unknown request");
+  Request& r = *f->second;
+  if (r.state == Q_QUEUED) {
+    s->queue.erase(std::find(s->queue.begin(), s->queue.end(), id));
+    finish_with_error(s, r, FCNS_ECANCELED, "cancelled");
+  } else if (r.state == Q_RUNNING) {
+    r.cancel = true;   // the next poll finishes it once its steps are done
+  }
   return FCNS_OK;
 }
 

@@ -37,6 +37,8 @@ struct ZArgs {
   const double* sigx;     // filter factors per direction (nkx, ny, N')
   const double* sigy;
   const double* sigz;
+  int* nonfinite;         // non-null: set to 1 by k_z_back when the state it
+                          // reads holds a NaN or an infinity
 };
 
 // Mixed-space arrays (nl, buoy) hold cpx<T> of the kernel's transform type T.

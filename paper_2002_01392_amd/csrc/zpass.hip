@@ -256,6 +256,14 @@ __global__ __launch_bounds__(ZNT) void k_z_back(ZArgs a, const cpx<double>* __re
     const int l = lt + r * ZLS;
     keep[r] = (pv && l < npr) ? src[(long long)l * g.npen + p] : zero<double>();
   }
+  if (a.nonfinite) {
+    // the step's non-finite check: every coefficient of the state passes here
+    bool bad = false;
+#pragma unroll
+    for (int r = 0; r < OWN; ++r)
+      bad = bad || !__builtin_isfinite(keep[r].x) || !__builtin_isfinite(keep[r].y);
+    if (bad) *a.nonfinite = 1;
+  }
   const double inv = 1.0 / npr;
   const int npass = dzdst ? 2 : 1;
   for (int pass = 0; pass < npass; ++pass) {

@@ -21,7 +21,8 @@ rb_512x512x257       Rayleigh-Benard, box 2 x 2 x 1, gamma=1, Ra=1e8, Pr=1,
                      the walls, dt=1e-3, 50 steps
 serving_stream       64 requests, Poisson arrivals at 20/s, channel or RB
                      (50/50), side in {32,64,96,128,192}, nz = side+1, C=31,
-                     Re ~ U[500,5000] or Ra ~ logU[1e4,1e8], 20 steps each
+                     Re ~ U[500,5000] or Ra ~ logU[1e4,1e8], 20 steps each,
+                     started from the App. A solenoidal no-slip noise
 """
 from __future__ import annotations
 
@@ -143,14 +144,20 @@ def curl_eigen_noise(nx, ny, nz, lx, ly, lz, rms, seed, kh2=(4, 25), mrange=(2, 
     and k^-3 (b) with k^2 = kx^2 + ky^2 + (lambda_m / Lz)^2.  The mode numbers
     count the box's fundamental wavenumbers (the paper's box is 2 pi wide).
     Component form: q = (d2 phi/dxdz + dpsi/dy, d2 phi/dydz - dpsi/dx,
-    -(d2/dx2 + d2/dy2) phi).  Scaled to the requested rms."""
+    -(d2/dx2 + d2/dy2) phi).  Scaled to the requested rms.
+
+    Evaluated as z profiles times horizontal harmonics: with phase
+    ph = kx x + ky y, cos(ph + alpha) = cos(ph) cos(alpha) - sin(ph) sin(alpha),
+    so each horizontal mode contributes (profile_c)(z) cos(ph) +
+    (profile_s)(z) sin(ph), and the sum over modes is one matrix product."""
     r = rng(seed)
     x, y, z = grid(nx, ny, nz, lx, ly, lz)
     X, Y = np.meshgrid(x, y, indexing="xy")
     zp = z / lz - 0.5
     lams = clamped_beam_lambdas(mrange[1])
     nmax = int(math.isqrt(kh2[1]))
-    v = np.zeros((3, nz, ny, nx))
+    prof = []    # per horizontal mode: (3 components, cos/sin, nz) profiles
+    harm = []    # per horizontal mode: (cos(ph), sin(ph)) flattened
     for n in range(-nmax, nmax + 1):
         for l in range(0, nmax + 1):
             if l == 0 and n < 0:
@@ -158,7 +165,7 @@ def curl_eigen_noise(nx, ny, nz, lx, ly, lz, rms, seed, kh2=(4, 25), mrange=(2, 
             if not kh2[0] <= n * n + l * l <= kh2[1]:
                 continue
             kx, ky = 2 * math.pi * n / lx, 2 * math.pi * l / ly
-            ph = kx * X + ky * Y
+            P = np.zeros((3, 2, nz))
             for m in range(mrange[0], mrange[1] + 1):
                 lam = lams[m - 1]
                 k = math.sqrt(kx * kx + ky * ky + (lam / lz) ** 2)
@@ -168,12 +175,29 @@ def curl_eigen_noise(nx, ny, nz, lx, ly, lz, rms, seed, kh2=(4, 25), mrange=(2, 
                 g, dg, _ = _g_cr(m, lam, zp)
                 dgz = dg / lz
                 sz = np.sin(m * math.pi * (zp + 0.5))
-                ca, sa = np.cos(ph + 2 * math.pi * pha), np.sin(ph + 2 * math.pi * pha)
-                cb, sb = np.cos(ph + 2 * math.pi * phb), np.sin(ph + 2 * math.pi * phb)
-                # phi = a cos(ph + alpha) g(z), psi = b cos(ph + beta) sin(...)
-                v[0] += (-a * kx * sa)[None] * dgz[:, None, None] + (-b * ky * sb)[None] * sz[:, None, None]
-                v[1] += (-a * ky * sa)[None] * dgz[:, None, None] + (b * kx * sb)[None] * sz[:, None, None]
-                v[2] += (a * (kx * kx + ky * ky) * ca)[None] * g[:, None, None]
+                al, be = 2 * math.pi * pha, 2 * math.pi * phb
+                # phi = a cos(ph + al) g(z), psi = b cos(ph + be) sin(m pi (z'+1/2)):
+                # u = -a kx sin(ph + al) g' - b ky sin(ph + be) sz,
+                # v = -a ky sin(ph + al) g' + b kx sin(ph + be) sz,
+                # w = a (kx^2 + ky^2) cos(ph + al) g;
+                # sin(ph + t) = sin(ph) cos t + cos(ph) sin t
+                for comp, ca, cb in ((0, -a * kx, -b * ky), (1, -a * ky, b * kx)):
+                    P[comp, 0] += ca * math.sin(al) * dgz + cb * math.sin(be) * sz
+                    P[comp, 1] += ca * math.cos(al) * dgz + cb * math.cos(be) * sz
+                aw = a * (kx * kx + ky * ky)
+                P[2, 0] += aw * math.cos(al) * g
+                P[2, 1] -= aw * math.sin(al) * g
+            ph = (kx * X + ky * Y).ravel()
+            prof.append(P)
+            harm.append((np.cos(ph), np.sin(ph)))
+    v = np.zeros((3, nz, ny * nx))
+    if prof:
+        Hc = np.stack([h[0] for h in harm])          # (modes, ny nx)
+        Hs = np.stack([h[1] for h in harm])
+        Pr = np.stack(prof)                          # (modes, 3, 2, nz)
+        for comp in range(3):
+            v[comp] = Pr[:, comp, 0].T @ Hc + Pr[:, comp, 1].T @ Hs
+    v = v.reshape(3, nz, ny, nx)
     cur = math.sqrt(float(np.mean(v ** 2)) * 3.0)
     return v * (rms / cur) if cur > 0 else v
 
@@ -287,37 +311,53 @@ class Workload:
             rms = self.extra.get("noise_rms", 1e-3)
             if self.extra.get("noise_rel_bulk"):
                 rms = rms * ubulk
-            v = solenoidal_noise(self.nx, self.ny, self.nz, self.lx, self.ly, self.lz,
-                                 self.extra.get("kmax", 4), self.extra.get("mmax", 4),
-                                 rms, self.seed)
+            if self.extra.get("perturbation") == "curl_eigen":
+                v = curl_eigen_noise(self.nx, self.ny, self.nz, self.lx, self.ly, self.lz, rms,
+                                     self.seed)
+            else:
+                v = solenoidal_noise(self.nx, self.ny, self.nz, self.lx, self.ly, self.lz,
+                                     self.extra.get("kmax", 4), self.extra.get("mmax", 4),
+                                     rms, self.seed)
             v[0] += U[:, None, None]
             return v, None
-        v = np.zeros((3, self.nz, self.ny, self.nx))
+        rms = self.extra.get("noise_rms", 1e-3)
+        if self.extra.get("perturbation") == "curl_eigen":
+            # App. A velocity noise beside the temperature noise (seed + 1)
+            v = curl_eigen_noise(self.nx, self.ny, self.nz, self.lx, self.ly, self.lz, rms,
+                                 self.seed + 1)
+        else:
+            v = np.zeros((3, self.nz, self.ny, self.nx))
         th = wall_vanishing_noise(self.nx, self.ny, self.nz, self.lx, self.ly, self.lz,
                                   self.extra.get("kmax", 8), self.extra.get("mmax", 8),
-                                  self.extra.get("noise_rms", 1e-3), self.seed)
+                                  rms, self.seed)
         return v, th
 
 
 def channel(nx, ny, nz, re, d=5, C=25, dt=1e-3, steps=10, seed=1, name=None,
-            noise_rms=1e-3, kmax=4, mmax=4):
-    """Laminar-scaled channel: u_max = 1, Re = Lz u_bulk / nu (Sec. 6)."""
+            noise_rms=1e-3, kmax=4, mmax=4, perturbation="solenoidal"):
+    """Laminar-scaled channel: u_max = 1, Re = Lz u_bulk / nu (Sec. 6).
+    perturbation: "solenoidal" (curl of a random vector potential with a wall
+    envelope) or "curl_eigen" (the App. A noise)."""
     lz = 2.0
     nu = lz * (2.0 / 3.0) / re
     G = 8.0 * nu / lz ** 2
     return Workload(name or f"channel_{nx}x{ny}x{nz}", nx, ny, nz, 4 * np.pi, 2 * np.pi,
                     lz, nu, d, C, dt, steps, seed, forcing_x=G, kind="channel",
-                    extra=dict(profile="laminar", noise_rms=noise_rms, kmax=kmax, mmax=mmax))
+                    extra=dict(profile="laminar", noise_rms=noise_rms, kmax=kmax, mmax=mmax,
+                               perturbation=perturbation))
 
 
 def rayleigh_benard(nx, ny, nz, ra, pr=1.0, d=5, C=31, dt=1e-3, steps=50, seed=3,
-                    name=None, noise_rms=1e-3, kmax=8, mmax=8):
-    """Boussinesq box 2 x 2 x 1 with gamma = 1 (Sec. 7, Ra = gamma^2 h^4/(nu kappa))."""
+                    name=None, noise_rms=1e-3, kmax=8, mmax=8, perturbation="none"):
+    """Boussinesq box 2 x 2 x 1 with gamma = 1 (Sec. 7, Ra = gamma^2 h^4/(nu kappa)).
+    perturbation: "none" (v = 0, temperature noise only) or "curl_eigen" (also
+    the App. A velocity noise, same rms)."""
     nu = math.sqrt(pr / ra)
     kappa = nu / pr
     return Workload(name or f"rb_{nx}x{ny}x{nz}", nx, ny, nz, 2.0, 2.0, 1.0, nu, d, C,
                     dt, steps, seed, boussinesq=True, kappa=kappa, gamma=1.0, kind="rb",
-                    extra=dict(noise_rms=noise_rms, kmax=kmax, mmax=mmax))
+                    extra=dict(noise_rms=noise_rms, kmax=kmax, mmax=mmax,
+                               perturbation=perturbation))
 
 
 WORKLOADS = {
@@ -354,8 +394,9 @@ def serving_stream(n=64, rate=20.0, steps=20, seed=5, sides=SERVING_SIDES, C=31)
     """List of (arrival_time_s, Workload) for the serving workload: Poisson
     arrivals, channel or Rayleigh-Benard with equal odds, side uniform over
     `sides` (nz = side + 1, so N' = side + 32 with C = 31), Re uniform in
-    [500, 5000] or Ra log-uniform in [1e4, 1e8], perturbations with few modes
-    (|k| <= 2 channel, 4 Rayleigh-Benard) to keep input generation short."""
+    [500, 5000] or Ra log-uniform in [1e4, 1e8].  Every request starts from
+    the App. A solenoidal no-slip noise (the paper's initial perturbation),
+    plus temperature noise (|k| <= 4) for Rayleigh-Benard."""
     r = rng(seed)
     t = 0.0
     out = []
@@ -365,11 +406,12 @@ def serving_stream(n=64, rate=20.0, steps=20, seed=5, sides=SERVING_SIDES, C=31)
         if r.random() < 0.5:
             re = float(r.uniform(500.0, 5000.0))
             w = channel(side, side, side + 1, re, d=5, C=C, steps=steps, seed=500 + i,
-                        name=f"req{i}_channel_{side}", kmax=2, mmax=2)
+                        name=f"req{i}_channel_{side}", perturbation="curl_eigen")
         else:
             ra = float(10 ** r.uniform(4.0, 8.0))
             w = rayleigh_benard(side, side, side + 1, ra, d=5, C=C, steps=steps,
-                                seed=500 + i, name=f"req{i}_rb_{side}", kmax=4, mmax=4)
+                                seed=500 + i, name=f"req{i}_rb_{side}", kmax=4, mmax=4,
+                                perturbation="curl_eigen")
         w = replace(w, dt=stable_dt(w))
         out.append((t, w))
     return out
