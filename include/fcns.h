@@ -106,6 +106,24 @@ fcns_status fcns_fc_extend(fcns_ctx* ctx, const double* in, int64_t nlines, int6
 fcns_status fcns_fc_derivative(fcns_ctx* ctx, int32_t order, const double* in, int64_t nlines,
                                int64_t ps, int64_t ls, double* out);
 
+/* fcns_fc_derivative for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): no context; the transform's twiddle table and the continuation
+ * matrix M_r = A_r Q_r^T are staged in a static device array of the library
+ * (64 KiB of twiddles and 256 float64 of M per device, held until the
+ * process ends) instead of context buffers.  nz, lz, fc_d, fc_C and
+ * fc_table (HOST, the layout of fcns_problem.fc_table) describe the lines as
+ * in fcns_problem; order, in, nlines, ps, ls, out as in fcns_fc_derivative;
+ * hip_stream: the stream to enqueue on (NULL = default).  EINVAL for bad
+ * sizes, N' = nz + C odd or above 512, C * d above 256, or a transform table
+ * above the array.  Allocates nothing (host or device).  Calls that overlap
+ * on one device (other host threads, or streams not ordered with each other)
+ * race on the shared array; its contents are rewritten by every call. */
+fcns_status fcns_fc_derivative_noalloc(int32_t nz, double lz, int32_t fc_d, int32_t fc_C,
+                                       const double* fc_table, int32_t order, const double* in,
+                                       int64_t nlines, int64_t ps, int64_t ls, double* out,
+                                       void* hip_stream);
+
 /* Advective term -(v.grad)v (and -(v.grad)theta when theta != NULL; needs a
  * Boussinesq context) from the FC-continued transform of v (Sec. 4.2:
  * derivatives in Fourier space, products in physical space, no padding).

@@ -44,6 +44,8 @@ SIGNATURES = {
     "fcns_destroy": (ctypes.c_int, [_P]),
     "fcns_fc_extend": (ctypes.c_int, [_P, _P, _I64, _I64, _I64, _P, _I64, _I64]),
     "fcns_fc_derivative": (ctypes.c_int, [_P, _I32, _P, _I64, _I64, _I64, _P]),
+    "fcns_fc_derivative_noalloc": (ctypes.c_int, [_I32, _D, _I32, _I32, _P, _I32, _P, _I64,
+                                                  _I64, _I64, _P, _P]),
     "fcns_rhs_nonlinear": (ctypes.c_int, [_P, _P, _P, _I32, _P, _P]),
     "fcns_pressure_project": (ctypes.c_int, [_P, _P, _D, _P, _P]),
     "fcns_set_state": (ctypes.c_int, [_P, _P, _P]),

@@ -10,7 +10,7 @@ import sys
 PKG = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libfcns.so")
-SOURCES = ["zpass.hip", "xypass.hip", "diag.hip", "fcns_api.cpp", "fcns_server.cpp"]
+SOURCES = ["zpass.hip", "xypass.hip", "diag.hip", "noalloc.hip", "fcns_api.cpp", "fcns_server.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 # Packed FP32 instructions are disabled for all device code (see the design
