@@ -72,6 +72,11 @@ def algorithmic_bytes(w, cls, stage, keep_pressure=False):
         return 6 * S + (M if keep_pressure else 0)   # read V*, write V
     if cls == "z_back":
         return F * S + 2 * F * M                     # read V, write v and dv/dz
+    if cls == "z_pass":
+        # the fused z pass: read NL, V^t and W (W = V^t at stage 1), write the
+        # new state and its v, dv/dz
+        reads_state = F * S if stage == 1 else 2 * F * S
+        return F * M + reads_state + F * S + 2 * F * M + (M if keep_pressure else 0)
     raise KeyError(cls)
 
 
@@ -141,6 +146,7 @@ def precision_run(name="channel_256x256x257", steps=100, warmup=2):
     for prec in ("fp64", "mixed"):
         s = Solver.from_workload(w, keep_pressure=True, precision=prec)
         s.set_state(v0)
+        out[prec + "_autotune"] = s.autotune()
         s.rk_step(w.dt, warmup)
         s.set_state(v0)
         torch.cuda.synchronize()
@@ -163,6 +169,7 @@ def precision_run(name="channel_256x256x257", steps=100, warmup=2):
     err["p"] = rel(pm, pd)
     return {"workload": name, "steps": steps, "unit": UNIT,
             "fp64": out["fp64"], "mixed": out["mixed"],
+            "autotune": {"fp64": out["fp64_autotune"], "mixed": out["mixed_autotune"]},
             "speedup": out["fp64"]["ms_per_step"] / out["mixed"]["ms_per_step"],
             "rel_l2_vs_fp64": err,
             "note": "nonlinear term in FP32 (back transforms of the state, x and y FFTs, "

@@ -165,9 +165,9 @@ fcns_status fcns_set_finite_check(fcns_ctx* ctx, int32_t mode);
 /* Synchronize the context stream and return FCNS_ENONFINITE if a step
  * enqueued so far left a non-finite state (FCNS_OK otherwise). */
 fcns_status fcns_check_finite(fcns_ctx* ctx);
-/* The host copy of the flag as of the last completed rk_step call, without
- * synchronizing (1: non-finite; valid once the work of that call is done,
- * e.g. after an event recorded behind it has completed). */
+/* The flag without synchronizing (1: non-finite).  It lives in pinned
+ * host-coherent memory that the kernels write directly, so it covers every
+ * step whose work has completed (e.g. behind an event that has completed). */
 int32_t fcns_nonfinite_flag(const fcns_ctx* ctx);
 
 /* Batched stepping of n independent contexts (HOST arrays of n context
@@ -191,6 +191,16 @@ fcns_status fcns_batch_step(fcns_ctx* const* ctxs, int32_t n, const double* dts,
  * reallocate the small z twiddle tables.  report (HOST, nullable) receives a
  * one-line summary of the choices. */
 fcns_status fcns_autotune(fcns_ctx* ctx, char* report, int32_t report_len);
+
+/* Choose how rk_step runs the z pass of a stage (continuation, z
+ * transforms, RK combine, projection and the back transforms of the new
+ * state): on = 1 one fused kernel per stage (V* and the new state pass
+ * through the caches within one workgroup), 0 three kernels (the default;
+ * fcns_autotune picks the faster).  The fused form applies to FP64 contexts
+ * with N' <= 288 and to stages whose output buffer is not their input (both
+ * stages of o = 2); other stages keep three kernels.  EINVAL if on = 1 for a
+ * context it does not apply to.  Results agree to rounding. */
+fcns_status fcns_set_z_fused(fcns_ctx* ctx, int32_t on);
 
 /* Same as fcns_rk_step, by replaying a HIP graph of one step.  The graph is
  * captured on the first call and again whenever dt changes (capture

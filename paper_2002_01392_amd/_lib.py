@@ -52,6 +52,7 @@ SIGNATURES = {
     "fcns_rk_step": (ctypes.c_int, [_P, _D, _I32]),
     "fcns_rk_graph": (ctypes.c_int, [_P, _D, _I32]),
     "fcns_set_finite_check": (ctypes.c_int, [_P, _I32]),
+    "fcns_set_z_fused": (ctypes.c_int, [_P, _I32]),
     "fcns_check_finite": (ctypes.c_int, [_P]),
     "fcns_nonfinite_flag": (ctypes.c_int32, [_P]),
     "fcns_autotune": (ctypes.c_int, [_P, ctypes.c_char_p, _I32]),
@@ -356,6 +357,10 @@ class Solver:
     def check_finite(self):
         self._check(self.lib.fcns_check_finite(self.ctx))
 
+    def set_z_fused(self, on=True):
+        """Run each stage's z pass as one fused kernel (FP64, N' <= 288)."""
+        self._check(self.lib.fcns_set_z_fused(self.ctx, int(bool(on))))
+
     def autotune(self):
         """Pick the fastest launch choices for this shape; returns the summary."""
         buf = ctypes.create_string_buffer(1024)
@@ -432,7 +437,7 @@ class Solver:
         self._keep = (fs, wg)
 
     TIMING_CLASSES = ("y_back_dy", "y_back_dz", "x_nl", "y_fwd", "z_stageA", "z_stageB",
-                      "z_back")
+                      "z_back", "z_pass")
 
     def set_timing(self, enable=True, classes=None):
         """Event-time rk_step's kernels: every class, or only those named in

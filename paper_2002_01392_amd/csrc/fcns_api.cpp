@@ -50,8 +50,9 @@ struct fcns_ctx {
   cpx<double>* GW = nullptr;   // wall tangential gradient [2][2][npen]
   cpx<double>* GWT = nullptr;  // scratch wall gradient
   double* DG = nullptr;        // diagnostics: per-plane sums [nz][5], then spectra
-  // non-finite check of the state: a device flag set by the z back transform
-  // of every stage, copied after each rk_step call into pinned host memory
+  // non-finite check of the state: a flag in pinned, host-coherent memory,
+  // raised by the z back transform of every stage (dflag: its device
+  // address), read by the host once the work is done; no copy per step
   int* dflag = nullptr;
   int* hflag = nullptr;
   int check_mode = FCNS_CHECK_SYNC;
@@ -65,6 +66,8 @@ struct fcns_ctx {
   int ynopf = 0;
   long long ygrid1 = 0;  // y back with d/dy (two transforms per tile)
   int ynopf1 = 0;
+  bool zfuse = false;    // FP64 stages writing the other state buffer: one fused z
+                         // pass (chosen by fcns_autotune where it is faster)
   bool has_state = false;
   bool has_pressure = false;
   std::string err;
@@ -85,9 +88,10 @@ struct fcns_ctx {
 };
 
 // Kernel classes timed by fcns_set_timing.
-enum { T_YBACK_DY = 0, T_YBACK_DZ, T_XNL, T_YFWD, T_ZSTAGEA, T_ZSTAGEB, T_ZBACK, T_NCLS };
+enum { T_YBACK_DY = 0, T_YBACK_DZ, T_XNL, T_YFWD, T_ZSTAGEA, T_ZSTAGEB, T_ZBACK, T_ZPASS,
+       T_NCLS };
 static const char* kTimingNames[T_NCLS] = {"y_back_dy", "y_back_dz", "x_nl", "y_fwd",
-                                           "z_stageA", "z_stageB", "z_back"};
+                                           "z_stageA", "z_stageB", "z_back", "z_pass"};
 
 static void timing_flush(fcns_ctx* c) {
   if (c->recs.empty()) return;
@@ -247,7 +251,7 @@ static void free_all(fcns_ctx* c) {
   for (hipEvent_t e : c->evpool) (void)hipEventDestroy(e);
   c->evpool.clear();
   void* ps[] = {c->twz, c->twx, c->twy, c->twz_f, c->twx_f, c->twy_f, c->rootz, c->fcM, c->sigx, c->sigy, c->sigz, c->P, c->Q,
-                c->VS, c->MV, c->MVT, c->XYB, c->NLB, c->PM, c->GW, c->GWT, c->DG, c->dflag};
+                c->VS, c->MV, c->MVT, c->XYB, c->NLB, c->PM, c->GW, c->GWT, c->DG};
   for (void* p : ps)
     if (p) (void)hipFree(p);
   if (c->hflag) (void)hipHostFree(c->hflag);
@@ -408,17 +412,19 @@ extern "C" fcns_status fcns_create(const fcns_problem* prob, void* hip_stream, f
       (st = alloc(c, &c->GW, 4 * g.npen)) || (st = alloc(c, &c->GWT, 4 * g.npen)) ||
       (st = hipMalloc((void**)&c->DG, sizeof(double) * (5 * (size_t)p.nz + g.nkx + p.ny)) ==
                     hipSuccess ? FCNS_OK : fail(c, FCNS_ENOMEM, "device allocation failed")) ||
-      (st = alloc(c, reinterpret_cast<cpx<double>**>(&c->dflag), 1)) ||
-      (st = hipHostMalloc((void**)&c->hflag, sizeof(int), hipHostMallocDefault) == hipSuccess
-                ? FCNS_OK : fail(c, FCNS_ENOMEM, "pinned host allocation failed"))) {
+      (st = hipHostMalloc((void**)&c->hflag, sizeof(cpx<double>),
+                          hipHostMallocMapped | hipHostMallocCoherent) == hipSuccess
+                ? FCNS_OK : fail(c, FCNS_ENOMEM, "pinned host allocation failed")) ||
+      (st = check_hip(c, hipHostGetDevicePointer((void**)&c->dflag, c->hflag, 0),
+                      "flag device address"))) {
     g_create_err = c->err;
     free_all(c);
     delete c;
     return st;
   }
   launch_fill(c->GW, 4 * g.npen, c->stream);
+  *(volatile int*)c->hflag = 0;
   launch_fill(reinterpret_cast<cpx<double>*>(c->dflag), 1, c->stream);
-  *c->hflag = 0;
   if ((st = check_launch(c, "fill")) != FCNS_OK) {
     g_create_err = c->err;
     free_all(c);
@@ -540,24 +546,20 @@ static void state_to_mv(fcns_ctx* c, const cpx<double>* src, bool check = false)
   }
 }
 
-// a new state: the device flag cleared, and its host copy once the stream
-// gets there
+static int read_flag(const fcns_ctx* c) { return *(volatile const int*)c->hflag; }
+
+// a new state: the flag cleared when the stream gets there
 static void clear_flag(fcns_ctx* c) {
   launch_fill(reinterpret_cast<cpx<double>*>(c->dflag), 1, c->stream);
-  (void)hipMemcpyAsync(c->hflag, c->dflag, sizeof(int), hipMemcpyDeviceToHost, c->stream);
 }
 
-// After the steps of one call: the flag into pinned host memory; in the
-// synchronous mode wait for it and report a non-finite state.
+// After the steps of one call: in the synchronous mode wait for them and
+// report a non-finite state.
 static fcns_status finish_steps(fcns_ctx* c, const char* what) {
   fcns_status st = check_launch(c, what);
-  if (st != FCNS_OK || c->check_mode == FCNS_CHECK_OFF) return st;
-  if ((st = check_hip(c, hipMemcpyAsync(c->hflag, c->dflag, sizeof(int), hipMemcpyDeviceToHost,
-                                        c->stream), what)))
-    return st;
-  if (c->check_mode != FCNS_CHECK_SYNC) return FCNS_OK;
+  if (st != FCNS_OK || c->check_mode != FCNS_CHECK_SYNC) return st;
   if ((st = check_hip(c, hipStreamSynchronize(c->stream), what))) return st;
-  if (*c->hflag) return fail(c, FCNS_ENONFINITE, "non-finite value in the state after a step");
+  if (read_flag(c)) return fail(c, FCNS_ENONFINITE, "non-finite value in the state after a step");
   return FCNS_OK;
 }
 
@@ -613,34 +615,35 @@ extern "C" fcns_status fcns_set_state(fcns_ctx* c, const double* v, const double
   return st;
 }
 
-// One RK stage j of o (Sec. 4.4), c = dt/(o-j+1).  T: type of the transforms
-// and arrays of the nonlinear term (float in a mixed-precision context); the
-// continued state, the FC extension, stage A's transforms of the RK combine,
-// and the projection are FP64 throughout.
+// The z pass of one stage (Sec. 4.4 steps 1-5 after the nonlinear term is in
+// NLB): W the previous stage's state, OUT the new one, cj the stage
+// coefficient, pressure: keep the mixed pressure.  fused: one kernel for the
+// whole pass (FP64, OUT != W, N' <= 288), else stage A, stage B and the back
+// transform of the new state.  T as in rk_stage.
 template <typename T>
-static void rk_stage(fcns_ctx* c, int j, int o, double dt) {
+static void z_part(fcns_ctx* c, cpx<double>* W, cpx<double>* OUT, double cj, bool pressure,
+                   bool fused) {
   const cpx<T>* mv = reinterpret_cast<const cpx<T>*>(c->MV);
   const cpx<T>* nlb = reinterpret_cast<const cpx<T>*>(c->NLB);
   const Geom& g = c->g;
   const long long S = c->S, M = c->M;
   const int nf = c->nf;
-  const double cj = dt / (double)(o - j + 1);
-  cpx<double>* W = (j == 1) ? c->P : c->Q;
-  cpx<double>* OUT = (j == o) ? c->P : c->Q;
-  // y-back, x-pass with products, y-fwd: nonlinear term in mixed space
-  nonlinear_from_mixed<T>(c, mv, nf, true);
-  // stage A: pressureless update, wall injection, FC re-extension
   StageAArgs A{};
   for (int f = 0; f < nf; ++f) {
     A.nl[f] = nlb + f * M;
     A.vt[f] = c->P + f * S;
     A.w[f] = W + f * S;
-    A.out[f] = (f < 3) ? c->VS + f * S : OUT + f * S;
+    A.out[f] = (f < 3 && !fused) ? c->VS + f * S : OUT + f * S;
     A.buoy[f] = nullptr;
   }
   if (nf == 4) {
-    A.buoy[2] = mv + (2 * 3) * M;  // mixed theta of the previous stage
-    A.buoy[3] = mv + (2 * 2) * M;  // mixed w of the previous stage
+    if (fused) {
+      A.buoy[2] = W + 3 * S;  // continued theta of the previous stage (for w)
+      A.buoy[3] = W + 2 * S;  // continued w of the previous stage (for theta)
+    } else {
+      A.buoy[2] = mv + (2 * 3) * M;  // mixed theta of the previous stage
+      A.buoy[3] = mv + (2 * 2) * M;  // mixed w of the previous stage
+    }
   }
   A.gwall = c->GW;
   A.c = cj;
@@ -648,18 +651,30 @@ static void rk_stage(fcns_ctx* c, int j, int o, double dt) {
   A.kappa = c->prob.kappa;
   A.gamma = c->prob.gamma;
   A.forcing_sum = c->prob.forcing_x * (double)g.nx * (double)g.ny;
-  tbeg(c, T_ZSTAGEA);
-  launch_z_stageA<T>(zargs(c), c->big_z, A, nf, c->stream);
-  tend(c);
-  // stage B: projection, next-stage wall gradient, mixed v and dv/dz
   StageBArgs B{};
   for (int i = 0; i < 3; ++i) {
-    B.vs[i] = c->VS + i * S;
+    B.vs[i] = fused ? OUT + i * S : c->VS + i * S;
     B.vout[i] = OUT + i * S;
   }
   B.gwall = c->GW;
-  B.pmix = (c->prob.keep_pressure && j == o) ? c->PM : nullptr;
+  B.pmix = pressure ? c->PM : nullptr;
   B.c = cj;
+  if (fused) {
+    // V* lives in OUT's velocity slots between its stage A and its
+    // projection, inside one workgroup
+    ZBackArgs Z{c->MV, M};
+    ZArgs za = zargs(c);
+    za.nonfinite = c->dflag;
+    tbeg(c, T_ZPASS);
+    launch_z_pass(za, c->big_z, A, B, Z, nf, c->stream);
+    tend(c);
+    return;
+  }
+  // stage A: pressureless update, wall injection, FC re-extension
+  tbeg(c, T_ZSTAGEA);
+  launch_z_stageA<T>(zargs(c), c->big_z, A, nf, c->stream);
+  tend(c);
+  // stage B: projection, next-stage wall gradient
   tbeg(c, T_ZSTAGEB);
   launch_z_stageB(zargs(c), c->big_z, B, c->stream);
   tend(c);
@@ -668,6 +683,23 @@ static void rk_stage(fcns_ctx* c, int j, int o, double dt) {
   tbeg(c, T_ZBACK);
   state_to_mv(c, OUT, true);
   tend(c);
+}
+
+static bool can_fuse(const fcns_ctx* c) { return !c->mixed && z_pass_fits(zargs(c)); }
+
+// One RK stage j of o (Sec. 4.4), c = dt/(o-j+1).  T: type of the transforms
+// and arrays of the nonlinear term (float in a mixed-precision context); the
+// continued state, the FC extension, stage A's transforms of the RK combine,
+// and the projection are FP64 throughout.
+template <typename T>
+static void rk_stage(fcns_ctx* c, int j, int o, double dt) {
+  const double cj = dt / (double)(o - j + 1);
+  cpx<double>* W = (j == 1) ? c->P : c->Q;
+  cpx<double>* OUT = (j == o) ? c->P : c->Q;
+  // y-back, x-pass with products, y-fwd: nonlinear term in mixed space
+  nonlinear_from_mixed<T>(c, reinterpret_cast<const cpx<T>*>(c->MV), c->nf, true);
+  const bool fused = c->zfuse && OUT != W && can_fuse(c);
+  z_part<T>(c, W, OUT, cj, c->prob.keep_pressure && j == o, fused);
 }
 
 extern "C" fcns_status fcns_rk_step(fcns_ctx* c, double dt, int32_t nsteps) {
@@ -686,6 +718,14 @@ extern "C" fcns_status fcns_rk_step(fcns_ctx* c, double dt, int32_t nsteps) {
   return finish_steps(c, "rk_step");
 }
 
+extern "C" fcns_status fcns_set_z_fused(fcns_ctx* c, int32_t on) {
+  if (!c) return FCNS_EINVAL;
+  if (on && !can_fuse(c))
+    return fail(c, FCNS_EINVAL, "the fused z pass needs an FP64 context and N' <= 288");
+  c->zfuse = on != 0;
+  return FCNS_OK;
+}
+
 extern "C" fcns_status fcns_set_finite_check(fcns_ctx* c, int32_t mode) {
   if (!c) return FCNS_EINVAL;
   if (mode != FCNS_CHECK_OFF && mode != FCNS_CHECK_SYNC && mode != FCNS_CHECK_DEFERRED)
@@ -698,12 +738,12 @@ extern "C" fcns_status fcns_check_finite(fcns_ctx* c) {
   if (!c) return FCNS_EINVAL;
   fcns_status st = check_hip(c, hipStreamSynchronize(c->stream), "check_finite");
   if (st != FCNS_OK) return st;
-  if (*c->hflag) return fail(c, FCNS_ENONFINITE, "non-finite value in the state after a step");
+  if (read_flag(c)) return fail(c, FCNS_ENONFINITE, "non-finite value in the state after a step");
   return FCNS_OK;
 }
 
 extern "C" int32_t fcns_nonfinite_flag(const fcns_ctx* c) {
-  return (c && c->hflag) ? *c->hflag : 0;
+  return (c && c->hflag) ? read_flag(c) : 0;
 }
 
 // Capture one step (all o stages) for this dt on a private stream; the graph
@@ -935,6 +975,21 @@ extern "C" fcns_status fcns_autotune(fcns_ctx* c, char* report, int32_t report_l
       snprintf(line, sizeof(line), " (%.3f ms)", best);
       rep += line;
     }
+  }
+  // z pass: one fused kernel or the three separate ones, timed as a first
+  // stage would run them (the wall gradient is saved and restored; Q, VS and
+  // the mixed arrays are scratch here)
+  if (can_fuse(c)) {
+    const size_t gwb = 4 * (size_t)g.npen * sizeof(cpx<double>);
+    (void)hipMemcpyAsync(c->GWT, c->GW, gwb, hipMemcpyDeviceToDevice, c->stream);
+    const double cj = 1e-3;
+    const float ms_f = time_ms(c, [&] { z_part<double>(c, c->P, c->Q, cj, false, true); }, reps);
+    const float ms_s = time_ms(c, [&] { z_part<double>(c, c->P, c->Q, cj, false, false); }, reps);
+    (void)hipMemcpyAsync(c->GW, c->GWT, gwb, hipMemcpyDeviceToDevice, c->stream);
+    c->zfuse = ms_f <= ms_s;
+    snprintf(line, sizeof(line), "; z pass: %s (fused %.3f ms, split %.3f ms)",
+             c->zfuse ? "fused" : "split", ms_f, ms_s);
+    rep += line;
   }
   // the mixed-space fields of the state were overwritten only in scratch; the
   // ones the next step reads are rebuilt from the state

@@ -109,6 +109,20 @@ void launch_z_back(const ZArgs& a, bool big, const cpx<double>* src, cpx<T>* dst
 template <typename TM>
 void launch_z_stageA(const ZArgs& a, bool big, const StageAArgs& s, int nfields, hipStream_t st);
 void launch_z_stageB(const ZArgs& a, bool big, const StageBArgs& s, hipStream_t st);
+
+// The fused z pass of one FP64 stage (stage A for every field, the
+// projection, the back transforms of the new state): sa.out velocity slots
+// receive V* and then the projected state (sb.vs = sb.vout = sa.out),
+// sa.buoy[2] / [3] are the continued W of theta / w, zb.mv gets v_f, dv_f/dz
+// at slots 2f, 2f + 1.  z_pass_fits: N' small enough for the rows a thread
+// keeps in registers (N' <= 288).
+struct ZBackArgs {
+  cpx<double>* mv;   // mixed v_f at slot 2f, dv_f/dz at 2f + 1
+  long long ms;      // mixed field stride (elements)
+};
+bool z_pass_fits(const ZArgs& a);
+void launch_z_pass(const ZArgs& a, bool big, const StageAArgs& sa, const StageBArgs& sb,
+                   const ZBackArgs& zb, int nfields, hipStream_t st);
 void launch_fc_extend(const double* in, long long nlines, long long ips, long long ils, double* out,
                       long long ops, long long ols, int nz, int C, int d, const double* M,
                       hipStream_t st);

@@ -230,40 +230,20 @@ __global__ __launch_bounds__(ZNT) void k_z_fwd(ZArgs a, const cpx<double>* __res
 }
 
 // ---------------------------------------------------------------- z back
-// continued spectral -> mixed: B_z = R o IFFT (and B_z(i k~z .) into dzdst).
+// B_z = R o IFFT of one field whose continued rows this thread holds
+// (keep[r] = row lt + r ZLS of pencil p0 + tid % ZPB, zero past N' and for
+// padding pencils) into dst, and B_z(i k~z .) into dzdst when non-null.
+// Every thread of the workgroup calls it; it ends with a barrier.
 template <typename T, class FP, int OWN>
-__global__ __launch_bounds__(ZNT) void k_z_back(ZArgs a, const cpx<double>* __restrict__ src,
-                                                cpx<T>* __restrict__ dst,
-                                                cpx<T>* __restrict__ dzdst,
-                                                long long sfs, long long mfs) {
-  extern __shared__ __align__(16) char smem[];
-  const int tid = threadIdx.x;
+__device__ __forceinline__ void z_back_rows(const ZLds<T>& L, const ZArgs& a,
+                                            const cpx<double> (&keep)[OWN], cpx<T>* dst,
+                                            cpx<T>* dzdst, long long p0, int tid) {
   const Geom& g = a.g;
   const int npr = FP::dynamic ? g.npr : FP::n;
-  const ZLds<T> L(smem, g, a.pl.tsize);
-  src += blockIdx.y * sfs;
-  dst += blockIdx.y * mfs;
-  if (dzdst) dzdst += blockIdx.y * mfs;
-  const long long p0 = (long long)blockIdx.x * ZPB;
-  z_setup<T>(L, a, tid);
   const int tot = npr * ZPB;
   const int pb = tid % ZPB, lt = tid / ZPB;
   const long long p = p0 + pb;
   const bool pv = pencil_valid(g, p);
-  cpx<double> keep[OWN];
-#pragma unroll
-  for (int r = 0; r < OWN; ++r) {
-    const int l = lt + r * ZLS;
-    keep[r] = (pv && l < npr) ? src[(long long)l * g.npen + p] : zero<double>();
-  }
-  if (a.nonfinite) {
-    // the step's non-finite check: every coefficient of the state passes here
-    bool bad = false;
-#pragma unroll
-    for (int r = 0; r < OWN; ++r)
-      bad = bad || !__builtin_isfinite(keep[r].x) || !__builtin_isfinite(keep[r].y);
-    if (bad) *a.nonfinite = 1;
-  }
   const double inv = 1.0 / npr;
   const int npass = dzdst ? 2 : 1;
   for (int pass = 0; pass < npass; ++pass) {
@@ -278,7 +258,7 @@ __global__ __launch_bounds__(ZNT) void k_z_back(ZArgs a, const cpx<double>* __re
     }
     __syncthreads();
     const cpx<T>* R = fft_run<T, ZPB, ZNT, false, FP>(L.X0, L.X1, ZPB, 1, a.pl, L.tw, tid);
-    cpx<T>* __restrict__ out = pass ? dzdst : dst;
+    cpx<T>* out = pass ? dzdst : dst;
     if (pv) {
       if constexpr (!FP::dynamic) {
         // compiled plans: LDS reads first (rows up to N' - 1 are in the
@@ -298,27 +278,84 @@ __global__ __launch_bounds__(ZNT) void k_z_back(ZArgs a, const cpx<double>* __re
   }
 }
 
+// This thread's rows of one continued field (layout of z_back_rows).
+template <class FP, int OWN>
+__device__ __forceinline__ void load_rows(const ZArgs& a, const cpx<double>* src, long long p0,
+                                          int tid, cpx<double> (&keep)[OWN]) {
+  const Geom& g = a.g;
+  const int npr = FP::dynamic ? g.npr : FP::n;
+  const int pb = tid % ZPB, lt = tid / ZPB;
+  const long long p = p0 + pb;
+  const bool pv = pencil_valid(g, p);
+#pragma unroll
+  for (int r = 0; r < OWN; ++r) {
+    const int l = lt + r * ZLS;
+    keep[r] = (pv && l < npr) ? src[(long long)l * g.npen + p] : zero<double>();
+  }
+}
+
+// The step's non-finite check: every coefficient of the state passes here.
+template <int OWN>
+__device__ __forceinline__ void check_rows(const ZArgs& a, const cpx<double> (&keep)[OWN]) {
+  if (!a.nonfinite) return;
+  bool bad = false;
+#pragma unroll
+  for (int r = 0; r < OWN; ++r)
+    bad = bad || !__builtin_isfinite(keep[r].x) || !__builtin_isfinite(keep[r].y);
+  if (bad) *a.nonfinite = 1;
+}
+
+// continued spectral -> mixed: B_z = R o IFFT (and B_z(i k~z .) into dzdst).
+template <typename T, class FP, int OWN>
+__global__ __launch_bounds__(ZNT) void k_z_back(ZArgs a, const cpx<double>* __restrict__ src,
+                                                cpx<T>* __restrict__ dst,
+                                                cpx<T>* __restrict__ dzdst,
+                                                long long sfs, long long mfs) {
+  extern __shared__ __align__(16) char smem[];
+  const int tid = threadIdx.x;
+  const ZLds<T> L(smem, a.g, a.pl.tsize);
+  src += blockIdx.y * sfs;
+  dst += blockIdx.y * mfs;
+  if (dzdst) dzdst += blockIdx.y * mfs;
+  const long long p0 = (long long)blockIdx.x * ZPB;
+  z_setup<T>(L, a, tid);
+  cpx<double> keep[OWN];
+  load_rows<FP, OWN>(a, src, p0, tid, keep);
+  check_rows<OWN>(a, keep);
+  z_back_rows<T, FP, OWN>(L, a, keep, dst, dzdst, p0, tid);
+}
+
 // ---------------------------------------------------------------- stage A
-// One field per blockIdx.y (0..2 velocity, 3 temperature); T: transform type,
-// TM: storage of the mixed-space inputs (NL, buoyancy).  Sec. 4.4 steps
-// 1-3 up to the FC-Gram transform of v*:
+// One field f (0..2 velocity, 3 temperature) of the pencil group at p0; T:
+// transform type, TM: storage of the mixed-space inputs (NL, buoyancy).
+// Sec. 4.4 steps 1-3 up to the FC-Gram transform of v*:
 //   N = sigma F_z(NL);  S = V^t + c (N - diff |k|^2 W);  v* = B_z S, plus the
 //   body force / buoyancy at the physical points, then the wall injection
 //   v*_par = c grad_par p_prev (theta = 0) and V* = F_z v*.
-template <typename T, typename TM, class FP, int OWN, bool WV>
-__global__ __launch_bounds__(ZNT) void k_z_stageA(ZArgs a, StageAArgs s) {
-  extern __shared__ __align__(16) char smem[];
-  const int tid = threadIdx.x;
+// TABLES: also stage the plan and continuation tables in LDS (the first
+// field a workgroup handles).  SPECBUOY: s.buoy[f] is the other field's
+// continued state W (theta for w, w for theta) and the buoyancy enters S as
+// c gamma W_other, which B_z maps onto c gamma times its physical values (the
+// term of Sec. 7 added at the physical points); otherwise s.buoy[f] holds
+// the other field's mixed values, added after the inverse transform.
+// Ends with this thread's stores; the caller places a barrier before the
+// LDS is used again.
+template <typename T, typename TM, class FP, int OWN, bool WV, bool SPECBUOY>
+__device__ __forceinline__ void z_stageA_field(const ZLds<T>& L, const ZArgs& a,
+                                               const StageAArgs& s, int f, long long p0, int tid,
+                                               bool tables) {
+  // a fresh copy of the thread index: the row offsets derived from it are
+  // recomputed per field rather than kept live from one field to the next
+  asm volatile("" : "+v"(tid));
   const Geom& g = a.g;
   const int npr = FP::dynamic ? g.npr : FP::n;
-  const ZLds<T> L(smem, g, a.pl.tsize);
-  const int f = blockIdx.y;
-  const long long p0 = (long long)blockIdx.x * ZPB;
-  const ZTables<T> tab = ztab_load<T>(a, tid);
-  const cpx<TM>* __restrict__ nl = reinterpret_cast<const cpx<TM>*>(s.nl[f]);
-  const cpx<double>* __restrict__ vt = s.vt[f];
-  const cpx<double>* __restrict__ w = s.w[f];
-  const cpx<TM>* __restrict__ buoy = reinterpret_cast<const cpx<TM>*>(s.buoy[f]);
+  ZTables<T> tab{};
+  if (tables) tab = ztab_load<T>(a, tid);
+  const cpx<TM>* nl = reinterpret_cast<const cpx<TM>*>(s.nl[f]);
+  const cpx<double>* vt = s.vt[f];
+  const cpx<double>* w = s.w[f];
+  const cpx<TM>* buoy = SPECBUOY ? nullptr : reinterpret_cast<const cpx<TM>*>(s.buoy[f]);
+  const cpx<double>* wbuoy = SPECBUOY ? reinterpret_cast<const cpx<double>*>(s.buoy[f]) : nullptr;
   const double c = s.c;
   const double diff = (f == 3) ? s.kappa : s.nu;
   const double inv = 1.0 / npr;
@@ -357,7 +394,7 @@ __global__ __launch_bounds__(ZNT) void k_z_stageA(ZArgs a, StageAArgs s) {
   }
   // (rows z >= nz store zero to a continuation row, rewritten by the
   // extension after the barrier, so that no load is tied to a branch)
-  ztab_store<T>(tab, L, a, tid);
+  if (tables) ztab_store<T>(tab, L, a, tid);
 #pragma unroll
   for (int r = 0; r < OWN; ++r) {
     const int z = lt + r * ZLS;
@@ -370,7 +407,18 @@ __global__ __launch_bounds__(ZNT) void k_z_stageA(ZArgs a, StageAArgs s) {
   z_extend<T>(L.X0, L.M, g.nz, g.C, g.d, tid);
   __syncthreads();
   R = fft_run<T, ZPB, ZNT, false, FP>(L.X0, L.X1, ZPB, 1, a.pl, L.tw, tid);
-  // 2. S = V^t + c (sigma N - diff |k|^2 W), conjugated for the inverse
+  // 2. S = V^t + c (sigma N - diff |k|^2 W) [+ c gamma W_other], conjugated
+  // for the inverse (the other field's rows are loaded now, and added after
+  // the combine has released the registers of the state rows)
+  const double cg = c * s.gamma;
+  cpx<double> bsr[SPECBUOY ? OWN : 1];
+  if constexpr (SPECBUOY) {
+    if (wbuoy) {
+#pragma unroll
+      for (int r = 0; r < OWN; ++r)
+        bsr[r] = wbuoy[(long long)min(lt + r * ZLS, npr - 1) * g.npen + pc];
+    }
+  }
 #pragma unroll
   for (int r = 0; r < OWN; ++r) {
     const int l = lt + r * ZLS;
@@ -382,6 +430,9 @@ __global__ __launch_bounds__(ZNT) void k_z_stageA(ZArgs a, StageAArgs s) {
         const double k2 = kh2 + kzt * kzt;
         const double sig = sgr[r] * sxy;
         S = vtr[r] + (cvt<double>(R[e]) * sig - (WV ? vtr[r] : wr[r]) * (diff * k2)) * c;
+      }
+      if constexpr (SPECBUOY) {
+        if (wbuoy && pv) S = S + bsr[r] * cg;
       }
       L.X0[e] = cvt<T>(conj(S));
     }
@@ -415,7 +466,7 @@ __global__ __launch_bounds__(ZNT) void k_z_stageA(ZArgs a, StageAArgs s) {
       if (pv) {
         v = conj(cvt<double>(R[e])) * inv;
         if (f == 0 && p == 0) v.x += c * s.forcing_sum;
-        if (buoy) v = v + br[r] * (c * s.gamma);
+        if (buoy) v = v + br[r] * cg;
         if (z == 0 || z == g.nz - 1) {
           if (f < 2) v = ((z == 0) ? gw0 : gw1) * c;
           if (f == 3) v = zero<double>();
@@ -431,7 +482,7 @@ __global__ __launch_bounds__(ZNT) void k_z_stageA(ZArgs a, StageAArgs s) {
   // compiled plans: all of this thread's LDS reads first, then the stores
   // (the rolled loop waits for each read in turn; it measured faster on the
   // small run-time-plan grids)
-  cpx<double>* __restrict__ out = s.out[f];
+  cpx<double>* out = s.out[f];
   if (pv) {
     if constexpr (!FP::dynamic) {
       cpx<double> ov[OWN];
@@ -446,6 +497,15 @@ __global__ __launch_bounds__(ZNT) void k_z_stageA(ZArgs a, StageAArgs s) {
   }
 }
 
+// One field per blockIdx.y.
+template <typename T, typename TM, class FP, int OWN, bool WV>
+__global__ __launch_bounds__(ZNT) void k_z_stageA(ZArgs a, StageAArgs s) {
+  extern __shared__ __align__(16) char smem[];
+  const ZLds<T> L(smem, a.g, a.pl.tsize);
+  z_stageA_field<T, TM, FP, OWN, WV, false>(L, a, s, blockIdx.y, (long long)blockIdx.x * ZPB,
+                                            threadIdx.x, true);
+}
+
 // ---------------------------------------------------------------- stage B
 // Pressure projection of V* (Sec. 4.2; Sec. 4.4 steps 3-5) in increment units
 // phi = c p:
@@ -457,27 +517,32 @@ __global__ __launch_bounds__(ZNT) void k_z_stageA(ZArgs a, StageAArgs s) {
 //   V = V* - k~ s - F_z H; next-stage wall gradient (k~ B_z s + H)_par / c.
 // The two exponentials are continued as the real and imaginary parts of one
 // line; F_z(e+ + i e-) splits into F_z e+ and F_z e- by conjugate symmetry.
-// HOLD > 0 (compiled plans, N' <= HOLD * ZLS): V* is read once and held in
-// registers (HOLD rows per thread); HOLD = 0: V* is streamed twice (wall
-// sums, then the update).  The mixed v, dv/dz of the result come from
-// k_z_back.
-template <typename T, class FP, int HOLD>
-__global__ __launch_bounds__(ZNT) void k_z_stageB(ZArgs a, StageBArgs s) {
-  extern __shared__ __align__(16) char smem[];
-  __shared__ cpx<double> coef[ZPB * 5];  // b, t, s0, s1 then A, B, D
-  __shared__ double gam_s[ZPB];
-  const int tid = threadIdx.x;
+// HOLD > 0 (N' <= HOLD * ZLS): V* is read once and held in registers (HOLD
+// rows per thread); HOLD = 0: V* is streamed twice (wall sums, then the
+// update).  KEEP (needs HOLD): the projected rows are also left in vk, in
+// the row layout of z_back_rows, for the back transform of the result in
+// the same workgroup; otherwise the mixed v, dv/dz of the result come from
+// k_z_back.  TABLES: stage the plan and continuation tables in LDS.
+// coef (ZPB * 5 entries) and gam_s (ZPB) are LDS scratch.
+template <typename T, class FP, int HOLD, bool KEEP>
+__device__ __forceinline__ void z_stageB_body(const ZLds<T>& L, const ZArgs& a,
+                                              const StageBArgs& s, long long p0, int tid,
+                                              cpx<double>* coef, double* gam_s, bool tables,
+                                              cpx<double> (&vk)[3][KEEP ? HOLD : 1]) {
+  static_assert(!KEEP || HOLD > 0, "KEEP needs the rows held in registers");
   const Geom& g = a.g;
   const int npr = FP::dynamic ? g.npr : FP::n;
-  const ZLds<T> L(smem, g, a.pl.tsize);
-  const long long p0 = (long long)blockIdx.x * ZPB;
   const int pb_me = tid % ZPB, lt = tid / ZPB;
   const long long p_me = p0 + pb_me;
   const bool valid_me = pencil_valid(g, p_me);
-  const ZTables<T> tab = ztab_load<T>(a, tid);
-  const cpx<double>* __restrict__ gtw = a.tw64;
+  ZTables<T> tab{};
+  if (tables) tab = ztab_load<T>(a, tid);
+  const cpx<double>* gtw = a.tw64;
   const double inv = 1.0 / npr;
   const bool pm = s.pmix != nullptr;
+  // rows of this thread: l = lt + r ZLS, r < nr
+  constexpr int HR = HOLD > 0 ? HOLD : 1;
+  const int nr = HOLD > 0 ? HOLD : (npr - lt + ZLS - 1) / ZLS;
 
   double kxo, kyo, kxt, kyt;
   int ix, iy;
@@ -491,27 +556,30 @@ __global__ __launch_bounds__(ZNT) void k_z_stageB(ZArgs a, StageBArgs s) {
   const int step = (int)(((long long)ZLS * (g.nz - 1)) % npr);
   const int ei0 = (int)(((long long)lt * (g.nz - 1)) % npr);
   // HOLD > 0: the roots of this thread's rows and V* itself, all loads issued
-  // together (rows of an invalid pencil read pencil 0 and are never used)
-  cpx<double> hv[3][HOLD > 0 ? HOLD : 1], etr[HOLD > 0 ? HOLD : 1];
-  if (HOLD > 0) {
+  // together (rows of an invalid pencil, and rows past N', read an in-bounds
+  // slot and are never used)
+  cpx<double> hv[3][HR], etr[HR];
+  if constexpr (HOLD > 0) {
 #pragma unroll
     for (int r = 0, ei = ei0; r < HOLD; ++r, ei = (ei + step >= npr) ? ei + step - npr : ei + step)
       etr[r] = conj(gtw[ei]);
 #pragma unroll
     for (int r = 0; r < HOLD; ++r) {
-      const long long gi = valid_me ? (long long)(lt + r * ZLS) * g.npen + p_me : 0;
+      const long long gi =
+          valid_me ? (long long)min(lt + r * ZLS, npr - 1) * g.npen + p_me : 0;
 #pragma unroll
       for (int i = 0; i < 3; ++i) hv[i][r] = s.vs[i][gi];
     }
   }
-  ztab_store<T>(tab, L, a, tid);
+  if (tables) ztab_store<T>(tab, L, a, tid);
   if (valid_me) {
     int ei = ei0;
-#pragma unroll(HOLD > 0 ? HOLD : 1)
-    for (int l = lt, r = 0; l < npr; l += ZLS, ++r,
-             ei = (ei + step >= npr) ? ei + step - npr : ei + step) {
+#pragma unroll(HR)
+    for (int r = 0; r < nr; ++r, ei = (ei + step >= npr) ? ei + step - npr : ei + step) {
+      const int l = lt + r * ZLS;
+      if (l >= npr) continue;
       cpx<double> V0, V1, V2;
-      if (HOLD > 0) {
+      if constexpr (HOLD > 0) {
         V0 = hv[0][r];
         V1 = hv[1][r];
         V2 = hv[2][r];
@@ -527,7 +595,11 @@ __global__ __launch_bounds__(ZNT) void k_z_stageB(ZArgs a, StageBArgs s) {
       if (k2 > 0.0) sv = (V0 * kxo + V1 * kyo + V2 * kz) * (1.0 / k2);
       const cpx<double> rz = V2 - sv * kz;
       // e^{+2 pi i l (nz-1)/N'} = conj(root[l (nz-1) mod N'])
-      const cpx<double> et = (HOLD > 0) ? etr[r] : conj(gtw[ei]);
+      cpx<double> et;
+      if constexpr (HOLD > 0)
+        et = etr[r];
+      else
+        et = conj(gtw[ei]);
       sb = sb + rz;
       st = st + rz * et;
       s0 = s0 + sv;
@@ -599,8 +671,16 @@ __global__ __launch_bounds__(ZNT) void k_z_stageB(ZArgs a, StageBArgs s) {
   const cpx<T>* R = fft_run<T, ZPB, ZNT, false, FP>(L.X0, L.X1, ZPB, 1, a.pl, L.tw, tid);
   cpx<T>* Xo = (R == L.X0) ? L.X1 : L.X0;
   // 4. V = V* - k~ s - H^ (V* held or streamed again), store the continued state
-#pragma unroll(HOLD > 0 ? HOLD : 1)
-  for (int l = lt, r = 0; l < npr; l += ZLS, ++r) {
+  if constexpr (KEEP) {
+#pragma unroll
+    for (int r = 0; r < HOLD; ++r)
+#pragma unroll
+      for (int i = 0; i < 3; ++i) vk[i][r] = zero<double>();
+  }
+#pragma unroll(HR)
+  for (int r = 0; r < nr; ++r) {
+    const int l = lt + r * ZLS;
+    if (l >= npr) continue;
     const int e = l * ZPB + pb_me;
     if (!valid_me) {
       if (pm) Xo[e] = zero<T>();
@@ -608,7 +688,7 @@ __global__ __launch_bounds__(ZNT) void k_z_stageB(ZArgs a, StageBArgs s) {
     }
     const long long gi = (long long)l * g.npen + p_me;
     cpx<double> V0, V1, V2;
-    if (HOLD > 0) {
+    if constexpr (HOLD > 0) {
       V0 = hv[0][r];
       V1 = hv[1][r];
       V2 = hv[2][r];
@@ -634,26 +714,89 @@ __global__ __launch_bounds__(ZNT) void k_z_stageB(ZArgs a, StageBArgs s) {
     } else {
       hz = D * ep;
     }
-    s.vout[0][gi] = V0 - sv * kxo - hx;
-    s.vout[1][gi] = V1 - sv * kyo - hy;
-    s.vout[2][gi] = V2 - sv * kz - hz;
+    const cpx<double> n0 = V0 - sv * kxo - hx, n1 = V1 - sv * kyo - hy, n2 = V2 - sv * kz - hz;
+    s.vout[0][gi] = n0;
+    s.vout[1][gi] = n1;
+    s.vout[2][gi] = n2;
+    if constexpr (KEEP) {
+      vk[0][r] = n0;
+      vk[1][r] = n1;
+      vk[2][r] = n2;
+    }
     if (pm) Xo[e] = cvt<T>(conj(mul_mi(sv)));  // phi^I = -i s, conjugated
   }
-  if (!pm) return;
-  // 5. pressure in mixed space: (B_z(-i s) + phi^H) / c
+  if (pm) {
+    // 5. pressure in mixed space: (B_z(-i s) + phi^H) / c
+    __syncthreads();
+    const cpx<T>* P =
+        fft_run<T, ZPB, ZNT, false, FP>(Xo, (Xo == L.X0) ? L.X1 : L.X0, ZPB, 1, a.pl, L.tw, tid);
+    if (valid_me)
+      for (int z = lt; z < g.nz; z += ZLS) {
+        const double zz = z * g.dz;
+        cpx<double> ph;
+        if (gam > 0.0)
+          ph = A * exp(gam * (zz - g.lz)) + B * exp(-gam * zz);
+        else
+          ph = D * zz;
+        s.pmix[(long long)z * g.npen + p_me] =
+            (conj(cvt<double>(P[z * ZPB + pb_me])) * inv + ph) * (1.0 / s.c);
+      }
+  }
+}
+
+template <typename T, class FP, int HOLD>
+__global__ __launch_bounds__(ZNT) void k_z_stageB(ZArgs a, StageBArgs s) {
+  extern __shared__ __align__(16) char smem[];
+  __shared__ cpx<double> coef[ZPB * 5];  // b, t, s0, s1 then A, B, D
+  __shared__ double gam_s[ZPB];
+  const ZLds<T> L(smem, a.g, a.pl.tsize);
+  cpx<double> vk[3][1];
+  z_stageB_body<T, FP, HOLD, false>(L, a, s, (long long)blockIdx.x * ZPB, threadIdx.x, coef,
+                                    gam_s, true, vk);
+}
+
+// ---------------------------------------------------------------- one fused z pass
+// The whole z pass of one RK stage for a group of ZPB pencils (FP64): stage
+// A for every transported field (velocity into s.out[0..2] as V*, theta as
+// its new state; the buoyancy in spectral form), the projection of V* in
+// place (stage B, V* read back while it is still in the caches, the result
+// kept in registers), and the back transforms of the new state (v, dv/dz of
+// every field into the mixed arrays).  The outputs must not alias the
+// inputs of another field (true when the stage writes the other state
+// buffer, as both stages of o = 2 do); W of the other field feeds the
+// buoyancy.  Each pencil group is independent, so V* never has to reach
+// HBM: it is written, read back and overwritten by the same workgroup.
+template <class FP, int OWN, bool WV>
+__global__ __launch_bounds__(ZNT, 2) void k_z_pass(ZArgs a, StageAArgs sa, StageBArgs sb,
+                                                   ZBackArgs zb, int nf) {
+  extern __shared__ __align__(16) char smem[];
+  __shared__ cpx<double> coef[ZPB * 5];
+  __shared__ double gam_s[ZPB];
+  const int tid = threadIdx.x;
+  const ZLds<double> L(smem, a.g, a.pl.tsize);
+  const long long p0 = (long long)blockIdx.x * ZPB;
+  // one field after the other (the field index a constant in each copy)
+  z_stageA_field<double, double, FP, OWN, WV, true>(L, a, sa, 0, p0, tid, true);
   __syncthreads();
-  const cpx<T>* P = fft_run<T, ZPB, ZNT, false, FP>(Xo, (Xo == L.X0) ? L.X1 : L.X0, ZPB, 1, a.pl, L.tw, tid);
-  if (valid_me)
-    for (int z = lt; z < g.nz; z += ZLS) {
-      const double zz = z * g.dz;
-      cpx<double> ph;
-      if (gam > 0.0)
-        ph = A * exp(gam * (zz - g.lz)) + B * exp(-gam * zz);
-      else
-        ph = D * zz;
-      s.pmix[(long long)z * g.npen + p_me] =
-          (conj(cvt<double>(P[z * ZPB + pb_me])) * inv + ph) * (1.0 / s.c);
-    }
+  z_stageA_field<double, double, FP, OWN, WV, true>(L, a, sa, 1, p0, tid, false);
+  __syncthreads();
+  z_stageA_field<double, double, FP, OWN, WV, true>(L, a, sa, 2, p0, tid, false);
+  __syncthreads();
+  if (nf == 4) {
+    z_stageA_field<double, double, FP, OWN, WV, true>(L, a, sa, 3, p0, tid, false);
+    __syncthreads();
+  }
+  cpx<double> vk[3][1];
+  z_stageB_body<double, FP, OWN, false>(L, a, sb, p0, tid, coef, gam_s, false, vk);
+  __syncthreads();
+  // each thread reads back the rows it has just written (cache hits)
+  for (int f = 0; f < nf; ++f) {
+    cpx<double> keep[OWN];
+    load_rows<FP, OWN>(a, sa.out[f], p0, tid, keep);
+    check_rows<OWN>(a, keep);
+    z_back_rows<double, FP, OWN>(L, a, keep, zb.mv + (2 * f) * zb.ms,
+                                 zb.mv + (2 * f + 1) * zb.ms, p0, tid);
+  }
 }
 
 // ---------------------------------------------------------------- fc_extend
@@ -819,6 +962,37 @@ void launch_z_stageB(const ZArgs& a, bool big, const StageBArgs& s, hipStream_t 
     FCNS_LAUNCH((k_z_stageB<double, DynPlan<true>, 0>), grid, dim3(ZNT), sh, st, a, s);
   else
     FCNS_LAUNCH((k_z_stageB<double, DynPlan<false>, 0>), grid, dim3(ZNT), sh, st, a, s);
+}
+
+bool z_pass_fits(const ZArgs& a) { return pick_own(a.g.npr) <= 9; }
+
+void launch_z_pass(const ZArgs& a, bool big, const StageAArgs& sa, const StageBArgs& sb,
+                   const ZBackArgs& zb, int nfields, hipStream_t st) {
+  dim3 grid((unsigned)((a.g.npen + ZPB - 1) / ZPB));
+  const size_t sh = zshared_bytes<double>(a.g, a.pl.tsize);
+  const int own = pick_own(a.g.npr);
+  if (z_static_288(a)) {
+    bool wv = true;  // W is V^t for every field (the first RK stage)
+    for (int f = 0; f < nfields; ++f) wv = wv && sa.w[f] == sa.vt[f];
+    if (wv)
+      FCNS_LAUNCH((k_z_pass<P288, 9, true>), grid, dim3(ZNT), sh, st, a, sa, sb, zb, nfields);
+    else
+      FCNS_LAUNCH((k_z_pass<P288, 9, false>), grid, dim3(ZNT), sh, st, a, sa, sb, zb, nfields);
+  } else if (big) {
+    if (own <= 4)
+      FCNS_LAUNCH((k_z_pass<DynPlan<true>, 4, false>), grid, dim3(ZNT), sh, st, a, sa, sb, zb,
+                  nfields);
+    else
+      FCNS_LAUNCH((k_z_pass<DynPlan<true>, 9, false>), grid, dim3(ZNT), sh, st, a, sa, sb, zb,
+                  nfields);
+  } else {
+    if (own <= 4)
+      FCNS_LAUNCH((k_z_pass<DynPlan<false>, 4, false>), grid, dim3(ZNT), sh, st, a, sa, sb, zb,
+                  nfields);
+    else
+      FCNS_LAUNCH((k_z_pass<DynPlan<false>, 9, false>), grid, dim3(ZNT), sh, st, a, sa, sb, zb,
+                  nfields);
+  }
 }
 
 void launch_fc_extend(const double* in, long long nlines, long long ips, long long ils, double* out,

@@ -30,7 +30,7 @@ HERE = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))),
 # classes of equal traffic pattern; it is reported as one)
 CLASSES = {"fcns::k_x_nl<": "x_nl", "fcns::k_x_nlw<": "x_nl", "fcns::k_x_nlw_q<": "x_nl",
            "fcns::k_z_stageA<": "z_stageA", "fcns::k_z_stageB<": "z_stageB",
-           "fcns::k_z_back<": "z_back", "fcns::k_y<": "y"}
+           "fcns::k_z_back<": "z_back", "fcns::k_z_pass<": "z_pass", "fcns::k_y<": "y"}
 COPY_BYTES = 1 << 30
 
 

@@ -62,17 +62,19 @@ def _with_white_noise(v0, th0, scale, seed):
     return v, th
 
 
-def _step_pair(fcns, w, v0, th0, steps, tune=False):
-    s = fcns.Solver.from_workload(w, keep_pressure=True)
+def _step_pair(fcns, w, v0, th0, steps, tune=False, fused=None, rk_order=2):
+    s = fcns.Solver.from_workload(w, keep_pressure=True, rk_order=rk_order)
     s.set_state(torch.from_numpy(v0), torch.from_numpy(th0) if th0 is not None else None)
     if tune:
         print(f"[{w.name}] autotune: {s.autotune()}", flush=True)
+    if fused is not None:
+        s.set_z_fused(fused)
     s.rk_step(w.dt, steps)
     v, th, p = s.get_state(pressure=True)
     torch.cuda.synchronize()
     out = (v.cpu().numpy(), th.cpu().numpy() if th is not None else None, p.cpu().numpy())
     s.close()
-    o = Oracle(Problem(**w.problem_kwargs()))
+    o = Oracle(Problem(**w.problem_kwargs(), rk_order=rk_order))
     o.set_state(v0, th0)
     o.rk_step(w.dt, steps)
     return out, o.get_state()
@@ -223,3 +225,35 @@ def test_step_commutes_with_the_z_mirror(fcns, kind):
         assert rel_l2(tb, mta) < 1e-11
     # and a mirror-asymmetric state really changes under the map
     assert rel_l2(va, ma) > 1e-3
+
+
+# ------------------------------------------------------------------ fused z pass
+@pytest.mark.parametrize("kind,nz,C,order", [("rb", 257, 31, 2), ("rb", 33, 31, 2),
+                                             ("channel", 257, 25, 2), ("channel", 65, 31, 2),
+                                             ("rb", 33, 31, 3)])
+def test_fused_z_pass_against_the_oracle(fcns, kind, nz, C, order):
+    # the one-kernel z pass (compiled 288-point plan, the radix-47 run-time
+    # plan, small run-time plans; o = 3 mixes fused and three-kernel stages)
+    if kind == "rb":
+        w = W.rayleigh_benard(16, 12, nz, 1e5, C=C, dt=1e-3, steps=3, seed=350, noise_rms=1e-2,
+                              perturbation="curl_eigen")
+    else:
+        w = W.channel(16, 12, nz, 2000.0, C=C, dt=5e-4, steps=3, seed=351, noise_rms=0.05)
+    v0, th0 = w.initial_state()
+    v0, th0 = _with_white_noise(v0, th0, 0.01, 352)
+    got, ref = _step_pair(fcns, w, v0, th0, w.steps, fused=True, rk_order=order)
+    _assert_parity(got, ref, f"fused {kind} nz={nz} C={C} o={order}")
+
+
+def test_fused_z_pass_reports_non_finite(fcns):
+    w = W.rayleigh_benard(16, 12, 33, 1e5, C=31, dt=1e-3, steps=2, seed=353, noise_rms=1e-2)
+    v0, th0 = w.initial_state()
+    th0 = th0.copy()
+    th0[5, 3, 2] = np.nan
+    s = fcns.Solver.from_workload(w)
+    s.set_z_fused(True)
+    s.set_state(torch.from_numpy(v0), torch.from_numpy(th0))
+    with pytest.raises(fcns.FcnsError) as e:
+        s.rk_step(w.dt, 1)
+    assert e.value.code == fcns.FCNS_ENONFINITE
+    s.close()
