@@ -13,6 +13,7 @@ from __future__ import annotations
 
 import argparse
 import hashlib
+from dataclasses import replace
 import json
 import os
 import sys
@@ -241,6 +242,67 @@ def serving_run(max_active=8, max_bytes=64 << 30, n=64, rate=20.0, steps=20):
                           / bat_sat["request_ms_p99"]}}
 
 
+def batch_leg(steps=20, sides=(32, 64, 96), per_side=3):
+    """Small problems of mixed shapes (the serving stream's smaller sizes,
+    channel and Rayleigh-Benard, C = 31): one after another, interleaved on
+    their own streams (fcns_batch_step), and with one fused z-pass launch per
+    stage for all of them (fcns_batch_run)."""
+    import torch
+
+    import workloads as W
+    from paper_2002_01392_amd import Batch, Solver, batch_step
+
+    ws = []
+    for i, side in enumerate([s for s in sides for _ in range(per_side)]):
+        if i % 2:
+            w = W.channel(side, side, side + 1, 2000.0, C=31, seed=900 + i)
+        else:
+            w = W.rayleigh_benard(side, side, side + 1, 1e6, C=31, seed=900 + i)
+        ws.append(replace(w, dt=W.stable_dt(w)))
+    states = [w.initial_state() for w in ws]
+
+    def fresh():
+        out = []
+        for w, (v0, th0) in zip(ws, states):
+            s = Solver.from_workload(w, stream=torch.cuda.Stream())
+            s.set_state(torch.from_numpy(v0), torch.from_numpy(th0) if th0 is not None else None)
+            s.autotune()
+            s.set_finite_check("deferred")
+            out.append(s)
+        torch.cuda.synchronize()
+        return out
+
+    work = sum(w.nx * w.ny * w.nz * 2 * steps for w in ws)
+    res = {"members": [w.name.split("_", 1)[-1] if "_" in w.name else w.name for w in ws],
+           "steps": steps, "unit": UNIT}
+    for mode in ("sequential", "interleaved", "one_launch"):
+        S = fresh()
+        b = Batch(S, [w.dt for w in ws]) if mode == "one_launch" else None
+        for _ in range(2):   # warmup, then timed
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            if mode == "sequential":
+                for s, w in zip(S, ws):
+                    s.rk_step(w.dt, steps)
+                    s.synchronize()
+            elif mode == "interleaved":
+                batch_step(S, [w.dt for w in ws], [steps] * len(ws))
+            else:
+                b.run(steps)
+            torch.cuda.synchronize()
+            el = time.perf_counter() - t0
+        for s in S:
+            s.check_finite()
+        res[mode] = {"s": el, "value": work / el}
+        if b is not None:
+            b.close()
+        for s in S:
+            s.close()
+    res["one_launch_vs_sequential"] = res["one_launch"]["value"] / res["sequential"]["value"]
+    res["one_launch_vs_interleaved"] = res["one_launch"]["value"] / res["interleaved"]["value"]
+    return res
+
+
 def graph_run(name="channel_32x32x33", steps=200, warmup=5):
     """Launch-bound small problem: eager rk_step against the replayed HIP graph
     of one step (same state, same steps)."""
@@ -303,6 +365,8 @@ def main():
     ap.add_argument("--no-serving", action="store_true", help="skip the serving run")
     ap.add_argument("--no-autotune", action="store_true", help="keep the default launch choices")
     ap.add_argument("--no-graph", action="store_true", help="skip the HIP graph comparison")
+    ap.add_argument("--no-batch", action="store_true",
+                    help="skip the one-launch batch of small mixed shapes")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one plain device copy of 1 GiB (counter calibration)")
     args = ap.parse_args()
@@ -424,6 +488,12 @@ def main():
         print("[bench] HIP graph replay on the small channel", file=sys.stderr, flush=True)
         graph = graph_run()
 
+    batch = None
+    if not args.no_batch:
+        print("[bench] small mixed shapes: sequential, interleaved, one launch", file=sys.stderr,
+              flush=True)
+        batch = batch_leg()
+
     serving = None
     if not args.no_serving:
         print("[bench] serving: 64 requests, sequential then overlapped", file=sys.stderr,
@@ -451,7 +521,7 @@ def main():
                           "the timed region only the roofline kernel" % SURVEY_STEPS)
         if survey else "the timed region",
         "precision": mixed,
-        "serving": serving, "graph": graph, "autotune": tuned,
+        "serving": serving, "graph": graph, "batch": batch, "autotune": tuned,
         "cpu_baseline": cpu, "kernel_source_hash": src_hash,
     }
     print(json.dumps(out))

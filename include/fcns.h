@@ -182,6 +182,27 @@ int32_t fcns_nonfinite_flag(const fcns_ctx* ctx);
 fcns_status fcns_batch_step(fcns_ctx* const* ctxs, int32_t n, const double* dts,
                             const int32_t* nsteps);
 
+/* One launch for several problems: a batch of n FP64 contexts (HOST array;
+ * different shapes allowed, N' <= 288 each, the same rk_order) and their
+ * time steps (HOST, copied).  fcns_batch_run advances every member nsteps
+ * steps: each context's x and y passes run on its own stream, and in every
+ * stage whose output buffer is not its input (both stages of o = 2) one
+ * kernel runs the fused z pass (continuation, z transforms, RK combine,
+ * projection, back transforms) of all members together, workgroup by
+ * workgroup over their pencil groups, on a stream of the batch; each member
+ * waits for it before its next pass.  Each member's result matches its own
+ * fcns_rk_step with the fused z pass to rounding (the same per-workgroup
+ * code).  The batch reads its members' parameters, tables and buffers at
+ * every run (a member retuned or given new parameters is picked up).
+ * Members report a non-finite state in their own check mode.  create
+ * allocates the batch's descriptors, stream and events; run allocates
+ * nothing. */
+typedef struct fcns_batch fcns_batch;
+fcns_status fcns_batch_create(fcns_ctx* const* ctxs, int32_t n, const double* dts,
+                              fcns_batch** out);
+fcns_status fcns_batch_run(fcns_batch* batch, int32_t nsteps);
+fcns_status fcns_batch_destroy(fcns_batch* batch);
+
 /* Autotuner: times, on this context's own buffers and stream, the launch
  * choices that depend on the shape -- the persistent grid of the y pass, the
  * tiling of the x pass with products, and the radix order of the run-time z

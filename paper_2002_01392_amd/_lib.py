@@ -58,6 +58,10 @@ SIGNATURES = {
     "fcns_autotune": (ctypes.c_int, [_P, ctypes.c_char_p, _I32]),
     "fcns_batch_step": (ctypes.c_int, [ctypes.POINTER(_P), _I32, ctypes.POINTER(_D),
                                        ctypes.POINTER(_I32)]),
+    "fcns_batch_create": (ctypes.c_int, [ctypes.POINTER(_P), _I32, ctypes.POINTER(_D),
+                                         ctypes.POINTER(_P)]),
+    "fcns_batch_run": (ctypes.c_int, [_P, _I32]),
+    "fcns_batch_destroy": (ctypes.c_int, [_P]),
     "fcns_get_state": (ctypes.c_int, [_P, _P, _P, _P]),
     "fcns_get_spectral": (ctypes.c_int, [_P, _I32, _P]),
     "fcns_set_spectral": (ctypes.c_int, [_P, ctypes.POINTER(_P), _P]),
@@ -148,6 +152,41 @@ def batch_step(solvers, dts, nsteps):
     st = lib.fcns_batch_step(ctxs, n, dt, ns)
     if st != FCNS_OK:
         raise FcnsError(st, "batch_step")
+
+
+class Batch:
+    """Several solvers (FP64, N' <= 288, one rk_order, any shapes) stepped
+    together with one fused z-pass launch per RK stage for all of them
+    (fcns_batch_*)."""
+
+    def __init__(self, solvers, dts):
+        self.lib = load_library()
+        self.solvers = list(solvers)
+        n = len(self.solvers)
+        ctxs = (_P * n)(*[s.ctx for s in self.solvers])
+        dt = (_D * n)(*[float(x) for x in dts])
+        h = _P()
+        st = self.lib.fcns_batch_create(ctxs, n, dt, ctypes.byref(h))
+        if st != FCNS_OK:
+            raise FcnsError(st, self.lib.fcns_last_error(self.solvers[0].ctx).decode()
+                            or self.lib.fcns_last_error(None).decode())
+        self.h = h
+
+    def run(self, nsteps):
+        st = self.lib.fcns_batch_run(self.h, int(nsteps))
+        if st != FCNS_OK:
+            raise FcnsError(st, "batch_run")
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.fcns_batch_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def footprint(prob):

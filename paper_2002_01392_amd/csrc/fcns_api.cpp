@@ -260,6 +260,7 @@ static void free_all(fcns_ctx* c) {
 // f32: the twiddle table of the FP32 kernels
 static ZArgs zargs(const fcns_ctx* c, bool f32 = false) {
   ZArgs a;
+  memset(&a, 0, sizeof(a));  // padding too: batch descriptors are compared bytewise
   a.g = c->g;
   a.pl = c->plz;
   a.tw = f32 ? (const void*)c->twz_f : (const void*)c->twz;
@@ -621,14 +622,14 @@ extern "C" fcns_status fcns_set_state(fcns_ctx* c, const double* v, const double
 // whole pass (FP64, OUT != W, N' <= 288), else stage A, stage B and the back
 // transform of the new state.  T as in rk_stage.
 template <typename T>
-static void z_part(fcns_ctx* c, cpx<double>* W, cpx<double>* OUT, double cj, bool pressure,
-                   bool fused) {
+static void z_part_args(const fcns_ctx* c, cpx<double>* W, cpx<double>* OUT, double cj,
+                        bool pressure, bool fused, StageAArgs& A, StageBArgs& B) {
   const cpx<T>* mv = reinterpret_cast<const cpx<T>*>(c->MV);
   const cpx<T>* nlb = reinterpret_cast<const cpx<T>*>(c->NLB);
   const Geom& g = c->g;
   const long long S = c->S, M = c->M;
   const int nf = c->nf;
-  StageAArgs A{};
+  memset(&A, 0, sizeof(A));
   for (int f = 0; f < nf; ++f) {
     A.nl[f] = nlb + f * M;
     A.vt[f] = c->P + f * S;
@@ -651,7 +652,7 @@ static void z_part(fcns_ctx* c, cpx<double>* W, cpx<double>* OUT, double cj, boo
   A.kappa = c->prob.kappa;
   A.gamma = c->prob.gamma;
   A.forcing_sum = c->prob.forcing_x * (double)g.nx * (double)g.ny;
-  StageBArgs B{};
+  memset(&B, 0, sizeof(B));
   for (int i = 0; i < 3; ++i) {
     B.vs[i] = fused ? OUT + i * S : c->VS + i * S;
     B.vout[i] = OUT + i * S;
@@ -659,6 +660,16 @@ static void z_part(fcns_ctx* c, cpx<double>* W, cpx<double>* OUT, double cj, boo
   B.gwall = c->GW;
   B.pmix = pressure ? c->PM : nullptr;
   B.c = cj;
+}
+
+template <typename T>
+static void z_part(fcns_ctx* c, cpx<double>* W, cpx<double>* OUT, double cj, bool pressure,
+                   bool fused) {
+  const long long M = c->M;
+  const int nf = c->nf;
+  StageAArgs A;
+  StageBArgs B;
+  z_part_args<T>(c, W, OUT, cj, pressure, fused, A, B);
   if (fused) {
     // V* lives in OUT's velocity slots between its stage A and its
     // projection, inside one workgroup
@@ -1037,6 +1048,173 @@ extern "C" fcns_status fcns_batch_step(fcns_ctx* const* ctxs, int32_t n, const d
     else if (st != FCNS_OK && st != FCNS_ENONFINITE) return st;
   }
   return worst;
+}
+
+// ---------------------------------------------------------------- batch
+// Several problems of different shapes stepped together with one launch of
+// the fused z pass per RK stage for all of them: each context's x and y
+// passes run on its own stream, the batch stream waits for all of them,
+// runs the z passes of every problem in one kernel, and every context stream
+// waits for that before its next pass.
+struct fcns_batch {
+  std::vector<fcns_ctx*> ctx;
+  int o = 2;
+  hipStream_t stream = nullptr;
+  hipEvent_t ev_z = nullptr;
+  std::vector<hipEvent_t> ev_ctx;
+  ZPassDesc* desc = nullptr;      // [o][n] on the device
+  std::vector<ZPassDesc> hdesc;   // the host copy they were made from
+  std::vector<double> dt;         // per context
+  std::vector<double> cj;         // [o][n]
+  std::vector<char> fusable;      // per stage: the output buffer is not the input
+  long long groups = 0;
+  int max_npr = 0;
+  bool big = false;
+  size_t lds = 0;
+};
+
+// The descriptors of every (stage, context) from the contexts as they are
+// now (their tables, parameters and buffers), and the launch shape.
+static void batch_descriptors(fcns_batch* b, std::vector<ZPassDesc>& h) {
+  const int n = (int)b->ctx.size(), o = b->o;
+  h.resize((size_t)o * n);
+  memset(h.data(), 0, h.size() * sizeof(ZPassDesc));
+  b->cj.assign((size_t)o * n, 0.0);
+  b->fusable.assign(o, 0);
+  b->max_npr = 0;
+  b->big = false;
+  b->lds = 0;
+  for (int j = 1; j <= o; ++j) {
+    long long wg = 0;
+    for (int i = 0; i < n; ++i) {
+      fcns_ctx* c = b->ctx[i];
+      cpx<double>* W = (j == 1) ? c->P : c->Q;
+      cpx<double>* OUT = (j == o) ? c->P : c->Q;
+      b->fusable[j - 1] = OUT != W;
+      const double cj = b->dt[i] / (double)(o - j + 1);
+      b->cj[(size_t)(j - 1) * n + i] = cj;
+      ZPassDesc& d = h[(size_t)(j - 1) * n + i];
+      d.a = zargs(c);
+      d.a.nonfinite = c->dflag;
+      z_part_args<double>(c, W, OUT, cj, c->prob.keep_pressure && j == o, true, d.sa, d.sb);
+      d.zb = ZBackArgs{c->MV, c->M};
+      d.nf = c->nf;
+      d.wg0 = wg;
+      wg += z_pass_groups(d.a);
+      b->max_npr = std::max(b->max_npr, c->g.npr);
+      b->big = b->big || c->big_z;
+      b->lds = std::max(b->lds, z_pass_lds(d.a));
+    }
+    b->groups = wg;
+  }
+}
+
+static void batch_free(fcns_batch* b) {
+  if (b->stream) (void)hipStreamSynchronize(b->stream);
+  if (b->desc) (void)hipFree(b->desc);
+  if (b->ev_z) (void)hipEventDestroy(b->ev_z);
+  for (hipEvent_t e : b->ev_ctx)
+    if (e) (void)hipEventDestroy(e);
+  if (b->stream) (void)hipStreamDestroy(b->stream);
+  delete b;
+}
+
+extern "C" fcns_status fcns_batch_create(fcns_ctx* const* ctxs, int32_t n, const double* dts,
+                                         fcns_batch** out) {
+  if (!out) return FCNS_EINVAL;
+  *out = nullptr;
+  if (n < 1 || !ctxs || !dts) return fail(nullptr, FCNS_EINVAL, "need n >= 1 contexts and dts");
+  const int o = ctxs[0] ? ctxs[0]->prob.rk_order : 0;
+  for (int i = 0; i < n; ++i) {
+    fcns_ctx* c = ctxs[i];
+    if (!c) return fail(nullptr, FCNS_EINVAL, "NULL context");
+    if (!can_fuse(c))
+      return fail(c, FCNS_EINVAL, "batched z pass needs FP64 contexts with N' <= 288");
+    if (c->prob.rk_order != o) return fail(c, FCNS_EINVAL, "contexts must share rk_order");
+    if (!(dts[i] > 0.0)) return fail(c, FCNS_EINVAL, "need dt > 0");
+  }
+  fcns_batch* b = new fcns_batch();
+  b->ctx.assign(ctxs, ctxs + n);
+  b->o = o;
+  b->dt.assign(dts, dts + n);
+  std::vector<ZPassDesc> h;
+  batch_descriptors(b, h);
+  b->hdesc = h;
+  fcns_status st = FCNS_OK;
+  if (hipMalloc((void**)&b->desc, h.size() * sizeof(ZPassDesc)) != hipSuccess) {
+    batch_free(b);
+    return fail(nullptr, FCNS_ENOMEM, "batch descriptors");
+  }
+  if (hipMemcpy(b->desc, h.data(), h.size() * sizeof(ZPassDesc), hipMemcpyHostToDevice) !=
+          hipSuccess ||
+      hipStreamCreateWithFlags(&b->stream, hipStreamNonBlocking) != hipSuccess ||
+      hipEventCreateWithFlags(&b->ev_z, hipEventDisableTiming) != hipSuccess)
+    st = FCNS_EDEVICE;
+  b->ev_ctx.assign(n, nullptr);
+  for (int i = 0; i < n && st == FCNS_OK; ++i)
+    if (hipEventCreateWithFlags(&b->ev_ctx[i], hipEventDisableTiming) != hipSuccess)
+      st = FCNS_EDEVICE;
+  if (st != FCNS_OK) {
+    batch_free(b);
+    return fail(nullptr, st, "batch set-up");
+  }
+  *out = b;
+  return FCNS_OK;
+}
+
+extern "C" fcns_status fcns_batch_run(fcns_batch* b, int32_t nsteps) {
+  if (!b) return FCNS_EINVAL;
+  if (nsteps < 0) return fail(b->ctx[0], FCNS_EINVAL, "nsteps < 0");
+  const int n = (int)b->ctx.size(), o = b->o;
+  for (fcns_ctx* c : b->ctx)
+    if (!c->has_state) return fail(c, FCNS_ESTATE, "batch_run before set_state");
+  // a member retuned (new z tables) or given new parameters since: new
+  // descriptors before any launch that reads them
+  std::vector<ZPassDesc> h;
+  batch_descriptors(b, h);
+  if (memcmp(h.data(), b->hdesc.data(), h.size() * sizeof(ZPassDesc)) != 0) {
+    fcns_status st = check_hip(b->ctx[0], hipStreamSynchronize(b->stream), "batch_run");
+    if (st == FCNS_OK)
+      st = check_hip(b->ctx[0], hipMemcpy(b->desc, h.data(), h.size() * sizeof(ZPassDesc),
+                                          hipMemcpyHostToDevice), "batch_run");
+    if (st != FCNS_OK) return st;
+    b->hdesc = h;
+  }
+  for (int k = 0; k < nsteps; ++k)
+    for (int j = 1; j <= o; ++j) {
+      for (int i = 0; i < n; ++i) {
+        fcns_ctx* c = b->ctx[i];
+        nonlinear_from_mixed<double>(c, c->MV, c->nf, true);
+        if (b->fusable[j - 1]) {
+          (void)hipEventRecord(b->ev_ctx[i], c->stream);
+          (void)hipStreamWaitEvent(b->stream, b->ev_ctx[i], 0);
+        } else {
+          cpx<double>* W = (j == 1) ? c->P : c->Q;
+          cpx<double>* OUT = (j == o) ? c->P : c->Q;
+          z_part<double>(c, W, OUT, b->cj[(size_t)(j - 1) * n + i],
+                         c->prob.keep_pressure && j == o, false);
+        }
+      }
+      if (b->fusable[j - 1]) {
+        launch_z_pass_batch(b->desc + (size_t)(j - 1) * n, n, b->groups, b->max_npr, b->big,
+                            b->lds, b->stream);
+        (void)hipEventRecord(b->ev_z, b->stream);
+        for (fcns_ctx* c : b->ctx) (void)hipStreamWaitEvent(c->stream, b->ev_z, 0);
+      }
+    }
+  fcns_status worst = FCNS_OK;
+  for (fcns_ctx* c : b->ctx) {
+    if (nsteps > 0 && c->prob.keep_pressure) c->has_pressure = true;
+    fcns_status st = finish_steps(c, "batch_run");
+    if (st == FCNS_ENONFINITE && worst == FCNS_OK) worst = st;
+    else if (st != FCNS_OK && st != FCNS_ENONFINITE) return st;
+  }
+  return worst;
+}
+
+extern "C" fcns_status fcns_batch_destroy(fcns_batch* b) {
+  if (b) batch_free(b);
+  return FCNS_OK;
 }
 
 extern "C" fcns_status fcns_get_state(fcns_ctx* c, double* v, double* theta, double* p) {

@@ -123,6 +123,24 @@ struct ZBackArgs {
 bool z_pass_fits(const ZArgs& a);
 void launch_z_pass(const ZArgs& a, bool big, const StageAArgs& sa, const StageBArgs& sb,
                    const ZBackArgs& zb, int nfields, hipStream_t st);
+
+// One launch of the fused z pass over several problems (device array of n
+// descriptors; wg0 = first workgroup of each problem, ascending from 0;
+// groups = total workgroups).  Every problem runs the run-time plan engine
+// (big: some plan has a prime radix above 7); max_npr picks the rows per
+// thread; lds = the largest z_pass_lds of the batch.
+struct ZPassDesc {
+  ZArgs a;
+  StageAArgs sa;
+  StageBArgs sb;
+  ZBackArgs zb;
+  int nf;
+  long long wg0;
+};
+size_t z_pass_lds(const ZArgs& a);
+long long z_pass_groups(const ZArgs& a);
+void launch_z_pass_batch(const ZPassDesc* d, int n, long long groups, int max_npr, bool big,
+                         size_t lds, hipStream_t st);
 void launch_fc_extend(const double* in, long long nlines, long long ips, long long ils, double* out,
                       long long ops, long long ols, int nz, int C, int d, const double* M,
                       hipStream_t st);

@@ -766,15 +766,12 @@ __global__ __launch_bounds__(ZNT) void k_z_stageB(ZArgs a, StageBArgs s) {
 // buffer, as both stages of o = 2 do); W of the other field feeds the
 // buoyancy.  Each pencil group is independent, so V* never has to reach
 // HBM: it is written, read back and overwritten by the same workgroup.
+// The fused z pass of one pencil group at p0 (every thread of the workgroup).
 template <class FP, int OWN, bool WV>
-__global__ __launch_bounds__(ZNT, 2) void k_z_pass(ZArgs a, StageAArgs sa, StageBArgs sb,
-                                                   ZBackArgs zb, int nf) {
-  extern __shared__ __align__(16) char smem[];
-  __shared__ cpx<double> coef[ZPB * 5];
-  __shared__ double gam_s[ZPB];
-  const int tid = threadIdx.x;
-  const ZLds<double> L(smem, a.g, a.pl.tsize);
-  const long long p0 = (long long)blockIdx.x * ZPB;
+__device__ __forceinline__ void z_pass_group(const ZLds<double>& L, const ZArgs& a,
+                                             const StageAArgs& sa, const StageBArgs& sb,
+                                             const ZBackArgs& zb, int nf, long long p0, int tid,
+                                             cpx<double>* coef, double* gam_s) {
   // one field after the other (the field index a constant in each copy)
   z_stageA_field<double, double, FP, OWN, WV, true>(L, a, sa, 0, p0, tid, true);
   __syncthreads();
@@ -797,6 +794,35 @@ __global__ __launch_bounds__(ZNT, 2) void k_z_pass(ZArgs a, StageAArgs sa, Stage
     z_back_rows<double, FP, OWN>(L, a, keep, zb.mv + (2 * f) * zb.ms,
                                  zb.mv + (2 * f + 1) * zb.ms, p0, tid);
   }
+}
+
+template <class FP, int OWN, bool WV>
+__global__ __launch_bounds__(ZNT, 2) void k_z_pass(ZArgs a, StageAArgs sa, StageBArgs sb,
+                                                   ZBackArgs zb, int nf) {
+  extern __shared__ __align__(16) char smem[];
+  __shared__ cpx<double> coef[ZPB * 5];
+  __shared__ double gam_s[ZPB];
+  const ZLds<double> L(smem, a.g, a.pl.tsize);
+  z_pass_group<FP, OWN, WV>(L, a, sa, sb, zb, nf, (long long)blockIdx.x * ZPB, threadIdx.x,
+                            coef, gam_s);
+}
+
+// The fused z pass of several problems of different shapes in one launch:
+// workgroup b serves problem r with d[r].wg0 <= b < d[r + 1].wg0, pencil
+// group b - d[r].wg0 of it, with that problem's own geometry, plan, tables
+// and buffers.  Each workgroup runs exactly the code of k_z_pass (FP and OWN
+// cover every problem of the batch; rows past a problem's N' are masked).
+template <class FP, int OWN>
+__global__ __launch_bounds__(ZNT, 2) void k_z_pass_batch(const ZPassDesc* d, int n) {
+  extern __shared__ __align__(16) char smem[];
+  __shared__ cpx<double> coef[ZPB * 5];
+  __shared__ double gam_s[ZPB];
+  int r = 0;
+  while (r + 1 < n && (long long)blockIdx.x >= d[r + 1].wg0) ++r;
+  const ZPassDesc& D = d[r];
+  const ZLds<double> L(smem, D.a.g, D.a.pl.tsize);
+  z_pass_group<FP, OWN, false>(L, D.a, D.sa, D.sb, D.zb, D.nf,
+                               ((long long)blockIdx.x - D.wg0) * ZPB, threadIdx.x, coef, gam_s);
 }
 
 // ---------------------------------------------------------------- fc_extend
@@ -965,6 +991,25 @@ void launch_z_stageB(const ZArgs& a, bool big, const StageBArgs& s, hipStream_t 
 }
 
 bool z_pass_fits(const ZArgs& a) { return pick_own(a.g.npr) <= 9; }
+
+size_t z_pass_lds(const ZArgs& a) { return zshared_bytes<double>(a.g, a.pl.tsize); }
+long long z_pass_groups(const ZArgs& a) { return (a.g.npen + ZPB - 1) / ZPB; }
+
+void launch_z_pass_batch(const ZPassDesc* d, int n, long long groups, int max_npr, bool big,
+                         size_t lds, hipStream_t st) {
+  dim3 grid((unsigned)groups);
+  if (pick_own(max_npr) <= 4) {
+    if (big)
+      FCNS_LAUNCH((k_z_pass_batch<DynPlan<true>, 4>), grid, dim3(ZNT), lds, st, d, n);
+    else
+      FCNS_LAUNCH((k_z_pass_batch<DynPlan<false>, 4>), grid, dim3(ZNT), lds, st, d, n);
+  } else {
+    if (big)
+      FCNS_LAUNCH((k_z_pass_batch<DynPlan<true>, 9>), grid, dim3(ZNT), lds, st, d, n);
+    else
+      FCNS_LAUNCH((k_z_pass_batch<DynPlan<false>, 9>), grid, dim3(ZNT), lds, st, d, n);
+  }
+}
 
 void launch_z_pass(const ZArgs& a, bool big, const StageAArgs& sa, const StageBArgs& sb,
                    const ZBackArgs& zb, int nfields, hipStream_t st) {
