@@ -223,6 +223,15 @@ fcns_status fcns_autotune(fcns_ctx* ctx, char* report, int32_t report_len);
  * context it does not apply to.  Results agree to rounding. */
 fcns_status fcns_set_z_fused(fcns_ctx* ctx, int32_t on);
 
+/* Choose how rk_step runs the y and x passes of a stage (Sec. 4.2: the y
+ * back transforms of v and its derivatives, the products in x, the y
+ * forward transform of the nonlinear term): planes = 0 over whole arrays
+ * (the default), planes > 0 slab by slab in z, that many planes at a time,
+ * so that each slab's intermediate arrays are read back from the caches
+ * (fcns_autotune picks the faster).  Results are bitwise the same.  EINVAL
+ * if planes < 0 or 4 planes > 3 nz. */
+fcns_status fcns_set_slab(fcns_ctx* ctx, int32_t planes);
+
 /* Same as fcns_rk_step, by replaying a HIP graph of one step.  The graph is
  * captured on the first call and again whenever dt changes (capture
  * synchronizes the stream and allocates the graph; replays allocate

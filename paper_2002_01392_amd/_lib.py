@@ -53,6 +53,7 @@ SIGNATURES = {
     "fcns_rk_graph": (ctypes.c_int, [_P, _D, _I32]),
     "fcns_set_finite_check": (ctypes.c_int, [_P, _I32]),
     "fcns_set_z_fused": (ctypes.c_int, [_P, _I32]),
+    "fcns_set_slab": (ctypes.c_int, [_P, _I32]),
     "fcns_check_finite": (ctypes.c_int, [_P]),
     "fcns_nonfinite_flag": (ctypes.c_int32, [_P]),
     "fcns_autotune": (ctypes.c_int, [_P, ctypes.c_char_p, _I32]),
@@ -400,6 +401,11 @@ class Solver:
         """Run each stage's z pass as one fused kernel (FP64, N' <= 288)."""
         self._check(self.lib.fcns_set_z_fused(self.ctx, int(bool(on))))
 
+    def set_slab(self, planes):
+        """Run rk_step's y and x passes slab by slab, `planes` z planes at a
+        time (0: whole arrays)."""
+        self._check(self.lib.fcns_set_slab(self.ctx, int(planes)))
+
     def autotune(self):
         """Pick the fastest launch choices for this shape; returns the summary."""
         buf = ctypes.create_string_buffer(1024)
@@ -476,7 +482,7 @@ class Solver:
         self._keep = (fs, wg)
 
     TIMING_CLASSES = ("y_back_dy", "y_back_dz", "x_nl", "y_fwd", "z_stageA", "z_stageB",
-                      "z_back", "z_pass")
+                      "z_back", "z_pass", "xy_slabs")
 
     def set_timing(self, enable=True, classes=None):
         """Event-time rk_step's kernels: every class, or only those named in

@@ -66,6 +66,8 @@ struct fcns_ctx {
   int ynopf = 0;
   long long ygrid1 = 0;  // y back with d/dy (two transforms per tile)
   int ynopf1 = 0;
+  int slab = 0;          // > 0: the y / x passes of rk_step run slab by slab, this
+                         // many z planes at a time (0: whole arrays)
   bool zfuse = false;    // FP64 stages writing the other state buffer: one fused z
                          // pass (chosen by fcns_autotune where it is faster)
   bool has_state = false;
@@ -89,9 +91,10 @@ struct fcns_ctx {
 
 // Kernel classes timed by fcns_set_timing.
 enum { T_YBACK_DY = 0, T_YBACK_DZ, T_XNL, T_YFWD, T_ZSTAGEA, T_ZSTAGEB, T_ZBACK, T_ZPASS,
-       T_NCLS };
+       T_XYSLAB, T_NCLS };
 static const char* kTimingNames[T_NCLS] = {"y_back_dy", "y_back_dz", "x_nl", "y_fwd",
-                                           "z_stageA", "z_stageB", "z_back", "z_pass"};
+                                           "z_stageA", "z_stageB", "z_back", "z_pass",
+                                           "xy_slabs"};
 
 static void timing_flush(fcns_ctx* c) {
   if (c->recs.empty()) return;
@@ -512,6 +515,30 @@ static void nonlinear_from_mixed(fcns_ctx* c, const cpx<T>* mv, int nfields, boo
   const bool f32 = sizeof(T) == sizeof(float);
   cpx<T>* xyb = reinterpret_cast<cpx<T>*>(c->XYB);
   cpx<T>* nlb = reinterpret_cast<cpx<T>*>(c->NLB);
+  if (fwd_y && c->slab > 0 && c->slab < g.nz) {
+    // slab by slab: the (kx, y, z) intermediates of a slab of planes are
+    // written and read back within its four launches, in the first part of
+    // XYB (4 nf slab fields), so they are reused from the caches rather than
+    // streamed through HBM; only the mixed nonlinear term reaches NLB
+    const long long P = (long long)g.ny * g.nkxp;
+    const long long Ms = (long long)c->slab * P;
+    cpx<T>* nls = xyb + 3 * nfields * Ms;
+    tbeg(c, T_XYSLAB);
+    for (int z0 = 0; z0 < g.nz; z0 += c->slab) {
+      const int nzs = std::min(c->slab, g.nz - z0);
+      const long long off = (long long)z0 * P;
+      launch_y<T>(yargs(c, f32, true), c->big_y, true, 1, mv + off, xyb, xyb + Ms, 2 * M, 3 * Ms,
+                  nzs, nfields, c->stream);
+      launch_y<T>(yargs(c, f32), c->big_y, true, 0, mv + M + off, xyb + 2 * Ms, nullptr, 2 * M,
+                  3 * Ms, nzs, nfields, c->stream);
+      launch_x_nl<T>(xargs(c, f32), c->big_x, xyb, nls, Ms, (long long)nzs * g.ny, nfields,
+                     c->stream);
+      launch_y<T>(yargs(c, f32), c->big_y, false, 0, nls, nlb + off, nullptr, Ms, M, nzs,
+                  nfields, c->stream);
+    }
+    tend(c);
+    return;
+  }
   tbeg(c, T_YBACK_DY);
   launch_y<T>(yargs(c, f32, true), c->big_y, true, 1, mv, xyb, xyb + M, 2 * M, 3 * M, g.nz, nfields,
               c->stream);
@@ -729,6 +756,16 @@ extern "C" fcns_status fcns_rk_step(fcns_ctx* c, double dt, int32_t nsteps) {
   return finish_steps(c, "rk_step");
 }
 
+extern "C" fcns_status fcns_set_slab(fcns_ctx* c, int32_t planes) {
+  if (!c) return FCNS_EINVAL;
+  if (planes < 0) return fail(c, FCNS_EINVAL, "slab planes must be >= 0");
+  // the slab scratch (4 nf slab fields) lives in XYB (3 nf whole fields)
+  if (planes > 0 && 4LL * planes > 3LL * c->g.nz)
+    return fail(c, FCNS_EINVAL, "slab larger than 3/4 of the planes");
+  c->slab = planes;
+  return FCNS_OK;
+}
+
 extern "C" fcns_status fcns_set_z_fused(fcns_ctx* c, int32_t on) {
   if (!c) return FCNS_EINVAL;
   if (on && !can_fuse(c))
@@ -872,6 +909,9 @@ extern "C" fcns_status fcns_autotune(fcns_ctx* c, char* report, int32_t report_l
   const bool f32 = c->mixed;
   std::string rep;
   char line[256];
+  // the timed trials carry no kernel-timing events
+  const bool timing = c->timing;
+  c->timing = false;
   // y pass: persistent grid size and prefetch, chosen separately for the back
   // transform with d/dy (two transforms per tile) and for the two launches of
   // one transform per tile (back of dv/dz, forward of NL), on the state's
@@ -952,6 +992,32 @@ extern "C" fcns_status fcns_autotune(fcns_ctx* c, char* report, int32_t report_l
     snprintf(line, sizeof(line), "x: variant %d (%.3f ms); ", bv, best);
     rep += line;
   }
+  // y and x passes over whole arrays or slab by slab (timed on the state's
+  // mixed fields; XYB and NLB are scratch)
+  {
+    float best = 1e30f;
+    int bs = 0;
+    for (int sl : {0, 16, 32, 48, 64, 96, 128}) {
+      if (sl > 0 && (sl >= g.nz || 4 * sl > 3 * g.nz)) continue;
+      c->slab = sl;
+      const float ms = time_ms(c, [&] {
+        if (f32)
+          nonlinear_from_mixed<float>(c, reinterpret_cast<const cpx<float>*>(c->MV), nf, true);
+        else
+          nonlinear_from_mixed<double>(c, c->MV, nf, true);
+      }, reps);
+      if (ms < best) {
+        best = ms;
+        bs = sl;
+      }
+    }
+    c->slab = bs;
+    if (bs > 0)
+      snprintf(line, sizeof(line), "y/x: slabs of %d planes (%.3f ms); ", bs, best);
+    else
+      snprintf(line, sizeof(line), "y/x: whole arrays (%.3f ms); ", best);
+    rep += line;
+  }
   // z: radix order of a run-time plan, timed on the back-transform of the
   // state (a compiled plan, when the length has one, is kept)
   {
@@ -965,7 +1031,10 @@ extern "C" fcns_status fcns_autotune(fcns_ctx* c, char* report, int32_t report_l
       int n = 0;
       do {
         fcns_status st = set_z_plan(c, perm);
-        if (st) return st;
+        if (st) {
+          c->timing = timing;
+          return st;
+        }
         const float ms = time_ms(c, [&] {
           launch_z_back<double>(zargs(c), c->big_z, c->P, c->MVT, c->MVT + M, c->S, 2 * M, nf,
                                 c->stream);
@@ -976,7 +1045,10 @@ extern "C" fcns_status fcns_autotune(fcns_ctx* c, char* report, int32_t report_l
         }
       } while (++n < 24 && std::next_permutation(perm.begin(), perm.end()));
       fcns_status st = set_z_plan(c, best_rs);
-      if (st) return st;
+      if (st) {
+        c->timing = timing;
+        return st;
+      }
     }
     rep += "z: radices";
     for (int r : best_rs) rep += " " + std::to_string(r);
@@ -1005,6 +1077,7 @@ extern "C" fcns_status fcns_autotune(fcns_ctx* c, char* report, int32_t report_l
   // the mixed-space fields of the state were overwritten only in scratch; the
   // ones the next step reads are rebuilt from the state
   state_to_mv(c, c->P);
+  c->timing = timing;
   fcns_status st = check_launch(c, "autotune");
   if (report && report_len > 0) {
     strncpy(report, rep.c_str(), (size_t)report_len - 1);

@@ -823,7 +823,11 @@ void launch_y(const YArgs& a, bool big, bool inv, int mode, const cpx<T>* src, c
   const long long nlines = (long long)nplanes * a.nkxp;
   const long long ntiles = (nlines + YL - 1) / YL;
   const long long yg = a.grid > 0 ? a.grid : Y_GRID;
-  dim3 grid((unsigned)(ntiles < yg ? ntiles : yg), nfields);
+  // fewer tiles than the persistent grid: one workgroup per tile, rounded up
+  // to whole chunks of 64 so that the XCD-aware order still applies
+  long long gx = ntiles < yg ? ntiles : yg;
+  if (gx < yg && gx % 64) gx = std::min(yg, (gx + 63) / 64 * 64);
+  dim3 grid((unsigned)gx, nfields);
   const size_t sh = y_lds_bytes(a.ny, a.pl.tsize, sizeof(cpx<T>));
   const int need = (a.ny + YNT / YL - 1) / (YNT / YL);
   const int iv = inv ? 1 : 0;

@@ -340,10 +340,13 @@ __global__ __launch_bounds__(ZNT) void k_z_back(ZArgs a, const cpx<double>* __re
 // the other field's mixed values, added after the inverse transform.
 // Ends with this thread's stores; the caller places a barrier before the
 // LDS is used again.
-template <typename T, typename TM, class FP, int OWN, bool WV, bool SPECBUOY>
+// KEEPOUT: the stored rows are also left in keep (the row layout of
+// z_back_rows, zero past N' and for padding pencils).
+template <typename T, typename TM, class FP, int OWN, bool WV, bool SPECBUOY,
+          bool KEEPOUT = false>
 __device__ __forceinline__ void z_stageA_field(const ZLds<T>& L, const ZArgs& a,
                                                const StageAArgs& s, int f, long long p0, int tid,
-                                               bool tables) {
+                                               bool tables, cpx<double>* keep = nullptr) {
   // a fresh copy of the thread index: the row offsets derived from it are
   // recomputed per field rather than kept live from one field to the next
   asm volatile("" : "+v"(tid));
@@ -483,6 +486,19 @@ __device__ __forceinline__ void z_stageA_field(const ZLds<T>& L, const ZArgs& a,
   // (the rolled loop waits for each read in turn; it measured faster on the
   // small run-time-plan grids)
   cpx<double>* out = s.out[f];
+  if constexpr (KEEPOUT) {
+#pragma unroll
+    for (int r = 0; r < OWN; ++r) {
+      const int l = lt + r * ZLS;
+      keep[r] = (pv && l < npr) ? cvt<double>(R[l * ZPB + pb]) : zero<double>();
+    }
+    if (pv) {
+#pragma unroll
+      for (int r = 0; r < OWN; ++r)
+        if (lt + r * ZLS < npr) out[(long long)(lt + r * ZLS) * g.npen + p] = keep[r];
+    }
+    return;
+  }
   if (pv) {
     if constexpr (!FP::dynamic) {
       cpx<double> ov[OWN];
@@ -772,22 +788,27 @@ __device__ __forceinline__ void z_pass_group(const ZLds<double>& L, const ZArgs&
                                              const StageAArgs& sa, const StageBArgs& sb,
                                              const ZBackArgs& zb, int nf, long long p0, int tid,
                                              cpx<double>* coef, double* gam_s) {
-  // one field after the other (the field index a constant in each copy)
-  z_stageA_field<double, double, FP, OWN, WV, true>(L, a, sa, 0, p0, tid, true);
+  // one field after the other (the field index a constant in each copy);
+  // theta first: its new state is final after stage A, so its back
+  // transforms follow at once from the rows still in registers
+  if (nf == 4) {
+    cpx<double> keep[OWN];
+    z_stageA_field<double, double, FP, OWN, WV, true, true>(L, a, sa, 3, p0, tid, true, keep);
+    __syncthreads();
+    check_rows<OWN>(a, keep);
+    z_back_rows<double, FP, OWN>(L, a, keep, zb.mv + 6 * zb.ms, zb.mv + 7 * zb.ms, p0, tid);
+  }
+  z_stageA_field<double, double, FP, OWN, WV, true>(L, a, sa, 0, p0, tid, nf != 4);
   __syncthreads();
   z_stageA_field<double, double, FP, OWN, WV, true>(L, a, sa, 1, p0, tid, false);
   __syncthreads();
   z_stageA_field<double, double, FP, OWN, WV, true>(L, a, sa, 2, p0, tid, false);
   __syncthreads();
-  if (nf == 4) {
-    z_stageA_field<double, double, FP, OWN, WV, true>(L, a, sa, 3, p0, tid, false);
-    __syncthreads();
-  }
   cpx<double> vk[3][1];
   z_stageB_body<double, FP, OWN, false>(L, a, sb, p0, tid, coef, gam_s, false, vk);
   __syncthreads();
-  // each thread reads back the rows it has just written (cache hits)
-  for (int f = 0; f < nf; ++f) {
+  // each thread reads back the velocity rows it has just written (cache hits)
+  for (int f = 0; f < 3; ++f) {
     cpx<double> keep[OWN];
     load_rows<FP, OWN>(a, sa.out[f], p0, tid, keep);
     check_rows<OWN>(a, keep);

@@ -1,0 +1,98 @@
+"""The y and x passes slab by slab in z (fcns_set_slab): every line and row
+is transformed by the same code as over whole arrays, so a step is bitwise
+the same for any slab size (ragged last slabs included), and the stepped
+state still matches the FP64 oracle at the 1e-11 bar."""
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle.ns import Oracle, Problem
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def fcns():
+    if not torch.cuda.is_available():
+        pytest.skip("no HIP device")
+    import paper_2002_01392_amd as P
+    P.load_library()
+    return P
+
+
+def rel_l2(a, b):
+    a = a.detach().cpu().numpy() if hasattr(a, "detach") else np.asarray(a)
+    b = np.asarray(b)
+    nb = np.linalg.norm(b)
+    return float(np.linalg.norm(a - b) / (nb if nb > 0 else 1.0))
+
+
+def _run(fcns, w, v0, th0, slab, steps, precision="fp64", fused=False):
+    s = fcns.Solver.from_workload(w, precision=precision, keep_pressure=True)
+    s.set_state(torch.from_numpy(v0), torch.from_numpy(th0) if th0 is not None else None)
+    if fused:
+        s.set_z_fused(True)
+    s.set_slab(slab)
+    s.rk_step(w.dt, steps)
+    v, th, p = s.get_state(pressure=True)
+    s.synchronize()
+    return v, th, p
+
+
+CASES = {
+    # 4 fields, 33 planes in slabs of 8 (a last slab of one plane) and 24
+    "rb": (lambda: W.rayleigh_benard(32, 32, 33, 1e5, C=31, dt=1e-3, steps=3, seed=811,
+                                     perturbation="curl_eigen", noise_rms=1e-2), (8, 24)),
+    # 3 fields, nx = 256 (two rows per wavefront in the x pass), N' = 282
+    "channel": (lambda: W.channel(256, 16, 257, 2000.0, C=25, dt=5e-4, steps=2, seed=812,
+                                  noise_rms=0.05), (32, 64, 100)),
+}
+
+
+@pytest.mark.parametrize("name", sorted(CASES))
+def test_slabs_are_bitwise_the_whole_array_step(fcns, name):
+    make, slabs = CASES[name]
+    w = make()
+    v0, th0 = w.initial_state()
+    ref = _run(fcns, w, v0, th0, 0, w.steps)
+    for sl in slabs:
+        got = _run(fcns, w, v0, th0, sl, w.steps)
+        for g, r in zip(got, ref):
+            if r is not None:
+                assert torch.equal(g, r), (name, sl)
+
+
+def test_slabs_match_the_oracle(fcns):
+    w = CASES["rb"][0]()
+    v0, th0 = w.initial_state()
+    v, th, p = _run(fcns, w, v0, th0, 8, w.steps, fused=True)
+    o = Oracle(Problem(**w.problem_kwargs()))
+    o.set_state(v0, th0)
+    o.rk_step(w.dt, w.steps)
+    rv, rth, rp = o.get_state()
+    assert rel_l2(v, rv) < 1e-11
+    assert rel_l2(th, rth) < 1e-11
+    assert rel_l2(p, rp) < 1e-10
+
+
+def test_slabs_in_mixed_precision_are_bitwise_the_whole_array_step(fcns):
+    w = W.channel(64, 32, 65, 2000.0, C=31, dt=5e-4, steps=2, seed=813, noise_rms=0.05)
+    v0, th0 = w.initial_state()
+    ref = _run(fcns, w, v0, th0, 0, w.steps, precision="mixed")
+    got = _run(fcns, w, v0, th0, 16, w.steps, precision="mixed")
+    for g, r in zip(got, ref):
+        if r is not None:
+            assert torch.equal(g, r)
+
+
+def test_slab_sizes_outside_the_scratch_are_refused(fcns):
+    w = W.channel(32, 32, 33, 1000.0, C=25, dt=1e-3, steps=1, seed=814)
+    s = fcns.Solver.from_workload(w)
+    for bad in (-1, 25, 33, 1000):   # 4 * planes must not exceed 3 * nz = 99
+        with pytest.raises(fcns.FcnsError) as e:
+            s.set_slab(bad)
+        assert e.value.code == fcns.FCNS_EINVAL
+    s.set_slab(24)
+    s.set_slab(0)
