@@ -340,10 +340,11 @@ __global__ __launch_bounds__(ZNT) void k_z_back(ZArgs a, const cpx<double>* __re
 // the other field's mixed values, added after the inverse transform.
 // Ends with this thread's stores; the caller places a barrier before the
 // LDS is used again.
-// KEEPOUT: the stored rows are also left in keep (the row layout of
-// z_back_rows, zero past N' and for padding pencils).
+// KEEPOUT: the result rows are also left in keep (the row layout of
+// z_back_rows, zero past N' and for padding pencils); STORE = false: they
+// are only left there.
 template <typename T, typename TM, class FP, int OWN, bool WV, bool SPECBUOY,
-          bool KEEPOUT = false>
+          bool KEEPOUT = false, bool STORE = true>
 __device__ __forceinline__ void z_stageA_field(const ZLds<T>& L, const ZArgs& a,
                                                const StageAArgs& s, int f, long long p0, int tid,
                                                bool tables, cpx<double>* keep = nullptr) {
@@ -492,7 +493,7 @@ __device__ __forceinline__ void z_stageA_field(const ZLds<T>& L, const ZArgs& a,
       const int l = lt + r * ZLS;
       keep[r] = (pv && l < npr) ? cvt<double>(R[l * ZPB + pb]) : zero<double>();
     }
-    if (pv) {
+    if (STORE && pv) {
 #pragma unroll
       for (int r = 0; r < OWN; ++r)
         if (lt + r * ZLS < npr) out[(long long)(lt + r * ZLS) * g.npen + p] = keep[r];
@@ -540,12 +541,16 @@ __global__ __launch_bounds__(ZNT) void k_z_stageA(ZArgs a, StageAArgs s) {
 // the same workgroup; otherwise the mixed v, dv/dz of the result come from
 // k_z_back.  TABLES: stage the plan and continuation tables in LDS.
 // coef (ZPB * 5 entries) and gam_s (ZPB) are LDS scratch.
-template <typename T, class FP, int HOLD, bool KEEP>
+// KF >= 0 (needs HOLD): V* of field KF is not read but taken from kv, this
+// thread's rows in the layout of z_back_rows.
+template <typename T, class FP, int HOLD, bool KEEP, int KF = -1>
 __device__ __forceinline__ void z_stageB_body(const ZLds<T>& L, const ZArgs& a,
                                               const StageBArgs& s, long long p0, int tid,
                                               cpx<double>* coef, double* gam_s, bool tables,
-                                              cpx<double> (&vk)[3][KEEP ? HOLD : 1]) {
+                                              cpx<double> (&vk)[3][KEEP ? HOLD : 1],
+                                              const cpx<double>* kv = nullptr) {
   static_assert(!KEEP || HOLD > 0, "KEEP needs the rows held in registers");
+  static_assert(KF < 0 || HOLD > 0, "KF needs the rows held in registers");
   const Geom& g = a.g;
   const int npr = FP::dynamic ? g.npr : FP::n;
   const int pb_me = tid % ZPB, lt = tid / ZPB;
@@ -584,7 +589,7 @@ __device__ __forceinline__ void z_stageB_body(const ZLds<T>& L, const ZArgs& a,
       const long long gi =
           valid_me ? (long long)min(lt + r * ZLS, npr - 1) * g.npen + p_me : 0;
 #pragma unroll
-      for (int i = 0; i < 3; ++i) hv[i][r] = s.vs[i][gi];
+      for (int i = 0; i < 3; ++i) hv[i][r] = (i == KF) ? kv[r] : s.vs[i][gi];
     }
   }
   if (tables) ztab_store<T>(tab, L, a, tid);
@@ -773,15 +778,16 @@ __global__ __launch_bounds__(ZNT) void k_z_stageB(ZArgs a, StageBArgs s) {
 
 // ---------------------------------------------------------------- one fused z pass
 // The whole z pass of one RK stage for a group of ZPB pencils (FP64): stage
-// A for every transported field (velocity into s.out[0..2] as V*, theta as
-// its new state; the buoyancy in spectral form), the projection of V* in
-// place (stage B, V* read back while it is still in the caches, the result
-// kept in registers), and the back transforms of the new state (v, dv/dz of
-// every field into the mixed arrays).  The outputs must not alias the
-// inputs of another field (true when the stage writes the other state
-// buffer, as both stages of o = 2 do); W of the other field feeds the
-// buoyancy.  Each pencil group is independent, so V* never has to reach
-// HBM: it is written, read back and overwritten by the same workgroup.
+// A for every transported field (velocity into s.out[0..2] as V*, except
+// the last one, which stays in registers; theta as its new state; the
+// buoyancy in spectral form), the projection of V* in place (stage B, V*
+// read back while it is still in the caches), and the back transforms of
+// the new state (v, dv/dz of every field into the mixed arrays).  The
+// outputs must not alias the inputs of another field (true when the stage
+// writes the other state buffer, as both stages of o = 2 do); W of the
+// other field feeds the buoyancy.  Each pencil group is independent, so V*
+// never has to reach HBM: it is written, read back and overwritten by the
+// same workgroup.
 // The fused z pass of one pencil group at p0 (every thread of the workgroup).
 template <class FP, int OWN, bool WV>
 __device__ __forceinline__ void z_pass_group(const ZLds<double>& L, const ZArgs& a,
@@ -798,14 +804,18 @@ __device__ __forceinline__ void z_pass_group(const ZLds<double>& L, const ZArgs&
     check_rows<OWN>(a, keep);
     z_back_rows<double, FP, OWN>(L, a, keep, zb.mv + 6 * zb.ms, zb.mv + 7 * zb.ms, p0, tid);
   }
-  z_stageA_field<double, double, FP, OWN, WV, true>(L, a, sa, 0, p0, tid, nf != 4);
+  // then w (its buoyancy reads theta's W again, soon after theta did), u,
+  // and v, whose V* goes to the projection in registers without a store
+  z_stageA_field<double, double, FP, OWN, WV, true>(L, a, sa, 2, p0, tid, nf != 4);
   __syncthreads();
-  z_stageA_field<double, double, FP, OWN, WV, true>(L, a, sa, 1, p0, tid, false);
+  z_stageA_field<double, double, FP, OWN, WV, true>(L, a, sa, 0, p0, tid, false);
   __syncthreads();
-  z_stageA_field<double, double, FP, OWN, WV, true>(L, a, sa, 2, p0, tid, false);
+  cpx<double> vstar1[OWN];
+  z_stageA_field<double, double, FP, OWN, WV, true, true, false>(L, a, sa, 1, p0, tid, false,
+                                                                  vstar1);
   __syncthreads();
   cpx<double> vk[3][1];
-  z_stageB_body<double, FP, OWN, false>(L, a, sb, p0, tid, coef, gam_s, false, vk);
+  z_stageB_body<double, FP, OWN, false, 1>(L, a, sb, p0, tid, coef, gam_s, false, vk, vstar1);
   __syncthreads();
   // each thread reads back the velocity rows it has just written (cache hits)
   for (int f = 0; f < 3; ++f) {
