@@ -542,13 +542,14 @@ __global__ __launch_bounds__(ZNT) void k_z_stageA(ZArgs a, StageAArgs s) {
 // k_z_back.  TABLES: stage the plan and continuation tables in LDS.
 // coef (ZPB * 5 entries) and gam_s (ZPB) are LDS scratch.
 // KF >= 0 (needs HOLD): V* of field KF is not read but taken from kv, this
-// thread's rows in the layout of z_back_rows.
+// thread's rows in the layout of z_back_rows, and kv receives the field's
+// projected rows in their place.
 template <typename T, class FP, int HOLD, bool KEEP, int KF = -1>
 __device__ __forceinline__ void z_stageB_body(const ZLds<T>& L, const ZArgs& a,
                                               const StageBArgs& s, long long p0, int tid,
                                               cpx<double>* coef, double* gam_s, bool tables,
                                               cpx<double> (&vk)[3][KEEP ? HOLD : 1],
-                                              const cpx<double>* kv = nullptr) {
+                                              cpx<double>* kv = nullptr) {
   static_assert(!KEEP || HOLD > 0, "KEEP needs the rows held in registers");
   static_assert(KF < 0 || HOLD > 0, "KF needs the rows held in registers");
   const Geom& g = a.g;
@@ -739,6 +740,7 @@ __device__ __forceinline__ void z_stageB_body(const ZLds<T>& L, const ZArgs& a,
     s.vout[0][gi] = n0;
     s.vout[1][gi] = n1;
     s.vout[2][gi] = n2;
+    if constexpr (KF >= 0) kv[r] = (KF == 0) ? n0 : (KF == 1) ? n1 : n2;
     if constexpr (KEEP) {
       vk[0][r] = n0;
       vk[1][r] = n1;
@@ -782,7 +784,8 @@ __global__ __launch_bounds__(ZNT) void k_z_stageB(ZArgs a, StageBArgs s) {
 // the last one, which stays in registers; theta as its new state; the
 // buoyancy in spectral form), the projection of V* in place (stage B, V*
 // read back while it is still in the caches), and the back transforms of
-// the new state (v, dv/dz of every field into the mixed arrays).  The
+// the new state (v, dv/dz of every field into the mixed arrays; theta's and
+// the last velocity field's from the rows still in registers).  The
 // outputs must not alias the inputs of another field (true when the stage
 // writes the other state buffer, as both stages of o = 2 do); W of the
 // other field feeds the buoyancy.  Each pencil group is independent, so V*
@@ -817,8 +820,11 @@ __device__ __forceinline__ void z_pass_group(const ZLds<double>& L, const ZArgs&
   cpx<double> vk[3][1];
   z_stageB_body<double, FP, OWN, false, 1>(L, a, sb, p0, tid, coef, gam_s, false, vk, vstar1);
   __syncthreads();
-  // each thread reads back the velocity rows it has just written (cache hits)
-  for (int f = 0; f < 3; ++f) {
+  // v's new state is in registers; each thread reads back the rows of u and
+  // w it has just written (cache hits)
+  check_rows<OWN>(a, vstar1);
+  z_back_rows<double, FP, OWN>(L, a, vstar1, zb.mv + 2 * zb.ms, zb.mv + 3 * zb.ms, p0, tid);
+  for (int f = 0; f < 3; f += 2) {
     cpx<double> keep[OWN];
     load_rows<FP, OWN>(a, sa.out[f], p0, tid, keep);
     check_rows<OWN>(a, keep);
