@@ -232,6 +232,20 @@ fcns_status fcns_set_z_fused(fcns_ctx* ctx, int32_t on);
  * if planes < 0 or 4 planes > 3 nz. */
 fcns_status fcns_set_slab(fcns_ctx* ctx, int32_t planes);
 
+/* Choose the layout of rk_step's (kx, y) intermediate arrays (Sec. 4.2: v
+ * and its y and z derivatives between the y back transforms and the
+ * products in x): on = 0 row-major (the default), 1 blocked (each group of
+ * 4 kx columns stored contiguously over y, so that the y back transforms
+ * write whole contiguous blocks; fcns_autotune picks the faster).  Results
+ * are bitwise the same.  EINVAL if on = 1 and the x pass cannot read that
+ * layout (it needs nx = 256 or 512 and the wave-level x kernel). */
+fcns_status fcns_set_blocked(fcns_ctx* ctx, int32_t on);
+
+/* Lines (kx columns) per workgroup tile of the y transforms: 4 (the
+ * default) or 8 (whole 128-byte rows; ny = 512 only, else EINVAL);
+ * fcns_autotune picks per launch kind.  Results are bitwise the same. */
+fcns_status fcns_set_y_lines(fcns_ctx* ctx, int32_t lines);
+
 /* Same as fcns_rk_step, by replaying a HIP graph of one step.  The graph is
  * captured on the first call and again whenever dt changes (capture
  * synchronizes the stream and allocates the graph; replays allocate

@@ -54,6 +54,8 @@ SIGNATURES = {
     "fcns_set_finite_check": (ctypes.c_int, [_P, _I32]),
     "fcns_set_z_fused": (ctypes.c_int, [_P, _I32]),
     "fcns_set_slab": (ctypes.c_int, [_P, _I32]),
+    "fcns_set_blocked": (ctypes.c_int, [_P, _I32]),
+    "fcns_set_y_lines": (ctypes.c_int, [_P, _I32]),
     "fcns_check_finite": (ctypes.c_int, [_P]),
     "fcns_nonfinite_flag": (ctypes.c_int32, [_P]),
     "fcns_autotune": (ctypes.c_int, [_P, ctypes.c_char_p, _I32]),
@@ -405,6 +407,14 @@ class Solver:
         """Run rk_step's y and x passes slab by slab, `planes` z planes at a
         time (0: whole arrays)."""
         self._check(self.lib.fcns_set_slab(self.ctx, int(planes)))
+
+    def set_blocked(self, on=True):
+        """Keep rk_step's (kx, y) intermediates in the blocked layout."""
+        self._check(self.lib.fcns_set_blocked(self.ctx, int(bool(on))))
+
+    def set_y_lines(self, lines):
+        """Lines per y-transform tile: 4, or 8 at ny = 512."""
+        self._check(self.lib.fcns_set_y_lines(self.ctx, int(lines)))
 
     def autotune(self):
         """Pick the fastest launch choices for this shape; returns the summary."""

@@ -66,6 +66,10 @@ struct fcns_ctx {
   int ynopf = 0;
   long long ygrid1 = 0;  // y back with d/dy (two transforms per tile)
   int ynopf1 = 0;
+  int ylines = 4;        // lines (kx columns) per y tile: 4, or 8 (whole 128-byte rows)
+  int ylines1 = 4;
+  bool xyblk = false;    // rk_step's (kx, y) intermediates in the blocked layout (y back
+                         // transforms write 4-column blocks contiguously; the x pass reads them)
   int slab = 0;          // > 0: the y / x passes of rk_step run slab by slab, this
                          // many z planes at a time (0: whole arrays)
   bool zfuse = false;    // FP64 stages writing the other state buffer: one fused z
@@ -276,7 +280,7 @@ static ZArgs zargs(const fcns_ctx* c, bool f32 = false) {
   return a;
 }
 static YArgs yargs(const fcns_ctx* c, bool f32 = false, bool dy = false) {
-  YArgs a;
+  YArgs a{};
   a.ny = c->g.ny;
   a.nkx = c->g.nkx;
   a.nkxp = c->g.nkxp;
@@ -285,10 +289,11 @@ static YArgs yargs(const fcns_ctx* c, bool f32 = false, bool dy = false) {
   a.tw = f32 ? (const void*)c->twy_f : (const void*)c->twy;
   a.grid = dy ? c->ygrid1 : c->ygrid;
   a.noprefetch = dy ? c->ynopf1 : c->ynopf;
+  a.lines = dy ? c->ylines1 : c->ylines;
   return a;
 }
 static XArgs xargs(const fcns_ctx* c, bool f32 = false) {
-  XArgs a;
+  XArgs a{};
   a.nx = c->g.nx;
   a.nkx = c->g.nkx;
   a.nkxp = c->g.nkxp;
@@ -515,6 +520,11 @@ static void nonlinear_from_mixed(fcns_ctx* c, const cpx<T>* mv, int nfields, boo
   const bool f32 = sizeof(T) == sizeof(float);
   cpx<T>* xyb = reinterpret_cast<cpx<T>*>(c->XYB);
   cpx<T>* nlb = reinterpret_cast<cpx<T>*>(c->NLB);
+  // y back transforms into XYB (blocked when the x pass reads that layout)
+  XArgs xa = xargs(c, f32);
+  xa.blk_in = (c->xyblk && x_reads_blocked(xa)) ? 1 : 0;
+  YArgs yb1 = yargs(c, f32, true), yb0 = yargs(c, f32);
+  yb1.blk = yb0.blk = xa.blk_in ? 2 : 0;
   if (fwd_y && c->slab > 0 && c->slab < g.nz) {
     // slab by slab: the (kx, y, z) intermediates of a slab of planes are
     // written and read back within its four launches, in the first part of
@@ -527,12 +537,11 @@ static void nonlinear_from_mixed(fcns_ctx* c, const cpx<T>* mv, int nfields, boo
     for (int z0 = 0; z0 < g.nz; z0 += c->slab) {
       const int nzs = std::min(c->slab, g.nz - z0);
       const long long off = (long long)z0 * P;
-      launch_y<T>(yargs(c, f32, true), c->big_y, true, 1, mv + off, xyb, xyb + Ms, 2 * M, 3 * Ms,
+      launch_y<T>(yb1, c->big_y, true, 1, mv + off, xyb, xyb + Ms, 2 * M, 3 * Ms, nzs, nfields,
+                  c->stream);
+      launch_y<T>(yb0, c->big_y, true, 0, mv + M + off, xyb + 2 * Ms, nullptr, 2 * M, 3 * Ms,
                   nzs, nfields, c->stream);
-      launch_y<T>(yargs(c, f32), c->big_y, true, 0, mv + M + off, xyb + 2 * Ms, nullptr, 2 * M,
-                  3 * Ms, nzs, nfields, c->stream);
-      launch_x_nl<T>(xargs(c, f32), c->big_x, xyb, nls, Ms, (long long)nzs * g.ny, nfields,
-                     c->stream);
+      launch_x_nl<T>(xa, c->big_x, xyb, nls, Ms, (long long)nzs * g.ny, nfields, c->stream);
       launch_y<T>(yargs(c, f32), c->big_y, false, 0, nls, nlb + off, nullptr, Ms, M, nzs,
                   nfields, c->stream);
     }
@@ -540,16 +549,14 @@ static void nonlinear_from_mixed(fcns_ctx* c, const cpx<T>* mv, int nfields, boo
     return;
   }
   tbeg(c, T_YBACK_DY);
-  launch_y<T>(yargs(c, f32, true), c->big_y, true, 1, mv, xyb, xyb + M, 2 * M, 3 * M, g.nz, nfields,
-              c->stream);
+  launch_y<T>(yb1, c->big_y, true, 1, mv, xyb, xyb + M, 2 * M, 3 * M, g.nz, nfields, c->stream);
   tend(c);
   tbeg(c, T_YBACK_DZ);
-  launch_y<T>(yargs(c, f32), c->big_y, true, 0, mv + M, xyb + 2 * M, nullptr, 2 * M, 3 * M, g.nz,
-              nfields, c->stream);
+  launch_y<T>(yb0, c->big_y, true, 0, mv + M, xyb + 2 * M, nullptr, 2 * M, 3 * M, g.nz, nfields,
+              c->stream);
   tend(c);
   tbeg(c, T_XNL);
-  launch_x_nl<T>(xargs(c, f32), c->big_x, xyb, nlb, M, (long long)g.nz * g.ny, nfields,
-                 c->stream);
+  launch_x_nl<T>(xa, c->big_x, xyb, nlb, M, (long long)g.nz * g.ny, nfields, c->stream);
   tend(c);
   if (fwd_y) {
     tbeg(c, T_YFWD);
@@ -756,6 +763,23 @@ extern "C" fcns_status fcns_rk_step(fcns_ctx* c, double dt, int32_t nsteps) {
   return finish_steps(c, "rk_step");
 }
 
+extern "C" fcns_status fcns_set_y_lines(fcns_ctx* c, int32_t lines) {
+  if (!c) return FCNS_EINVAL;
+  if (lines != 4 && lines != 8) return fail(c, FCNS_EINVAL, "y tiles have 4 or 8 lines");
+  if (lines == 8 && !y_wide_tiles(yargs(c)))
+    return fail(c, FCNS_EINVAL, "8-line y tiles need ny = 512");
+  c->ylines = c->ylines1 = lines;
+  return FCNS_OK;
+}
+
+extern "C" fcns_status fcns_set_blocked(fcns_ctx* c, int32_t on) {
+  if (!c) return FCNS_EINVAL;
+  if (on && !x_reads_blocked(xargs(c)))
+    return fail(c, FCNS_EINVAL, "the blocked layout needs the wave-level x pass (nx = 256, 512)");
+  c->xyblk = on != 0;
+  return FCNS_OK;
+}
+
 extern "C" fcns_status fcns_set_slab(fcns_ctx* c, int32_t planes) {
   if (!c) return FCNS_EINVAL;
   if (planes < 0) return fail(c, FCNS_EINVAL, "slab planes must be >= 0");
@@ -929,11 +953,15 @@ extern "C" fcns_status fcns_autotune(fcns_ctx* c, char* report, int32_t report_l
     };
     float best1 = 1e30f, best0 = 1e30f;
     long long bg1 = Y_GRID, bg0 = Y_GRID;
-    int bpf1 = 0, bpf0 = 0;
+    int bpf1 = 0, bpf0 = 0, bl1 = 4, bl0 = 4;
+    const bool wide = y_wide_tiles(yargs(c));
+    for (int lines : {4, 8})
     for (int nopf : {0, 1})
       for (long long gsz : {256LL, 512LL, 1024LL, 2048LL, 4096LL}) {
+        if (lines == 8 && !wide) continue;
         c->ygrid = c->ygrid1 = gsz;
         c->ynopf = c->ynopf1 = nopf;
+        c->ylines = c->ylines1 = lines;
         const float ms1 = time_ms(c, [&] {
           if (f32)
             pass_dy(reinterpret_cast<cpx<float>*>(c->MV), reinterpret_cast<cpx<float>*>(c->XYB),
@@ -952,19 +980,24 @@ extern "C" fcns_status fcns_autotune(fcns_ctx* c, char* report, int32_t report_l
           best1 = ms1;
           bg1 = gsz;
           bpf1 = nopf;
+          bl1 = lines;
         }
         if (ms0 < best0) {
           best0 = ms0;
           bg0 = gsz;
           bpf0 = nopf;
+          bl0 = lines;
         }
       }
     c->ygrid1 = bg1;
     c->ynopf1 = bpf1;
+    c->ylines1 = bl1;
     c->ygrid = bg0;
     c->ynopf = bpf0;
-    snprintf(line, sizeof(line), "y: grid %lld%s (%.3f ms), with d/dy %lld%s (%.3f ms); ", bg0,
-             bpf0 ? " no-prefetch" : "", best0, bg1, bpf1 ? " no-prefetch" : "", best1);
+    c->ylines = bl0;
+    snprintf(line, sizeof(line),
+             "y: grid %lld%s, %d lines (%.3f ms), with d/dy %lld%s, %d lines (%.3f ms); ", bg0,
+             bpf0 ? " no-prefetch" : "", bl0, best0, bg1, bpf1 ? " no-prefetch" : "", bl1, best1);
     rep += line;
   }
   // x pass with products: kernel variant (inputs: the y pass just run)
@@ -997,25 +1030,32 @@ extern "C" fcns_status fcns_autotune(fcns_ctx* c, char* report, int32_t report_l
   {
     float best = 1e30f;
     int bs = 0;
-    for (int sl : {0, 16, 32, 48, 64, 96, 128}) {
-      if (sl > 0 && (sl >= g.nz || 4 * sl > 3 * g.nz)) continue;
-      c->slab = sl;
-      const float ms = time_ms(c, [&] {
-        if (f32)
-          nonlinear_from_mixed<float>(c, reinterpret_cast<const cpx<float>*>(c->MV), nf, true);
-        else
-          nonlinear_from_mixed<double>(c, c->MV, nf, true);
-      }, reps);
-      if (ms < best) {
-        best = ms;
-        bs = sl;
+    bool bb = false;
+    for (int blk : {0, 1}) {
+      if (blk && !x_reads_blocked(xargs(c))) continue;
+      for (int sl : {0, 16, 32, 48, 64, 96, 128}) {
+        if (sl > 0 && (sl >= g.nz || 4 * sl > 3 * g.nz)) continue;
+        c->slab = sl;
+        c->xyblk = blk != 0;
+        const float ms = time_ms(c, [&] {
+          if (f32)
+            nonlinear_from_mixed<float>(c, reinterpret_cast<const cpx<float>*>(c->MV), nf, true);
+          else
+            nonlinear_from_mixed<double>(c, c->MV, nf, true);
+        }, reps);
+        if (ms < best) {
+          best = ms;
+          bs = sl;
+          bb = blk != 0;
+        }
       }
     }
     c->slab = bs;
-    if (bs > 0)
-      snprintf(line, sizeof(line), "y/x: slabs of %d planes (%.3f ms); ", bs, best);
-    else
-      snprintf(line, sizeof(line), "y/x: whole arrays (%.3f ms); ", best);
+    c->xyblk = bb;
+    snprintf(line, sizeof(line), "y/x: %s, %s (%.3f ms); ",
+             bb ? "blocked intermediates" : "row-major intermediates",
+             bs > 0 ? ("slabs of " + std::to_string(bs) + " planes").c_str() : "whole arrays",
+             best);
     rep += line;
   }
   // z: radix order of a run-time plan, timed on the back-transform of the

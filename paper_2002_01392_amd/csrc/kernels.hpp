@@ -69,7 +69,11 @@ struct YArgs {
   const void* tw;    // ny twiddles
   long long grid;    // persistent workgroups per field (0: Y_GRID)
   int noprefetch;    // 1: load each tile when needed instead of one tile ahead
+  int blk;           // bit 0: src, bit 1: dst in the blocked (kx, ky) layout
+  int lines;         // lines per tile: YL, or 8 where y_wide_tiles (whole 128-byte rows)
 };
+// 8-line tiles (512 threads) exist for the compiled 512-point plan
+bool y_wide_tiles(const YArgs& a);
 
 struct XArgs {
   int nx, nkx, nkxp, ny;
@@ -77,10 +81,12 @@ struct XArgs {
   FFTPlan pl;        // nx-point plan (lines = XR/2, threads = XNT)
   const void* tw;    // nx twiddles
   int variant;       // x pass with products: 0 default, 1 tiled 4 rows x 256, 2 tiled 8 x 512
+  int blk_in;        // 1: x pass with products reads xyb in the blocked (kx, y) layout
+                     // (variant 0 at nx = 512 and 256 only)
 };
 
 int z_max_npr();
-size_t y_lds_bytes(int ny, int tsize, size_t elem);  // LDS of one y-pass workgroup
+size_t y_lds_bytes(int ny, int tsize, size_t elem, int lines = YL);  // LDS of one y workgroup
 size_t z_lds_bytes(const Geom& g);
 
 // Dynamic LDS above 64 KiB needs an explicit per-kernel opt-in.
@@ -168,6 +174,8 @@ void launch_x_c2r(const XArgs& a, bool big, const cpx<double>* xy, double* phys,
 template <typename T>
 void launch_x_nl(const XArgs& a, bool big, const cpx<T>* xyb, cpx<T>* nl, long long fstride,
                  long long nrows, int nfields, hipStream_t st);
+// the x pass with products can read xyb in the blocked layout (a.blk_in)
+bool x_reads_blocked(const XArgs& a);
 
 // diagnostics (mv: slots 2f = q_f, 2f+1 = dq_f/dz, stride ms)
 void launch_diag_planes(const Geom& g, const cpx<double>* mv, long long ms, int nf, double* out,

@@ -22,25 +22,29 @@ namespace fcns {
 // Lines are interleaved without padding: two workgroups of 512-point lines
 // (2 x 4 lines x 512 points x 2 buffers) then fit the 160 KB of LDS per CU,
 // which matters more than the 2-way bank conflicts of the first stage.
-__host__ __device__ inline int y_span(int ny) { return YL * ny; }
+__host__ __device__ inline int y_span(int ny, int lines) { return lines * ny; }
 
-size_t y_lds_bytes(int ny, int tsize, size_t elem) {
-  return ((size_t)tsize + 2 * (size_t)y_span(ny)) * elem;
+size_t y_lds_bytes(int ny, int tsize, size_t elem, int lines) {
+  return ((size_t)tsize + 2 * (size_t)y_span(ny, lines)) * elem;
 }
+
+bool y_wide_tiles(const YArgs& a) { return a.ny == 512 && plan_is(a.pl, {8, 8, 8}); }
 
 // PF: load the next tile into registers while the current one is transformed
 // (more registers, fewer waves per SIMD) or load each tile when it is needed.
-template <typename T, class FP, int OWN, bool PF>
-__global__ __launch_bounds__(YNT) void k_y(YArgs a, const cpx<T>* src, cpx<T>* dst, cpx<T>* dst2,
-                                           long long sfs, long long dfs, long long nlines, int inv,
-                                           int mode) {
+// LT lines per tile, 64 LT threads (64 rows stepped per thread either way).
+template <typename T, class FP, int OWN, bool PF, int LT>
+__global__ __launch_bounds__(64 * LT) void k_y(YArgs a, const cpx<T>* src, cpx<T>* dst,
+                                               cpx<T>* dst2, long long sfs, long long dfs,
+                                               long long nlines, int inv, int mode) {
+  constexpr int YL = LT, YNT = 64 * LT;
   extern __shared__ __align__(16) char smem[];
   const int tid = threadIdx.x;
   const int ny = FP::dynamic ? a.ny : FP::n;
   const int nkx = a.nkx, nkxp = a.nkxp;
   cpx<T>* tw = reinterpret_cast<cpx<T>*>(smem);
   cpx<T>* X0 = tw + a.pl.tsize;
-  cpx<T>* X1 = X0 + y_span(ny);
+  cpx<T>* X1 = X0 + y_span(ny, YL);
   src += blockIdx.y * sfs;
   dst += blockIdx.y * dfs;
   if (mode == 1) dst2 += blockIdx.y * dfs;
@@ -67,37 +71,44 @@ __global__ __launch_bounds__(YNT) void k_y(YArgs a, const cpx<T>* src, cpx<T>* d
     const int j = blockIdx.x / 8, x = blockIdx.x % 8;
     t = (long long)(j / 8) * 64 + x * 8 + j % 8;
   }
-  auto line_base = [&](long long tt, bool& ok) {
+  // element ky of line (plane, kx) at base + ky * stride: row-major
+  // (stride nkxp) or blocked (stride 4: the 4 columns of a tile contiguous)
+  const bool sblk = a.blk & 1, dblk = a.blk & 2;
+  const int sstr = sblk ? 4 : nkxp, dstr = dblk ? 4 : nkxp;
+  auto line_at = [&](long long tt, bool& ok, bool blocked) {
     const long long q = tt * YL + l;
     const long long pl = q / nkxp, kx = q - pl * nkxp;
     ok = q < nlines && kx < nkx;
-    return ok ? pl * ny * nkxp + kx : 0;  // element ky at base + ky * nkxp
+    if (!ok) return 0LL;
+    return pl * ny * nkxp + (blocked ? (kx >> 2) * ny * 4 + (kx & 3) : kx);
   };
+  auto line_base = [&](long long tt, bool& ok) { return line_at(tt, ok, sblk); };
   if constexpr (PF) {
     bool ok;
     const long long base = line_base(t, ok);
 #pragma unroll
     for (int r = 0; r < OWN; ++r) {
       const int ky = ky0 + r * KYS;
-      cur[r] = (ok && ky < ny) ? src[base + (long long)ky * nkxp] : zero<T>();
+      cur[r] = (ok && ky < ny) ? src[base + (long long)ky * sstr] : zero<T>();
     }
   }
   for (; t < ntiles; t += gridDim.x) {
     bool ok;
     const long long base = line_base(t, ok);
+    const long long dbase = line_at(t, ok, dblk);
     if constexpr (PF) {
       bool okn;
       const long long basen = line_base(t + gridDim.x, okn);
 #pragma unroll
       for (int r = 0; r < OWN; ++r) {
         const int ky = ky0 + r * KYS;
-        nxt[r] = (okn && ky < ny) ? src[basen + (long long)ky * nkxp] : zero<T>();
+        nxt[r] = (okn && ky < ny) ? src[basen + (long long)ky * sstr] : zero<T>();
       }
     } else {
 #pragma unroll
       for (int r = 0; r < OWN; ++r) {
         const int ky = ky0 + r * KYS;
-        cur[r] = (ok && ky < ny) ? src[base + (long long)ky * nkxp] : zero<T>();
+        cur[r] = (ok && ky < ny) ? src[base + (long long)ky * sstr] : zero<T>();
       }
     }
     for (int pass = 0; pass < npass; ++pass) {
@@ -132,7 +143,7 @@ __global__ __launch_bounds__(YNT) void k_y(YArgs a, const cpx<T>* src, cpx<T>* d
         if (ok) {
 #pragma unroll
           for (int m = 0; m < 8; ++m)
-            out[base + (long long)(ky0 + 64 * m) * nkxp] = (inv ? conj(v[m]) : v[m]) * sc;
+            out[dbase + (long long)(ky0 + 64 * m) * dstr] = (inv ? conj(v[m]) : v[m]) * sc;
         }
         continue;
       }
@@ -154,7 +165,7 @@ __global__ __launch_bounds__(YNT) void k_y(YArgs a, const cpx<T>* src, cpx<T>* d
           const int ky = ky0 + r * KYS;
           if (ky < ny) {
             const cpx<T> v = R[lds_pos<false>(l, ky, YL, 1)];
-            out[base + (long long)ky * nkxp] = (inv ? conj(v) : v) * sc;
+            out[dbase + (long long)ky * dstr] = (inv ? conj(v) : v) * sc;
           }
         }
       }
@@ -589,6 +600,19 @@ __device__ __forceinline__ void xw_forward(cpx<T> (&z)[8], cpx<T>* __restrict__ 
   wave_sync();
 }
 
+// Input addressing of the wave-level x pass: element kk of (kx, y) row `row`
+// (plane row / ny) at rb + xo, with rb per row and xo per register; row-major
+// rows (stride nkxp) or the blocked layout of the y pass (the 4 kx columns of
+// a block contiguous over y, blocks ny * 4 apart).
+__device__ __forceinline__ long long xw_row_base(long long row, int ny, int nkxp, bool blk) {
+  if (!blk) return row * nkxp;
+  const long long pl = row / ny;
+  return pl * ny * nkxp + (row - pl * ny) * 4;
+}
+__device__ __forceinline__ int xw_col_off(int kk, int ny, bool blk) {
+  return blk ? (kk >> 2) * ny * 4 + (kk & 3) : kk;
+}
+
 // NL_f = -(u dq_f/dx + v dq_f/dy + w dq_f/dz) on rows of N points.
 // The generic schedule: real quantities in the order u, v, w, then per field
 // dq/dx, dq/dy, dq/dz, consecutive pairs sharing one inverse transform (the
@@ -596,7 +620,7 @@ __device__ __forceinline__ void xw_forward(cpx<T> (&z)[8], cpx<T>* __restrict__ 
 // finished fields as soon as both are complete.  Used for three fields, where
 // the one-read schedule below needs more registers than two waves per SIMD
 // allow.
-template <typename T, int NF, int N>
+template <typename T, int NF, int N, bool BLK>
 __global__ __launch_bounds__(64 * XW_WAVES) void k_x_nlw_q(XArgs a, const cpx<T>* __restrict__ xyb,
                                                            cpx<T>* __restrict__ nl, long long fs,
                                                            long long nrows) {
@@ -613,6 +637,15 @@ __global__ __launch_bounds__(64 * XW_WAVES) void k_x_nlw_q(XArgs a, const cpx<T>
   const int nkxp = a.nkxp;
   const T kxs = (T)a.kxs;
   const T sc = T(1) / T(N);
+  // input offsets per register: kk itself (row-major, folded into the
+  // loads) or its place in the blocked layout
+  constexpr bool blk = BLK;
+  int xo[8];
+#pragma unroll
+  for (int m = 0; m < 8; ++m) {
+    const int k = t + S * m;
+    xo[m] = xw_col_off(k <= N / 2 ? k : N - k, a.ny, blk);
+  }
   for (long long rw = (long long)blockIdx.x * XW_WAVES + wv; rw * RPW < nrows;
        rw += (long long)gridDim.x * XW_WAVES) {
     // a row past the end (second row of the last wave) computes on a copy of
@@ -630,12 +663,13 @@ __global__ __launch_bounds__(64 * XW_WAVES) void k_x_nlw_q(XArgs a, const cpx<T>
       // the two quantities of this pair (qb = NQ: none)
       const int qa = 2 * p, qb = 2 * p + 1;
       cpx<T> r[8];
+      const long long rb = xw_row_base(row, a.ny, nkxp, blk);
       auto src = [&](int q, bool& dx) -> const cpx<T>* {
         dx = false;
-        if (q < 3) return xyb + (3 * q) * fs + row * nkxp;
+        if (q < 3) return xyb + (3 * q) * fs + rb;
         const int f = (q - 3) / 3, d = (q - 3) % 3;
         dx = d == 0;
-        return xyb + (3 * f + d) * fs + row * nkxp;
+        return xyb + (3 * f + d) * fs + rb;
       };
       bool dxa, dxb = false;
       const cpx<T>* pa = src(qa, dxa);
@@ -644,8 +678,8 @@ __global__ __launch_bounds__(64 * XW_WAVES) void k_x_nlw_q(XArgs a, const cpx<T>
       for (int m = 0; m < 8; ++m) {
         const int k = t + S * m;
         const int kk = k <= N / 2 ? k : N - k;
-        cpx<T> A = pa[kk];
-        cpx<T> B = pb ? pb[kk] : zero<T>();
+        cpx<T> A = pa[xo[m]];
+        cpx<T> B = pb ? pb[xo[m]] : zero<T>();
         const T kx = (kk == N / 2) ? T(0) : kxs * (T)kk;
         if (dxa) A = mul_i(A) * kx;
         if (dxb) B = mul_i(B) * kx;
@@ -692,7 +726,7 @@ __global__ __launch_bounds__(64 * XW_WAVES) void k_x_nlw_q(XArgs a, const cpx<T>
   }
 }
 
-template <typename T, int NF, int N>
+template <typename T, int NF, int N, bool BLK>
 __global__ __launch_bounds__(64 * XW_WAVES) void k_x_nlw(XArgs a, const cpx<T>* __restrict__ xyb,
                                                          cpx<T>* __restrict__ nl, long long fs,
                                                          long long nrows) {
@@ -717,6 +751,15 @@ __global__ __launch_bounds__(64 * XW_WAVES) void k_x_nlw(XArgs a, const cpx<T>* 
   const int nkxp = a.nkxp;
   const T kxs = (T)a.kxs;
   const T sc = T(1) / T(N);
+  // input offsets per register: kk itself (row-major, folded into the
+  // loads) or its place in the blocked layout
+  constexpr bool blk = BLK;
+  int xo[8];
+#pragma unroll
+  for (int m = 0; m < 8; ++m) {
+    const int k = t + S * m;
+    xo[m] = xw_col_off(k <= N / 2 ? k : N - k, a.ny, blk);
+  }
   for (long long rw = (long long)blockIdx.x * XW_WAVES + wv; rw * RPW < nrows;
        rw += (long long)gridDim.x * XW_WAVES) {
     // a row past the end (second row of the last wave) computes on a copy of
@@ -737,16 +780,17 @@ __global__ __launch_bounds__(64 * XW_WAVES) void k_x_nlw(XArgs a, const cpx<T>* 
       const bool sameB = p < 3;
       const bool hasB = p < 7;
       const int slotB = p < 3 ? slotA : p < 6 ? 3 * (p - 3) + 2 : 10;
-      const cpx<T>* pa = xyb + slotA * fs + row * nkxp;
-      const cpx<T>* pb = xyb + slotB * fs + row * nkxp;
+      const long long rb = xw_row_base(row, a.ny, nkxp, blk);
+      const cpx<T>* pa = xyb + slotA * fs + rb;
+      const cpx<T>* pb = xyb + slotB * fs + rb;
       cpx<T> r[8];
 #pragma unroll
       for (int m = 0; m < 8; ++m) {
         const int k = t + S * m;
         const int kk = k <= N / 2 ? k : N - k;
         const T kx = (kk == N / 2) ? T(0) : kxs * (T)kk;
-        cpx<T> A = pa[kk];
-        cpx<T> B = sameB ? mul_i(A) * kx : (hasB ? pb[kk] : zero<T>());
+        cpx<T> A = pa[xo[m]];
+        cpx<T> B = sameB ? mul_i(A) * kx : (hasB ? pb[xo[m]] : zero<T>());
         if (dxA) A = mul_i(A) * kx;
         if (kk == 0 || kk == N / 2) {
           A.y = T(0);
@@ -820,29 +864,34 @@ template <typename T>
 void launch_y(const YArgs& a, bool big, bool inv, int mode, const cpx<T>* src, cpx<T>* dst,
               cpx<T>* dst2, long long sfs, long long dfs, int nplanes, int nfields,
               hipStream_t st) {
+  const int L = (a.lines == 8 && y_wide_tiles(a)) ? 8 : YL;
   const long long nlines = (long long)nplanes * a.nkxp;
-  const long long ntiles = (nlines + YL - 1) / YL;
+  const long long ntiles = (nlines + L - 1) / L;
   const long long yg = a.grid > 0 ? a.grid : Y_GRID;
   // fewer tiles than the persistent grid: one workgroup per tile, rounded up
   // to whole chunks of 64 so that the XCD-aware order still applies
   long long gx = ntiles < yg ? ntiles : yg;
   if (gx < yg && gx % 64) gx = std::min(yg, (gx + 63) / 64 * 64);
   dim3 grid((unsigned)gx, nfields);
-  const size_t sh = y_lds_bytes(a.ny, a.pl.tsize, sizeof(cpx<T>));
+  const size_t sh = y_lds_bytes(a.ny, a.pl.tsize, sizeof(cpx<T>), L);
   const int need = (a.ny + YNT / YL - 1) / (YNT / YL);
   const int iv = inv ? 1 : 0;
-#define FCNS_Y(FPV, OWNV)                                                                    \
+#define FCNS_YL(FPV, OWNV, LV)                                                                \
   do {                                                                                      \
     if (a.noprefetch)                                                                       \
-      FCNS_LAUNCH((k_y<T, FPV, OWNV, false>), grid, dim3(YNT), sh, st, a, src, dst, dst2, sfs, \
-                  dfs, nlines, iv, mode);                                                   \
+      FCNS_LAUNCH((k_y<T, FPV, OWNV, false, LV>), grid, dim3(64 * LV), sh, st, a, src, dst,   \
+                  dst2, sfs, dfs, nlines, iv, mode);                                        \
     else                                                                                    \
-      FCNS_LAUNCH((k_y<T, FPV, OWNV, true>), grid, dim3(YNT), sh, st, a, src, dst, dst2, sfs,  \
-                  dfs, nlines, iv, mode);                                                   \
+      FCNS_LAUNCH((k_y<T, FPV, OWNV, true, LV>), grid, dim3(64 * LV), sh, st, a, src, dst,    \
+                  dst2, sfs, dfs, nlines, iv, mode);                                        \
   } while (0)
-  if (a.ny == 512 && plan_is(a.pl, {8, 8, 8})) {
+#define FCNS_Y(FPV, OWNV) FCNS_YL(FPV, OWNV, YL)
+  if (y_wide_tiles(a)) {
     using P512 = SPlan<8, 8, 8>;
-    FCNS_Y(P512, 8);
+    if (L == 8)
+      FCNS_YL(P512, 8, 8);
+    else
+      FCNS_Y(P512, 8);
   } else if (a.ny == 256 && plan_is(a.pl, {8, 8, 4})) {
     using P256 = SPlan<8, 8, 4>;
     FCNS_Y(P256, 4);
@@ -852,6 +901,7 @@ void launch_y(const YArgs& a, bool big, bool inv, int mode, const cpx<T>* src, c
     if (need <= 4) FCNS_Y(DynPlan<false>, 4); else if (need <= 8) FCNS_Y(DynPlan<false>, 8); else FCNS_Y(DynPlan<false>, 16);
   }
 #undef FCNS_Y
+#undef FCNS_YL
 }
 template void launch_y<double>(const YArgs&, bool, bool, int, const cpx<double>*, cpx<double>*,
                                cpx<double>*, long long, long long, int, int, hipStream_t);
@@ -887,6 +937,8 @@ static void launch_x_nl_v(const XArgs& a, const cpx<T>* xyb, cpx<T>* nl, long lo
               nfields);
 }
 
+bool x_reads_blocked(const XArgs& a) { return (a.nx == 512 || a.nx == 256) && a.variant == 0; }
+
 // nx = 512 and 256: wave-level rows (variant 0) or the tiled kernels; other
 // nx: 4 rows x 256 threads (variant 0, 1) or 8 rows x 512 threads (variant 2),
 // with compile-time plans for 512 and 256
@@ -905,14 +957,24 @@ void launch_x_nl(const XArgs& a, bool big, const cpx<T>* xyb, cpx<T>* nl, long l
     const long long rpw = 64 / (a.nx / 8);
     const long long need = (nrows + rpw * XW_WAVES - 1) / (rpw * XW_WAVES);
     dim3 grid((unsigned)(need < 4096 ? need : 4096));
+#define FCNS_XW(K, NFV, NV)                                                                  \
+  do {                                                                                      \
+    if (a.blk_in)                                                                           \
+      FCNS_LAUNCH((K<T, NFV, NV, true>), grid, dim3(64 * XW_WAVES), 0, st, a, xyb, nl, fs,   \
+                  nrows);                                                                   \
+    else                                                                                    \
+      FCNS_LAUNCH((K<T, NFV, NV, false>), grid, dim3(64 * XW_WAVES), 0, st, a, xyb, nl, fs,  \
+                  nrows);                                                                   \
+  } while (0)
     if (a.nx == 512 && nfields == 4)
-      FCNS_LAUNCH((k_x_nlw<T, 4, 512>), grid, dim3(64 * XW_WAVES), 0, st, a, xyb, nl, fs, nrows);
+      FCNS_XW(k_x_nlw, 4, 512);
     else if (a.nx == 512)
-      FCNS_LAUNCH((k_x_nlw_q<T, 3, 512>), grid, dim3(64 * XW_WAVES), 0, st, a, xyb, nl, fs, nrows);
+      FCNS_XW(k_x_nlw_q, 3, 512);
     else if (nfields == 4)
-      FCNS_LAUNCH((k_x_nlw<T, 4, 256>), grid, dim3(64 * XW_WAVES), 0, st, a, xyb, nl, fs, nrows);
+      FCNS_XW(k_x_nlw, 4, 256);
     else
-      FCNS_LAUNCH((k_x_nlw_q<T, 3, 256>), grid, dim3(64 * XW_WAVES), 0, st, a, xyb, nl, fs, nrows);
+      FCNS_XW(k_x_nlw_q, 3, 256);
+#undef FCNS_XW
   } else if (a.nx == 512 && plan_is(a.pl, {8, 8, 8}))
     launch_x_nl_v<T, SPlan<8, 8, 8>, 4, 256, 2>(a, xyb, nl, fs, nrows, nfields, st);
   else if (a.nx == 256 && plan_is(a.pl, {8, 8, 4}))

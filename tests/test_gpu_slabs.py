@@ -1,7 +1,9 @@
-"""The y and x passes slab by slab in z (fcns_set_slab): every line and row
-is transformed by the same code as over whole arrays, so a step is bitwise
-the same for any slab size (ragged last slabs included), and the stepped
-state still matches the FP64 oracle at the 1e-11 bar."""
+"""Launch choices of the y and x passes that move data differently but
+compute the same: slab by slab in z (fcns_set_slab), the blocked layout of
+the (kx, y) intermediates (fcns_set_blocked) and 8-line y tiles
+(fcns_set_y_lines).  Every line and row is transformed by the same code, so
+a step is bitwise the same under any of them (ragged last slabs included),
+and the stepped state still matches the FP64 oracle at the 1e-11 bar."""
 import numpy as np
 import pytest
 
@@ -29,12 +31,15 @@ def rel_l2(a, b):
     return float(np.linalg.norm(a - b) / (nb if nb > 0 else 1.0))
 
 
-def _run(fcns, w, v0, th0, slab, steps, precision="fp64", fused=False):
+def _run(fcns, w, v0, th0, slab, steps, precision="fp64", fused=False, blocked=False,
+         lines=4):
     s = fcns.Solver.from_workload(w, precision=precision, keep_pressure=True)
     s.set_state(torch.from_numpy(v0), torch.from_numpy(th0) if th0 is not None else None)
     if fused:
         s.set_z_fused(True)
     s.set_slab(slab)
+    s.set_blocked(blocked)
+    s.set_y_lines(lines)
     s.rk_step(w.dt, steps)
     v, th, p = s.get_state(pressure=True)
     s.synchronize()
@@ -96,3 +101,55 @@ def test_slab_sizes_outside_the_scratch_are_refused(fcns):
         assert e.value.code == fcns.FCNS_EINVAL
     s.set_slab(24)
     s.set_slab(0)
+
+
+LAYOUT_CASES = {
+    # 4 fields, nx = 256 (two rows per wavefront), ny = 512 (8-line tiles)
+    "rb": lambda: W.rayleigh_benard(256, 512, 17, 1e5, C=31, dt=1e-3, steps=2, seed=815,
+                                    perturbation="curl_eigen", noise_rms=1e-2),
+    # 3 fields, nx = 512 (one row per wavefront), N' = 58 = 2 * 29
+    "channel": lambda: W.channel(512, 16, 33, 2000.0, C=25, dt=5e-4, steps=2, seed=816,
+                                 noise_rms=0.05),
+}
+
+
+@pytest.mark.parametrize("name", sorted(LAYOUT_CASES))
+def test_blocked_intermediates_and_wide_y_tiles_are_bitwise_the_plain_step(fcns, name):
+    w = LAYOUT_CASES[name]()
+    v0, th0 = w.initial_state()
+    ref = _run(fcns, w, v0, th0, 0, w.steps)
+    variants = [dict(blocked=True), dict(blocked=True, slab=8)]
+    if w.ny == 512:
+        variants += [dict(lines=8), dict(blocked=True, lines=8, slab=4)]
+    for kw in variants:
+        got = _run(fcns, w, v0, th0, kw.pop("slab", 0), w.steps, **kw)
+        for g, r in zip(got, ref):
+            if r is not None:
+                assert torch.equal(g, r), (name, kw)
+
+
+def test_blocked_intermediates_match_the_oracle(fcns):
+    # nz = 33 with C = 31 (N' = 64), the wall-normal grid of the other
+    # Rayleigh-Benard parity cases
+    w = W.rayleigh_benard(256, 512, 33, 1e5, C=31, dt=1e-3, steps=2, seed=818,
+                          perturbation="curl_eigen", noise_rms=1e-2)
+    v0, th0 = w.initial_state()
+    v, th, p = _run(fcns, w, v0, th0, 4, w.steps, fused=True, blocked=True, lines=8)
+    o = Oracle(Problem(**w.problem_kwargs()))
+    o.set_state(v0, th0)
+    o.rk_step(w.dt, w.steps)
+    rv, rth, rp = o.get_state()
+    assert rel_l2(v, rv) < 1e-11
+    assert rel_l2(th, rth) < 1e-11
+    assert rel_l2(p, rp) < 1e-10
+
+
+def test_layout_choices_the_kernels_lack_are_refused(fcns):
+    w = W.channel(32, 32, 33, 1000.0, C=25, dt=1e-3, steps=1, seed=817)
+    s = fcns.Solver.from_workload(w)
+    for call, arg in ((s.set_blocked, True), (s.set_y_lines, 8), (s.set_y_lines, 6)):
+        with pytest.raises(fcns.FcnsError) as e:
+            call(arg)
+        assert e.value.code == fcns.FCNS_EINVAL
+    s.set_blocked(False)
+    s.set_y_lines(4)
