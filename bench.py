@@ -372,6 +372,9 @@ def main():
                     help="skip the mixed-precision run on the channel grid")
     ap.add_argument("--no-serving", action="store_true", help="skip the serving run")
     ap.add_argument("--no-autotune", action="store_true", help="keep the default launch choices")
+    ap.add_argument("--choices", default="",
+                    help="apply these launch choices (the 'choices' text of an earlier run) "
+                         "instead of autotuning")
     ap.add_argument("--no-graph", action="store_true", help="skip the HIP graph comparison")
     ap.add_argument("--no-batch", action="store_true",
                     help="skip the one-launch batch of small mixed shapes")
@@ -397,9 +400,15 @@ def main():
     del v0, th0
     torch.cuda.synchronize()
     tuned = None
-    if not args.no_autotune:
+    if args.choices:
+        # launch choices saved from an earlier run (no autotuning trials, so a
+        # profiler sees only the steps)
+        s.set_choices(args.choices)
+        tuned = "given"
+    elif not args.no_autotune:
         print("[bench] autotune", file=sys.stderr, flush=True)
         tuned = s.autotune()
+    choices = s.choices()
     print(f"[bench] warmup {args.warmup} steps", file=sys.stderr, flush=True)
     s.rk_step(w.dt, args.warmup)
     torch.cuda.synchronize()
@@ -529,7 +538,7 @@ def main():
                           "the timed region only the roofline kernel" % SURVEY_STEPS)
         if survey else "the timed region",
         "precision": mixed,
-        "serving": serving, "graph": graph, "batch": batch, "autotune": tuned,
+        "serving": serving, "graph": graph, "batch": batch, "autotune": tuned, "choices": choices,
         "cpu_baseline": cpu, "kernel_source_hash": src_hash,
     }
     print(json.dumps(out))

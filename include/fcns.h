@@ -246,6 +246,17 @@ fcns_status fcns_set_blocked(fcns_ctx* ctx, int32_t on);
  * fcns_autotune picks per launch kind.  Results are bitwise the same. */
 fcns_status fcns_set_y_lines(fcns_ctx* ctx, int32_t lines);
 
+/* The context's launch choices (y grid, prefetch and tile lines per launch
+ * kind, x kernel variant, slab size, intermediate layout, fused z pass, z
+ * radix order) as text, "key=value" pairs separated by ';', so that a tuned
+ * configuration can be kept and applied again without autotuning.
+ * fcns_get_choices writes it NUL-terminated into out (EINVAL if len is too
+ * small); fcns_set_choices applies such a text (keys may be omitted; EINVAL,
+ * changing nothing, for an unknown key or a choice the context cannot take).
+ * Choices change launch shapes only: results are the same to rounding. */
+fcns_status fcns_get_choices(const fcns_ctx* ctx, char* out, int32_t len);
+fcns_status fcns_set_choices(fcns_ctx* ctx, const char* text);
+
 /* Same as fcns_rk_step, by replaying a HIP graph of one step.  The graph is
  * captured on the first call and again whenever dt changes (capture
  * synchronizes the stream and allocates the graph; replays allocate

@@ -56,6 +56,8 @@ SIGNATURES = {
     "fcns_set_slab": (ctypes.c_int, [_P, _I32]),
     "fcns_set_blocked": (ctypes.c_int, [_P, _I32]),
     "fcns_set_y_lines": (ctypes.c_int, [_P, _I32]),
+    "fcns_get_choices": (ctypes.c_int, [_P, ctypes.c_char_p, _I32]),
+    "fcns_set_choices": (ctypes.c_int, [_P, ctypes.c_char_p]),
     "fcns_check_finite": (ctypes.c_int, [_P]),
     "fcns_nonfinite_flag": (ctypes.c_int32, [_P]),
     "fcns_autotune": (ctypes.c_int, [_P, ctypes.c_char_p, _I32]),
@@ -415,6 +417,16 @@ class Solver:
     def set_y_lines(self, lines):
         """Lines per y-transform tile: 4, or 8 at ny = 512."""
         self._check(self.lib.fcns_set_y_lines(self.ctx, int(lines)))
+
+    def choices(self):
+        """The launch choices as text (see set_choices)."""
+        buf = ctypes.create_string_buffer(512)
+        self._check(self.lib.fcns_get_choices(self.ctx, buf, len(buf)))
+        return buf.value.decode()
+
+    def set_choices(self, text):
+        """Apply launch choices saved by choices() (no autotuning)."""
+        self._check(self.lib.fcns_set_choices(self.ctx, text.encode()))
 
     def autotune(self):
         """Pick the fastest launch choices for this shape; returns the summary."""

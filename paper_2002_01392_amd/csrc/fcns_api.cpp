@@ -1126,6 +1126,101 @@ extern "C" fcns_status fcns_autotune(fcns_ctx* c, char* report, int32_t report_l
   return st;
 }
 
+// The launch choices as "key=value" pairs separated by ';' (what
+// fcns_autotune chose, or the defaults), and the inverse.
+static std::string choices_string(const fcns_ctx* c) {
+  std::string z;
+  for (int s = 0; s < c->plz.nst; ++s) z += (s ? "." : "") + std::to_string(c->plz.r[s]);
+  char buf[512];
+  snprintf(buf, sizeof(buf),
+           "ygrid=%lld;ynopf=%d;ylines=%d;ygrid1=%lld;ynopf1=%d;ylines1=%d;xvar=%d;slab=%d;"
+           "blocked=%d;zfused=%d;zplan=%s",
+           c->ygrid, c->ynopf, c->ylines, c->ygrid1, c->ynopf1, c->ylines1, c->xvar, c->slab,
+           c->xyblk ? 1 : 0, c->zfuse ? 1 : 0, z.c_str());
+  return buf;
+}
+
+extern "C" fcns_status fcns_get_choices(const fcns_ctx* c, char* out, int32_t len) {
+  if (!c || !out || len <= 0) return FCNS_EINVAL;
+  const std::string s = choices_string(c);
+  if ((int32_t)s.size() >= len) return FCNS_EINVAL;
+  memcpy(out, s.c_str(), s.size() + 1);
+  return FCNS_OK;
+}
+
+extern "C" fcns_status fcns_set_choices(fcns_ctx* c, const char* text) {
+  if (!c || !text) return FCNS_EINVAL;
+  // parse and check everything before changing anything
+  struct {
+    long long ygrid, ygrid1;
+    int ynopf, ylines, ynopf1, ylines1, xvar, slab;
+    bool xyblk, zfuse;
+  } t{c->ygrid, c->ygrid1, c->ynopf, c->ylines, c->ynopf1, c->ylines1, c->xvar, c->slab,
+      c->xyblk, c->zfuse};
+  std::vector<int> zplan;
+  std::string all(text);
+  size_t pos = 0;
+  while (pos < all.size()) {
+    size_t end = all.find(';', pos);
+    if (end == std::string::npos) end = all.size();
+    const std::string item = all.substr(pos, end - pos);
+    pos = end + 1;
+    if (item.empty()) continue;
+    const size_t eq = item.find('=');
+    if (eq == std::string::npos) return fail(c, FCNS_EINVAL, "choice without '=': " + item);
+    const std::string k = item.substr(0, eq), v = item.substr(eq + 1);
+    char* e = nullptr;
+    if (k == "zplan") {
+      size_t q = 0;
+      while (q < v.size()) {
+        size_t d = v.find('.', q);
+        if (d == std::string::npos) d = v.size();
+        zplan.push_back(atoi(v.substr(q, d - q).c_str()));
+        q = d + 1;
+      }
+      continue;
+    }
+    const long long x = strtoll(v.c_str(), &e, 10);
+    if (v.empty() || *e) return fail(c, FCNS_EINVAL, "bad value: " + item);
+    if (k == "ygrid") t.ygrid = x;
+    else if (k == "ynopf") t.ynopf = (int)x;
+    else if (k == "ylines") t.ylines = (int)x;
+    else if (k == "ygrid1") t.ygrid1 = x;
+    else if (k == "ynopf1") t.ynopf1 = (int)x;
+    else if (k == "ylines1") t.ylines1 = (int)x;
+    else if (k == "xvar") t.xvar = (int)x;
+    else if (k == "slab") t.slab = (int)x;
+    else if (k == "blocked") t.xyblk = x != 0;
+    else if (k == "zfused") t.zfuse = x != 0;
+    else return fail(c, FCNS_EINVAL, "unknown choice: " + k);
+  }
+  const YArgs ya = yargs(c);
+  XArgs xa = xargs(c);
+  xa.variant = t.xvar;
+  if (t.ygrid < 0 || t.ygrid1 < 0 || t.ygrid > (1 << 20) || t.ygrid1 > (1 << 20) ||
+      (t.ylines != 4 && t.ylines != 8) || (t.ylines1 != 4 && t.ylines1 != 8) ||
+      ((t.ylines == 8 || t.ylines1 == 8) && !y_wide_tiles(ya)) || t.xvar < 0 || t.xvar > 2 ||
+      (t.xvar == 2 && c->g.nx > 512) || t.slab < 0 ||
+      (t.slab > 0 && 4LL * t.slab > 3LL * c->g.nz) || (t.xyblk && !x_reads_blocked(xa)) ||
+      (t.zfuse && !can_fuse(c)))
+    return fail(c, FCNS_EINVAL, "a choice this context cannot take");
+  if (!zplan.empty()) {
+    fcns_status st = set_z_plan(c, zplan);
+    if (st) return st;
+  }
+  c->ygrid = t.ygrid;
+  c->ynopf = t.ynopf != 0;
+  c->ylines = t.ylines;
+  c->ygrid1 = t.ygrid1;
+  c->ynopf1 = t.ynopf1 != 0;
+  c->ylines1 = t.ylines1;
+  c->xvar = t.xvar;
+  c->slab = t.slab;
+  c->xyblk = t.xyblk;
+  c->zfuse = t.zfuse;
+  return FCNS_OK;
+}
+
 // Several problems stepped together: step k of every context is enqueued
 // before step k + 1 of any, each on its own context stream, so that the
 // problems overlap on the device; each context's work is exactly its

@@ -153,3 +153,29 @@ def test_layout_choices_the_kernels_lack_are_refused(fcns):
         assert e.value.code == fcns.FCNS_EINVAL
     s.set_blocked(False)
     s.set_y_lines(4)
+
+
+def test_tuned_choices_round_trip(fcns):
+    w = LAYOUT_CASES["rb"]()
+    v0, th0 = w.initial_state()
+    a = fcns.Solver.from_workload(w)
+    a.set_state(torch.from_numpy(v0), torch.from_numpy(th0))
+    a.autotune()
+    text = a.choices()
+    assert "zplan=" in text and "slab=" in text
+    a.set_state(torch.from_numpy(v0), torch.from_numpy(th0))
+    a.rk_step(w.dt, w.steps)
+    b = fcns.Solver.from_workload(w)
+    b.set_choices(text)
+    assert b.choices() == text
+    b.set_state(torch.from_numpy(v0), torch.from_numpy(th0))
+    b.rk_step(w.dt, w.steps)
+    va, tha, _ = a.get_state()
+    vb, thb, _ = b.get_state()
+    torch.cuda.synchronize()
+    assert torch.equal(va, vb) and torch.equal(tha, thb)
+    for bad in ("nosuch=1", "ylines=6", "slab=-1", "zfused", "zplan=7.7", "xvar=x"):
+        with pytest.raises(fcns.FcnsError) as e:
+            b.set_choices(bad)
+        assert e.value.code == fcns.FCNS_EINVAL
+    assert b.choices() == text
