@@ -229,12 +229,28 @@ __global__ __launch_bounds__(ZNT) void k_z_fwd(ZArgs a, const cpx<double>* __res
   }
 }
 
+// Streaming accesses (data loaded or stored once by the workgroup): the
+// nontemporal hint keeps those lines from displacing the ones it reads back.
+template <typename T>
+__device__ __forceinline__ cpx<T> ld_stream(const cpx<T>* p) {
+  using V = T __attribute__((ext_vector_type(2)));
+  const V v = __builtin_nontemporal_load(reinterpret_cast<const V*>(p));
+  return mk(v.x, v.y);
+}
+template <typename T>
+__device__ __forceinline__ void st_stream(cpx<T>* p, cpx<T> a) {
+  using V = T __attribute__((ext_vector_type(2)));
+  const V v = {a.x, a.y};
+  __builtin_nontemporal_store(v, reinterpret_cast<V*>(p));
+}
+
 // ---------------------------------------------------------------- z back
 // B_z = R o IFFT of one field whose continued rows this thread holds
 // (keep[r] = row lt + r ZLS of pencil p0 + tid % ZPB, zero past N' and for
 // padding pencils) into dst, and B_z(i k~z .) into dzdst when non-null.
 // Every thread of the workgroup calls it; it ends with a barrier.
-template <typename T, class FP, int OWN>
+// NTS: streaming stores.
+template <typename T, class FP, int OWN, bool NTS = false>
 __device__ __forceinline__ void z_back_rows(const ZLds<T>& L, const ZArgs& a,
                                             const cpx<double> (&keep)[OWN], cpx<T>* dst,
                                             cpx<T>* dzdst, long long p0, int tid) {
@@ -268,7 +284,13 @@ __device__ __forceinline__ void z_back_rows(const ZLds<T>& L, const ZArgs& a,
         for (int r = 0; r < OWN; ++r) ov[r] = R[min(lt + r * ZLS, npr - 1) * ZPB + pb];
 #pragma unroll
         for (int r = 0; r < OWN; ++r)
-          if (lt + r * ZLS < g.nz) out[(long long)(lt + r * ZLS) * g.npen + p] = conj(ov[r]) * (T)inv;
+          if (lt + r * ZLS < g.nz) {
+            cpx<T>* o = out + (long long)(lt + r * ZLS) * g.npen + p;
+            if constexpr (NTS)
+              st_stream(o, conj(ov[r]) * (T)inv);
+            else
+              *o = conj(ov[r]) * (T)inv;
+          }
       } else {
         for (int z = lt; z < g.nz; z += ZLS)
           out[(long long)z * g.npen + p] = conj(R[z * ZPB + pb]) * (T)inv;
@@ -375,12 +397,20 @@ __device__ __forceinline__ void z_stageA_field(const ZLds<T>& L, const ZArgs& a,
   // any is waited for: the nonlinear term's rows (rows past nz and invalid
   // pencils read an in-bounds slot that is then discarded), then the
   // continued state and filter factors, in flight during the transform.
+  // (the fused pass streams them: they are read once, V* is read back)
+  constexpr bool NT = SPECBUOY;
+  auto ld = [](const auto* q) {
+    if constexpr (NT)
+      return ld_stream(q);
+    else
+      return *q;
+  };
   cpx<TM> nr[OWN];
   const long long pc = pv ? p : 0;
 #pragma unroll
   for (int r = 0; r < OWN; ++r) {
     const int z = min(lt + r * ZLS, g.nz - 1);
-    nr[r] = nl[(long long)z * g.npen + pc];
+    nr[r] = ld(nl + (long long)z * g.npen + pc);
   }
   // keep these loads ahead of the ones below (loads complete in order, so a
   // later one issued first would hold up the LDS writes of these rows)
@@ -392,8 +422,8 @@ __device__ __forceinline__ void z_stageA_field(const ZLds<T>& L, const ZArgs& a,
   for (int r = 0; r < OWN; ++r) {
     const int l = min(lt + r * ZLS, npr - 1);  // rows past N' are never used
     const long long gi = (long long)l * g.npen + pc;
-    vtr[r] = vt[gi];
-    if constexpr (!WV) wr[r] = w[gi];
+    vtr[r] = ld(vt + gi);
+    if constexpr (!WV) wr[r] = ld(w + gi);
     sgr[r] = a.sigz[l];
   }
   // (rows z >= nz store zero to a continuation row, rewritten by the
@@ -420,7 +450,7 @@ __device__ __forceinline__ void z_stageA_field(const ZLds<T>& L, const ZArgs& a,
     if (wbuoy) {
 #pragma unroll
       for (int r = 0; r < OWN; ++r)
-        bsr[r] = wbuoy[(long long)min(lt + r * ZLS, npr - 1) * g.npen + pc];
+        bsr[r] = ld(wbuoy + (long long)min(lt + r * ZLS, npr - 1) * g.npen + pc);
     }
   }
 #pragma unroll
@@ -805,7 +835,8 @@ __device__ __forceinline__ void z_pass_group(const ZLds<double>& L, const ZArgs&
     z_stageA_field<double, double, FP, OWN, WV, true, true>(L, a, sa, 3, p0, tid, true, keep);
     __syncthreads();
     check_rows<OWN>(a, keep);
-    z_back_rows<double, FP, OWN>(L, a, keep, zb.mv + 6 * zb.ms, zb.mv + 7 * zb.ms, p0, tid);
+    z_back_rows<double, FP, OWN, true>(L, a, keep, zb.mv + 6 * zb.ms, zb.mv + 7 * zb.ms, p0,
+                                       tid);
   }
   // then w (its buoyancy reads theta's W again, soon after theta did), u,
   // and v, whose V* goes to the projection in registers without a store
@@ -823,13 +854,14 @@ __device__ __forceinline__ void z_pass_group(const ZLds<double>& L, const ZArgs&
   // v's new state is in registers; each thread reads back the rows of u and
   // w it has just written (cache hits)
   check_rows<OWN>(a, vstar1);
-  z_back_rows<double, FP, OWN>(L, a, vstar1, zb.mv + 2 * zb.ms, zb.mv + 3 * zb.ms, p0, tid);
+  z_back_rows<double, FP, OWN, true>(L, a, vstar1, zb.mv + 2 * zb.ms, zb.mv + 3 * zb.ms, p0,
+                                     tid);
   for (int f = 0; f < 3; f += 2) {
     cpx<double> keep[OWN];
     load_rows<FP, OWN>(a, sa.out[f], p0, tid, keep);
     check_rows<OWN>(a, keep);
-    z_back_rows<double, FP, OWN>(L, a, keep, zb.mv + (2 * f) * zb.ms,
-                                 zb.mv + (2 * f + 1) * zb.ms, p0, tid);
+    z_back_rows<double, FP, OWN, true>(L, a, keep, zb.mv + (2 * f) * zb.ms,
+                                       zb.mv + (2 * f + 1) * zb.ms, p0, tid);
   }
 }
 
