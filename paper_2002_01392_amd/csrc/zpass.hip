@@ -300,8 +300,9 @@ __device__ __forceinline__ void z_back_rows(const ZLds<T>& L, const ZArgs& a,
   }
 }
 
-// This thread's rows of one continued field (layout of z_back_rows).
-template <class FP, int OWN>
+// This thread's rows of one continued field (layout of z_back_rows); NT:
+// the last read of them (streaming loads).
+template <class FP, int OWN, bool NT = false>
 __device__ __forceinline__ void load_rows(const ZArgs& a, const cpx<double>* src, long long p0,
                                           int tid, cpx<double> (&keep)[OWN]) {
   const Geom& g = a.g;
@@ -312,7 +313,10 @@ __device__ __forceinline__ void load_rows(const ZArgs& a, const cpx<double>* src
 #pragma unroll
   for (int r = 0; r < OWN; ++r) {
     const int l = lt + r * ZLS;
-    keep[r] = (pv && l < npr) ? src[(long long)l * g.npen + p] : zero<double>();
+    if constexpr (NT)
+      keep[r] = (pv && l < npr) ? ld_stream(src + (long long)l * g.npen + p) : zero<double>();
+    else
+      keep[r] = (pv && l < npr) ? src[(long long)l * g.npen + p] : zero<double>();
   }
 }
 
@@ -526,7 +530,14 @@ __device__ __forceinline__ void z_stageA_field(const ZLds<T>& L, const ZArgs& a,
     if (STORE && pv) {
 #pragma unroll
       for (int r = 0; r < OWN; ++r)
-        if (lt + r * ZLS < npr) out[(long long)(lt + r * ZLS) * g.npen + p] = keep[r];
+        if (lt + r * ZLS < npr) {
+          // (not read again by the workgroup)
+          cpx<double>* o = out + (long long)(lt + r * ZLS) * g.npen + p;
+          if constexpr (NT)
+            st_stream(o, keep[r]);
+          else
+            *o = keep[r];
+        }
     }
     return;
   }
@@ -767,9 +778,10 @@ __device__ __forceinline__ void z_stageB_body(const ZLds<T>& L, const ZArgs& a,
       hz = D * ep;
     }
     const cpx<double> n0 = V0 - sv * kxo - hx, n1 = V1 - sv * kyo - hy, n2 = V2 - sv * kz - hz;
-    s.vout[0][gi] = n0;
-    s.vout[1][gi] = n1;
-    s.vout[2][gi] = n2;
+    // (field KF's rows go back in kv and are not read again: streaming store)
+    if constexpr (KF == 0) st_stream(&s.vout[0][gi], n0); else s.vout[0][gi] = n0;
+    if constexpr (KF == 1) st_stream(&s.vout[1][gi], n1); else s.vout[1][gi] = n1;
+    if constexpr (KF == 2) st_stream(&s.vout[2][gi], n2); else s.vout[2][gi] = n2;
     if constexpr (KF >= 0) kv[r] = (KF == 0) ? n0 : (KF == 1) ? n1 : n2;
     if constexpr (KEEP) {
       vk[0][r] = n0;
@@ -858,7 +870,7 @@ __device__ __forceinline__ void z_pass_group(const ZLds<double>& L, const ZArgs&
                                      tid);
   for (int f = 0; f < 3; f += 2) {
     cpx<double> keep[OWN];
-    load_rows<FP, OWN>(a, sa.out[f], p0, tid, keep);
+    load_rows<FP, OWN, true>(a, sa.out[f], p0, tid, keep);
     check_rows<OWN>(a, keep);
     z_back_rows<double, FP, OWN, true>(L, a, keep, zb.mv + (2 * f) * zb.ms,
                                        zb.mv + (2 * f + 1) * zb.ms, p0, tid);
