@@ -17,6 +17,20 @@ __host__ __device__ __forceinline__ cpx<T> mk(T a, T b) {
   r.y = b;
   return r;
 }
+// Streaming accesses (data a workgroup loads or stores once): the
+// nontemporal hint keeps those lines from displacing the ones it reuses.
+template <typename T>
+__device__ __forceinline__ cpx<T> ld_stream(const cpx<T>* p) {
+  using V = T __attribute__((ext_vector_type(2)));
+  const V v = __builtin_nontemporal_load(reinterpret_cast<const V*>(p));
+  return mk(v.x, v.y);
+}
+template <typename T>
+__device__ __forceinline__ void st_stream(cpx<T>* p, cpx<T> a) {
+  using V = T __attribute__((ext_vector_type(2)));
+  const V v = {a.x, a.y};
+  __builtin_nontemporal_store(v, reinterpret_cast<V*>(p));
+}
 template <typename T>
 __host__ __device__ __forceinline__ cpx<T> operator+(cpx<T> a, cpx<T> b) {
   return mk(a.x + b.x, a.y + b.y);

@@ -229,21 +229,6 @@ __global__ __launch_bounds__(ZNT) void k_z_fwd(ZArgs a, const cpx<double>* __res
   }
 }
 
-// Streaming accesses (data loaded or stored once by the workgroup): the
-// nontemporal hint keeps those lines from displacing the ones it reads back.
-template <typename T>
-__device__ __forceinline__ cpx<T> ld_stream(const cpx<T>* p) {
-  using V = T __attribute__((ext_vector_type(2)));
-  const V v = __builtin_nontemporal_load(reinterpret_cast<const V*>(p));
-  return mk(v.x, v.y);
-}
-template <typename T>
-__device__ __forceinline__ void st_stream(cpx<T>* p, cpx<T> a) {
-  using V = T __attribute__((ext_vector_type(2)));
-  const V v = {a.x, a.y};
-  __builtin_nontemporal_store(v, reinterpret_cast<V*>(p));
-}
-
 // ---------------------------------------------------------------- z back
 // B_z = R o IFFT of one field whose continued rows this thread holds
 // (keep[r] = row lt + r ZLS of pencil p0 + tid % ZPB, zero past N' and for
