@@ -198,15 +198,36 @@ def serving_run(max_active=8, max_bytes=64 << 30, n=64, rate=20.0, steps=20):
     import workloads as W
     from paper_2002_01392_amd import Server, workload_problem
 
+    import torch
+
+    from paper_2002_01392_amd import Solver
+
     stream = W.serving_stream(n=n, rate=rate, steps=steps)
     reqs = []
     for t, w in stream:
         v0, th0 = w.initial_state()
         prob, tab = workload_problem(w)
         reqs.append((t, w, prob, tab, v0, th0))
+    # launch choices tuned once per shape before the clock starts (a serving
+    # system keeps such a table; the contexts it creates take them)
+    tuned = {}
+    for _, w, prob, _tab, v0, th0 in reqs:
+        key = (w.nx, w.ny, w.nz, w.C, w.boussinesq)
+        if key in tuned:
+            continue
+        s = Solver.from_workload(w)
+        s.set_state(torch.from_numpy(v0), torch.from_numpy(th0) if th0 is not None else None)
+        s.autotune()
+        tuned[key] = (prob, s.choices())
+        s.close()
+        del s
+    torch.cuda.empty_cache()
 
-    def run(slots, replay=True):
+    def run(slots, replay=True, tune=True):
         srv = Server(max_active=slots, max_bytes=max_bytes)
+        if tune:
+            for prob, text in tuned.values():
+                srv.set_choices(prob, text)
         t0 = srv.now()
         ids, k = [], 0
         while True:
@@ -240,14 +261,22 @@ def serving_run(max_active=8, max_bytes=64 << 30, n=64, rate=20.0, steps=20):
     # the same requests all submitted at once (offered load above capacity)
     seq_sat = run(1, replay=False)
     bat_sat = run(max_active, replay=False)
+    # and with the default launch choices (no tuning table)
+    seq_def = run(1, replay=False, tune=False)
+    bat_def = run(max_active, replay=False, tune=False)
     return {"requests": n, "rate_per_s": rate, "steps_each": steps,
-            "sides": list(W.SERVING_SIDES), "batched": bat, "sequential": seq,
+            "sides": list(W.SERVING_SIDES), "tuned_shapes": len(tuned),
+            "batched": bat, "sequential": seq,
             "throughput_gain": bat["value"] / seq["value"],
             "p99_request_gain": seq["request_ms_p99"] / bat["request_ms_p99"],
             "saturated": {"batched": bat_sat, "sequential": seq_sat,
                           "throughput_gain": bat_sat["value"] / seq_sat["value"],
                           "p99_request_gain": seq_sat["request_ms_p99"]
-                          / bat_sat["request_ms_p99"]}}
+                          / bat_sat["request_ms_p99"]},
+            "saturated_default_choices": {
+                "batched": bat_def, "sequential": seq_def,
+                "throughput_gain": bat_def["value"] / seq_def["value"],
+                "p99_request_gain": seq_def["request_ms_p99"] / bat_def["request_ms_p99"]}}
 
 
 def batch_leg(steps=20, sides=(32, 64, 96), per_side=3):

@@ -353,6 +353,14 @@ void* fcns_stream(const fcns_ctx* ctx);
 typedef struct fcns_server fcns_server;
 
 fcns_status fcns_server_create(int32_t max_active, int64_t max_bytes, fcns_server** out);
+/* Launch choices for one shape (the text of fcns_get_choices, e.g. from a
+ * context of that shape tuned beforehand with fcns_autotune): every context
+ * the server creates afterwards for a problem of this shape (grid, box, FC
+ * parameters and table, order, precision, filter) takes them.  HOST
+ * pointers; the text is copied.  A context that cannot take them fails the
+ * request that needed it. */
+fcns_status fcns_server_set_choices(fcns_server* srv, const fcns_problem* prob,
+                                    const char* choices);
 /* HOST pointers.  The problem (and its fc_table) is copied.  v0
  * [3][nz][ny][nx] and theta0 [nz][ny][nx] (Boussinesq) are read when the
  * request is admitted, v_out and theta_out (same shapes) are written when it

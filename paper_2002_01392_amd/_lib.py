@@ -92,6 +92,7 @@ SIGNATURES = {
     "fcns_server_step_times": (ctypes.c_int, [_P, _I64, _I32, _P, ctypes.POINTER(_I32)]),
     "fcns_server_release": (ctypes.c_int, [_P, _I64]),
     "fcns_server_cancel": (ctypes.c_int, [_P, _I64]),
+    "fcns_server_set_choices": (ctypes.c_int, [_P, ctypes.POINTER(FcnsProblem), ctypes.c_char_p]),
     "fcns_server_destroy": (ctypes.c_int, [_P]),
     "fcns_server_last_error": (ctypes.c_char_p, [_P]),
 }
@@ -221,6 +222,11 @@ class Server:
     def _check(self, st):
         if st != FCNS_OK:
             raise FcnsError(st, self.lib.fcns_server_last_error(self.srv).decode())
+
+    def set_choices(self, prob, text):
+        """Launch choices for every context of prob's shape created from now on."""
+        self._check(self.lib.fcns_server_set_choices(self.srv, ctypes.byref(prob),
+                                                     text.encode()))
 
     def submit(self, prob, v0, theta0, dt, nsteps):
         v0 = np.ascontiguousarray(v0, dtype=np.float64)

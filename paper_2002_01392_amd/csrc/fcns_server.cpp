@@ -100,6 +100,7 @@ struct fcns_server {
   int64_t n_done = 0;
   uint64_t tick = 0;
   std::string err;
+  std::map<std::string, std::string> choices;   // shape key -> tuned launch choices
 
   double now() const { return std::chrono::duration<double>(Clock::now() - t0).count(); }
 };
@@ -131,6 +132,20 @@ extern "C" fcns_status fcns_server_create(int32_t max_active, int64_t max_bytes,
 }
 
 extern "C" double fcns_server_now(const fcns_server* s) { return s ? s->now() : 0.0; }
+
+extern "C" fcns_status fcns_server_set_choices(fcns_server* s, const fcns_problem* prob,
+                                               const char* choices) {
+  if (!s) return FCNS_EINVAL;
+  if (!prob || !prob->fc_table || !choices) return srv_fail(s, FCNS_EINVAL, "NULL argument");
+  int64_t need = 0;
+  if (fcns_footprint(prob, &need) != FCNS_OK) return srv_fail(s, FCNS_EINVAL, "bad problem");
+  const int d = prob->fc_d, C = prob->fc_C;
+  std::vector<double> table(prob->fc_table, prob->fc_table + (size_t)d * d + (size_t)C * d);
+  fcns_problem p = *prob;
+  p.fc_table = nullptr;
+  s->choices[shape_key(p, table)] = choices;
+  return FCNS_OK;
+}
 
 extern "C" fcns_status fcns_server_submit(fcns_server* s, const fcns_problem* prob,
                                           const double* v0, const double* theta0, double dt,
@@ -209,6 +224,14 @@ static PoolCtx* acquire(fcns_server* s, Request& r, const std::string& key, fcns
   }
   // rk_step stays asynchronous; the flag is read as each step completes
   (void)fcns_set_finite_check(pc->ctx, FCNS_CHECK_DEFERRED);
+  // launch choices tuned for this shape beforehand (fcns_server_set_choices)
+  const auto ch = s->choices.find(key);
+  if (ch != s->choices.end() && (st = fcns_set_choices(pc->ctx, ch->second.c_str())) != FCNS_OK) {
+    s->err = std::string("choices: ") + fcns_last_error(pc->ctx);
+    fcns_destroy(pc->ctx);
+    (void)hipStreamDestroy(pc->stream);
+    return nullptr;
+  }
   const size_t sb = (size_t)nphys * npts * sizeof(double);
   if (hipMalloc((void**)&pc->dphys, sb) != hipSuccess ||
       hipHostMalloc((void**)&pc->hphys, sb, hipHostMallocDefault) != hipSuccess) {

@@ -127,3 +127,48 @@ def test_batch_step_matches_single_solves(fcns):
         assert np.array_equal(v.cpu().numpy(), rv), w.name
         if th is not None:
             assert np.array_equal(th.cpu().numpy(), rth), w.name
+
+
+def test_server_applies_tuned_choices_per_shape(fcns):
+    ws = _requests()
+    states = [w.initial_state() for w in ws]
+    # a tuning table for the 64^3 Rayleigh-Benard shape, and choices the
+    # 32^3 channel shape cannot take (8-line y tiles need ny = 512)
+    rb64 = ws[4]
+    t = fcns.Solver.from_workload(rb64)
+    t.set_state(torch.from_numpy(states[4][0]), torch.from_numpy(states[4][1]))
+    t.autotune()
+    text = t.choices()
+    t.close()
+    srv = fcns.Server(max_active=4, max_bytes=8 << 30)
+    # (each problem's table must stay alive while the call reads it)
+    p_rb, tab_rb = fcns.workload_problem(rb64)
+    p_ch, tab_ch = fcns.workload_problem(ws[0])
+    srv.set_choices(p_rb, text)
+    srv.set_choices(p_ch, "ylines=8")
+    ids = []
+    for w, (v0, th0) in zip(ws, states):
+        prob, _tab = fcns.workload_problem(w)
+        ids.append(srv.submit(prob, v0, th0, w.dt, w.steps))
+    deadline = time.monotonic() + 120
+    while srv.poll()[2] < len(ids):
+        assert time.monotonic() < deadline, "server did not finish"
+        time.sleep(1e-4)
+    for i, (w, (v0, th0), rid) in enumerate(zip(ws, states, ids)):
+        if i in (0, 1):   # the shape whose choices its contexts cannot take
+            with pytest.raises(fcns.FcnsError) as e:
+                srv.result(rid)
+            assert e.value.code == fcns.FCNS_EINVAL
+            continue
+        v, th, info = srv.result(rid)
+        s = fcns.Solver.from_workload(w)
+        if i == 4:
+            s.set_choices(text)
+        s.set_state(torch.from_numpy(v0), torch.from_numpy(th0) if th0 is not None else None)
+        s.rk_step(w.dt, w.steps)
+        rv, rth, _ = s.get_state()
+        torch.cuda.synchronize()
+        assert np.array_equal(v, rv.cpu().numpy()), w.name
+        if th is not None:
+            assert np.array_equal(th, rth.cpu().numpy()), w.name
+    srv.close()
