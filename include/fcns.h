@@ -361,6 +361,13 @@ fcns_status fcns_server_create(int32_t max_active, int64_t max_bytes, fcns_serve
  * request that needed it. */
 fcns_status fcns_server_set_choices(fcns_server* srv, const fcns_problem* prob,
                                     const char* choices);
+/* Size-aware admission: at most max_large running requests with at least
+ * large_points grid points (nx ny nz) each; while that many run, a waiting
+ * large request keeps its place in the queue and smaller requests behind it
+ * are admitted (small solves fill the device around large ones instead of
+ * large ones sharing it).  max_large = 0 (the default): arrival order only.
+ * EINVAL for max_large < 0, or max_large > 0 with large_points < 1. */
+fcns_status fcns_server_set_mix(fcns_server* srv, int32_t max_large, int64_t large_points);
 /* HOST pointers.  The problem (and its fc_table) is copied.  v0
  * [3][nz][ny][nx] and theta0 [nz][ny][nx] (Boussinesq) are read when the
  * request is admitted, v_out and theta_out (same shapes) are written when it

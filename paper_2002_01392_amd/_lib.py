@@ -93,6 +93,7 @@ SIGNATURES = {
     "fcns_server_release": (ctypes.c_int, [_P, _I64]),
     "fcns_server_cancel": (ctypes.c_int, [_P, _I64]),
     "fcns_server_set_choices": (ctypes.c_int, [_P, ctypes.POINTER(FcnsProblem), ctypes.c_char_p]),
+    "fcns_server_set_mix": (ctypes.c_int, [_P, _I32, _I64]),
     "fcns_server_destroy": (ctypes.c_int, [_P]),
     "fcns_server_last_error": (ctypes.c_char_p, [_P]),
 }
@@ -222,6 +223,10 @@ class Server:
     def _check(self, st):
         if st != FCNS_OK:
             raise FcnsError(st, self.lib.fcns_server_last_error(self.srv).decode())
+
+    def set_mix(self, max_large, large_points):
+        """At most max_large running requests of >= large_points grid points."""
+        self._check(self.lib.fcns_server_set_mix(self.srv, int(max_large), int(large_points)))
 
     def set_choices(self, prob, text):
         """Launch choices for every context of prob's shape created from now on."""

@@ -101,6 +101,8 @@ struct fcns_server {
   uint64_t tick = 0;
   std::string err;
   std::map<std::string, std::string> choices;   // shape key -> tuned launch choices
+  int max_large = 0;          // > 0: at most this many running requests of
+  int64_t large_points = 0;   // at least large_points grid points
 
   double now() const { return std::chrono::duration<double>(Clock::now() - t0).count(); }
 };
@@ -132,6 +134,16 @@ extern "C" fcns_status fcns_server_create(int32_t max_active, int64_t max_bytes,
 }
 
 extern "C" double fcns_server_now(const fcns_server* s) { return s ? s->now() : 0.0; }
+
+extern "C" fcns_status fcns_server_set_mix(fcns_server* s, int32_t max_large,
+                                           int64_t large_points) {
+  if (!s) return FCNS_EINVAL;
+  if (max_large < 0 || (max_large > 0 && large_points < 1))
+    return srv_fail(s, FCNS_EINVAL, "need max_large >= 0 and large_points >= 1");
+  s->max_large = max_large;
+  s->large_points = large_points;
+  return FCNS_OK;
+}
 
 extern "C" fcns_status fcns_server_set_choices(fcns_server* s, const fcns_problem* prob,
                                                const char* choices) {
@@ -379,9 +391,20 @@ extern "C" fcns_status fcns_server_poll(fcns_server* s, int32_t* n_queued, int32
       ++i;
     }
   }
-  // 2. admission, first fit in arrival order
+  // 2. admission, first fit in arrival order; with a mix limit, a large
+  // request waits (keeping its place) while max_large of them run, and
+  // smaller ones behind it go ahead
+  auto is_large = [&](const Request& q) {
+    return s->max_large > 0 && (int64_t)q.prob.nx * q.prob.ny * q.prob.nz >= s->large_points;
+  };
+  int n_large = 0;
+  for (int64_t id : s->active) n_large += is_large(*s->reqs[id]) ? 1 : 0;
   for (auto it = s->queue.begin(); it != s->queue.end() && (int)s->active.size() < s->max_active;) {
     Request& r = *s->reqs[*it];
+    if (is_large(r) && n_large >= s->max_large) {
+      ++it;
+      continue;
+    }
     fcns_status st;
     PoolCtx* pc = acquire(s, r, shape_key(r.prob, r.table), st);
     if (!pc) {
@@ -411,6 +434,7 @@ extern "C" fcns_status fcns_server_poll(fcns_server* s, int32_t* n_queued, int32
     } else {
       r.state = Q_RUNNING;
       s->active.push_back(r.id);
+      n_large += is_large(r) ? 1 : 0;
     }
     it = s->queue.erase(it);
   }

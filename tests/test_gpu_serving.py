@@ -172,3 +172,34 @@ def test_server_applies_tuned_choices_per_shape(fcns):
         if th is not None:
             assert np.array_equal(th, rth.cpu().numpy()), w.name
     srv.close()
+
+
+def test_server_mix_limit_keeps_large_requests_apart(fcns):
+    ws = _requests() + [W.rayleigh_benard(64, 64, 65, 1e5, C=31, dt=5e-4, steps=4, seed=607)]
+    states = [w.initial_state() for w in ws]
+    srv = fcns.Server(max_active=4, max_bytes=8 << 30)
+    srv.set_mix(1, 64 * 64 * 65)      # the three 64^3 requests are large
+    ids = []
+    for w, (v0, th0) in zip(ws, states):
+        prob, _tab = fcns.workload_problem(w)
+        ids.append(srv.submit(prob, v0, th0, w.dt, w.steps))
+    deadline = time.monotonic() + 120
+    while srv.poll()[2] < len(ids):
+        assert time.monotonic() < deadline, "server did not finish"
+        time.sleep(1e-4)
+    spans = []
+    for w, (v0, th0), rid in zip(ws, states, ids):
+        v, th, info = srv.result(rid)
+        if w.nx == 64:
+            spans.append((info["t_admit"], info["t_done"]))
+        rv, rth = _alone(fcns, w, v0, th0)
+        assert np.array_equal(v, rv), w.name
+        if th is not None:
+            assert np.array_equal(th, rth), w.name
+    spans.sort()
+    assert len(spans) == 3
+    for (a0, a1), (b0, b1) in zip(spans, spans[1:]):
+        assert a1 <= b0, "two large requests ran together"
+    with pytest.raises(fcns.FcnsError):
+        srv.set_mix(-1, 10)
+    srv.close()
