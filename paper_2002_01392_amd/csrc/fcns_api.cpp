@@ -1004,8 +1004,8 @@ extern "C" fcns_status fcns_autotune(fcns_ctx* c, char* report, int32_t report_l
   {
     float best = 1e30f;
     int bv = 0;
-    for (int v : {0, 1, 2}) {
-      if (v == 2 && g.nx > 512) continue;
+    for (int v : {0, 1, 2, 3}) {
+      if ((v == 2 && g.nx > 512) || (v == 3 && g.nx > 256)) continue;
       c->xvar = v;
       const float ms = time_ms(c, [&] {
         if (f32)
@@ -1199,8 +1199,8 @@ extern "C" fcns_status fcns_set_choices(fcns_ctx* c, const char* text) {
   xa.variant = t.xvar;
   if (t.ygrid < 0 || t.ygrid1 < 0 || t.ygrid > (1 << 20) || t.ygrid1 > (1 << 20) ||
       (t.ylines != 4 && t.ylines != 8) || (t.ylines1 != 4 && t.ylines1 != 8) ||
-      ((t.ylines == 8 || t.ylines1 == 8) && !y_wide_tiles(ya)) || t.xvar < 0 || t.xvar > 2 ||
-      (t.xvar == 2 && c->g.nx > 512) || t.slab < 0 ||
+      ((t.ylines == 8 || t.ylines1 == 8) && !y_wide_tiles(ya)) || t.xvar < 0 || t.xvar > 3 ||
+      (t.xvar == 2 && c->g.nx > 512) || (t.xvar == 3 && c->g.nx > 256) || t.slab < 0 ||
       (t.slab > 0 && 4LL * t.slab > 3LL * c->g.nz) || (t.xyblk && !x_reads_blocked(xa)) ||
       (t.zfuse && !can_fuse(c)))
     return fail(c, FCNS_EINVAL, "a choice this context cannot take");

@@ -80,7 +80,8 @@ struct XArgs {
   double kxs;
   FFTPlan pl;        // nx-point plan (lines = XR/2, threads = XNT)
   const void* tw;    // nx twiddles
-  int variant;       // x pass with products: 0 default, 1 tiled 4 rows x 256, 2 tiled 8 x 512
+  int variant;       // x pass with products: 0 default, 1 tiled 4 rows x 256, 2 tiled 8 x 512,
+                     // 3 tiled 8 rows x nx threads (nx <= 256)
   int blk_in;        // 1: x pass with products reads xyb in the blocked (kx, y) layout
                      // (variant 0 at nx = 512 and 256 only)
 };

@@ -941,11 +941,33 @@ bool x_reads_blocked(const XArgs& a) { return (a.nx == 512 || a.nx == 256) && a.
 
 // nx = 512 and 256: wave-level rows (variant 0) or the tiled kernels; other
 // nx: 4 rows x 256 threads (variant 0, 1) or 8 rows x 512 threads (variant 2),
-// with compile-time plans for 512 and 256
+// with compile-time plans for 512 and 256; nx <= 256: 8 rows x nx threads
+// (variant 3)
 template <typename T>
 void launch_x_nl(const XArgs& a, bool big, const cpx<T>* xyb, cpx<T>* nl, long long fs,
                  long long nrows, int nfields, hipStream_t st) {
-  if (a.variant == 2 && a.nx <= 512) {
+  if (a.variant == 3 && a.nx <= 256) {
+    // short rows: 8 rows (4 complex lines) per workgroup and one thread per
+    // column (a radix-8 stage keeps half the threads busy; 4 or 16 rows, or
+    // 4 rows over 256 threads, measured slower)
+    const int nt = (a.nx + 63) / 64 * 64;
+#define FCNS_XS(NTV)                                                                        \
+  do {                                                                                      \
+    if (big)                                                                                \
+      launch_x_nl_v<T, DynPlan<true>, 8, NTV, 1>(a, xyb, nl, fs, nrows, nfields, st);       \
+    else                                                                                    \
+      launch_x_nl_v<T, DynPlan<false>, 8, NTV, 1>(a, xyb, nl, fs, nrows, nfields, st);      \
+  } while (0)
+    if (nt == 64)
+      FCNS_XS(64);
+    else if (nt == 128)
+      FCNS_XS(128);
+    else if (nt == 192)
+      FCNS_XS(192);
+    else
+      FCNS_XS(256);
+#undef FCNS_XS
+  } else if (a.variant == 2 && a.nx <= 512) {
     if (a.nx == 512 && plan_is(a.pl, {8, 8, 8}))
       launch_x_nl_v<T, SPlan<8, 8, 8>, 8, 512, 1>(a, xyb, nl, fs, nrows, nfields, st);
     else if (big)

@@ -179,3 +179,32 @@ def test_tuned_choices_round_trip(fcns):
             b.set_choices(bad)
         assert e.value.code == fcns.FCNS_EINVAL
     assert b.choices() == text
+
+
+@pytest.mark.parametrize("shape", [("rb", 96, 64, 33), ("ch", 192, 16, 33), ("ch", 64, 32, 65)])
+def test_x_pass_variants_are_bitwise_the_same(fcns, shape):
+    kind, nx, ny, nz = shape
+    if kind == "rb":
+        w = W.rayleigh_benard(nx, ny, nz, 1e5, C=31, dt=1e-3, steps=2, seed=819,
+                              perturbation="curl_eigen", noise_rms=1e-2)
+    else:
+        w = W.channel(nx, ny, nz, 2000.0, C=31, dt=5e-4, steps=2, seed=820, noise_rms=0.05)
+    v0, th0 = w.initial_state()
+    for precision in ("fp64", "mixed"):
+        ref = None
+        for xv in (0, 1, 2, 3):
+            s = fcns.Solver.from_workload(w, precision=precision, keep_pressure=True)
+            s.set_state(torch.from_numpy(v0), torch.from_numpy(th0) if th0 is not None else None)
+            s.set_choices(f"xvar={xv}")
+            s.rk_step(w.dt, w.steps)
+            got = s.get_state(pressure=True)
+            s.synchronize()
+            if ref is None:
+                ref = got
+                continue
+            for g, r in zip(got, ref):
+                if r is not None:
+                    assert torch.equal(g, r), (shape, precision, xv)
+    with pytest.raises(fcns.FcnsError):
+        fcns.Solver.from_workload(W.channel(512, 8, 33, 2000.0, C=31, dt=1e-3, steps=1,
+                                            seed=821)).set_choices("xvar=3")
