@@ -26,7 +26,7 @@ METRIC = ("grid-point RK-substeps/sec (FP64 & mixed) + p50/p99 step latency in b
           "serving")
 UNIT = "grid-point RK-substeps/s"
 HBM_PEAK_GBPS = 8000.0
-SURVEY_STEPS = 2  # steps with every kernel class event-timed, before the timed region
+BREAKDOWN_STEPS = 2  # steps with every kernel class event-timed, before the timed region
 CSRC = os.path.join(ROOT, "paper_2002_01392_amd", "csrc")
 PROFILES = os.path.join(ROOT, "profiles")
 
@@ -403,7 +403,7 @@ def main():
     ap.add_argument("--timing", type=int, default=1,
                     help="1: event-time every kernel class over %d steps before the timed "
                          "region and the dominant class inside it; 2: every class inside "
-                         "it; 0: none" % SURVEY_STEPS)
+                         "it; 0: none" % BREAKDOWN_STEPS)
     ap.add_argument("--no-mixed", action="store_true",
                     help="skip the mixed-precision run on the channel grid")
     ap.add_argument("--no-serving", action="store_true", help="skip the serving run")
@@ -418,7 +418,7 @@ def main():
                     help="also run one plain device copy of 1 GiB (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported",
+        print(f"bench.py: the benchmark runs on one GPU; --gpus {args.gpus} is not supported",
               file=sys.stderr)
         sys.exit(2)
 
@@ -449,16 +449,16 @@ def main():
     s.rk_step(w.dt, args.warmup)
     torch.cuda.synchronize()
 
-    survey = {}
+    breakdown = {}
     if args.timing == 1:
         # every class event-timed over a few steps before the timed region
         # (per-kernel breakdown, and which class dominates); in the timed
         # region only the dominant class carries events
         s.set_timing(True)
         s.timing_reset()
-        s.rk_step(w.dt, SURVEY_STEPS)
-        survey = s.timing_report()
-        tot = {k: ms for k, (n, ms) in survey.items() if n > 0 and k not in CHAINS}
+        s.rk_step(w.dt, BREAKDOWN_STEPS)
+        breakdown = s.timing_report()
+        tot = {k: ms for k, (n, ms) in breakdown.items() if n > 0 and k not in CHAINS}
         s.set_timing(True, classes=[max(tot, key=tot.get)])
         s.timing_reset()
     elif args.timing:
@@ -514,7 +514,7 @@ def main():
         roof = {"bound": "hbm", "kernel": dom, "achieved": round(ach, 1), "peak": HBM_PEAK_GBPS,
                 "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBPS, 4), "traffic": traffic,
                 "bytes_per_launch": int(b), "mean_launch_ms": round(ms_dom / n_dom, 4)}
-        brk = survey if survey else rep
+        brk = breakdown if breakdown else rep
         btot = sum(ms for n, ms in brk.values() if n > 0)
         for k, (n, ms) in brk.items():
             if n == 0:
@@ -571,8 +571,8 @@ def main():
         "wall_s": wall, "state_finite": finite,
         "roofline": roof, "pass_model": pass_model, "kernels": kernels,
         "kernels_timed": ("%d steps before the timed region, every class event-timed; in "
-                          "the timed region only the roofline kernel" % SURVEY_STEPS)
-        if survey else "the timed region",
+                          "the timed region only the roofline kernel" % BREAKDOWN_STEPS)
+        if breakdown else "the timed region",
         "precision": mixed,
         "serving": serving, "graph": graph, "batch": batch, "autotune": tuned, "choices": choices,
         "cpu_baseline": cpu, "kernel_source_hash": src_hash,
