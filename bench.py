@@ -186,7 +186,7 @@ def precision_run(name="channel_256x256x257", steps=100, warmup=2):
                     "transforms that form v*, and the projection"}
 
 
-def serving_run(max_active=8, max_bytes=64 << 30, n=64, rate=20.0, steps=20, max_large=2,
+def serving_run(max_active=8, max_bytes=64 << 30, n=64, rate=20.0, steps=20, max_large=1,
                 large_points=4 << 20):
     """The serving workload: n requests with Poisson arrivals at `rate`/s, each
     a `steps`-step solve (channel or Rayleigh-Benard, side 32..192), served by
@@ -231,7 +231,8 @@ def serving_run(max_active=8, max_bytes=64 << 30, n=64, rate=20.0, steps=20, max
                 srv.set_choices(prob, text)
         if mix and slots > 1:
             # at most max_large of the largest shapes (192^2 x 193: 7.1e6
-            # points) at a time; the smaller ones fill the device around them
+            # points) at a time (one keeps their latency tail short); the
+            # smaller ones fill the device around them
             srv.set_mix(max_large, large_points)
         t0 = srv.now()
         ids, k = [], 0
