@@ -763,12 +763,23 @@ extern "C" fcns_status fcns_rk_step(fcns_ctx* c, double dt, int32_t nsteps) {
   return finish_steps(c, "rk_step");
 }
 
+// A captured step (fcns_rk_graph) holds the launch choices it was captured
+// with: a change of choices drops it, and the next fcns_rk_graph captures
+// the step again.
+static void drop_graph(fcns_ctx* c) {
+  if (c->graph) {
+    (void)hipGraphExecDestroy(c->graph);
+    c->graph = nullptr;
+  }
+}
+
 extern "C" fcns_status fcns_set_y_lines(fcns_ctx* c, int32_t lines) {
   if (!c) return FCNS_EINVAL;
   if (lines != 4 && lines != 8) return fail(c, FCNS_EINVAL, "y tiles have 4 or 8 lines");
   if (lines == 8 && !y_wide_tiles(yargs(c)))
     return fail(c, FCNS_EINVAL, "8-line y tiles need ny = 512");
   c->ylines = c->ylines1 = lines;
+  drop_graph(c);
   return FCNS_OK;
 }
 
@@ -777,6 +788,7 @@ extern "C" fcns_status fcns_set_blocked(fcns_ctx* c, int32_t on) {
   if (on && !x_reads_blocked(xargs(c)))
     return fail(c, FCNS_EINVAL, "the blocked layout needs the wave-level x pass (nx = 256, 512)");
   c->xyblk = on != 0;
+  drop_graph(c);
   return FCNS_OK;
 }
 
@@ -787,6 +799,7 @@ extern "C" fcns_status fcns_set_slab(fcns_ctx* c, int32_t planes) {
   if (planes > 0 && 4LL * planes > 3LL * c->g.nz)
     return fail(c, FCNS_EINVAL, "slab larger than 3/4 of the planes");
   c->slab = planes;
+  drop_graph(c);
   return FCNS_OK;
 }
 
@@ -795,6 +808,7 @@ extern "C" fcns_status fcns_set_z_fused(fcns_ctx* c, int32_t on) {
   if (on && !can_fuse(c))
     return fail(c, FCNS_EINVAL, "the fused z pass needs an FP64 context and N' <= 288");
   c->zfuse = on != 0;
+  drop_graph(c);
   return FCNS_OK;
 }
 
@@ -917,10 +931,7 @@ static fcns_status set_z_plan(fcns_ctx* c, const std::vector<int>& rs) {
   c->twz_f = f;
   c->plz = pl;
   c->big_z = big;
-  if (c->graph) {  // a captured step holds the old tables
-    (void)hipGraphExecDestroy(c->graph);
-    c->graph = nullptr;
-  }
+  drop_graph(c);   // a captured step holds the old tables
   return FCNS_OK;
 }
 
@@ -1118,6 +1129,7 @@ extern "C" fcns_status fcns_autotune(fcns_ctx* c, char* report, int32_t report_l
   // ones the next step reads are rebuilt from the state
   state_to_mv(c, c->P);
   c->timing = timing;
+  drop_graph(c);
   fcns_status st = check_launch(c, "autotune");
   if (report && report_len > 0) {
     strncpy(report, rep.c_str(), (size_t)report_len - 1);
@@ -1218,6 +1230,7 @@ extern "C" fcns_status fcns_set_choices(fcns_ctx* c, const char* text) {
   c->slab = t.slab;
   c->xyblk = t.xyblk;
   c->zfuse = t.zfuse;
+  drop_graph(c);
   return FCNS_OK;
 }
 
