@@ -258,9 +258,11 @@ fcns_status fcns_get_choices(const fcns_ctx* ctx, char* out, int32_t len);
 fcns_status fcns_set_choices(fcns_ctx* ctx, const char* text);
 
 /* Same as fcns_rk_step, by replaying a HIP graph of one step.  The graph is
- * captured on the first call and again whenever dt changes (capture
- * synchronizes the stream and allocates the graph; replays allocate
- * nothing), which removes the per-kernel launch cost of small problems.
+ * captured on the first call and again whenever dt changes or the launch
+ * choices have changed since (fcns_set_z_fused, fcns_set_slab,
+ * fcns_set_blocked, fcns_set_y_lines, fcns_set_choices, fcns_autotune);
+ * capture synchronizes the stream and allocates the graph, replays allocate
+ * nothing, which removes the per-kernel launch cost of small problems.
  * Results are bitwise those of fcns_rk_step.  Kernel timing does not cover
  * graph replays. */
 fcns_status fcns_rk_graph(fcns_ctx* ctx, double dt, int32_t nsteps);
