@@ -356,9 +356,14 @@ __global__ __launch_bounds__(ZNT) void k_z_back(ZArgs a, const cpx<double>* __re
 // are only left there.
 template <typename T, typename TM, class FP, int OWN, bool WV, bool SPECBUOY,
           bool KEEPOUT = false, bool STORE = true>
+// nl_in: this field's nonlinear-term rows, already loaded (else they are
+// loaded here); nl_out: receives field fnext's rows, loaded before the last
+// transform so that they arrive while it runs.
 __device__ __forceinline__ void z_stageA_field(const ZLds<T>& L, const ZArgs& a,
                                                const StageAArgs& s, int f, long long p0, int tid,
-                                               bool tables, cpx<double>* keep = nullptr) {
+                                               bool tables, cpx<double>* keep = nullptr,
+                                               const cpx<TM>* nl_in = nullptr, int fnext = -1,
+                                               cpx<TM>* nl_out = nullptr) {
   // a fresh copy of the thread index: the row offsets derived from it are
   // recomputed per field rather than kept live from one field to the next
   asm volatile("" : "+v"(tid));
@@ -396,10 +401,15 @@ __device__ __forceinline__ void z_stageA_field(const ZLds<T>& L, const ZArgs& a,
   };
   cpx<TM> nr[OWN];
   const long long pc = pv ? p : 0;
+  if (nl_in) {
 #pragma unroll
-  for (int r = 0; r < OWN; ++r) {
-    const int z = min(lt + r * ZLS, g.nz - 1);
-    nr[r] = ld(nl + (long long)z * g.npen + pc);
+    for (int r = 0; r < OWN; ++r) nr[r] = nl_in[r];
+  } else {
+#pragma unroll
+    for (int r = 0; r < OWN; ++r) {
+      const int z = min(lt + r * ZLS, g.nz - 1);
+      nr[r] = ld(nl + (long long)z * g.npen + pc);
+    }
   }
   // keep these loads ahead of the ones below (loads complete in order, so a
   // later one issued first would hold up the LDS writes of these rows)
@@ -500,6 +510,12 @@ __device__ __forceinline__ void z_stageA_field(const ZLds<T>& L, const ZArgs& a,
   }
   __syncthreads();
   z_extend<T>(L.X0, L.M, g.nz, g.C, g.d, tid);
+  if (nl_out) {
+    const cpx<TM>* nln = reinterpret_cast<const cpx<TM>*>(s.nl[fnext]);
+#pragma unroll
+    for (int r = 0; r < OWN; ++r)
+      nl_out[r] = ld(nln + (long long)min(lt + r * ZLS, g.nz - 1) * g.npen + pc);
+  }
   __syncthreads();
   R = fft_run<T, ZPB, ZNT, false, FP>(L.X0, L.X1, ZPB, 1, a.pl, L.tw, tid);
   // compiled plans: all of this thread's LDS reads first, then the stores
@@ -827,9 +843,13 @@ __device__ __forceinline__ void z_pass_group(const ZLds<double>& L, const ZArgs&
   // one field after the other (the field index a constant in each copy);
   // theta first: its new state is final after stage A, so its back
   // transforms follow at once from the rows still in registers
+  // (each field's nonlinear-term rows are loaded during the previous field's
+  // last transform)
+  cpx<double> pre_w[OWN], pre_u[OWN], pre_v[OWN];
   if (nf == 4) {
     cpx<double> keep[OWN];
-    z_stageA_field<double, double, FP, OWN, WV, true, true>(L, a, sa, 3, p0, tid, true, keep);
+    z_stageA_field<double, double, FP, OWN, WV, true, true>(L, a, sa, 3, p0, tid, true, keep,
+                                                            nullptr, 2, pre_w);
     __syncthreads();
     check_rows<OWN>(a, keep);
     z_back_rows<double, FP, OWN, true>(L, a, keep, zb.mv + 6 * zb.ms, zb.mv + 7 * zb.ms, p0,
@@ -837,13 +857,23 @@ __device__ __forceinline__ void z_pass_group(const ZLds<double>& L, const ZArgs&
   }
   // then w (its buoyancy reads theta's W again, soon after theta did), u,
   // and v, whose V* goes to the projection in registers without a store
-  z_stageA_field<double, double, FP, OWN, WV, true>(L, a, sa, 2, p0, tid, nf != 4);
+  if (nf != 4) {   // (no theta to load them during)
+    const int pb = tid % ZPB, lt = tid / ZPB;
+    const long long pc = pencil_valid(a.g, p0 + pb) ? p0 + pb : 0;
+    const cpx<double>* nlw = reinterpret_cast<const cpx<double>*>(sa.nl[2]);
+#pragma unroll
+    for (int r = 0; r < OWN; ++r)
+      pre_w[r] = ld_stream(nlw + (long long)min(lt + r * ZLS, a.g.nz - 1) * a.g.npen + pc);
+  }
+  z_stageA_field<double, double, FP, OWN, WV, true>(L, a, sa, 2, p0, tid, nf != 4, nullptr,
+                                                    pre_w, 0, pre_u);
   __syncthreads();
-  z_stageA_field<double, double, FP, OWN, WV, true>(L, a, sa, 0, p0, tid, false);
+  z_stageA_field<double, double, FP, OWN, WV, true>(L, a, sa, 0, p0, tid, false, nullptr, pre_u,
+                                                    1, pre_v);
   __syncthreads();
   cpx<double> vstar1[OWN];
   z_stageA_field<double, double, FP, OWN, WV, true, true, false>(L, a, sa, 1, p0, tid, false,
-                                                                  vstar1);
+                                                                  vstar1, pre_v);
   __syncthreads();
   cpx<double> vk[3][1];
   z_stageB_body<double, FP, OWN, false, 1>(L, a, sb, p0, tid, coef, gam_s, false, vk, vstar1);
