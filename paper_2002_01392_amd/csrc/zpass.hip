@@ -358,12 +358,16 @@ template <typename T, typename TM, class FP, int OWN, bool WV, bool SPECBUOY,
           bool KEEPOUT = false, bool STORE = true>
 // nl_in: this field's nonlinear-term rows, already loaded (else they are
 // loaded here); nl_out: receives field fnext's rows, loaded before the last
-// transform so that they arrive while it runs.
+// transform so that they arrive while it runs; cs_out likewise receives the
+// rows of the continued field cs_next (rows past N' clamped; the layout of
+// z_back_rows).
 __device__ __forceinline__ void z_stageA_field(const ZLds<T>& L, const ZArgs& a,
                                                const StageAArgs& s, int f, long long p0, int tid,
                                                bool tables, cpx<double>* keep = nullptr,
                                                const cpx<TM>* nl_in = nullptr, int fnext = -1,
-                                               cpx<TM>* nl_out = nullptr) {
+                                               cpx<TM>* nl_out = nullptr,
+                                               const cpx<double>* cs_next = nullptr,
+                                               cpx<double>* cs_out = nullptr) {
   // a fresh copy of the thread index: the row offsets derived from it are
   // recomputed per field rather than kept live from one field to the next
   asm volatile("" : "+v"(tid));
@@ -516,6 +520,11 @@ __device__ __forceinline__ void z_stageA_field(const ZLds<T>& L, const ZArgs& a,
     for (int r = 0; r < OWN; ++r)
       nl_out[r] = ld(nln + (long long)min(lt + r * ZLS, g.nz - 1) * g.npen + pc);
   }
+  if (cs_out) {
+#pragma unroll
+    for (int r = 0; r < OWN; ++r)
+      cs_out[r] = cs_next[(long long)min(lt + r * ZLS, npr - 1) * g.npen + pc];
+  }
   __syncthreads();
   R = fft_run<T, ZPB, ZNT, false, FP>(L.X0, L.X1, ZPB, 1, a.pl, L.tw, tid);
   // compiled plans: all of this thread's LDS reads first, then the stores
@@ -586,12 +595,15 @@ __global__ __launch_bounds__(ZNT) void k_z_stageA(ZArgs a, StageAArgs s) {
 // KF >= 0 (needs HOLD): V* of field KF is not read but taken from kv, this
 // thread's rows in the layout of z_back_rows, and kv receives the field's
 // projected rows in their place.
-template <typename T, class FP, int HOLD, bool KEEP, int KF = -1>
+// KP >= 0 (needs HOLD): V* of field KP is taken from kp (rows already
+// loaded) instead of being read here.
+template <typename T, class FP, int HOLD, bool KEEP, int KF = -1, int KP = -1>
 __device__ __forceinline__ void z_stageB_body(const ZLds<T>& L, const ZArgs& a,
                                               const StageBArgs& s, long long p0, int tid,
                                               cpx<double>* coef, double* gam_s, bool tables,
                                               cpx<double> (&vk)[3][KEEP ? HOLD : 1],
-                                              cpx<double>* kv = nullptr) {
+                                              cpx<double>* kv = nullptr,
+                                              const cpx<double>* kp = nullptr) {
   static_assert(!KEEP || HOLD > 0, "KEEP needs the rows held in registers");
   static_assert(KF < 0 || HOLD > 0, "KF needs the rows held in registers");
   const Geom& g = a.g;
@@ -632,7 +644,7 @@ __device__ __forceinline__ void z_stageB_body(const ZLds<T>& L, const ZArgs& a,
       const long long gi =
           valid_me ? (long long)min(lt + r * ZLS, npr - 1) * g.npen + p_me : 0;
 #pragma unroll
-      for (int i = 0; i < 3; ++i) hv[i][r] = (i == KF) ? kv[r] : s.vs[i][gi];
+      for (int i = 0; i < 3; ++i) hv[i][r] = (i == KF) ? kv[r] : (i == KP) ? kp[r] : s.vs[i][gi];
     }
   }
   if (tables) ztab_store<T>(tab, L, a, tid);
@@ -871,12 +883,15 @@ __device__ __forceinline__ void z_pass_group(const ZLds<double>& L, const ZArgs&
   z_stageA_field<double, double, FP, OWN, WV, true>(L, a, sa, 0, p0, tid, false, nullptr, pre_u,
                                                     1, pre_v);
   __syncthreads();
-  cpx<double> vstar1[OWN];
+  // (w's V* rows for the projection are loaded during v's last transform)
+  cpx<double> vstar1[OWN], vstar2[OWN];
   z_stageA_field<double, double, FP, OWN, WV, true, true, false>(L, a, sa, 1, p0, tid, false,
-                                                                  vstar1, pre_v);
+                                                                  vstar1, pre_v, -1, nullptr,
+                                                                  sa.out[2], vstar2);
   __syncthreads();
   cpx<double> vk[3][1];
-  z_stageB_body<double, FP, OWN, false, 1>(L, a, sb, p0, tid, coef, gam_s, false, vk, vstar1);
+  z_stageB_body<double, FP, OWN, false, 1, 2>(L, a, sb, p0, tid, coef, gam_s, false, vk, vstar1,
+                                              vstar2);
   __syncthreads();
   // v's new state is in registers; each thread reads back the rows of u and
   // w it has just written (cache hits)
