@@ -227,9 +227,9 @@ fcns_status fcns_set_z_fused(fcns_ctx* ctx, int32_t on);
  * back transforms of v and its derivatives, the products in x, the y
  * forward transform of the nonlinear term): planes = 0 over whole arrays
  * (the default), planes > 0 slab by slab in z, that many planes at a time,
- * so that each slab's intermediate arrays are read back from the caches
- * (fcns_autotune picks the faster).  Results are bitwise the same.  EINVAL
- * if planes < 0 or 4 planes > 3 nz. */
+ * so that each slab's intermediate arrays are read back soon after they
+ * are written (fcns_autotune picks the faster).  Results are bitwise the
+ * same.  EINVAL if planes < 0 or 4 planes > 3 nz. */
 fcns_status fcns_set_slab(fcns_ctx* ctx, int32_t planes);
 
 /* Choose the layout of rk_step's (kx, y) intermediate arrays (Sec. 4.2: v

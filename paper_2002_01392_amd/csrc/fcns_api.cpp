@@ -528,8 +528,8 @@ static void nonlinear_from_mixed(fcns_ctx* c, const cpx<T>* mv, int nfields, boo
   if (fwd_y && c->slab > 0 && c->slab < g.nz) {
     // slab by slab: the (kx, y, z) intermediates of a slab of planes are
     // written and read back within its four launches, in the first part of
-    // XYB (4 nf slab fields), so they are reused from the caches rather than
-    // streamed through HBM; only the mixed nonlinear term reaches NLB
+    // XYB (4 nf slab fields), soon after they are written (the last ones
+    // still in the caches); only the mixed nonlinear term reaches NLB
     const long long P = (long long)g.ny * g.nkxp;
     const long long Ms = (long long)c->slab * P;
     cpx<T>* nls = xyb + 3 * nfields * Ms;
