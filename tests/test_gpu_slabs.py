@@ -208,3 +208,31 @@ def test_x_pass_variants_are_bitwise_the_same(fcns, shape):
     with pytest.raises(fcns.FcnsError):
         fcns.Solver.from_workload(W.channel(512, 8, 33, 2000.0, C=31, dt=1e-3, steps=1,
                                             seed=821)).set_choices("xvar=3")
+
+
+def test_tuned_choices_round_trip_with_a_prime_length(fcns):
+    # N' = 282 = 2 * 3 * 47: the saved radix order is rebuilt on the new context
+    w = W.channel(16, 8, 257, 2000.0, d=5, C=25, dt=5e-4, steps=2, seed=822, noise_rms=0.05)
+    v0, _ = w.initial_state()
+    a = fcns.Solver.from_workload(w)
+    a.set_state(torch.from_numpy(v0))
+    a.autotune()
+    text = a.choices()
+    a.set_choices("zplan=3.47.2")      # another order, then back to the tuned one
+    a.set_choices(text)
+    a.set_state(torch.from_numpy(v0))
+    a.rk_step(w.dt, w.steps)
+    b = fcns.Solver.from_workload(w)
+    b.set_choices(text)
+    assert b.choices() == text
+    b.set_state(torch.from_numpy(v0))
+    b.rk_step(w.dt, w.steps)
+    va, _, _ = a.get_state()
+    vb, _, _ = b.get_state()
+    torch.cuda.synchronize()
+    assert torch.equal(va, vb)
+    o = Oracle(Problem(**w.problem_kwargs()))
+    o.set_state(v0)
+    o.rk_step(w.dt, w.steps)
+    rv, _, _ = o.get_state()
+    assert rel_l2(vb, rv) < 1e-11
