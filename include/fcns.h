@@ -238,7 +238,7 @@ fcns_status fcns_set_slab(fcns_ctx* ctx, int32_t planes);
  * 4 kx columns stored contiguously over y, so that the y back transforms
  * write whole contiguous blocks; fcns_autotune picks the faster).  Results
  * are bitwise the same.  EINVAL if on = 1 and the x pass cannot read that
- * layout (it needs nx = 256 or 512 and the wave-level x kernel). */
+ * layout (it needs nx = 64, 128, 256 or 512 and the wave-level x kernel). */
 fcns_status fcns_set_blocked(fcns_ctx* ctx, int32_t on);
 
 /* Lines (kx columns) per workgroup tile of the y transforms: 4 (the

@@ -437,9 +437,10 @@ __global__ __launch_bounds__(NT) void k_x_nl(XArgs a, const cpx<T>* __restrict__
 }
 
 // ---------------------------------------------------------------- x pass, wave-level rows
-// Rows of N = 512 or 256 points with 8 points per lane: a row occupies
-// S = N / 8 lanes (one row per wavefront at 512, two at 256), and lane t of a
-// row (t < S) holds index t + S m (m = 0..7) of every transform, in and out.
+// Rows of N = 512, 256, 128 or 64 points with 8 points per lane: a row
+// occupies S = N / 8 lanes (one row per wavefront at 512, two at 256, four at
+// 128, eight at 64), and lane t of a row (t < S) holds index t + S m
+// (m = 0..7) of every transform, in and out.
 //
 // N = 512 = 8 x 8 x 8: n = n0 + 8 n1 + 64 n2, k = k0 + 8 k1 + 64 k2 (t = n0 + 8 n1):
 //   a radix-8 DFT over n2 in registers, twiddle w64^(n1 k0);
@@ -454,6 +455,15 @@ __global__ __launch_bounds__(NT) void k_x_nl(XArgs a, const cpx<T>* __restrict__
 //   exchange so that lane L holds t0 = 0..3 of c = a + 8 j1 = L and L + 32,
 //   two radix-4 DFTs over t0,
 // which leaves X[c + 64 j0] = X[L + 32 (h + 2 j0)] (c = L + 32 h) in lane L.
+// N = 128 = 8 x 16: n = t + 16 m, k = a + 8 b:
+//   a radix-8 DFT over m in registers, twiddle w128^(t a);
+//   the eight 16-point DFTs over t = h + 2 t1 (b = j + 8 c): exchange so that
+//   lane 2 a + h holds t1 = 0..7, radix-8 over t1, twiddle w16^(h j);
+//   exchange so that lane a + 8 j0 holds, for j = j0 + 2 j1 (j1 = 0..3),
+//   both halves h of output j, and a radix-2 DFT over h,
+// which leaves X[a + 8 j + 64 c] = X[L + 16 (j1 + 4 c)] in lane L.
+// N = 64 = 8 x 8: a radix-8 DFT over m, twiddle w64^(t a), one exchange so
+// that lane a holds t = 0..7, radix-8 over t: X[a + 8 b] in lane a.
 // The exchanges go through a padded per-row LDS buffer (conflict-free
 // 16-byte accesses) and need only wave-level ordering, no workgroup barrier.
 // Two real transforms share one complex transform: z = a + i b (inverse from
@@ -479,7 +489,8 @@ __device__ __forceinline__ int xw_nat(int i) { return i + (i >> 3); }
 // N = 512: tw[k0 - 1][t] = w64^(n1 k0) (k0 = 1..7) with t = n0 + 8 n1, and
 // tw[7 + k1][t] = w512^(n0 (k0' + 8 k1)) with t = n0 + 8 k0'.
 // N = 256: tw[a - 1][t] = w256^(t a) (a = 1..7), tw[6 + j1][t] = w32^(t0 j1)
-// (j1 = 1..7) with t = t0 + 4 a.
+// (j1 = 1..7) with t = t0 + 4 a.  N = 128: tw[a - 1][t] = w128^(t a),
+// tw[6 + j][L] = w16^(h j) with h = L & 1.  N = 64: tw[a - 1][t] = w64^(t a).
 constexpr int XW_TW = 15 * 64;
 
 template <typename T, int N>
@@ -491,8 +502,12 @@ __device__ __forceinline__ void xw_twiddles(cpx<T>* tw, int tid) {
     int j;  // power of wN
     if (N == 512)
       j = reg < 7 ? 8 * (t >> 3) * (reg + 1) : (t & 7) * ((t >> 3) + 8 * (reg - 7));
-    else
+    else if (N == 256)
       j = reg < 7 ? t * (reg + 1) : 8 * (t & 3) * (reg - 6);
+    else if (N == 128)   // tw[6 + j][L] = w16^(h j), h = L & 1
+      j = reg < 7 ? t * (reg + 1) : 8 * (t & 1) * (reg - 6);
+    else
+      j = reg < 7 ? t * (reg + 1) : 0;
     double sn, cs;
     sincospi(2.0 * j / N, &sn, &cs);
     tw[e] = mk((T)cs, (T)(-sn));   // exp(-2 pi i j / N)
@@ -564,13 +579,70 @@ __device__ __forceinline__ void wave_fft256(cpx<T> (&r)[8], cpx<T>* __restrict__
   for (int m = 0; m < 8; ++m) r[m] = q[4 * (m & 1) + (m >> 1)];
 }
 
+template <typename T>
+__device__ __forceinline__ void wave_fft128(cpx<T> (&r)[8], cpx<T>* __restrict__ buf,
+                                            const cpx<T>* __restrict__ tw, int t) {
+  Codelet<T, 8>::run(r, nullptr);
+#pragma unroll
+  for (int a = 1; a < 8; ++a) r[a] = r[a] * tw[(a - 1) * 16 + t];
+  // exchange 1: element (a, t) at 17 a + t
+  cpx<T>* w1 = buf + t;
+#pragma unroll
+  for (int a = 0; a < 8; ++a) w1[17 * a] = r[a];
+  wave_sync();
+  const int a = t >> 1, h = t & 1;  // the lane's (a, h) after exchange 1
+  const cpx<T>* r1 = buf + 17 * a + h;
+#pragma unroll
+  for (int t1 = 0; t1 < 8; ++t1) r[t1] = r1[2 * t1];
+  wave_sync();
+  Codelet<T, 8>::run(r, nullptr);
+#pragma unroll
+  for (int j = 1; j < 8; ++j) r[j] = r[j] * tw[(6 + j) * 16 + t];
+  // exchange 2: output j of lane L = 2 a + h at 9 L + j
+  cpx<T>* w2 = buf + 9 * t;
+#pragma unroll
+  for (int j = 0; j < 8; ++j) w2[j] = r[j];
+  wave_sync();
+  const int a2 = t & 7, j0 = t >> 3;
+  const cpx<T>* r2 = buf + 18 * a2 + j0;
+#pragma unroll
+  for (int j1 = 0; j1 < 4; ++j1) {
+    const cpx<T> p0 = r2[2 * j1], p1 = r2[9 + 2 * j1];
+    r[j1] = p0 + p1;
+    r[j1 + 4] = p0 - p1;
+  }
+  wave_sync();
+}
+
+template <typename T>
+__device__ __forceinline__ void wave_fft64(cpx<T> (&r)[8], cpx<T>* __restrict__ buf,
+                                           const cpx<T>* __restrict__ tw, int t) {
+  Codelet<T, 8>::run(r, nullptr);
+#pragma unroll
+  for (int a = 1; a < 8; ++a) r[a] = r[a] * tw[(a - 1) * 8 + t];
+  // element (a, t) at 9 a + t; lane a then reads t = 0..7
+  cpx<T>* w1 = buf + t;
+#pragma unroll
+  for (int a = 0; a < 8; ++a) w1[9 * a] = r[a];
+  wave_sync();
+  const cpx<T>* r1 = buf + 9 * t;
+#pragma unroll
+  for (int t1 = 0; t1 < 8; ++t1) r[t1] = r1[t1];
+  wave_sync();
+  Codelet<T, 8>::run(r, nullptr);
+}
+
 template <typename T, int N>
 __device__ __forceinline__ void wave_fft(cpx<T> (&r)[8], cpx<T>* __restrict__ buf,
                                          const cpx<T>* __restrict__ tw, int t) {
   if constexpr (N == 512)
     wave_fft512<T>(r, buf, tw, t);
-  else
+  else if constexpr (N == 256)
     wave_fft256<T>(r, buf, tw, t);
+  else if constexpr (N == 128)
+    wave_fft128<T>(r, buf, tw, t);
+  else
+    wave_fft64<T>(r, buf, tw, t);
 }
 
 // Forward transform of two finished real fields (b: none when !two), unpacked
@@ -726,8 +798,10 @@ __global__ __launch_bounds__(64 * XW_WAVES) void k_x_nlw_q(XArgs a, const cpx<T>
   }
 }
 
+// (two waves per SIMD asked for explicitly at N = 128, where the compiler
+// would otherwise go past 256 registers)
 template <typename T, int NF, int N, bool BLK>
-__global__ __launch_bounds__(64 * XW_WAVES) void k_x_nlw(XArgs a, const cpx<T>* __restrict__ xyb,
+__global__ __launch_bounds__(64 * XW_WAVES, N == 128 ? 2 : 1) void k_x_nlw(XArgs a, const cpx<T>* __restrict__ xyb,
                                                          cpx<T>* __restrict__ nl, long long fs,
                                                          long long nrows) {
   // Four fields: pairs of real quantities per complex transform, each
@@ -937,9 +1011,11 @@ static void launch_x_nl_v(const XArgs& a, const cpx<T>* xyb, cpx<T>* nl, long lo
               nfields);
 }
 
-bool x_reads_blocked(const XArgs& a) { return (a.nx == 512 || a.nx == 256) && a.variant == 0; }
+bool x_reads_blocked(const XArgs& a) {
+  return (a.nx == 512 || a.nx == 256 || a.nx == 128 || a.nx == 64) && a.variant == 0;
+}
 
-// nx = 512 and 256: wave-level rows (variant 0) or the tiled kernels; other
+// nx = 512, 256, 128 and 64: wave-level rows (variant 0) or the tiled kernels; other
 // nx: 4 rows x 256 threads (variant 0, 1) or 8 rows x 512 threads (variant 2),
 // with compile-time plans for 512 and 256; nx <= 256: 8 rows x nx threads
 // (variant 3)
@@ -974,7 +1050,7 @@ void launch_x_nl(const XArgs& a, bool big, const cpx<T>* xyb, cpx<T>* nl, long l
       launch_x_nl_v<T, DynPlan<true>, 8, 512, 1>(a, xyb, nl, fs, nrows, nfields, st);
     else
       launch_x_nl_v<T, DynPlan<false>, 8, 512, 1>(a, xyb, nl, fs, nrows, nfields, st);
-  } else if ((a.nx == 512 || a.nx == 256) && a.variant == 0) {
+  } else if ((a.nx == 512 || a.nx == 256 || a.nx == 128 || a.nx == 64) && a.variant == 0) {
     // wave-level rows; enough workgroups to fill the chip several times
     const long long rpw = 64 / (a.nx / 8);
     const long long need = (nrows + rpw * XW_WAVES - 1) / (rpw * XW_WAVES);
@@ -992,10 +1068,18 @@ void launch_x_nl(const XArgs& a, bool big, const cpx<T>* xyb, cpx<T>* nl, long l
       FCNS_XW(k_x_nlw, 4, 512);
     else if (a.nx == 512)
       FCNS_XW(k_x_nlw_q, 3, 512);
-    else if (nfields == 4)
+    else if (a.nx == 256 && nfields == 4)
       FCNS_XW(k_x_nlw, 4, 256);
-    else
+    else if (a.nx == 256)
       FCNS_XW(k_x_nlw_q, 3, 256);
+    else if (a.nx == 128 && nfields == 4)
+      FCNS_XW(k_x_nlw, 4, 128);
+    else if (a.nx == 128)
+      FCNS_XW(k_x_nlw_q, 3, 128);
+    else if (nfields == 4)
+      FCNS_XW(k_x_nlw, 4, 64);
+    else
+      FCNS_XW(k_x_nlw_q, 3, 64);
 #undef FCNS_XW
   } else if (a.nx == 512 && plan_is(a.pl, {8, 8, 8}))
     launch_x_nl_v<T, SPlan<8, 8, 8>, 4, 256, 2>(a, xyb, nl, fs, nrows, nfields, st);
