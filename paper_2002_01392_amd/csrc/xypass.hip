@@ -437,10 +437,10 @@ __global__ __launch_bounds__(NT) void k_x_nl(XArgs a, const cpx<T>* __restrict__
 }
 
 // ---------------------------------------------------------------- x pass, wave-level rows
-// Rows of N = 512, 256, 128 or 64 points with 8 points per lane: a row
-// occupies S = N / 8 lanes (one row per wavefront at 512, two at 256, four at
-// 128, eight at 64), and lane t of a row (t < S) holds index t + S m
-// (m = 0..7) of every transform, in and out.
+// Rows of N = 512, 256, 192, 128, 96 or 64 points with 8 points per lane: a
+// row occupies S = N / 8 lanes (one row per wavefront at 512, two at 256 and
+// 192, four at 128, five at 96, eight at 64), and lane t of a row (t < S)
+// holds index t + S m (m = 0..7) of every transform, in and out.
 //
 // N = 512 = 8 x 8 x 8: n = n0 + 8 n1 + 64 n2, k = k0 + 8 k1 + 64 k2 (t = n0 + 8 n1):
 //   a radix-8 DFT over n2 in registers, twiddle w64^(n1 k0);
@@ -464,6 +464,14 @@ __global__ __launch_bounds__(NT) void k_x_nl(XArgs a, const cpx<T>* __restrict__
 // which leaves X[a + 8 j + 64 c] = X[L + 16 (j1 + 4 c)] in lane L.
 // N = 64 = 8 x 8: a radix-8 DFT over m, twiddle w64^(t a), one exchange so
 // that lane a holds t = 0..7, radix-8 over t: X[a + 8 b] in lane a.
+// N = 192 = 8 x 24 and 96 = 8 x 12 (S = 24, 12 lanes; 2 and 5 rows per
+// wavefront, the 64 mod S spare lanes repeat a row's last lanes and store
+// nothing): a radix-8 DFT over m, twiddle wN^(t a); the S-point DFTs over
+// t = h + 3 t1 (b = j + (S/3) c): exchange so that a lane holds, for its
+// (a, h), t1 = 0..S/3-1 (at 96 two values of a per lane), radix-8 (192) or
+// two radix-4 (96) DFTs over t1, twiddle wS^(h j); exchange, radix-3 DFTs
+// over h (X[a + 8 j + (8 S/3) c], c = 0..2) spread over the lanes, and a
+// last exchange into natural order.
 // The exchanges go through a padded per-row LDS buffer (conflict-free
 // 16-byte accesses) and need only wave-level ordering, no workgroup barrier.
 // Two real transforms share one complex transform: z = a + i b (inverse from
@@ -491,6 +499,8 @@ __device__ __forceinline__ int xw_nat(int i) { return i + (i >> 3); }
 // N = 256: tw[a - 1][t] = w256^(t a) (a = 1..7), tw[6 + j1][t] = w32^(t0 j1)
 // (j1 = 1..7) with t = t0 + 4 a.  N = 128: tw[a - 1][t] = w128^(t a),
 // tw[6 + j][L] = w16^(h j) with h = L & 1.  N = 64: tw[a - 1][t] = w64^(t a).
+// N = 192, 96: tw[a - 1][t] = wN^(t a), tw[6 + j][L] = w(N/8)^(h j) with
+// h = L mod 3.
 constexpr int XW_TW = 15 * 64;
 
 template <typename T, int N>
@@ -506,6 +516,8 @@ __device__ __forceinline__ void xw_twiddles(cpx<T>* tw, int tid) {
       j = reg < 7 ? t * (reg + 1) : 8 * (t & 3) * (reg - 6);
     else if (N == 128)   // tw[6 + j][L] = w16^(h j), h = L & 1
       j = reg < 7 ? t * (reg + 1) : 8 * (t & 1) * (reg - 6);
+    else if (N == 192 || N == 96)   // tw[6 + j][L] = w(N/8)^(h j), h = L mod 3
+      j = reg < 7 ? t * (reg + 1) : 8 * (t % 3) * (reg - 6);
     else
       j = reg < 7 ? t * (reg + 1) : 0;
     double sn, cs;
@@ -632,6 +644,112 @@ __device__ __forceinline__ void wave_fft64(cpx<T> (&r)[8], cpx<T>* __restrict__ 
   Codelet<T, 8>::run(r, nullptr);
 }
 
+// Outputs of the N = 192 and 96 transforms: P_h[a][j] (twiddled) sits at
+// PS h + b, b = a + 8 j < Q = 8 S / 3; lane t takes the radix-3 DFTs over h
+// of b = t, t + S, ... (< Q), X[b + Q c] for c = 0, 1, 2, writes them in
+// natural order (slots xw_nat), and reads back its own X[t + S m].
+template <typename T, int S, int PS>
+__device__ __forceinline__ void xw_radix3_out(cpx<T> (&r)[8], cpx<T>* __restrict__ buf,
+                                              int t) {
+  constexpr int Q = 8 * S / 3;          // radix-3 DFTs per row (64 at 192, 32 at 96)
+  constexpr int NB = (Q + S - 1) / S;   // per lane, the last one partial
+  const T s3 = T(0.86602540378443864676);  // sqrt(3) / 2
+  cpx<T> o[3 * NB];
+#pragma unroll
+  for (int i = 0; i < NB; ++i) {
+    const int b = t + S * i;
+    if (b < Q) {
+      const cpx<T> p0 = buf[b], p1 = buf[PS + b], p2 = buf[2 * PS + b];
+      const cpx<T> sm = p1 + p2, df = p1 - p2;
+      const cpx<T> e = mul_i(df) * s3;
+      const cpx<T> base = p0 - sm * T(0.5);
+      o[3 * i] = p0 + sm;
+      o[3 * i + 1] = base - e;   // w3 = -1/2 - i sqrt(3)/2
+      o[3 * i + 2] = base + e;
+    }
+  }
+  wave_sync();
+#pragma unroll
+  for (int i = 0; i < NB; ++i) {
+    const int b = t + S * i;
+    if (b < Q) {
+#pragma unroll
+      for (int c = 0; c < 3; ++c) buf[xw_nat(b + Q * c)] = o[3 * i + c];
+    }
+  }
+  wave_sync();
+#pragma unroll
+  for (int m = 0; m < 8; ++m) r[m] = buf[xw_nat(t + S * m)];
+}
+
+template <typename T>
+__device__ __forceinline__ void wave_fft192(cpx<T> (&r)[8], cpx<T>* __restrict__ buf,
+                                            const cpx<T>* __restrict__ tw, int t) {
+  Codelet<T, 8>::run(r, nullptr);
+#pragma unroll
+  for (int a = 1; a < 8; ++a) r[a] = r[a] * tw[(a - 1) * 24 + t];
+  // exchange 1: element (a, t) at 25 a + t; lane 3 a + h reads t = h + 3 t1
+  cpx<T>* w1 = buf + t;
+#pragma unroll
+  for (int a = 0; a < 8; ++a) w1[25 * a] = r[a];
+  wave_sync();
+  const int a = t / 3, h = t - 3 * a;
+  const cpx<T>* r1 = buf + 25 * a + h;
+#pragma unroll
+  for (int t1 = 0; t1 < 8; ++t1) r[t1] = r1[3 * t1];
+  wave_sync();
+  Codelet<T, 8>::run(r, nullptr);
+#pragma unroll
+  for (int j = 1; j < 8; ++j) r[j] = r[j] * tw[(6 + j) * 24 + t];
+  // exchange 2: P_h[a][j] at 65 h + a + 8 j
+  cpx<T>* w2 = buf + 65 * h + a;
+#pragma unroll
+  for (int j = 0; j < 8; ++j) w2[8 * j] = r[j];
+  wave_sync();
+  xw_radix3_out<T, 24, 65>(r, buf, t);
+  wave_sync();
+}
+
+template <typename T>
+__device__ __forceinline__ void wave_fft96(cpx<T> (&r)[8], cpx<T>* __restrict__ buf,
+                                           const cpx<T>* __restrict__ tw, int t) {
+  Codelet<T, 8>::run(r, nullptr);
+#pragma unroll
+  for (int a = 1; a < 8; ++a) r[a] = r[a] * tw[(a - 1) * 12 + t];
+  // exchange 1: element (a, t) at 13 a + t; lane 3 ap + h reads t = h + 3 t1
+  // of a = 2 ap (registers 0..3) and 2 ap + 1 (registers 4..7)
+  cpx<T>* w1 = buf + t;
+#pragma unroll
+  for (int a = 0; a < 8; ++a) w1[13 * a] = r[a];
+  wave_sync();
+  const int ap = t / 3, h = t - 3 * ap;
+  const cpx<T>* r1 = buf + 26 * ap + h;
+#pragma unroll
+  for (int t1 = 0; t1 < 4; ++t1) {
+    r[t1] = r1[3 * t1];
+    r[4 + t1] = r1[13 + 3 * t1];
+  }
+  wave_sync();
+  dft4_reg(r[0], r[1], r[2], r[3]);
+  dft4_reg(r[4], r[5], r[6], r[7]);
+#pragma unroll
+  for (int j = 1; j < 4; ++j) {
+    const cpx<T> f = tw[(6 + j) * 12 + t];
+    r[j] = r[j] * f;
+    r[4 + j] = r[4 + j] * f;
+  }
+  // exchange 2: P_h[a][j] at 33 h + a + 8 j
+  cpx<T>* w2 = buf + 33 * h + 2 * ap;
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    w2[8 * j] = r[j];
+    w2[8 * j + 1] = r[4 + j];
+  }
+  wave_sync();
+  xw_radix3_out<T, 12, 33>(r, buf, t);
+  wave_sync();
+}
+
 template <typename T, int N>
 __device__ __forceinline__ void wave_fft(cpx<T> (&r)[8], cpx<T>* __restrict__ buf,
                                          const cpx<T>* __restrict__ tw, int t) {
@@ -639,8 +757,12 @@ __device__ __forceinline__ void wave_fft(cpx<T> (&r)[8], cpx<T>* __restrict__ bu
     wave_fft512<T>(r, buf, tw, t);
   else if constexpr (N == 256)
     wave_fft256<T>(r, buf, tw, t);
+  else if constexpr (N == 192)
+    wave_fft192<T>(r, buf, tw, t);
   else if constexpr (N == 128)
     wave_fft128<T>(r, buf, tw, t);
+  else if constexpr (N == 96)
+    wave_fft96<T>(r, buf, tw, t);
   else
     wave_fft64<T>(r, buf, tw, t);
 }
@@ -655,16 +777,18 @@ __device__ __forceinline__ void xw_forward(cpx<T> (&z)[8], cpx<T>* __restrict__ 
                                            int nkxp, int fa, bool two, bool valid) {
   constexpr int S = N / 8, SN = S + S / 8;  // SN: natural-order slots per register
   wave_fft<T, N>(z, buf, tw, t);
-  cpx<T>* wn = buf + xw_nat(t);
+  // slot of element t + S m (S a multiple of 8: a fixed step per register)
+  const int t0 = xw_nat(t);
+  auto slot = [&](int m) { return S % 8 == 0 ? t0 + SN * m : xw_nat(t + S * m); };
 #pragma unroll
-  for (int m = 0; m < 8; ++m) wn[SN * m] = z[m];
+  for (int m = 0; m < 8; ++m) buf[slot(m)] = z[m];
   wave_sync();
 #pragma unroll
   for (int m = 0; m < 5; ++m) {
     const int k = t + S * m;
     if (k <= N / 2 && valid) {
-      const cpx<T> Zk = wn[SN * m];
-      const cpx<T> Zm = conj(buf[xw_nat((N - k) & (N - 1))]);
+      const cpx<T> Zk = buf[slot(m)];
+      const cpx<T> Zm = conj(buf[xw_nat(k == 0 ? 0 : N - k)]);
       nl[fa * fs + row * nkxp + k] = (Zk + Zm) * T(0.5);
       if (two) nl[(fa + 1) * fs + row * nkxp + k] = mul_mi(Zk - Zm) * T(0.5);
     }
@@ -693,7 +817,7 @@ __device__ __forceinline__ int xw_col_off(int kk, int ny, bool blk) {
 // the one-read schedule below needs more registers than two waves per SIMD
 // allow.
 template <typename T, int NF, int N, bool BLK>
-__global__ __launch_bounds__(64 * XW_WAVES) void k_x_nlw_q(XArgs a, const cpx<T>* __restrict__ xyb,
+__global__ __launch_bounds__(64 * XW_WAVES, (N == 192 || N == 96) ? 2 : 1) void k_x_nlw_q(XArgs a, const cpx<T>* __restrict__ xyb,
                                                            cpx<T>* __restrict__ nl, long long fs,
                                                            long long nrows) {
   constexpr int NQ = 3 + 3 * NF, NP = (NQ + 1) / 2;
@@ -704,7 +828,10 @@ __global__ __launch_bounds__(64 * XW_WAVES) void k_x_nlw_q(XArgs a, const cpx<T>
   const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);  // wave-uniform
   xw_twiddles<T, N>(tw, tid);
   __syncthreads();
-  const int t = lane % S, half = lane / S;
+  // the 64 mod S spare lanes (192, 96) repeat the last lanes of row RPW - 1
+  const bool spare = lane >= S * RPW;
+  const int ln = spare ? lane - S : lane;
+  const int t = ln % S, half = ln / S;
   cpx<T>* buf = xbuf[wv] + half * (XW_BUF / RPW);
   const int nkxp = a.nkxp;
   const T kxs = (T)a.kxs;
@@ -720,11 +847,12 @@ __global__ __launch_bounds__(64 * XW_WAVES) void k_x_nlw_q(XArgs a, const cpx<T>
   }
   for (long long rw = (long long)blockIdx.x * XW_WAVES + wv; rw * RPW < nrows;
        rw += (long long)gridDim.x * XW_WAVES) {
-    // a row past the end (second row of the last wave) computes on a copy of
-    // the last row and stores nothing
+    // a row past the end (in the last wave) computes on a copy of the last
+    // row and stores nothing; spare lanes compute what their twin lanes do
     const long long row0 = rw * RPW + half;
-    const bool valid = RPW == 1 || row0 < nrows;
-    const long long row = valid ? row0 : nrows - 1;
+    const bool inr = RPW == 1 || row0 < nrows;
+    const bool valid = inr && !spare;
+    const long long row = inr ? row0 : nrows - 1;
     T U[3][8];
     T acc[NF][8];
 #pragma unroll
@@ -798,10 +926,10 @@ __global__ __launch_bounds__(64 * XW_WAVES) void k_x_nlw_q(XArgs a, const cpx<T>
   }
 }
 
-// (two waves per SIMD asked for explicitly at N = 128, where the compiler
-// would otherwise go past 256 registers)
+// (two waves per SIMD asked for explicitly at N = 192, 128 and 96, where the
+// compiler would otherwise go past 256 registers)
 template <typename T, int NF, int N, bool BLK>
-__global__ __launch_bounds__(64 * XW_WAVES, N == 128 ? 2 : 1) void k_x_nlw(XArgs a, const cpx<T>* __restrict__ xyb,
+__global__ __launch_bounds__(64 * XW_WAVES, (N == 192 || N == 128 || N == 96) ? 2 : 1) void k_x_nlw(XArgs a, const cpx<T>* __restrict__ xyb,
                                                          cpx<T>* __restrict__ nl, long long fs,
                                                          long long nrows) {
   // Four fields: pairs of real quantities per complex transform, each
@@ -820,7 +948,10 @@ __global__ __launch_bounds__(64 * XW_WAVES, N == 128 ? 2 : 1) void k_x_nlw(XArgs
   const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);  // wave-uniform
   xw_twiddles<T, N>(tw, tid);
   __syncthreads();
-  const int t = lane % S, half = lane / S;
+  // the 64 mod S spare lanes (192, 96) repeat the last lanes of row RPW - 1
+  const bool spare = lane >= S * RPW;
+  const int ln = spare ? lane - S : lane;
+  const int t = ln % S, half = ln / S;
   cpx<T>* buf = xbuf[wv] + half * (XW_BUF / RPW);
   const int nkxp = a.nkxp;
   const T kxs = (T)a.kxs;
@@ -836,11 +967,12 @@ __global__ __launch_bounds__(64 * XW_WAVES, N == 128 ? 2 : 1) void k_x_nlw(XArgs
   }
   for (long long rw = (long long)blockIdx.x * XW_WAVES + wv; rw * RPW < nrows;
        rw += (long long)gridDim.x * XW_WAVES) {
-    // a row past the end (second row of the last wave) computes on a copy of
-    // the last row and stores nothing
+    // a row past the end (in the last wave) computes on a copy of the last
+    // row and stores nothing; spare lanes compute what their twin lanes do
     const long long row0 = rw * RPW + half;
-    const bool valid = RPW == 1 || row0 < nrows;
-    const long long row = valid ? row0 : nrows - 1;
+    const bool inr = RPW == 1 || row0 < nrows;
+    const bool valid = inr && !spare;
+    const long long row = inr ? row0 : nrows - 1;
     T U[3][8];
     T acc[NF][8];
 #pragma unroll
@@ -1011,11 +1143,13 @@ static void launch_x_nl_v(const XArgs& a, const cpx<T>* xyb, cpx<T>* nl, long lo
               nfields);
 }
 
-bool x_reads_blocked(const XArgs& a) {
-  return (a.nx == 512 || a.nx == 256 || a.nx == 128 || a.nx == 64) && a.variant == 0;
+static bool x_wave_rows(int nx) {
+  return nx == 512 || nx == 256 || nx == 192 || nx == 128 || nx == 96 || nx == 64;
 }
 
-// nx = 512, 256, 128 and 64: wave-level rows (variant 0) or the tiled kernels; other
+bool x_reads_blocked(const XArgs& a) { return x_wave_rows(a.nx) && a.variant == 0; }
+
+// nx = 512, 256, 192, 128, 96 and 64: wave-level rows (variant 0) or the tiled kernels; other
 // nx: 4 rows x 256 threads (variant 0, 1) or 8 rows x 512 threads (variant 2),
 // with compile-time plans for 512 and 256; nx <= 256: 8 rows x nx threads
 // (variant 3)
@@ -1050,7 +1184,7 @@ void launch_x_nl(const XArgs& a, bool big, const cpx<T>* xyb, cpx<T>* nl, long l
       launch_x_nl_v<T, DynPlan<true>, 8, 512, 1>(a, xyb, nl, fs, nrows, nfields, st);
     else
       launch_x_nl_v<T, DynPlan<false>, 8, 512, 1>(a, xyb, nl, fs, nrows, nfields, st);
-  } else if ((a.nx == 512 || a.nx == 256 || a.nx == 128 || a.nx == 64) && a.variant == 0) {
+  } else if (x_wave_rows(a.nx) && a.variant == 0) {
     // wave-level rows; enough workgroups to fill the chip several times
     const long long rpw = 64 / (a.nx / 8);
     const long long need = (nrows + rpw * XW_WAVES - 1) / (rpw * XW_WAVES);
@@ -1072,10 +1206,18 @@ void launch_x_nl(const XArgs& a, bool big, const cpx<T>* xyb, cpx<T>* nl, long l
       FCNS_XW(k_x_nlw, 4, 256);
     else if (a.nx == 256)
       FCNS_XW(k_x_nlw_q, 3, 256);
+    else if (a.nx == 192 && nfields == 4)
+      FCNS_XW(k_x_nlw, 4, 192);
+    else if (a.nx == 192)
+      FCNS_XW(k_x_nlw_q, 3, 192);
     else if (a.nx == 128 && nfields == 4)
       FCNS_XW(k_x_nlw, 4, 128);
     else if (a.nx == 128)
       FCNS_XW(k_x_nlw_q, 3, 128);
+    else if (a.nx == 96 && nfields == 4)
+      FCNS_XW(k_x_nlw, 4, 96);
+    else if (a.nx == 96)
+      FCNS_XW(k_x_nlw_q, 3, 96);
     else if (nfields == 4)
       FCNS_XW(k_x_nlw, 4, 64);
     else
