@@ -1101,6 +1101,18 @@ void launch_y(const YArgs& a, bool big, bool inv, int mode, const cpx<T>* src, c
   } else if (a.ny == 256 && plan_is(a.pl, {8, 8, 4})) {
     using P256 = SPlan<8, 8, 4>;
     FCNS_Y(P256, 4);
+  } else if (a.ny == 192 && plan_is(a.pl, {8, 8, 3})) {
+    using P192 = SPlan<8, 8, 3>;
+    FCNS_Y(P192, 4);
+  } else if (a.ny == 128 && plan_is(a.pl, {8, 8, 2})) {
+    using P128 = SPlan<8, 8, 2>;
+    FCNS_Y(P128, 4);
+  } else if (a.ny == 96 && plan_is(a.pl, {8, 4, 3})) {
+    using P96 = SPlan<8, 4, 3>;
+    FCNS_Y(P96, 4);
+  } else if (a.ny == 64 && plan_is(a.pl, {8, 8})) {
+    using P64 = SPlan<8, 8>;
+    FCNS_Y(P64, 4);
   } else if (big) {
     if (need <= 4) FCNS_Y(DynPlan<true>, 4); else if (need <= 8) FCNS_Y(DynPlan<true>, 8); else FCNS_Y(DynPlan<true>, 16);
   } else {

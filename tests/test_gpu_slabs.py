@@ -301,3 +301,60 @@ def test_tuned_choices_round_trip_with_a_prime_length(fcns):
     o.rk_step(w.dt, w.steps)
     rv, _, _ = o.get_state()
     assert rel_l2(vb, rv) < 1e-11
+
+
+@pytest.mark.parametrize("shape", [("rb", 16, 192, 33), ("ch", 16, 96, 33), ("rb", 16, 128, 33),
+                                   ("ch", 16, 64, 33)])
+def test_compiled_y_plans_match_the_oracle(fcns, shape):
+    # ny = 192, 96, 128 and 64 take the compiled 8 x 8 x 3, 8 x 4 x 3,
+    # 8 x 8 x 2 and 8 x 8 y transforms,
+    # in FP64 (1e-11) and in the mixed mode (its velocity and temperature
+    # bound; the small channel's pressure moves by ~3e-10 under a 1e-15
+    # change of the start, so FP32 rounding is not bounded there by 2e-5:
+    # its pressure is checked in FP64 only)
+    kind, nx, ny, nz = shape
+    w = _xshape(kind, nx, ny, nz, 824)
+    v0, th0 = w.initial_state()
+    o = Oracle(Problem(**w.problem_kwargs()))
+    o.set_state(v0, th0)
+    o.rk_step(w.dt, w.steps)
+    rv, rth, rp = o.get_state()
+    pbar = _pressure_bar(w, v0, th0, rp)
+    for precision, vbar, pb in (("fp64", 1e-11, pbar), ("mixed", 2e-6, None)):
+        s = fcns.Solver.from_workload(w, precision=precision, keep_pressure=True)
+        s.set_state(torch.from_numpy(v0), torch.from_numpy(th0) if th0 is not None else None)
+        s.rk_step(w.dt, w.steps)
+        v, th, p = s.get_state(pressure=True)
+        s.synchronize()
+        print(shape, precision, f"v {rel_l2(v, rv):.1e} p {rel_l2(p, rp):.1e}", flush=True)
+        assert rel_l2(v, rv) < vbar, (shape, precision)
+        if rth is not None:
+            assert rel_l2(th, rth) < vbar, (shape, precision)
+        if pb is not None:
+            assert rel_l2(p, rp) < pb, (shape, precision)
+
+
+@pytest.mark.parametrize("shape", [("rb", 16, 16, 193), ("ch", 16, 16, 129), ("rb", 16, 16, 97),
+                                   ("ch", 16, 16, 65), ("rb", 16, 16, 33)])
+def test_compiled_z_plans_match_the_oracle(fcns, shape):
+    # N' = 224, 160, 128, 96 and 64 (C = 31): the fused z pass with the
+    # compiled 8 x 4 x 7, 8 x 4 x 5, 8 x 8 x 2, 8 x 4 x 3 and 8 x 8 transforms
+    kind, nx, ny, nz = shape
+    w = _xshape(kind, nx, ny, nz, 825)
+    v0, th0 = w.initial_state()
+    s = fcns.Solver.from_workload(w, keep_pressure=True)
+    s.set_state(torch.from_numpy(v0), torch.from_numpy(th0) if th0 is not None else None)
+    s.set_choices("zfused=1")
+    s.rk_step(w.dt, w.steps)
+    v, th, p = s.get_state(pressure=True)
+    s.synchronize()
+    o = Oracle(Problem(**w.problem_kwargs()))
+    o.set_state(v0, th0)
+    o.rk_step(w.dt, w.steps)
+    rv, rth, rp = o.get_state()
+    pbar = _pressure_bar(w, v0, th0, rp)
+    print(shape, f"v {rel_l2(v, rv):.1e} p {rel_l2(p, rp):.1e} (bar {pbar:.1e})", flush=True)
+    assert rel_l2(v, rv) < 1e-11
+    if rth is not None:
+        assert rel_l2(th, rth) < 1e-11
+    assert rel_l2(p, rp) < pbar
