@@ -1136,7 +1136,7 @@ void launch_z_pass(const ZArgs& a, bool big, const StageAArgs& sa, const StageBA
       FCNS_LAUNCH((k_z_pass<P288, 9, false>), grid, dim3(ZNT), sh, st, a, sa, sb, zb, nfields);
   } else if (own == 9 && plan_is(a.pl, {8, 4, 7})) {
     // N' = 224, 160, 128, 96 and 64 (the sides 192, 128, 96, 64 and 32 with
-    // C = 31): compiled plans, 7 and 5 rows per thread at 224 and 160
+    // C = 31): compiled plans, N' / 32 rows per thread
     FCNS_LAUNCH((k_z_pass<SPlan<8, 4, 7>, 7, false>), grid, dim3(ZNT), sh, st, a, sa, sb, zb,
                 nfields);
   } else if (own == 9 && plan_is(a.pl, {8, 4, 5})) {
@@ -1146,10 +1146,10 @@ void launch_z_pass(const ZArgs& a, bool big, const StageAArgs& sa, const StageBA
     FCNS_LAUNCH((k_z_pass<SPlan<8, 8, 2>, 4, false>), grid, dim3(ZNT), sh, st, a, sa, sb, zb,
                 nfields);
   } else if (own == 4 && plan_is(a.pl, {8, 4, 3})) {
-    FCNS_LAUNCH((k_z_pass<SPlan<8, 4, 3>, 4, false>), grid, dim3(ZNT), sh, st, a, sa, sb, zb,
+    FCNS_LAUNCH((k_z_pass<SPlan<8, 4, 3>, 3, false>), grid, dim3(ZNT), sh, st, a, sa, sb, zb,
                 nfields);
   } else if (own == 4 && plan_is(a.pl, {8, 8})) {
-    FCNS_LAUNCH((k_z_pass<SPlan<8, 8>, 4, false>), grid, dim3(ZNT), sh, st, a, sa, sb, zb,
+    FCNS_LAUNCH((k_z_pass<SPlan<8, 8>, 2, false>), grid, dim3(ZNT), sh, st, a, sa, sb, zb,
                 nfields);
   } else if (big) {
     if (own <= 4)
