@@ -437,10 +437,11 @@ __global__ __launch_bounds__(NT) void k_x_nl(XArgs a, const cpx<T>* __restrict__
 }
 
 // ---------------------------------------------------------------- x pass, wave-level rows
-// Rows of N = 512, 256, 192, 128, 96 or 64 points with 8 points per lane: a
-// row occupies S = N / 8 lanes (one row per wavefront at 512, two at 256 and
-// 192, four at 128, five at 96, eight at 64), and lane t of a row (t < S)
-// holds index t + S m (m = 0..7) of every transform, in and out.
+// Rows of N = 512, 256, 192, 128, 96, 64 or 32 points with 8 points per
+// lane: a row occupies S = N / 8 lanes (one row per wavefront at 512, two at
+// 256 and 192, four at 128, five at 96, eight at 64, sixteen at 32), and
+// lane t of a row (t < S) holds index t + S m (m = 0..7) of every
+// transform, in and out.
 //
 // N = 512 = 8 x 8 x 8: n = n0 + 8 n1 + 64 n2, k = k0 + 8 k1 + 64 k2 (t = n0 + 8 n1):
 //   a radix-8 DFT over n2 in registers, twiddle w64^(n1 k0);
@@ -464,6 +465,9 @@ __global__ __launch_bounds__(NT) void k_x_nl(XArgs a, const cpx<T>* __restrict__
 // which leaves X[a + 8 j + 64 c] = X[L + 16 (j1 + 4 c)] in lane L.
 // N = 64 = 8 x 8: a radix-8 DFT over m, twiddle w64^(t a), one exchange so
 // that lane a holds t = 0..7, radix-8 over t: X[a + 8 b] in lane a.
+// N = 32 = 8 x 4: a radix-8 DFT over m, twiddle w32^(t a), one exchange so
+// that lane L holds t = 0..3 of a = 2L and 2L + 1, two radix-4 DFTs, and a
+// last exchange into natural order.
 // N = 192 = 8 x 24 and 96 = 8 x 12 (S = 24, 12 lanes; 2 and 5 rows per
 // wavefront, the 64 mod S spare lanes repeat a row's last lanes and store
 // nothing): a radix-8 DFT over m, twiddle wN^(t a); the S-point DFTs over
@@ -500,7 +504,7 @@ __device__ __forceinline__ int xw_nat(int i) { return i + (i >> 3); }
 // (j1 = 1..7) with t = t0 + 4 a.  N = 128: tw[a - 1][t] = w128^(t a),
 // tw[6 + j][L] = w16^(h j) with h = L & 1.  N = 64: tw[a - 1][t] = w64^(t a).
 // N = 192, 96: tw[a - 1][t] = wN^(t a), tw[6 + j][L] = w(N/8)^(h j) with
-// h = L mod 3.
+// h = L mod 3.  N = 32: tw[a - 1][t] = w32^(t a).
 constexpr int XW_TW = 15 * 64;
 
 template <typename T, int N>
@@ -750,6 +754,36 @@ __device__ __forceinline__ void wave_fft96(cpx<T> (&r)[8], cpx<T>* __restrict__ 
   wave_sync();
 }
 
+template <typename T>
+__device__ __forceinline__ void wave_fft32(cpx<T> (&r)[8], cpx<T>* __restrict__ buf,
+                                           const cpx<T>* __restrict__ tw, int t) {
+  Codelet<T, 8>::run(r, nullptr);
+#pragma unroll
+  for (int a = 1; a < 8; ++a) r[a] = r[a] * tw[(a - 1) * 4 + t];
+  // element (a, t) at 4 a + t; lane L reads a = 2L (registers 0..3) and
+  // 2L + 1 (registers 4..7)
+  cpx<T>* w1 = buf + t;
+#pragma unroll
+  for (int a = 0; a < 8; ++a) w1[4 * a] = r[a];
+  wave_sync();
+  const cpx<T>* r1 = buf + 8 * t;
+#pragma unroll
+  for (int i = 0; i < 8; ++i) r[i] = r1[i];
+  wave_sync();
+  dft4_reg(r[0], r[1], r[2], r[3]);
+  dft4_reg(r[4], r[5], r[6], r[7]);
+  // X[2L + 8 b] and X[2L + 1 + 8 b] into natural order, then X[t + 4 m]
+#pragma unroll
+  for (int b = 0; b < 4; ++b) {
+    buf[xw_nat(2 * t + 8 * b)] = r[b];
+    buf[xw_nat(2 * t + 1 + 8 * b)] = r[4 + b];
+  }
+  wave_sync();
+#pragma unroll
+  for (int m = 0; m < 8; ++m) r[m] = buf[xw_nat(t + 4 * m)];
+  wave_sync();
+}
+
 template <typename T, int N>
 __device__ __forceinline__ void wave_fft(cpx<T> (&r)[8], cpx<T>* __restrict__ buf,
                                          const cpx<T>* __restrict__ tw, int t) {
@@ -763,8 +797,10 @@ __device__ __forceinline__ void wave_fft(cpx<T> (&r)[8], cpx<T>* __restrict__ bu
     wave_fft128<T>(r, buf, tw, t);
   else if constexpr (N == 96)
     wave_fft96<T>(r, buf, tw, t);
-  else
+  else if constexpr (N == 64)
     wave_fft64<T>(r, buf, tw, t);
+  else
+    wave_fft32<T>(r, buf, tw, t);
 }
 
 // Forward transform of two finished real fields (b: none when !two), unpacked
@@ -817,7 +853,7 @@ __device__ __forceinline__ int xw_col_off(int kk, int ny, bool blk) {
 // the one-read schedule below needs more registers than two waves per SIMD
 // allow.
 template <typename T, int NF, int N, bool BLK>
-__global__ __launch_bounds__(64 * XW_WAVES, (N == 192 || N == 96) ? 2 : 1) void k_x_nlw_q(XArgs a, const cpx<T>* __restrict__ xyb,
+__global__ __launch_bounds__(64 * XW_WAVES, (N == 192 || N == 96 || N == 32) ? 2 : 1) void k_x_nlw_q(XArgs a, const cpx<T>* __restrict__ xyb,
                                                            cpx<T>* __restrict__ nl, long long fs,
                                                            long long nrows) {
   constexpr int NQ = 3 + 3 * NF, NP = (NQ + 1) / 2;
@@ -1156,12 +1192,13 @@ static void launch_x_nl_v(const XArgs& a, const cpx<T>* xyb, cpx<T>* nl, long lo
 }
 
 static bool x_wave_rows(int nx) {
-  return nx == 512 || nx == 256 || nx == 192 || nx == 128 || nx == 96 || nx == 64;
+  return nx == 512 || nx == 256 || nx == 192 || nx == 128 || nx == 96 || nx == 64 ||
+         nx == 32;
 }
 
 bool x_reads_blocked(const XArgs& a) { return x_wave_rows(a.nx) && a.variant == 0; }
 
-// nx = 512, 256, 192, 128, 96 and 64: wave-level rows (variant 0) or the tiled kernels; other
+// nx = 512, 256, 192, 128, 96, 64 and 32: wave-level rows (variant 0) or the tiled kernels; other
 // nx: 4 rows x 256 threads (variant 0, 1) or 8 rows x 512 threads (variant 2),
 // with compile-time plans for 512 and 256; nx <= 256: 8 rows x nx threads
 // (variant 3)
@@ -1230,10 +1267,14 @@ void launch_x_nl(const XArgs& a, bool big, const cpx<T>* xyb, cpx<T>* nl, long l
       FCNS_XW(k_x_nlw, 4, 96);
     else if (a.nx == 96)
       FCNS_XW(k_x_nlw_q, 3, 96);
-    else if (nfields == 4)
+    else if (a.nx == 64 && nfields == 4)
       FCNS_XW(k_x_nlw, 4, 64);
-    else
+    else if (a.nx == 64)
       FCNS_XW(k_x_nlw_q, 3, 64);
+    else if (nfields == 4)
+      FCNS_XW(k_x_nlw, 4, 32);
+    else
+      FCNS_XW(k_x_nlw_q, 3, 32);
 #undef FCNS_XW
   } else if (a.nx == 512 && plan_is(a.pl, {8, 8, 8}))
     launch_x_nl_v<T, SPlan<8, 8, 8>, 4, 256, 2>(a, xyb, nl, fs, nrows, nfields, st);

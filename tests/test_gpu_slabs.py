@@ -185,7 +185,7 @@ def test_tuned_choices_round_trip(fcns):
 # under variant 0 (another factorisation: equal up to rounding, checked
 # against the oracle below); the tiled variants 1-3 share one plan and agree
 # bitwise
-WAVE_ROWS = (64, 96, 128, 192, 256, 512)
+WAVE_ROWS = (32, 64, 96, 128, 192, 256, 512)
 
 
 def _xshape(kind, nx, ny, nz, seed):
@@ -235,15 +235,17 @@ def _pressure_bar(w, v0, th0, rp):
 
 
 # rows = ny * nz leaves a partial last wave (2 of 4 rows at 128; 4 or 2 of 8
-# at 64; 1 or 2 of 5 at 96), whose spare rows compute and store nothing; at
-# 192 and 96 the 16 and 4 lanes past the last whole row repeat its lanes
+# at 64; 1 or 2 of 5 at 96; 10 or 14 of 16 at 32), whose spare rows compute
+# and store nothing; at 192 and 96 the 16 and 4 lanes past the last whole
+# row repeat its lanes
 @pytest.mark.parametrize("shape", [("rb", 128, 10, 33), ("ch", 128, 14, 33), ("rb", 64, 12, 33),
                                    ("ch", 64, 10, 33), ("rb", 192, 10, 33), ("ch", 192, 14, 33),
-                                   ("rb", 96, 12, 33), ("ch", 96, 14, 33)])
+                                   ("rb", 96, 12, 33), ("ch", 96, 14, 33), ("rb", 32, 10, 33),
+                                   ("ch", 32, 14, 33)])
 def test_wave_level_x_rows_match_the_oracle(fcns, shape):
-    # two rows (192), four (128), five (96) or eight (64) per wavefront, 4 and
-    # 3 fields; the blocked intermediates are bitwise the row-major ones, and
-    # the tiled variant agrees to rounding
+    # two rows (192), four (128), five (96), eight (64) or sixteen (32) per
+    # wavefront, 4 and 3 fields; the blocked intermediates are bitwise the
+    # row-major ones, and the tiled variant agrees to rounding
     kind, nx, ny, nz = shape
     w = _xshape(kind, nx, ny, nz, 823)
     v0, th0 = w.initial_state()
