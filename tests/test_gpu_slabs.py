@@ -145,7 +145,8 @@ def test_blocked_intermediates_match_the_oracle(fcns):
 
 
 def test_layout_choices_the_kernels_lack_are_refused(fcns):
-    w = W.channel(32, 32, 33, 1000.0, C=25, dt=1e-3, steps=1, seed=817)
+    # nx = 48: no wave-level x rows (so no blocked reads); ny = 32: no 8-line tiles
+    w = W.channel(48, 32, 33, 1000.0, C=25, dt=1e-3, steps=1, seed=817)
     s = fcns.Solver.from_workload(w)
     for call, arg in ((s.set_blocked, True), (s.set_y_lines, 8), (s.set_y_lines, 6)):
         with pytest.raises(fcns.FcnsError) as e:
