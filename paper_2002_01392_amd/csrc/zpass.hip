@@ -1029,6 +1029,10 @@ int z_max_npr() { return 16 * ZNT / ZPB; }
 // the run-time engine.
 using P288 = SPlan<16, 18>;
 static bool z_static_288(const ZArgs& a) { return a.g.npr == 288 && plan_is(a.pl, {16, 18}); }
+// N' = 282 (nz = 257 with C = 25) in the radix order 47, 2, 3 (the prime
+// stage first, so it needs no twiddle pass): compiled as well
+using P282 = SPlan<47, 2, 3>;
+static bool z_static_282(const ZArgs& a) { return a.g.npr == 282 && plan_is(a.pl, {47, 2, 3}); }
 
 void launch_z_fwd(const ZArgs& a, bool big, const cpx<double>* src, cpx<double>* dst,
                   long long sfs, long long dfs, int nfields, int filter, hipStream_t st) {
@@ -1036,6 +1040,8 @@ void launch_z_fwd(const ZArgs& a, bool big, const cpx<double>* src, cpx<double>*
   const size_t sh = zshared_bytes<double>(a.g, a.pl.tsize);
   if (z_static_288(a))
     FCNS_LAUNCH((k_z_fwd<double, P288>), grid, dim3(ZNT), sh, st, a, src, dst, sfs, dfs, filter);
+  else if (z_static_282(a))
+    FCNS_LAUNCH((k_z_fwd<double, P282>), grid, dim3(ZNT), sh, st, a, src, dst, sfs, dfs, filter);
   else if (big)
     FCNS_LAUNCH((k_z_fwd<double, DynPlan<true>>), grid, dim3(ZNT), sh, st, a, src, dst, sfs, dfs,
                 filter);
@@ -1053,6 +1059,8 @@ void launch_z_back(const ZArgs& a, bool big, const cpx<double>* src, cpx<T>* dst
   const int own = pick_own(a.g.npr);
   if (z_static_288(a)) {
     FCNS_LAUNCH((k_z_back<T, P288, 9>), grid, dim3(ZNT), sh, st, a, src, dst, dzdst, sfs, mfs);
+  } else if (z_static_282(a)) {
+    FCNS_LAUNCH((k_z_back<T, P282, 9>), grid, dim3(ZNT), sh, st, a, src, dst, dzdst, sfs, mfs);
   } else if (big) {
     FCNS_OWN_SWITCH(own, FCNS_LAUNCH((k_z_back<T, DynPlan<true>, OWN>), grid, dim3(ZNT), sh, st,
                                      a, src, dst, dzdst, sfs, mfs))
@@ -1079,6 +1087,8 @@ void launch_z_stageA(const ZArgs& a, bool big, const StageAArgs& s, int nfields,
       FCNS_LAUNCH((k_z_stageA<T, TM, P288, 9, true>), grid, dim3(ZNT), sh, st, a, s);
     else
       FCNS_LAUNCH((k_z_stageA<T, TM, P288, 9, false>), grid, dim3(ZNT), sh, st, a, s);
+  } else if (z_static_282(a)) {
+    FCNS_LAUNCH((k_z_stageA<T, TM, P282, 9, false>), grid, dim3(ZNT), sh, st, a, s);
   } else if (big) {
     FCNS_OWN_SWITCH(own, FCNS_LAUNCH((k_z_stageA<T, TM, DynPlan<true>, OWN, false>), grid, dim3(ZNT),
                                      sh, st, a, s))
@@ -1095,6 +1105,8 @@ void launch_z_stageB(const ZArgs& a, bool big, const StageBArgs& s, hipStream_t 
   const size_t sh = zshared_bytes<double>(a.g, a.pl.tsize);
   if (z_static_288(a))
     FCNS_LAUNCH((k_z_stageB<double, P288, 288 / ZLS>), grid, dim3(ZNT), sh, st, a, s);
+  else if (z_static_282(a))
+    FCNS_LAUNCH((k_z_stageB<double, P282, 9>), grid, dim3(ZNT), sh, st, a, s);
   else if (big)
     FCNS_LAUNCH((k_z_stageB<double, DynPlan<true>, 0>), grid, dim3(ZNT), sh, st, a, s);
   else
@@ -1134,6 +1146,8 @@ void launch_z_pass(const ZArgs& a, bool big, const StageAArgs& sa, const StageBA
       FCNS_LAUNCH((k_z_pass<P288, 9, true>), grid, dim3(ZNT), sh, st, a, sa, sb, zb, nfields);
     else
       FCNS_LAUNCH((k_z_pass<P288, 9, false>), grid, dim3(ZNT), sh, st, a, sa, sb, zb, nfields);
+  } else if (z_static_282(a)) {
+    FCNS_LAUNCH((k_z_pass<P282, 9, false>), grid, dim3(ZNT), sh, st, a, sa, sb, zb, nfields);
   } else if (own == 9 && plan_is(a.pl, {8, 4, 7})) {
     // N' = 224, 160, 128, 96 and 64 (the sides 192, 128, 96, 64 and 32 with
     // C = 31): compiled plans, N' / 32 rows per thread

@@ -361,3 +361,27 @@ def test_compiled_z_plans_match_the_oracle(fcns, shape):
     if rth is not None:
         assert rel_l2(th, rth) < 1e-11
     assert rel_l2(p, rp) < pbar
+
+
+def test_compiled_prime_plan_matches_the_oracle(fcns):
+    # N' = 282 (nz = 257, C = 25) in the radix order 47, 2, 3 runs a compiled
+    # plan whose first stage is the cooperative 47-point DFT: split and
+    # fused z pass in FP64, split in the mixed mode
+    w = W.channel(16, 8, 257, 2000.0, d=5, C=25, dt=5e-4, steps=2, seed=826, noise_rms=0.05)
+    v0, _ = w.initial_state()
+    o = Oracle(Problem(**w.problem_kwargs()))
+    o.set_state(v0)
+    o.rk_step(w.dt, w.steps)
+    rv, _, rp = o.get_state()
+    pbar = _pressure_bar(w, v0, None, rp)
+    for precision, fused, vbar in (("fp64", 0, 1e-11), ("fp64", 1, 1e-11), ("mixed", 0, 2e-6)):
+        s = fcns.Solver.from_workload(w, precision=precision, keep_pressure=True)
+        s.set_state(torch.from_numpy(v0))
+        s.set_choices(f"zplan=47.2.3;zfused={fused}")
+        s.rk_step(w.dt, w.steps)
+        v, _, p = s.get_state(pressure=True)
+        s.synchronize()
+        print(precision, fused, f"v {rel_l2(v, rv):.1e} p {rel_l2(p, rp):.1e}", flush=True)
+        assert rel_l2(v, rv) < vbar, (precision, fused)
+        if precision == "fp64":
+            assert rel_l2(p, rp) < pbar, (precision, fused)
