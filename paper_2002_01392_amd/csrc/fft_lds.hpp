@@ -487,7 +487,7 @@ __device__ __forceinline__ cpx<T>* sfft_from(cpx<T>* src, cpx<T>* dst, int es, i
                                              int tid) {
   const cpx<T>* tws = tw + (NS > 1 ? pl.toff[S] : 0);
   const cpx<T>* cw = tw + ((R & 1) ? pl.coff[S] : 0);
-  if constexpr (R > 8)  // odd primes: the cooperative stage, with constant sizes
+  if constexpr (R % 2 == 1 && R > 8)  // odd primes: the cooperative stage, constant sizes
     fft_stage_prime<T, PAD>(src, dst, R, L, es, ls, N, NS, tws, cw, tid, NT);
   else
     sfft_stage<T, R, NS, N, L, NT, PAD>(src, dst, es, ls, tws, cw, tid);
