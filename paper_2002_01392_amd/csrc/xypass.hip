@@ -849,9 +849,10 @@ __device__ __forceinline__ int xw_col_off(int kk, int ny, bool blk) {
 // The generic schedule: real quantities in the order u, v, w, then per field
 // dq/dx, dq/dy, dq/dz, consecutive pairs sharing one inverse transform (the
 // value slots are read twice), and the forward transform of a pair of
-// finished fields as soon as both are complete.  Used for three fields, where
-// the one-read schedule below needs more registers than two waves per SIMD
-// allow.
+// finished fields as soon as both are complete.  Used for three fields at
+// 512 points, where the one-read schedule below needs more registers than
+// two waves per SIMD allow, and at 192, where it spills more (three fields
+// elsewhere: the one-read schedule, 7% faster at 256 and 9% at 128).
 template <typename T, int NF, int N, bool BLK>
 __global__ __launch_bounds__(64 * XW_WAVES, (N == 192 || N == 96 || N == 32) ? 2 : 1) void k_x_nlw_q(XArgs a, const cpx<T>* __restrict__ xyb,
                                                            cpx<T>* __restrict__ nl, long long fs,
@@ -968,15 +969,16 @@ template <typename T, int NF, int N, bool BLK>
 __global__ __launch_bounds__(64 * XW_WAVES, (N == 192 || N == 128 || N == 96) ? 2 : 1) void k_x_nlw(XArgs a, const cpx<T>* __restrict__ xyb,
                                                          cpx<T>* __restrict__ nl, long long fs,
                                                          long long nrows) {
-  // Four fields: pairs of real quantities per complex transform, each
-  // spectral slot read once: (u, du/dx), (v, dv/dx), (w, dw/dx) from one
-  // load each (the x derivative is i k~x times the same coefficients), then
-  // (dq_f/dy, dq_f/dz) for f = 0..2, and for theta (dq/dx, dq/dy), (dq/dz).
+  // Three or four fields: pairs of real quantities per complex transform,
+  // each spectral slot read once: (u, du/dx), (v, dv/dx), (w, dw/dx) from
+  // one load each (the x derivative is i k~x times the same coefficients),
+  // then (dq_f/dy, dq_f/dz) for f = 0..2, and for theta (dq/dx, dq/dy), (dq/dz).
   // NL_f = -(u dq_f/dx + v dq_f/dy + w dq_f/dz) accumulates in that order
   // as soon as u is known; each pair of finished fields is transformed
   // forward together.
-  static_assert(NF == 4, "three fields use k_x_nlw_q");
-  constexpr int NP = 8;
+  static_assert(NF == 3 || NF == 4, "three or four fields");
+  constexpr int NP = NF == 4 ? 8 : 6;
+  constexpr int TH = NF - 1;  // theta's accumulator (four fields)
   constexpr int S = N / 8, RPW = 64 / S;  // lanes per row, rows per wave
   __shared__ cpx<T> tw[XW_TW];
   __shared__ cpx<T> xbuf[XW_WAVES][XW_BUF];
@@ -1053,10 +1055,10 @@ __global__ __launch_bounds__(64 * XW_WAVES, (N == 192 || N == 128 || N == 96) ? 
           acc[p - 3][m] -= U[1][m] * va;    // -v dq/dy
           acc[p - 3][m] -= U[2][m] * vb;    // -w dq/dz
         } else if (p == 6) {
-          acc[3][m] = -U[0][m] * va;
-          acc[3][m] -= U[1][m] * vb;
+          acc[TH][m] = -U[0][m] * va;
+          acc[TH][m] -= U[1][m] * vb;
         } else {
-          acc[3][m] -= U[2][m] * va;
+          acc[TH][m] -= U[2][m] * va;
         }
       }
       if (p == 4) {
@@ -1065,11 +1067,12 @@ __global__ __launch_bounds__(64 * XW_WAVES, (N == 192 || N == 128 || N == 96) ? 
         for (int m = 0; m < 8; ++m) z[m] = mk(acc[0][m], acc[1][m]);
         xw_forward<T, N>(z, buf, tw, t, nl, fs, row, nkxp, 0, true, valid);
       }
-      if (p == 7) {
+      if (p == NP - 1) {
+        // the last field(s): 2 and theta together, or 2 alone
         cpx<T> z[8];
 #pragma unroll
-        for (int m = 0; m < 8; ++m) z[m] = mk(acc[2][m], acc[3][m]);
-        xw_forward<T, N>(z, buf, tw, t, nl, fs, row, nkxp, 2, true, valid);
+        for (int m = 0; m < 8; ++m) z[m] = mk(acc[2][m], NF == 4 ? acc[TH][m] : T(0));
+        xw_forward<T, N>(z, buf, tw, t, nl, fs, row, nkxp, 2, NF == 4, valid);
       }
     }
     // (the next row's loads stay behind this row's last transform)
@@ -1254,7 +1257,7 @@ void launch_x_nl(const XArgs& a, bool big, const cpx<T>* xyb, cpx<T>* nl, long l
     else if (a.nx == 256 && nfields == 4)
       FCNS_XW(k_x_nlw, 4, 256);
     else if (a.nx == 256)
-      FCNS_XW(k_x_nlw_q, 3, 256);
+      FCNS_XW(k_x_nlw, 3, 256);
     else if (a.nx == 192 && nfields == 4)
       FCNS_XW(k_x_nlw, 4, 192);
     else if (a.nx == 192)
@@ -1262,19 +1265,19 @@ void launch_x_nl(const XArgs& a, bool big, const cpx<T>* xyb, cpx<T>* nl, long l
     else if (a.nx == 128 && nfields == 4)
       FCNS_XW(k_x_nlw, 4, 128);
     else if (a.nx == 128)
-      FCNS_XW(k_x_nlw_q, 3, 128);
+      FCNS_XW(k_x_nlw, 3, 128);
     else if (a.nx == 96 && nfields == 4)
       FCNS_XW(k_x_nlw, 4, 96);
     else if (a.nx == 96)
-      FCNS_XW(k_x_nlw_q, 3, 96);
+      FCNS_XW(k_x_nlw, 3, 96);
     else if (a.nx == 64 && nfields == 4)
       FCNS_XW(k_x_nlw, 4, 64);
     else if (a.nx == 64)
-      FCNS_XW(k_x_nlw_q, 3, 64);
+      FCNS_XW(k_x_nlw, 3, 64);
     else if (nfields == 4)
       FCNS_XW(k_x_nlw, 4, 32);
     else
-      FCNS_XW(k_x_nlw_q, 3, 32);
+      FCNS_XW(k_x_nlw, 3, 32);
 #undef FCNS_XW
   } else if (a.nx == 512 && plan_is(a.pl, {8, 8, 8}))
     launch_x_nl_v<T, SPlan<8, 8, 8>, 4, 256, 2>(a, xyb, nl, fs, nrows, nfields, st);
