@@ -1103,12 +1103,19 @@ template void launch_z_stageA<float>(const ZArgs&, bool, const StageAArgs&, int,
 void launch_z_stageB(const ZArgs& a, bool big, const StageBArgs& s, hipStream_t st) {
   dim3 grid((unsigned)((a.g.npen + ZPB - 1) / ZPB), 1);
   const size_t sh = zshared_bytes<double>(a.g, a.pl.tsize);
+  const int own = pick_own(a.g.npr);
   if (z_static_288(a))
     FCNS_LAUNCH((k_z_stageB<double, P288, 288 / ZLS>), grid, dim3(ZNT), sh, st, a, s);
   else if (z_static_282(a))
     FCNS_LAUNCH((k_z_stageB<double, P282, 9>), grid, dim3(ZNT), sh, st, a, s);
+  // run-time plans: V* held in registers (9 rows per thread) for
+  // 128 < N' <= 288 without primes above 7 (224: 0.145 -> 0.113 ms at side
+  // 192; with such primes it would leave one wave per SIMD, and 4 rows for
+  // N' <= 128 measured no faster than streaming V* twice)
   else if (big)
     FCNS_LAUNCH((k_z_stageB<double, DynPlan<true>, 0>), grid, dim3(ZNT), sh, st, a, s);
+  else if (own == 9)
+    FCNS_LAUNCH((k_z_stageB<double, DynPlan<false>, 9>), grid, dim3(ZNT), sh, st, a, s);
   else
     FCNS_LAUNCH((k_z_stageB<double, DynPlan<false>, 0>), grid, dim3(ZNT), sh, st, a, s);
 }

@@ -341,26 +341,30 @@ def test_compiled_y_plans_match_the_oracle(fcns, shape):
                                    ("ch", 16, 16, 65), ("rb", 16, 16, 33)])
 def test_compiled_z_plans_match_the_oracle(fcns, shape):
     # N' = 224, 160, 128, 96 and 64 (C = 31): the fused z pass with the
-    # compiled 8 x 4 x 7, 8 x 4 x 5, 8 x 8 x 2, 8 x 4 x 3 and 8 x 8 transforms
+    # compiled 8 x 4 x 7, 8 x 4 x 5, 8 x 8 x 2, 8 x 4 x 3 and 8 x 8
+    # transforms, and the split z kernels (run-time plans; stage B holds V*
+    # in registers for 128 < N' <= 288)
     kind, nx, ny, nz = shape
     w = _xshape(kind, nx, ny, nz, 825)
     v0, th0 = w.initial_state()
-    s = fcns.Solver.from_workload(w, keep_pressure=True)
-    s.set_state(torch.from_numpy(v0), torch.from_numpy(th0) if th0 is not None else None)
-    s.set_choices("zfused=1")
-    s.rk_step(w.dt, w.steps)
-    v, th, p = s.get_state(pressure=True)
-    s.synchronize()
     o = Oracle(Problem(**w.problem_kwargs()))
     o.set_state(v0, th0)
     o.rk_step(w.dt, w.steps)
     rv, rth, rp = o.get_state()
     pbar = _pressure_bar(w, v0, th0, rp)
-    print(shape, f"v {rel_l2(v, rv):.1e} p {rel_l2(p, rp):.1e} (bar {pbar:.1e})", flush=True)
-    assert rel_l2(v, rv) < 1e-11
-    if rth is not None:
-        assert rel_l2(th, rth) < 1e-11
-    assert rel_l2(p, rp) < pbar
+    for fused in (1, 0):
+        s = fcns.Solver.from_workload(w, keep_pressure=True)
+        s.set_state(torch.from_numpy(v0), torch.from_numpy(th0) if th0 is not None else None)
+        s.set_choices(f"zfused={fused}")
+        s.rk_step(w.dt, w.steps)
+        v, th, p = s.get_state(pressure=True)
+        s.synchronize()
+        print(shape, fused, f"v {rel_l2(v, rv):.1e} p {rel_l2(p, rp):.1e} (bar {pbar:.1e})",
+              flush=True)
+        assert rel_l2(v, rv) < 1e-11, fused
+        if rth is not None:
+            assert rel_l2(th, rth) < 1e-11, fused
+        assert rel_l2(p, rp) < pbar, fused
 
 
 def test_compiled_prime_plan_matches_the_oracle(fcns):
