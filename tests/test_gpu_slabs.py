@@ -276,6 +276,22 @@ def test_wave_level_x_rows_match_the_oracle(fcns, shape):
             assert rel_l2(th, rth) < 1e-11, (shape, name)
         assert rel_l2(p, rp) < pbar, (shape, name)
     assert rel_l2(got["rows"][0], got["tiled"][0].cpu().numpy()) < 1e-13
+    # the FP32 instances of the same kernels (mixed mode): velocity and
+    # temperature at the mixed bound, blocked and row-major bitwise alike
+    mixed = []
+    for blk in (0, 1):
+        s = fcns.Solver.from_workload(w, precision="mixed")
+        s.set_state(torch.from_numpy(v0), torch.from_numpy(th0) if th0 is not None else None)
+        s.set_choices(f"xvar=0;blocked={blk}")
+        s.rk_step(w.dt, w.steps)
+        mixed.append(s.get_state())
+        s.synchronize()
+    v, th, _ = mixed[0]
+    print(shape, "mixed", f"v {rel_l2(v, rv):.1e}", flush=True)
+    assert rel_l2(v, rv) < 2e-6, shape
+    if rth is not None:
+        assert rel_l2(th, rth) < 2e-6, shape
+    assert torch.equal(mixed[0][0], mixed[1][0])
 
 
 def test_tuned_choices_round_trip_with_a_prime_length(fcns):
